@@ -1,0 +1,295 @@
+"""Reference oracle for the Randompack hot path -- TEST INFRASTRUCTURE ONLY.
+
+Plain, slow CPU implementations of what the GPU library computes, written from
+the paper (Randompack, arXiv 2605.05099) and pinned in tests/test_oracle_*.py.
+Only the test suite, ``__graft_entry__.smoke`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package; the product path never does.
+
+The C core is ``oracle/oracle.c`` (built into ``liboracle.so`` by
+``oracle/build.py``); this module wraps it with ctypes and adds the stream
+construction recipes (seeding, stream setters, jumps) used by the workloads.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+from . import jumppoly
+
+X256PP, PCG64, PHILOX4X32, PHILOX4X64, SFC64, RANLUX = range(6)
+ENGINE_IDS = {"x256++": X256PP, "pcg64": PCG64, "philox4x32": PHILOX4X32,
+              "philox": PHILOX4X64, "sfc64": SFC64, "ranlux++": RANLUX}
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.build()
+        _lib = ctypes.CDLL(path)
+        vp, sz, u64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64
+        sig = {
+            "or_stream_words": ([], sz), "or_counts_words": ([], sz),
+            "or_seed": ([vp, u64, u64, vp, sz], ctypes.c_int),
+            "or_set_state": ([vp, u64, vp, sz, u64], ctypes.c_int),
+            "or_pcg64_set_inc": ([vp, u64, u64], ctypes.c_int),
+            "or_philox_set_key": ([vp, u64, u64], ctypes.c_int),
+            "or_sfc64_set_abc": ([vp, u64, u64, u64], None),
+            "or_x256_apply_poly": ([vp, vp], ctypes.c_int),
+            "or_x256_linear_steps": ([vp, vp, sz], None),
+            "or_pcg64_advance": ([vp, u64, u64], ctypes.c_int),
+            "or_philox_advance": ([vp, u64, u64], ctypes.c_int),
+            "or_ranlux_advance": ([vp, u64, u64], ctypes.c_int),
+            "or_raw64": ([vp, vp, sz], None), "or_raw32": ([vp, vp, sz], None),
+            "or_u01": ([vp, vp, sz, ctypes.c_int], None),
+            "or_u01f": ([vp, vp, sz, ctypes.c_int], None),
+            "or_bounded64": ([vp, u64, vp, sz], None),
+            "or_bounded32": ([vp, ctypes.c_uint32, vp, sz], None),
+            "or_norm": ([vp, vp, sz, vp], None), "or_exp": ([vp, vp, sz, vp], None),
+            "or_norm_moments": ([vp, sz, vp, vp], None),
+            "or_gamma": ([vp, ctypes.c_double, vp, sz, vp], None),
+            "or_beta": ([vp, ctypes.c_double, ctypes.c_double, vp, sz], None),
+            "or_gamma_batched": ([vp, vp, vp, sz, vp], None),
+            "or_beta_batched": ([vp, vp, vp, vp, sz, vp], None),
+            "or_gamma_elem": ([vp, vp, vp, sz], None),
+            "or_beta_elem": ([vp, vp, vp, vp, sz], None),
+            "or_mvn_z": ([vp, ctypes.c_int, sz, vp], None),
+            "or_boost_pow": ([ctypes.c_double, ctypes.c_double], ctypes.c_double),
+            "or_seed_seq": ([vp, sz, vp, sz], None),
+            "or_philox4x32_block": ([vp, vp, vp], None),
+            "or_philox4x64_block": ([vp, vp, vp], None),
+            "or_philox_constants": ([vp], None),
+            "or_ranlux_constants": ([vp, vp, vp], None),
+            "or_ranlux_mulmod": ([vp, vp, vp], None),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(_lib, name)
+            fn.argtypes = args
+            fn.restype = res
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _split(n):
+    n = int(n)
+    return ctypes.c_uint64(n & (2**64 - 1)), ctypes.c_uint64(n >> 64)
+
+
+class Counts:
+    FIELDS = ("words", "candidates", "pdf_evals", "tail_entries", "tail_logs", "rejections",
+              "mt_attempts", "mt_logtests")
+
+    def __init__(self):
+        self.buf = np.zeros(lib().or_counts_words(), dtype=np.uint64)
+
+    def __getattr__(self, k):
+        if k in Counts.FIELDS:
+            return int(self.buf[Counts.FIELDS.index(k)])
+        raise AttributeError(k)
+
+
+class Stream:
+    """One serial stream of the oracle (a copy of the C struct)."""
+
+    def __init__(self, engine):
+        self.engine = ENGINE_IDS[engine] if isinstance(engine, str) else int(engine)
+        self.buf = np.zeros(lib().or_stream_words(), dtype=np.uint64)
+        self.buf[0] = self.engine
+
+    # ---- construction ------------------------------------------------------
+    @classmethod
+    def seeded(cls, engine, seed, spawn_key=()):
+        s = cls(engine)
+        key = np.array(list(spawn_key), dtype=np.uint32)
+        rc = lib().or_seed(_p(s.buf), s.engine, ctypes.c_uint64(seed), _p(key) if len(key) else None,
+                           len(key))
+        assert rc == 0
+        return s
+
+    @classmethod
+    def from_state(cls, engine, words, phase=0):
+        s = cls(engine)
+        w = np.array([int(x) for x in words], dtype=np.uint64)
+        assert lib().or_set_state(_p(s.buf), s.engine, _p(w), len(w), phase) == 0
+        return s
+
+    def copy(self):
+        s = Stream(self.engine)
+        s.buf[:] = self.buf
+        return s
+
+    @property
+    def state(self):
+        return [int(x) for x in self.buf[2:18]]
+
+    @property
+    def phase(self):
+        return int(self.buf[1])
+
+    # ---- stream control ----------------------------------------------------
+    def pcg64_set_inc(self, inc):
+        lo, hi = _split(inc)
+        assert lib().or_pcg64_set_inc(_p(self.buf), lo, hi) == 0
+        return self
+
+    def philox_set_key(self, k0, k1=0):
+        assert lib().or_philox_set_key(_p(self.buf), ctypes.c_uint64(k0), ctypes.c_uint64(k1)) == 0
+        return self
+
+    def sfc64_set_abc(self, a, b, c):
+        lib().or_sfc64_set_abc(_p(self.buf), a, b, c)
+        return self
+
+    def x256_apply_poly(self, poly):
+        w = jumppoly.poly_words(poly)
+        assert lib().or_x256_apply_poly(_p(self.buf), _p(w)) == 0
+        return self
+
+    def advance(self, n):
+        """Move forward by n engine steps (blocks for block engines)."""
+        n = int(n)
+        if self.engine == X256PP:
+            p = jumppoly.x256_char_poly(lib())
+            return self.x256_apply_poly(jumppoly.xpow_mod(n, p))
+        lo, hi = _split(n)
+        fn = {PCG64: lib().or_pcg64_advance, PHILOX4X32: lib().or_philox_advance,
+              PHILOX4X64: lib().or_philox_advance, RANLUX: lib().or_ranlux_advance}[self.engine]
+        assert fn(_p(self.buf), lo, hi) == 0
+        return self
+
+    # ---- samplers ----------------------------------------------------------
+    def raw(self, n):
+        out = np.empty(n, dtype=np.uint64)
+        lib().or_raw64(_p(self.buf), _p(out), n)
+        return out
+
+    def raw32(self, n):
+        out = np.empty(n, dtype=np.uint32)
+        lib().or_raw32(_p(self.buf), _p(out), n)
+        return out
+
+    def u01(self, n, full_mantissa=True):
+        out = np.empty(n, dtype=np.float64)
+        lib().or_u01(_p(self.buf), _p(out), n, int(full_mantissa))
+        return out
+
+    def u01f(self, n, full_mantissa=True):
+        out = np.empty(n, dtype=np.float32)
+        lib().or_u01f(_p(self.buf), _p(out), n, int(full_mantissa))
+        return out
+
+    def bounded64(self, b, n):
+        out = np.empty(n, dtype=np.uint64)
+        lib().or_bounded64(_p(self.buf), ctypes.c_uint64(b), _p(out), n)
+        return out
+
+    def bounded32(self, b, n):
+        out = np.empty(n, dtype=np.uint32)
+        lib().or_bounded32(_p(self.buf), ctypes.c_uint32(b), _p(out), n)
+        return out
+
+    def norm(self, n, counts=None):
+        out = np.empty(n, dtype=np.float64)
+        lib().or_norm(_p(self.buf), _p(out), n, _p(counts.buf) if counts else None)
+        return out
+
+    def exp(self, n, counts=None):
+        out = np.empty(n, dtype=np.float64)
+        lib().or_exp(_p(self.buf), _p(out), n, _p(counts.buf) if counts else None)
+        return out
+
+    def norm_moments(self, n):
+        s = np.zeros(1)
+        q = np.zeros(1)
+        lib().or_norm_moments(_p(self.buf), n, _p(s), _p(q))
+        return float(s[0]), float(q[0])
+
+    def gamma(self, alpha, n, counts=None):
+        out = np.empty(n, dtype=np.float64)
+        lib().or_gamma(_p(self.buf), float(alpha), _p(out), n, _p(counts.buf) if counts else None)
+        return out
+
+    def beta(self, a, b, n):
+        out = np.empty(n, dtype=np.float64)
+        lib().or_beta(_p(self.buf), float(a), float(b), _p(out), n)
+        return out
+
+
+class StreamArray:
+    """Contiguous array of C stream structs (one per substream)."""
+
+    def __init__(self, streams):
+        self.n = len(streams)
+        w = lib().or_stream_words()
+        self.buf = np.zeros((self.n, w), dtype=np.uint64)
+        for i, s in enumerate(streams):
+            self.buf[i] = s.buf
+
+    def stream(self, i):
+        s = Stream(int(self.buf[i, 0]))
+        s.buf[:] = self.buf[i]
+        return s
+
+    def gamma_batched(self, alpha, count):
+        alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+        count = np.ascontiguousarray(count, dtype=np.int64)
+        out = np.empty(int(count.sum()), dtype=np.float64)
+        lib().or_gamma_batched(_p(self.buf), _p(alpha), _p(count), self.n, _p(out))
+        return out
+
+    def beta_batched(self, a, b, count):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        count = np.ascontiguousarray(count, dtype=np.int64)
+        out = np.empty(int(count.sum()), dtype=np.float64)
+        lib().or_beta_batched(_p(self.buf), _p(a), _p(b), _p(count), self.n, _p(out))
+        return out
+
+    def gamma_elem(self, alpha):
+        alpha = np.ascontiguousarray(alpha, dtype=np.float32)
+        z = np.empty(self.n, dtype=np.float32)
+        lib().or_gamma_elem(_p(self.buf), _p(alpha), _p(z), self.n)
+        return z
+
+    def beta_elem(self, a, b):
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        b = np.ascontiguousarray(b, dtype=np.float32)
+        z = np.empty(self.n, dtype=np.float32)
+        lib().or_beta_elem(_p(self.buf), _p(a), _p(b), _p(z), self.n)
+        return z
+
+    def mvn_z(self, d):
+        z = np.empty((self.n, d), dtype=np.float32)
+        lib().or_mvn_z(_p(self.buf), d, self.n, _p(z))
+        return z
+
+
+# ---- substream recipes (Section 2.3: duplicate, then set the stream or jump) --
+
+def substream(engine, seed, kind, i, jump_log2=64):
+    """Stream i of a substream family built from a base seeded with `seed`.
+
+    kind: "key"   philox: key := i (counter from the seeded base)
+          "inc"   pcg64: increment := 2 i + 1
+          "spawn" seed mixer with spawn key [i]
+          "jump"  base advanced by i * 2^jump_log2 engine steps
+    """
+    if kind == "spawn":
+        return Stream.seeded(engine, seed, [i])
+    s = Stream.seeded(engine, seed)
+    if kind == "key":
+        return s.philox_set_key(i, 0)
+    if kind == "inc":
+        return s.pcg64_set_inc(2 * i + 1)
+    if kind == "jump":
+        return s.advance(i << jump_log2)
+    raise ValueError(kind)
+
+
+def boost_pow(u, a):
+    return lib().or_boost_pow(float(u), float(a))

@@ -1,0 +1,332 @@
+"""Pins of the oracle's engines, seeding and stream control (CPU only).
+
+Each engine is pinned against something other than the oracle itself:
+NumPy's bit generators (the paper validates pcg64 against NumPy), rocRAND's
+host-side Philox4x32-10, number theory (primitivity and periods, Table 2),
+brute-force stepping, and Python big-integer arithmetic.
+"""
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+import sympy
+
+import oracle
+from oracle import Stream, jumppoly
+
+M64 = 2**64 - 1
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _pcg_np(state, inc):
+    bg = np.random.PCG64DXSM()
+    d = bg.state
+    d["state"] = {"state": state, "inc": inc}
+    bg.state = d
+    return bg
+
+
+def _pcg_or(state, inc):
+    return Stream.from_state("pcg64", [state & M64, state >> 64, inc & M64, inc >> 64])
+
+
+# ---------------------------------------------------------------- pcg64 ------
+@pytest.mark.parametrize("seed", [0, 1, 12345, 2**127 + 99])
+def test_pcg64_raw_matches_numpy(seed):
+    rng = np.random.default_rng(seed)
+    state = int(rng.integers(0, 2**63)) << 65 | int(rng.integers(0, 2**63))
+    inc = (int(rng.integers(0, 2**63)) << 64 | int(rng.integers(0, 2**63))) | 1
+    assert (_pcg_or(state, inc).raw(5000) == _pcg_np(state, inc).random_raw(5000)).all()
+
+
+@pytest.mark.parametrize("delta", [1, 7, 1000, 2**64 + 3, 2**127 - 1])
+def test_pcg64_advance_matches_numpy(delta):
+    state, inc = 0xDEADBEEF << 70 | 12345, (0xABCDEF << 80 | 777) | 1
+    s = _pcg_or(state, inc).advance(delta)
+    ref = _pcg_np(state, inc)
+    ref.advance(delta)
+    assert (s.raw(100) == ref.random_raw(100)).all()
+
+
+def test_pcg64_advance_is_brute_force():
+    state, inc = 987654321 << 64 | 5, 99 | 1
+    a = _pcg_or(state, inc).advance(3000)
+    b = _pcg_or(state, inc)
+    b.raw(3000)
+    assert a.state[:4] == b.state[:4]
+
+
+# --------------------------------------------------------------- philox ------
+def _philox64_np(ctr, key):
+    # NumPy increments the 256-bit counter before computing a block.
+    c = (sum(int(v) << (64 * i) for i, v in enumerate(ctr)) - 1) % 2**256
+    c = np.array([(c >> (64 * i)) & M64 for i in range(4)], dtype=np.uint64)
+    return np.random.Philox(counter=c, key=np.array(key, dtype=np.uint64))
+
+
+@pytest.mark.parametrize("ctr,key", [([0, 0, 0, 0], [0, 0]), ([5, 6, 7, 8], [9, 10]),
+                                     ([M64, 3, 0, 1], [M64, 2**63])])
+def test_philox4x64_matches_numpy(ctr, key):
+    s = Stream.from_state("philox", ctr + key)
+    assert (s.raw(4 * 257 + 3) == _philox64_np(ctr, key).random_raw(4 * 257 + 3)).all()
+
+
+def test_philox4x64_advance_is_counter_addition():
+    s = Stream.from_state("philox", [M64 - 2, 0, 0, 0, 1, 2]).advance(10)
+    assert s.state[:4] == [7, 1, 0, 0]
+    ref = _philox64_np([7, 1, 0, 0], [1, 2])
+    assert (s.raw(40) == ref.random_raw(40)).all()
+
+
+def test_philox_weyl_constants_derived():
+    import mpmath as mp
+    mp.mp.dps = 50
+    c = np.zeros(8, dtype=np.uint64)
+    oracle.lib().or_philox_constants(oracle._p(c))
+    phi_m1 = (mp.sqrt(5) - 1) / 2
+    s3_m1 = mp.sqrt(3) - 1
+    assert int(c[2]) == int(mp.floor(2**32 * phi_m1))
+    assert int(c[3]) == int(mp.floor(2**32 * s3_m1))
+    assert int(c[6]) == int(mp.floor(2**64 * phi_m1))
+    assert int(c[7]) == int(mp.floor(2**64 * s3_m1))
+
+
+def _rocrand_anchor(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    exe = tmp_path_factory.mktemp("anchor") / "rocrand_philox"
+    subprocess.run([hipcc, "-O1", os.path.join(ROOT, "tests", "anchors", "rocrand_philox.cpp"),
+                    "-o", str(exe)], check=True, capture_output=True)
+    return exe
+
+
+@pytest.fixture(scope="module")
+def rocrand_anchor(tmp_path_factory):
+    return _rocrand_anchor(tmp_path_factory)
+
+
+@pytest.mark.parametrize("seed,sub", [(0, 0), (42, 0), (M64, M64), (0x0123456789ABCDEF, 2**40 + 17)])
+def test_philox4x32_matches_rocrand(rocrand_anchor, seed, sub):
+    n = 4 * 50
+    out = subprocess.run([str(rocrand_anchor), str(seed), str(sub), str(n)], check=True,
+                         capture_output=True, text=True).stdout.split()
+    ref = np.array([int(x) for x in out], dtype=np.uint32)
+    # oracle stream: counter (0, 0, sub lo, sub hi) as two 64-bit words, key = seed
+    s = Stream.from_state("philox4x32", [0, sub, seed])
+    got = s.raw32(n)
+    assert (got == ref).all()
+
+
+def test_philox4x32_word_layout():
+    """A 64-bit word holds two consecutive 32-bit outputs, earlier one low."""
+    s1 = Stream.from_state("philox4x32", [3, 0, 77])
+    s2 = Stream.from_state("philox4x32", [3, 0, 77])
+    w = s1.raw(6)
+    h = s2.raw32(12)
+    assert (w == (h[0::2].astype(np.uint64) | (h[1::2].astype(np.uint64) << np.uint64(32)))).all()
+
+
+def test_philox4x32_phase_and_advance():
+    a = Stream.from_state("philox4x32", [M64, 0, 5])
+    a.raw(3)  # 1.5 blocks
+    assert a.phase == 1 and a.state[:2] == [0, 1]  # counter carried into the high word
+    b = Stream.from_state("philox4x32", [M64, 0, 5]).advance(1)
+    b.raw(1)
+    assert b.state[:3] == a.state[:3] and b.phase == a.phase
+    assert (a.raw(9) == b.raw(9)).all()
+
+
+# ---------------------------------------------------------------- sfc64 ------
+def test_sfc64_matches_numpy():
+    bg = np.random.SFC64()
+    d = bg.state
+    d["state"]["state"] = np.array([1, 2, 3, 4], dtype=np.uint64)
+    bg.state = d
+    assert (Stream.from_state("sfc64", [1, 2, 3, 4]).raw(3000) == bg.random_raw(3000)).all()
+
+
+def test_sfc64_setter_warmup_is_18_steps():
+    """Table 3 caption: the sfc64 setter advances 18 states after setting (a, b, c)."""
+    a, b, c = 0x1111, 0x2222222222, 0x3333333333333
+    s = Stream("sfc64").sfc64_set_abc(a, b, c)
+    bg = np.random.SFC64()
+    d = bg.state
+    d["state"]["state"] = np.array([a, b, c, 1], dtype=np.uint64)
+    bg.state = d
+    bg.random_raw(18)
+    assert s.state[:4] == [int(x) for x in bg.state["state"]["state"]]
+    assert s.state[3] == 19
+
+
+# --------------------------------------------------------------- xoshiro -----
+def _factor_2_256_minus_1():
+    # 2^256 - 1 = F0 F1 ... F7 (Fermat numbers); factor with sympy and verify
+    f = sympy.factorint(2**256 - 1, limit=None)
+    assert sympy.prod([p**e for p, e in f.items()]) == 2**256 - 1
+    assert all(e == 1 and sympy.isprime(p) for p, e in f.items())
+    return list(f)
+
+
+@pytest.mark.slow
+def test_x256_linear_core_is_primitive():
+    """Table 2: period 2^256 - 1 <=> the characteristic polynomial of T is primitive."""
+    p = jumppoly.x256_char_poly(oracle.lib())
+    assert p.bit_length() - 1 == 256
+    order = 2**256 - 1
+    assert jumppoly.xpow_mod(order, p) == 1
+    for q in _factor_2_256_minus_1():
+        assert jumppoly.xpow_mod(order // q, p) != 1, q
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 256, 257, 1000, 4097])
+def test_x256_jump_equals_brute_force(n):
+    base = Stream.seeded("x256++", 12345)
+    a = base.copy().advance(n)
+    b = base.copy()
+    b.raw(n)
+    assert a.state[:4] == b.state[:4]
+
+
+def test_x256_jump_composes():
+    base = Stream.seeded("x256++", 7)
+    a = base.copy().advance(2**64).advance(2**64)
+    b = base.copy().advance(2**65)
+    assert a.state[:4] == b.state[:4]
+    c = base.copy().advance(2**256 - 1)  # full period returns to the start
+    assert c.state[:4] == base.state[:4]
+
+
+# --------------------------------------------------------------- ranlux++ ----
+def _ranlux_consts():
+    m = np.zeros(10, dtype=np.uint64)
+    a = np.zeros(9, dtype=np.uint64)
+    A = np.zeros(9, dtype=np.uint64)
+    oracle.lib().or_ranlux_constants(oracle._p(m), oracle._p(a), oracle._p(A))
+    to_int = lambda v: sum(int(x) << (64 * i) for i, x in enumerate(v))
+    return to_int(m), to_int(a), to_int(A)
+
+
+def test_ranlux_modulus_and_multiplier():
+    m, a, A = _ranlux_consts()
+    b, r, s = 2**24, 24, 10   # RANLUX subtract-with-borrow parameters
+    assert m == b**r - b**s + 1
+    assert sympy.isprime(m)
+    assert a == m - (m - 1) // b
+    assert (a * b) % m == 1          # multiplying by a divides by the base
+    assert A == pow(a, 2048, m)
+
+
+@pytest.mark.slow
+def test_ranlux_period_about_2_570():
+    """Table 2: period ~2^570 (order of a in the multiplicative group mod m)."""
+    m, a, _ = _ranlux_consts()
+    n = (m - 1) // 48
+    assert pow(a, n, m) == 1
+    assert pow(a, n // 2, m) != 1 and pow(a, n // 3, m) != 1
+    assert 570 < np.log2(float(n)) < 571
+
+
+def test_ranlux_mulmod_matches_bigint():
+    m, _, _ = _ranlux_consts()
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        x = int.from_bytes(rng.bytes(72), "little") % m
+        y = int.from_bytes(rng.bytes(72), "little") % m
+        xa = np.array([(x >> (64 * i)) & M64 for i in range(9)], dtype=np.uint64)
+        ya = np.array([(y >> (64 * i)) & M64 for i in range(9)], dtype=np.uint64)
+        r = np.zeros(9, dtype=np.uint64)
+        oracle.lib().or_ranlux_mulmod(oracle._p(r), oracle._p(xa), oracle._p(ya))
+        assert sum(int(v) << (64 * i) for i, v in enumerate(r)) == (x * y) % m
+    # edge: m - 1 squared
+    x = m - 1
+    xa = np.array([(x >> (64 * i)) & M64 for i in range(9)], dtype=np.uint64)
+    r = np.zeros(9, dtype=np.uint64)
+    oracle.lib().or_ranlux_mulmod(oracle._p(r), oracle._p(xa), oracle._p(xa))
+    assert sum(int(v) << (64 * i) for i, v in enumerate(r)) == 1
+
+
+def test_ranlux_output_is_limbs_of_successive_states():
+    m, _, A = _ranlux_consts()
+    s = Stream.seeded("ranlux++", 42)
+    x = sum(v << (64 * i) for i, v in enumerate(s.state[:9]))
+    assert 0 < x < m
+    words = s.raw(9 * 5 + 4)
+    for blk in range(6):
+        x = (A * x) % m
+        limbs = [(x >> (64 * i)) & M64 for i in range(9)]
+        got = [int(w) for w in words[9 * blk: 9 * blk + 9]]
+        assert got == limbs[: len(got)]
+
+
+def test_ranlux_advance():
+    m, _, A = _ranlux_consts()
+    s = Stream.seeded("ranlux++", 42)
+    x = sum(v << (64 * i) for i, v in enumerate(s.state[:9]))
+    n = 3 * 2**64 + 5
+    t = s.copy().advance(n)
+    assert sum(v << (64 * i) for i, v in enumerate(t.state[:9])) == (pow(A, n, m) * x) % m
+    u = s.copy()
+    u.raw(9 * 7)
+    assert u.state[:9] == s.copy().advance(7).state[:9]
+
+
+# --------------------------------------------------------------- seeding -----
+@pytest.mark.parametrize("words", [[42, 0], [12345, 0], [0, 0], [42, 0, 7], [1, 2, 3, 4],
+                                   [5, 6, 7, 8, 9, 10, 11], list(range(40))])
+@pytest.mark.parametrize("n_out", [1, 6, 18])
+def test_seed_mixer_matches_numpy_seedsequence(words, n_out):
+    """Section 2.3: seed_seq_fe128; NumPy's SeedSequence implements the same mixer."""
+    w = np.array(words, dtype=np.uint32)
+    out = np.zeros(n_out, dtype=np.uint32)
+    oracle.lib().or_seed_seq(oracle._p(w), len(w), oracle._p(out), n_out)
+    assert (out == np.random.SeedSequence(entropy=w).generate_state(n_out, np.uint32)).all()
+
+
+@pytest.mark.parametrize("seed", [42, 12345, 0x0000000100000002, 2**64 - 1])
+@pytest.mark.parametrize("key", [(), (0,), (9,), (1, 2, 3)])
+def test_seeding_layout(seed, key):
+    """Seed words [lo(seed), hi(seed)], zero-padded to the pool size when a spawn
+    key follows; 64-bit state words from pairs of mixer words, low first.  This
+    equals NumPy's SeedSequence(seed, spawn_key=key)."""
+    ss = np.random.SeedSequence(entropy=seed, spawn_key=key).generate_state(8, np.uint64)
+    s = Stream.seeded("x256++", seed, key)
+    assert s.state[:4] == [int(x) for x in ss[:4]]
+    p = Stream.seeded("pcg64", seed, key)
+    assert p.state[:4] == [int(ss[0]), int(ss[1]), int(ss[2]) | 1, int(ss[3])]
+
+
+def test_seeding_avalanche():
+    """O'Neill's aim (Section 2.3): flipping one seed bit flips each output bit w.p. 1/2."""
+    base = Stream.seeded("x256++", 42).state[:4]
+    flips = []
+    for bit in range(64):
+        other = Stream.seeded("x256++", 42 ^ (1 << bit)).state[:4]
+        flips.append(sum(bin(a ^ b).count("1") for a, b in zip(base, other)))
+    flips = np.array(flips)
+    # 64 trials of Binomial(256, 1/2): mean 128, sd 8
+    assert abs(flips.mean() - 128) < 4
+    assert flips.min() > 128 - 48 and flips.max() < 128 + 48
+
+
+def test_distinct_seeds_and_keys_give_distinct_streams():
+    outs = {tuple(Stream.seeded(e, sd, k).raw(4)) for e in ["x256++", "pcg64", "sfc64", "philox4x32"]
+            for sd in [0, 1, 42] for k in [(), (0,), (1,)]}
+    assert len(outs) == 4 * 3 * 3
+
+
+def test_same_seed_same_stream():
+    for e in oracle.ENGINE_IDS:
+        assert (Stream.seeded(e, 99, [3]).raw(50) == Stream.seeded(e, 99, [3]).raw(50)).all()
+
+
+def test_substream_recipes():
+    base = Stream.seeded("philox4x32", 42)
+    s5 = oracle.substream("philox4x32", 42, "key", 5)
+    assert s5.state[:2] == base.state[:2] and s5.state[2] == 5
+    p = oracle.substream("pcg64", 42, "inc", 7)
+    assert p.state[2] == 15 and p.state[3] == 0
+    r = oracle.substream("ranlux++", 42, "jump", 3)
+    assert r.state[:9] == Stream.seeded("ranlux++", 42).advance(3 << 64).state[:9]
