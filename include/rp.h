@@ -1,0 +1,160 @@
+/*
+ * rp.h -- C ABI of the MI355X (gfx950) implementation of the Randompack hot
+ * path: bulk generation from the paper's engines on many independent
+ * substreams, fed through its distribution layer (Randompack, arXiv
+ * 2605.05099).
+ *
+ * Conventions (Section 2.1, Section 4.4 "Thread safety"):
+ *   - Every call returns int: RP_OK (0) or a negative RP_E* code.  No
+ *     exception crosses the ABI.  A message describing the last failure is
+ *     kept per handle (rp_last_error) and per thread (rp_errmsg) for calls
+ *     without a handle.
+ *   - Handles (rp_rng, rp_streams) are opaque, created and freed by the
+ *     library.  One handle must not be used by two threads at once; distinct
+ *     handles are independent (no global mutable state except the per-thread
+ *     error slot and read-only tables).
+ *   - NULL pointers where an object is required give RP_ENULL.  A count of
+ *     zero is valid and does nothing.
+ *   - Device pointers ("d_" prefix) point to GPU memory the caller owns;
+ *     host pointers point to host memory.  Launches are asynchronous on the
+ *     given HIP stream (a hipStream_t passed as void*; NULL = default
+ *     stream).  Errors found before launch are reported synchronously; a
+ *     launch failure is reported as RP_EDEVICE.
+ *
+ * Engines (Table 2; philox4x32 is the 32-bit member of the paper's Philox
+ * family).  Identifiers are matched case-insensitively with no aliases
+ * (Section 4.4, "Engine query").
+ */
+#ifndef RP_H
+#define RP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+enum {
+    RP_OK = 0,
+    RP_EINVAL = -1,       /* invalid argument value                          */
+    RP_ENOMEM = -2,       /* host or device allocation failed                */
+    RP_EUNSUPPORTED = -3, /* operation not defined for this engine / dtype   */
+    RP_EDEVICE = -4,      /* HIP runtime or kernel launch error              */
+    RP_ENOTSPD = -5,      /* matrix is not symmetric positive definite       */
+    RP_ENULL = -6         /* required pointer was NULL                       */
+};
+
+/* ---- engines (Table 2) -------------------------------------------------- */
+enum {
+    RP_X256PP = 0,     /* "x256++"     xoshiro256++, 4 state words          */
+    RP_PCG64 = 1,      /* "pcg64"      PCG64 DXSM, state 2 + increment 2    */
+    RP_PHILOX4X32 = 2, /* "philox4x32" Philox4x32-10, counter 2 + key 1     */
+    RP_PHILOX = 3,     /* "philox"     Philox-4x64-10, counter 4 + key 2    */
+    RP_SFC64 = 4,      /* "sfc64"      sfc64, (a, b, c) + counter           */
+    RP_RANLUX = 5,     /* "ranlux++"   ranlux++, 9 words (576-bit LCG)      */
+    RP_NENGINES = 6
+};
+
+typedef struct rp_rng rp_rng;         /* one serial stream, host resident  */
+typedef struct rp_streams rp_streams; /* n substreams, device resident     */
+
+/* ---- errors and engine query -------------------------------------------- */
+/* Message of the last failed call on this thread ("" if none). */
+const char *rp_errmsg(void);
+/* Message of the last failed call on this handle; NULL handle = rp_errmsg. */
+const char *rp_last_error(const rp_rng *rng);
+/* Writes "id: description" lines for all engines into buf (NUL-terminated,
+ * truncated to len).  Returns the length needed (excluding NUL). */
+int rp_engines(char *buf, size_t len);
+/* Engine number of an identifier (case-insensitive), or RP_EINVAL. */
+int rp_engine_id(const char *name);
+
+/* ---- serial streams (Section 2.1, Section 2.3) -------------------------- */
+/* Creates a stream; NULL or "" selects x256++.  The state is seeded from
+ * seed 0 with no spawn key (randomisation from OS entropy is not part of this
+ * library; call rp_seed).  Returns NULL on failure (see rp_errmsg). */
+rp_rng *rp_create(const char *engine);
+void rp_free(rp_rng *rng);
+/* Exact copy (Section 2.3 "duplicate"). */
+rp_rng *rp_duplicate(const rp_rng *rng);
+/* Deterministic seeding (Section 2.3): the seed (two 32-bit words, low
+ * first), zero-padded to four words when a spawn key follows, then the
+ * spawn-key words, go through the seed_seq_fe128 mixer, which is asked for
+ * two 32-bit words per 64-bit state word.  n_key = 0 means no key. */
+int rp_seed(rp_rng *rng, uint64_t seed, const uint32_t *spawn_key, size_t n_key);
+/* Number of 64-bit state words of the engine (Table 2 "State words"). */
+int rp_state_words(const rp_rng *rng);
+/* Exact state get/set (Section 2.3 "set_state").  words has
+ * rp_state_words() entries in Table 3 order; phase is the number of 64-bit
+ * words already used from the current output block (always 0 except for
+ * philox4x32 (< 2), philox (< 4) and ranlux++ (< 9)). */
+int rp_get_state(const rp_rng *rng, uint64_t *words, size_t n, uint32_t *phase);
+int rp_set_state(rp_rng *rng, const uint64_t *words, size_t n, uint32_t phase);
+/* Jump by 2^k engine steps, k in {32, 64, 96, 128, 192} (Section 2.3). */
+int rp_jump(rp_rng *rng, int k);
+/* Advance by n = lo + hi 2^64 engine steps (a block for block engines):
+ * PCG64 affine powering, Philox counter addition, xoshiro256++ jump
+ * polynomial x^n mod P(x) (Section 4.4 "Jumping"), ranlux++ A^n mod m.
+ * sfc64 has no jump: RP_EUNSUPPORTED. */
+int rp_advance(rp_rng *rng, uint64_t lo, uint64_t hi);
+/* Stream setters (Table 3). */
+int rp_pcg64_set_inc(rp_rng *rng, uint64_t lo, uint64_t hi);       /* inc |= 1 */
+int rp_philox_set_key(rp_rng *rng, uint64_t k0, uint64_t k1);      /* 4x32: key = k0 */
+int rp_sfc64_set_abc(rp_rng *rng, uint64_t a, uint64_t b, uint64_t c); /* +18 steps */
+/* Checkpointing (Section 4.4): opaque byte image of the stream.  With
+ * buf == NULL only *needed is set. */
+int rp_serialize(const rp_rng *rng, void *buf, size_t len, size_t *needed);
+int rp_deserialize(rp_rng *rng, const void *buf, size_t len);
+/* Host reference draw of raw 64-bit words (used for state checks). */
+int rp_raw_host(rp_rng *rng, uint64_t *out, size_t n);
+
+/* ---- device substreams (Section 2.3: duplicate, then set stream or jump) - */
+enum {
+    RP_SUB_KEY = 0,   /* philox*: substream i has key i (k1 = 0)             */
+    RP_SUB_INC = 1,   /* pcg64: substream i has increment 2 i + 1            */
+    RP_SUB_SPAWN = 2, /* any engine: seeded with (seed, spawn key [i])       */
+    RP_SUB_JUMP = 3   /* x256++, pcg64, ranlux++, philox*: base advanced by  */
+                      /*   i * 2^jump_log2 engine steps                      */
+};
+/* Builds n substreams from `base` (its seed is remembered by rp_seed) and
+ * copies them to device memory owned by the returned handle.  The state
+ * layout in device memory is structure-of-arrays: state word k of substream
+ * i at words[k * n + i], phase[i] separately. */
+int rp_streams_create(const rp_rng *base, int kind, uint64_t n, int jump_log2, rp_streams **out);
+void rp_streams_free(rp_streams *s);
+uint64_t rp_streams_count(const rp_streams *s);
+int rp_streams_engine(const rp_streams *s);
+/* Copies substream states to / from host memory: words is
+ * state_words * n (SoA as above), phase is n entries. */
+int rp_streams_get(const rp_streams *s, uint64_t *words, uint32_t *phase);
+int rp_streams_set(rp_streams *s, const uint64_t *words, const uint32_t *phase);
+/* New handle holding a device copy of the current states. */
+int rp_streams_duplicate(const rp_streams *s, rp_streams **out);
+
+/* ---- bulk fills (Tables 4 and 5, Section 3) ------------------------------ */
+enum {
+    RP_RAW = 0,     /* raw bits: U64 words, or U32 halves (low half first)   */
+    RP_U01 = 1,     /* uniform [0,1): F64 from the top 53 bits (or 52, flag),*/
+                    /*   F32 from the top 24 bits of a 32-bit half (or 23)   */
+    RP_BOUNDED = 2, /* {0..b-1} by Lemire's method, U64 or U32; b = 0: full  */
+    RP_NORM = 3,    /* standard normal, ziggurat, F64                        */
+    RP_EXP = 4      /* standard exponential, ziggurat, F64                   */
+};
+enum { RP_U64 = 0, RP_U32 = 1, RP_F64 = 2, RP_F32 = 3 };
+enum { RP_FLAG_52BIT = 1 }; /* uniform method 2 (mantissa fill, 52/23 bits) */
+
+/* Fills d_out[i * per_stream + t] (substream-major) with the next per_stream
+ * values of substream i, for every substream, and advances each substream
+ * past the words it used, so a second call continues the streams.  32-bit
+ * outputs use the two halves of each word, low first; a half left over at
+ * the end of a call is dropped.  d_out must hold n * per_stream elements of
+ * dtype and be aligned to the element size. */
+int rp_fill(rp_streams *s, int dist, int dtype, uint64_t bound, int flags, void *d_out,
+            uint64_t per_stream, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RP_H */

@@ -40,8 +40,8 @@ def lib():
             "or_x256_apply_poly": ([vp, vp], ctypes.c_int),
             "or_x256_linear_steps": ([vp, vp, sz], None),
             "or_pcg64_advance": ([vp, u64, u64], ctypes.c_int),
-            "or_philox_advance": ([vp, u64, u64], ctypes.c_int),
-            "or_ranlux_advance": ([vp, u64, u64], ctypes.c_int),
+            "or_philox_advance": ([vp, vp], ctypes.c_int),
+            "or_ranlux_advance": ([vp, vp], ctypes.c_int),
             "or_raw64": ([vp, vp, sz], None), "or_raw32": ([vp, vp, sz], None),
             "or_u01": ([vp, vp, sz, ctypes.c_int], None),
             "or_u01f": ([vp, vp, sz, ctypes.c_int], None),
@@ -156,10 +156,15 @@ class Stream:
         if self.engine == X256PP:
             p = jumppoly.x256_char_poly(lib())
             return self.x256_apply_poly(jumppoly.xpow_mod(n, p))
-        lo, hi = _split(n)
-        fn = {PCG64: lib().or_pcg64_advance, PHILOX4X32: lib().or_philox_advance,
-              PHILOX4X64: lib().or_philox_advance, RANLUX: lib().or_ranlux_advance}[self.engine]
-        assert fn(_p(self.buf), lo, hi) == 0
+        if self.engine == PCG64:
+            lo, hi = _split(n % 2**128)
+            assert lib().or_pcg64_advance(_p(self.buf), lo, hi) == 0
+            return self
+        limbs = np.array([(n >> (64 * i)) & (2**64 - 1) for i in range(4)], dtype=np.uint64)
+        assert n < 2**256
+        fn = {PHILOX4X32: lib().or_philox_advance, PHILOX4X64: lib().or_philox_advance,
+              RANLUX: lib().or_ranlux_advance}[self.engine]
+        assert fn(_p(self.buf), _p(limbs)) == 0
         return self
 
     # ---- samplers ----------------------------------------------------------

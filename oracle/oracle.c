@@ -726,17 +726,17 @@ int or_pcg64_advance(or_stream *s, uint64_t dlo, uint64_t dhi)
     return 0;
 }
 
-/* philox: advance the block counter by delta blocks (256-bit counter for
- * 4x64 with a 128-bit delta; 128-bit counter for 4x32). */
-int or_philox_advance(or_stream *s, uint64_t dlo, uint64_t dhi)
+/* philox: advance the block counter by delta blocks; delta is given as four
+ * 64-bit limbs (the 4x64 counter is 256 bits, the 4x32 counter 128 bits,
+ * both wrapping). */
+int or_philox_advance(or_stream *s, const uint64_t d[4])
 {
     if (s->engine == OR_PHILOX4X32) {
         u128 c = ((u128)s->st[1] << 64) | s->st[0];
-        c += ((u128)dhi << 64) | dlo;
+        c += ((u128)d[1] << 64) | d[0];
         s->st[0] = (uint64_t)c;
         s->st[1] = (uint64_t)(c >> 64);
     } else if (s->engine == OR_PHILOX4X64) {
-        uint64_t d[4] = {dlo, dhi, 0, 0};
         mp_add(&s->st[0], &s->st[0], d, 4);
     } else {
         return -1;
@@ -745,12 +745,13 @@ int or_philox_advance(or_stream *s, uint64_t dlo, uint64_t dhi)
     return 0;
 }
 
-/* ranlux++: jump by N engine steps (N = lo + hi 2^64): x <- A^N x mod m. */
-int or_ranlux_advance(or_stream *s, uint64_t nlo, uint64_t nhi)
+/* ranlux++: jump by N engine steps, N given as four 64-bit limbs:
+ * x <- A^N x mod m. */
+int or_ranlux_advance(or_stream *s, const uint64_t e[4])
 {
     if (s->engine != OR_RANLUX) return -1;
-    uint64_t e[2] = {nlo, nhi}, An[RL_N];
-    rl_powmod(An, rl_step_multiplier(), e, 2);
+    uint64_t An[RL_N];
+    rl_powmod(An, rl_step_multiplier(), e, 4);
     rl_mulmod(s->st, s->st, An);
     s->blk_ok = 0;
     return 0;

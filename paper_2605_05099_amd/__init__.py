@@ -1,0 +1,274 @@
+"""MI355X (gfx950) implementation of the Randompack hot path (arXiv 2605.05099).
+
+A thin ctypes binding over the C ABI in include/rp.h (library: librp.so next to
+this file).  Functions keep the C names (``rp_create``, ``rp_fill``, ...) and
+only marshal arguments: every step of generation runs in the HIP kernels.
+PyTorch supplies device memory (tensors) and the current HIP stream.
+
+There is no fallback: importing works without a GPU (host-side calls such as
+seeding and jumps run anywhere), but if librp.so is missing the import fails
+with an error telling how to build it.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librp.so")
+
+# status codes, engines, distributions, dtypes (include/rp.h)
+RP_OK, RP_EINVAL, RP_ENOMEM, RP_EUNSUPPORTED, RP_EDEVICE, RP_ENOTSPD, RP_ENULL = 0, -1, -2, -3, -4, -5, -6
+RP_X256PP, RP_PCG64, RP_PHILOX4X32, RP_PHILOX, RP_SFC64, RP_RANLUX = range(6)
+RP_SUB_KEY, RP_SUB_INC, RP_SUB_SPAWN, RP_SUB_JUMP = range(4)
+RP_RAW, RP_U01, RP_BOUNDED, RP_NORM, RP_EXP = range(5)
+RP_U64, RP_U32, RP_F64, RP_F32 = range(4)
+RP_FLAG_52BIT = 1
+
+ENGINES = {"x256++": RP_X256PP, "pcg64": RP_PCG64, "philox4x32": RP_PHILOX4X32, "philox": RP_PHILOX,
+           "sfc64": RP_SFC64, "ranlux++": RP_RANLUX}
+STATE_WORDS = {RP_X256PP: 4, RP_PCG64: 4, RP_PHILOX4X32: 3, RP_PHILOX: 6, RP_SFC64: 4, RP_RANLUX: 9}
+
+_vp, _sz, _u64, _u32, _int = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+_SIGS = {
+    "rp_errmsg": ([], ctypes.c_char_p),
+    "rp_last_error": ([_vp], ctypes.c_char_p),
+    "rp_engines": ([ctypes.c_char_p, _sz], _int),
+    "rp_engine_id": ([ctypes.c_char_p], _int),
+    "rp_create": ([ctypes.c_char_p], _vp),
+    "rp_free": ([_vp], None),
+    "rp_duplicate": ([_vp], _vp),
+    "rp_seed": ([_vp, _u64, _vp, _sz], _int),
+    "rp_state_words": ([_vp], _int),
+    "rp_get_state": ([_vp, _vp, _sz, _vp], _int),
+    "rp_set_state": ([_vp, _vp, _sz, _u32], _int),
+    "rp_jump": ([_vp, _int], _int),
+    "rp_advance": ([_vp, _u64, _u64], _int),
+    "rp_pcg64_set_inc": ([_vp, _u64, _u64], _int),
+    "rp_philox_set_key": ([_vp, _u64, _u64], _int),
+    "rp_sfc64_set_abc": ([_vp, _u64, _u64, _u64], _int),
+    "rp_serialize": ([_vp, _vp, _sz, _vp], _int),
+    "rp_deserialize": ([_vp, _vp, _sz], _int),
+    "rp_raw_host": ([_vp, _vp, _sz], _int),
+    "rp_streams_create": ([_vp, _int, _u64, _int, _vp], _int),
+    "rp_streams_free": ([_vp], None),
+    "rp_streams_count": ([_vp], _u64),
+    "rp_streams_engine": ([_vp], _int),
+    "rp_streams_get": ([_vp, _vp, _vp], _int),
+    "rp_streams_set": ([_vp, _vp, _vp], _int),
+    "rp_streams_duplicate": ([_vp, _vp], _int),
+    "rp_fill": ([_vp, _int, _int, _u64, _int, _vp, _u64, _vp], _int),
+}
+
+
+class RpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded librp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2605_05099_amd.build` (hipcc, gfx950)")
+        l = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(l, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = l
+    return _lib
+
+
+def _check(rc, handle=None):
+    if rc < 0:
+        msg = lib().rp_last_error(handle) if handle else lib().rp_errmsg()
+        raise RpError(rc, (msg or b"").decode())
+    return rc
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if isinstance(a, np.ndarray) else ctypes.c_void_p(int(a))
+
+
+def _dev_ptr(t):
+    """Device pointer of a torch tensor (or an integer address)."""
+    return ctypes.c_void_p(t if isinstance(t, int) else t.data_ptr())
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ---- the C names ----------------------------------------------------------------
+def rp_errmsg():
+    return lib().rp_errmsg().decode()
+
+
+def rp_engines():
+    n = lib().rp_engines(None, 0)
+    buf = ctypes.create_string_buffer(n + 1)
+    lib().rp_engines(buf, n + 1)
+    return buf.value.decode()
+
+
+def rp_engine_id(name):
+    return _check(lib().rp_engine_id(name.encode()))
+
+
+def rp_create(engine="x256++"):
+    h = lib().rp_create(engine.encode() if engine is not None else None)
+    if not h:
+        raise RpError(RP_EINVAL, rp_errmsg())
+    return Rng(h)
+
+
+def rp_streams_create(base, kind, n, jump_log2=0):
+    out = ctypes.c_void_p()
+    _check(lib().rp_streams_create(base.h, kind, n, jump_log2, ctypes.byref(out)))
+    return Streams(out.value)
+
+
+def rp_fill(streams, dist, dtype, bound, flags, out, per_stream, stream=None):
+    _check(lib().rp_fill(streams.h, dist, dtype, bound, flags, _dev_ptr(out), per_stream, _stream_ptr(stream)))
+
+
+# ---- object wrappers ----------------------------------------------------------------
+class Rng:
+    """rp_rng*: one serial stream (host resident)."""
+
+    def __init__(self, h):
+        self.h = ctypes.c_void_p(h)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.rp_free(self.h)
+            self.h = None
+
+    @property
+    def engine(self):
+        return self._engine if hasattr(self, "_engine") else None
+
+    def seed(self, seed, spawn_key=()):
+        key = np.asarray(list(spawn_key), dtype=np.uint32)
+        _check(lib().rp_seed(self.h, seed, _ptr(key) if len(key) else None, len(key)), self.h)
+        return self
+
+    def state_words(self):
+        return _check(lib().rp_state_words(self.h))
+
+    def get_state(self):
+        n = self.state_words()
+        w = np.zeros(n, dtype=np.uint64)
+        ph = np.zeros(1, dtype=np.uint32)
+        _check(lib().rp_get_state(self.h, _ptr(w), n, _ptr(ph)), self.h)
+        return [int(x) for x in w], int(ph[0])
+
+    def set_state(self, words, phase=0):
+        w = np.asarray([int(x) for x in words], dtype=np.uint64)
+        _check(lib().rp_set_state(self.h, _ptr(w), len(w), phase), self.h)
+        return self
+
+    def jump(self, k):
+        _check(lib().rp_jump(self.h, k), self.h)
+        return self
+
+    def advance(self, n):
+        n = int(n)
+        _check(lib().rp_advance(self.h, n & (2**64 - 1), n >> 64), self.h)
+        return self
+
+    def pcg64_set_inc(self, inc):
+        _check(lib().rp_pcg64_set_inc(self.h, inc & (2**64 - 1), inc >> 64), self.h)
+        return self
+
+    def philox_set_key(self, k0, k1=0):
+        _check(lib().rp_philox_set_key(self.h, k0, k1), self.h)
+        return self
+
+    def sfc64_set_abc(self, a, b, c):
+        _check(lib().rp_sfc64_set_abc(self.h, a, b, c), self.h)
+        return self
+
+    def duplicate(self):
+        h = lib().rp_duplicate(self.h)
+        if not h:
+            raise RpError(RP_ENOMEM, rp_errmsg())
+        return Rng(h)
+
+    def serialize(self):
+        need = ctypes.c_size_t()
+        _check(lib().rp_serialize(self.h, None, 0, ctypes.byref(need)), self.h)
+        buf = ctypes.create_string_buffer(need.value)
+        _check(lib().rp_serialize(self.h, buf, need.value, None), self.h)
+        return buf.raw
+
+    def deserialize(self, data):
+        buf = ctypes.create_string_buffer(bytes(data), len(data))
+        _check(lib().rp_deserialize(self.h, buf, len(data)), self.h)
+        return self
+
+    def raw_host(self, n):
+        out = np.zeros(n, dtype=np.uint64)
+        _check(lib().rp_raw_host(self.h, _ptr(out), n), self.h)
+        return out
+
+    def last_error(self):
+        return lib().rp_last_error(self.h).decode()
+
+
+class Streams:
+    """rp_streams*: n substreams resident in device memory."""
+
+    def __init__(self, h):
+        self.h = ctypes.c_void_p(h)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.rp_streams_free(self.h)
+            self.h = None
+
+    def __len__(self):
+        return int(lib().rp_streams_count(self.h))
+
+    @property
+    def engine(self):
+        return _check(lib().rp_streams_engine(self.h))
+
+    def get(self):
+        n = len(self)
+        w = np.zeros(STATE_WORDS[self.engine] * n, dtype=np.uint64)
+        ph = np.zeros(n, dtype=np.uint32)
+        _check(lib().rp_streams_get(self.h, _ptr(w), _ptr(ph)))
+        return w.reshape(STATE_WORDS[self.engine], n), ph
+
+    def set(self, words, phase):
+        w = np.ascontiguousarray(words, dtype=np.uint64).reshape(-1)
+        ph = np.ascontiguousarray(phase, dtype=np.uint32)
+        _check(lib().rp_streams_set(self.h, _ptr(w), _ptr(ph)))
+
+    def duplicate(self):
+        out = ctypes.c_void_p()
+        _check(lib().rp_streams_duplicate(self.h, ctypes.byref(out)))
+        return Streams(out.value)
+
+    def fill(self, dist, out, per_stream, bound=0, flags=0, stream=None):
+        """Fill a device tensor of n * per_stream elements (dtype decides the form)."""
+        import torch
+        dt = {torch.uint64: RP_U64, torch.int64: RP_U64, torch.uint32: RP_U32, torch.int32: RP_U32,
+              torch.float64: RP_F64, torch.float32: RP_F32}[out.dtype]
+        if out.numel() != len(self) * per_stream or not out.is_contiguous() or not out.is_cuda:
+            raise ValueError("out must be a contiguous device tensor of n * per_stream elements")
+        rp_fill(self, dist, dt, bound, flags, out, per_stream, stream)
+        return out

@@ -1,0 +1,262 @@
+// engines.h -- engine arithmetic shared by the host core and the kernels.
+//
+// All functions are __host__ __device__ so the host core (substream setup,
+// jumps, rp_raw_host) and the gfx950 kernels run the same arithmetic.
+// Engine definitions follow Table 2 of the paper and the publications it
+// cites for each engine.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#define RP_HD __host__ __device__ __forceinline__
+
+namespace rp {
+
+RP_HD uint64_t rotl(uint64_t x, int k) { return (x << k) | (x >> (64 - k)); }
+
+RP_HD uint64_t mulhi64(uint64_t a, uint64_t b)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __umul64hi(a, b);
+#else
+    return (uint64_t)(((unsigned __int128)a * b) >> 64);
+#endif
+}
+
+// ---------------------------------------------------------------------------
+// 128-bit unsigned arithmetic (PCG64 state, Philox4x32 counter).
+struct u128 {
+    uint64_t lo, hi;
+};
+
+RP_HD u128 add128(u128 a, u128 b)
+{
+    u128 r;
+    r.lo = a.lo + b.lo;
+    r.hi = a.hi + b.hi + (r.lo < a.lo ? 1u : 0u);
+    return r;
+}
+
+// low 128 bits of a * b
+RP_HD u128 mul128(u128 a, u128 b)
+{
+    u128 r;
+    r.lo = a.lo * b.lo;
+    r.hi = mulhi64(a.lo, b.lo) + a.lo * b.hi + a.hi * b.lo;
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// xoshiro256++: linear map T on F_2^256 and the "++" scrambler applied to
+// the state before the update.
+struct X256 {
+    uint64_t s0, s1, s2, s3;
+
+    RP_HD void linear()
+    {
+        uint64_t t = s1 << 17;
+        s2 ^= s0;
+        s3 ^= s1;
+        s1 ^= s2;
+        s0 ^= s3;
+        s2 ^= t;
+        s3 = rotl(s3, 45);
+    }
+    RP_HD uint64_t next()
+    {
+        uint64_t r = rotl(s0 + s3, 23) + s0;
+        linear();
+        return r;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// PCG64 DXSM: s <- s * M + inc (mod 2^128) with the 64-bit multiplier M;
+// the output permutes the state before the step.
+static constexpr uint64_t kPcgMult = 0xda942042e4dd58b5ull;
+
+RP_HD uint64_t pcg_dxsm(u128 s)
+{
+    uint64_t hi = s.hi;
+    uint64_t lo = s.lo | 1u;
+    hi ^= hi >> 32;
+    hi *= kPcgMult;
+    hi ^= hi >> 48;
+    hi *= lo;
+    return hi;
+}
+
+RP_HD u128 pcg_step(u128 s, u128 inc)
+{
+    u128 r;
+    r.lo = s.lo * kPcgMult;
+    r.hi = mulhi64(s.lo, kPcgMult) + s.hi * kPcgMult;
+    return add128(r, inc);
+}
+
+// ---------------------------------------------------------------------------
+// Philox (Salmon et al. 2011), ten rounds, key bumped after every round.
+static constexpr uint32_t kPh32M0 = 0xD2511F53u, kPh32M1 = 0xCD9E8D57u;
+static constexpr uint32_t kPh32W0 = 0x9E3779B9u, kPh32W1 = 0xBB67AE85u;
+static constexpr uint64_t kPh64M0 = 0xD2E7470EE14C6C93ull, kPh64M1 = 0xCA5A826395121157ull;
+static constexpr uint64_t kPh64W0 = 0x9E3779B97F4A7C15ull, kPh64W1 = 0xBB67AE8584CAA73Bull;
+
+// Block for 128-bit counter (c_lo, c_hi) and key (k0 | k1 << 32); returns the
+// two 64-bit words (earlier 32-bit output in the low half).
+RP_HD void philox4x32(uint64_t c_lo, uint64_t c_hi, uint64_t key, uint64_t &w0, uint64_t &w1)
+{
+    uint32_t x0 = (uint32_t)c_lo, x1 = (uint32_t)(c_lo >> 32);
+    uint32_t x2 = (uint32_t)c_hi, x3 = (uint32_t)(c_hi >> 32);
+    uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
+#pragma unroll
+    for (int r = 0; r < 10; r++) {
+        uint64_t p0 = (uint64_t)kPh32M0 * x0;
+        uint64_t p1 = (uint64_t)kPh32M1 * x2;
+        uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        x1 = (uint32_t)p1;
+        x3 = (uint32_t)p0;
+        x0 = y0;
+        x2 = y2;
+        k0 += kPh32W0;
+        k1 += kPh32W1;
+    }
+    w0 = (uint64_t)x0 | ((uint64_t)x1 << 32);
+    w1 = (uint64_t)x2 | ((uint64_t)x3 << 32);
+}
+
+RP_HD void philox4x64(const uint64_t c[4], uint64_t k0, uint64_t k1, uint64_t out[4])
+{
+    uint64_t x0 = c[0], x1 = c[1], x2 = c[2], x3 = c[3];
+#pragma unroll
+    for (int r = 0; r < 10; r++) {
+        uint64_t h0 = mulhi64(kPh64M0, x0), l0 = kPh64M0 * x0;
+        uint64_t h1 = mulhi64(kPh64M1, x2), l1 = kPh64M1 * x2;
+        uint64_t y0 = h1 ^ x1 ^ k0;
+        uint64_t y2 = h0 ^ x3 ^ k1;
+        x1 = l1;
+        x3 = l0;
+        x0 = y0;
+        x2 = y2;
+        k0 += kPh64W0;
+        k1 += kPh64W1;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+// ---------------------------------------------------------------------------
+// sfc64: state (a, b, c, counter); output a + b + counter.
+struct Sfc64 {
+    uint64_t a, b, c, ctr;
+    RP_HD uint64_t next()
+    {
+        uint64_t r = a + b + ctr;
+        ctr += 1;
+        a = b ^ (b >> 11);
+        b = c + (c << 3);
+        c = rotl(c, 24) + r;
+        return r;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// ranlux++: x <- A x mod m, m = 2^576 - 2^240 + 1, on nine 64-bit limbs
+// (little-endian).
+//
+// A product of two residues has 18 limbs, P = H 2^576 + L.  Since
+// 2^576 = 2^240 - 1 (mod m), P = L + (H << 240) - H (mod m) ("fold").
+// Fold 1 (H: 9 limbs) leaves a value below 2^817 (13 limbs); fold 2 (H: the
+// top 241 bits, 4 limbs) leaves a value below 2^576 + 2^481 (10 limbs);
+// fold 3 (H: 0 or 1) leaves a value below 2^576.  Every fold result is
+// non-negative because (H << 240) >= H.  Finally m is subtracted once if the
+// value is >= m, tested as "value + 2^240 - 1 carries out of 2^576".
+static constexpr int kRlLimbs = 9;
+
+// out[0..NOUT) = L + (H << 240) - H, with L = in[0..9) and H = in[9..9+NH)
+template <int NH, int NOUT>
+RP_HD void rl_fold(const uint64_t *in, uint64_t *out)
+{
+    const uint64_t *H = in + 9;
+    uint64_t carry = 0;
+#pragma unroll
+    for (int k = 0; k < NOUT; k++) {
+        uint64_t l = (k < 9) ? in[k] : 0;
+        uint64_t sh = 0;
+        if (k - 3 >= 0 && k - 3 < NH) sh |= H[k - 3] << 48;
+        if (k - 4 >= 0 && k - 4 < NH) sh |= H[k - 4] >> 16;
+        uint64_t t = l + sh;
+        uint64_t c = (t < l) ? 1u : 0u;
+        uint64_t t2 = t + carry;
+        c += (t2 < t) ? 1u : 0u;
+        out[k] = t2;
+        carry = c;
+    }
+    uint64_t borrow = 0;
+#pragma unroll
+    for (int k = 0; k < NOUT; k++) {
+        uint64_t h = (k < NH) ? H[k] : 0;
+        uint64_t v = out[k];
+        uint64_t d = v - h;
+        uint64_t b = (v < h) ? 1u : 0u;
+        uint64_t d2 = d - borrow;
+        b += (d < borrow) ? 1u : 0u;
+        out[k] = d2;
+        borrow = b;
+    }
+}
+
+// x = p mod m for an 18-limb product p
+RP_HD void rl_reduce(const uint64_t p[18], uint64_t x[9])
+{
+    uint64_t r1[13], r2[10], r3[9];
+    rl_fold<9, 13>(p, r1);
+    rl_fold<4, 10>(r1, r2);
+    rl_fold<1, 9>(r2, r3);
+    // t = r3 + 2^240 - 1; if it carries out of 2^576 then r3 >= m and the
+    // reduced value is t mod 2^576 = r3 - m.
+    uint64_t t[9];
+    uint64_t carry = 0;
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        uint64_t add = (k < 3) ? ~0ull : (k == 3 ? ((1ull << 48) - 1) : 0ull);
+        uint64_t s1 = r3[k] + add;
+        uint64_t c = (s1 < add) ? 1u : 0u;
+        uint64_t s2 = s1 + carry;
+        c += (s2 < s1) ? 1u : 0u;
+        t[k] = s2;
+        carry = c;
+    }
+#pragma unroll
+    for (int k = 0; k < 9; k++) x[k] = carry ? t[k] : r3[k];
+}
+
+RP_HD void rl_mul_full(const uint64_t a[9], const uint64_t b[9], uint64_t p[18])
+{
+#pragma unroll
+    for (int i = 0; i < 18; i++) p[i] = 0;
+#pragma unroll
+    for (int i = 0; i < 9; i++) {
+        uint64_t carry = 0;
+#pragma unroll
+        for (int j = 0; j < 9; j++) {
+            uint64_t lo = a[i] * b[j];
+            uint64_t hi = mulhi64(a[i], b[j]);
+            uint64_t t = p[i + j] + lo;
+            hi += (t < lo) ? 1u : 0u;
+            uint64_t t2 = t + carry;
+            hi += (t2 < t) ? 1u : 0u;
+            p[i + j] = t2;
+            carry = hi;
+        }
+        p[i + 9] = carry;
+    }
+}
+
+RP_HD void rl_mulmod(const uint64_t a[9], const uint64_t b[9], uint64_t x[9])
+{
+    uint64_t p[18];
+    rl_mul_full(a, b, p);
+    rl_reduce(p, x);
+}
+
+}  // namespace rp

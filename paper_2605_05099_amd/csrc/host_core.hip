@@ -1,0 +1,948 @@
+// host_core.hip -- host side of the C ABI: handles, errors, seeding, stream
+// control (jump / advance / setters), substream construction and dispatch.
+//
+// Section 2.1 (interface), Section 2.3 (seeding, substreams, Table 3),
+// Section 4.4 (thread safety, serialization, engine query, jumping).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cctype>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+
+#include "rp_internal.h"
+
+using namespace rp;
+
+// ---------------------------------------------------------------------------
+// errors (per thread for handle-less calls, per handle otherwise)
+static thread_local std::string t_err;
+
+namespace rp {
+
+static void vformat(std::string &dst, const char *fmt, va_list ap)
+{
+    char buf[512];
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    dst = buf;
+}
+
+void set_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vformat(t_err, fmt, ap);
+    va_end(ap);
+}
+
+void set_error_rng(rp_rng *rng, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vformat(t_err, fmt, ap);
+    va_end(ap);
+    if (rng) rng->err = t_err;
+}
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vformat(t_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+}  // namespace rp
+
+static int fail_rng(const rp_rng *rng, int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vformat(t_err, fmt, ap);
+    va_end(ap);
+    if (rng) const_cast<rp_rng *>(rng)->err = t_err;
+    return code;
+}
+
+// ---------------------------------------------------------------------------
+// engine table (Table 2)
+struct EngineInfo {
+    const char *id;
+    const char *desc;
+    int words;  // state words (Table 2 "State words"; philox4x32: counter 2 + key 1)
+    int block;  // 64-bit words per output block
+};
+
+static const EngineInfo kEngines[RP_NENGINES] = {
+    {"x256++", "xoshiro256++ (Vigna and Blackman, 2019), 4 state words, period 2^256-1", 4, 1},
+    {"pcg64", "PCG64 DXSM (O'Neill, 2019), 4 state words, period 2^128 per increment", 4, 1},
+    {"philox4x32", "Philox4x32-10 (Salmon and Moraes, 2011), 3 state words, period 2^129 per key", 3, 2},
+    {"philox", "Philox-4x64-10 (Salmon and Moraes, 2011), 6 state words, period 2^258 per key", 6, 4},
+    {"sfc64", "sfc64 (Chris Doty-Humphrey, 2010), 4 state words, average period >= 2^64", 4, 1},
+    {"ranlux++", "ranlux++ (Sibidanov, 2017), 9 state words, period about 2^570", 9, 9},
+};
+
+namespace rp {
+int state_words(int e) { return kEngines[e].words; }
+int block_words(int e) { return kEngines[e].block; }
+}  // namespace rp
+
+extern "C" const char *rp_errmsg(void) { return t_err.c_str(); }
+
+extern "C" const char *rp_last_error(const rp_rng *rng)
+{
+    if (!rng) return t_err.c_str();
+    return rng->err.c_str();
+}
+
+extern "C" int rp_engines(char *buf, size_t len)
+{
+    std::string s;
+    for (const auto &e : kEngines) {
+        s += e.id;
+        s += ": ";
+        s += e.desc;
+        s += "\n";
+    }
+    if (buf && len > 0) {
+        size_t n = std::min(len - 1, s.size());
+        memcpy(buf, s.data(), n);
+        buf[n] = 0;
+    }
+    return (int)s.size();
+}
+
+extern "C" int rp_engine_id(const char *name)
+{
+    if (!name) return fail(RP_ENULL, "rp_engine_id: NULL name");
+    for (int e = 0; e < RP_NENGINES; e++) {
+        const char *a = kEngines[e].id;
+        const char *b = name;
+        while (*a && *b && std::tolower((unsigned char)*a) == std::tolower((unsigned char)*b)) {
+            a++;
+            b++;
+        }
+        if (!*a && !*b) return e;
+    }
+    return fail(RP_EINVAL, "unknown engine identifier '%s'", name);
+}
+
+// ---------------------------------------------------------------------------
+// seed_seq_fe128 mixer (Section 2.3): a 128-bit entropy pool of four 32-bit
+// words.  Input words are hashed into the pool (short inputs padded with
+// hashed zeros), every pool word is mixed with a hash of every other, any
+// further input words are mixed into all pool words, and output words are
+// produced by hashing the pool words round-robin with a second hash sequence.
+namespace {
+class SeedMixer {
+  public:
+    explicit SeedMixer(const std::vector<uint32_t> &in)
+    {
+        uint32_t mult = kInitA;
+        auto hash = [&mult](uint32_t v) {
+            v ^= mult;
+            mult *= kMultA;
+            v *= mult;
+            return v ^ (v >> 16);
+        };
+        auto mix = [](uint32_t x, uint32_t y) {
+            uint32_t r = kMixL * x - kMixR * y;
+            return r ^ (r >> 16);
+        };
+        for (size_t i = 0; i < 4; i++) pool_[i] = hash(i < in.size() ? in[i] : 0u);
+        for (size_t s = 0; s < 4; s++)
+            for (size_t d = 0; d < 4; d++)
+                if (s != d) pool_[d] = mix(pool_[d], hash(pool_[s]));
+        for (size_t i = 4; i < in.size(); i++)
+            for (size_t d = 0; d < 4; d++) pool_[d] = mix(pool_[d], hash(in[i]));
+    }
+    void generate(uint32_t *out, size_t n) const
+    {
+        uint32_t mult = kInitB;
+        for (size_t i = 0; i < n; i++) {
+            uint32_t v = pool_[i & 3] ^ mult;
+            mult *= kMultB;
+            v *= mult;
+            out[i] = v ^ (v >> 16);
+        }
+    }
+
+  private:
+    static constexpr uint32_t kInitA = 0x43b0d7e5u, kMultA = 0x931e8875u;
+    static constexpr uint32_t kInitB = 0x8b51f9ddu, kMultB = 0x58f38dedu;
+    static constexpr uint32_t kMixL = 0xca01f9ddu, kMixR = 0x4973f715u;
+    uint32_t pool_[4];
+};
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// ranlux++ constants: m = 2^576 - 2^240 + 1, a = m - (m - 1) / 2^24 (the LCG
+// equivalent of RANLUX with base 2^24, lags 24 and 10), A = a^2048 (the luxury
+// taken: 2048 subtract-with-borrow steps per engine step).
+static void ranlux_base(uint64_t a[9])
+{
+    // m - 1 = 2^576 - 2^240;  (m - 1) / 2^24 = 2^552 - 2^216
+    // a = m - (2^552 - 2^216) = 2^576 - 2^552 - 2^240 + 2^216 + 1
+    // limbs: 2^576 - 2^552 = (2^24 - 1) 2^552 -> limb 8 bits 40..63 set
+    uint64_t v[9] = {0};
+    v[8] = 0xFFFFFF0000000000ull;             // 2^576 - 2^552
+    // subtract 2^240 (limb 3, bit 48), add 2^216 (limb 3, bit 24), add 1
+    // 2^216 - 2^240 = -(2^240 - 2^216) = -(2^24 - 1) 2^216
+    // v - (2^24-1) 2^216: borrow from limb 8 through limbs 4..7
+    uint64_t sub = ((1ull << 24) - 1) << 24;  // (2^24 - 1) 2^216 in limb 3
+    // v[3] = 0 - sub with borrow propagating to limb 8
+    v[3] = 0 - sub;
+    for (int k = 4; k < 8; k++) v[k] = ~0ull;  // borrow chain 0 - 1
+    v[8] -= 1;
+    v[0] = 1;
+    memcpy(a, v, sizeof v);
+}
+
+static uint64_t g_rl_A[9];
+static std::once_flag g_rl_once;
+
+namespace rp {
+const uint64_t *ranlux_A()
+{
+    std::call_once(g_rl_once, [] {
+        uint64_t a[9], acc[9] = {1}, base[9];
+        ranlux_base(a);
+        memcpy(base, a, sizeof a);
+        for (uint32_t e = 2048; e; e >>= 1) {
+            if (e & 1) rl_mulmod(acc, base, acc);
+            rl_mulmod(base, base, base);
+        }
+        memcpy(g_rl_A, acc, sizeof acc);
+    });
+    return g_rl_A;
+}
+}  // namespace rp
+
+// base^e (e given as 64-bit limbs, little-endian) mod m
+static void ranlux_pow(const uint64_t base_in[9], const uint64_t *e, int ne, uint64_t out[9])
+{
+    uint64_t acc[9] = {1}, b[9];
+    memcpy(b, base_in, sizeof b);
+    for (int i = 0; i < ne; i++)
+        for (int bit = 0; bit < 64; bit++) {
+            if ((e[i] >> bit) & 1) rl_mulmod(acc, b, acc);
+            rl_mulmod(b, b, b);
+        }
+    memcpy(out, acc, sizeof acc);
+}
+
+static void ranlux_fixup(uint64_t x[9])
+{
+    uint64_t p[18] = {0};
+    memcpy(p, x, 9 * 8);
+    rl_reduce(p, x);
+    bool zero = true;
+    for (int k = 0; k < 9; k++) zero = zero && x[k] == 0;
+    if (zero) x[0] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// xoshiro256 jump polynomials (Section 4.4 "Jumping"): T^N = p(T) with
+// p(x) = x^N mod P(x), P the characteristic polynomial of the linear core.
+// P is found with the Berlekamp-Massey algorithm from 512 output bits of
+// one state bit; polynomials over GF(2) are 5 x 64-bit bitsets.
+namespace {
+struct Poly {
+    uint64_t w[5] = {0, 0, 0, 0, 0};
+    bool bit(int i) const { return (w[i >> 6] >> (i & 63)) & 1; }
+    void flip(int i) { w[i >> 6] ^= 1ull << (i & 63); }
+};
+
+Poly g_charpoly;
+std::once_flag g_charpoly_once;
+
+const Poly &x256_charpoly()
+{
+    std::call_once(g_charpoly_once, [] {
+        X256 s{0x9E3779B97F4A7C15ull, 0x3C6EF372FE94F82Aull, 0xDAA66D2C7DDF743Full, 1};
+        std::vector<int> bits(512);
+        for (int i = 0; i < 512; i++) {
+            bits[i] = (int)(s.s0 & 1);
+            s.linear();
+        }
+        // Berlekamp-Massey over GF(2): connection polynomial C (degree L)
+        std::vector<int> C(513, 0), B(513, 0), T;
+        C[0] = B[0] = 1;
+        int L = 0, m = 1;
+        for (int n = 0; n < 512; n++) {
+            int d = bits[n];
+            for (int i = 1; i <= L; i++) d ^= C[i] & bits[n - i];
+            if (!d) {
+                m++;
+                continue;
+            }
+            T = C;
+            for (int i = 0; i + m <= 512; i++) C[i + m] ^= B[i];
+            if (2 * L <= n) {
+                L = n + 1 - L;
+                B = T;
+                m = 1;
+            } else {
+                m++;
+            }
+        }
+        // characteristic polynomial = reciprocal of C: P(x) = x^L C(1/x)
+        Poly p;
+        for (int i = 0; i <= L; i++)
+            if (C[i]) p.flip(L - i);
+        g_charpoly = p;  // L is 256 (primitive polynomial of degree 256)
+    });
+    return g_charpoly;
+}
+
+// a * x mod P (deg P = 256)
+void poly_mulx(Poly &a, const Poly &P)
+{
+    uint64_t carry = 0;
+    for (int k = 0; k < 5; k++) {
+        uint64_t nc = a.w[k] >> 63;
+        a.w[k] = (a.w[k] << 1) | carry;
+        carry = nc;
+    }
+    if (a.bit(256))
+        for (int k = 0; k < 5; k++) a.w[k] ^= P.w[k];
+}
+
+Poly poly_mulmod(const Poly &a, const Poly &b, const Poly &P)
+{
+    Poly r;
+    for (int i = 255; i >= 0; i--) {
+        poly_mulx(r, P);
+        if (b.bit(i))
+            for (int k = 0; k < 5; k++) r.w[k] ^= a.w[k];
+    }
+    return r;
+}
+
+// x^N mod P for N = lo + hi 2^64
+Poly poly_xpow(uint64_t lo, uint64_t hi, const Poly &P)
+{
+    Poly r, base;
+    r.flip(0);
+    base.flip(1);
+    for (int half = 0; half < 2; half++) {
+        uint64_t e = half ? hi : lo;
+        for (int bit = 0; bit < 64; bit++) {
+            if ((e >> bit) & 1) r = poly_mulmod(r, base, P);
+            base = poly_mulmod(base, base, P);
+        }
+    }
+    return r;
+}
+
+void x256_apply(uint64_t st[4], const Poly &p)
+{
+    X256 cur{st[0], st[1], st[2], st[3]};
+    uint64_t acc[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 256; k++) {
+        if (p.bit(k)) {
+            acc[0] ^= cur.s0;
+            acc[1] ^= cur.s1;
+            acc[2] ^= cur.s2;
+            acc[3] ^= cur.s3;
+        }
+        cur.linear();
+    }
+    memcpy(st, acc, sizeof acc);
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// PCG64 affine powering: stepping N times maps s to A^N s + G_N inc with
+// G_N = 1 + A + ... + A^(N-1); binary powering composes the maps for 2^k.
+static PcgAffine pcg_power(uint64_t lo, uint64_t hi)
+{
+    PcgAffine acc{{1, 0}, {0, 0}};
+    PcgAffine cur{{kPcgMult, 0}, {1, 0}};
+    for (int half = 0; half < 2; half++) {
+        uint64_t e = half ? hi : lo;
+        for (int bit = 0; bit < 64; bit++) {
+            if ((e >> bit) & 1) {
+                // acc <- cur o acc : s -> cur.m (acc.m s + acc.p inc) + cur.p inc
+                acc.plus = add128(mul128(cur.mult, acc.plus), cur.plus);
+                acc.mult = mul128(cur.mult, acc.mult);
+            }
+            // cur <- cur o cur
+            cur.plus = add128(mul128(cur.mult, cur.plus), cur.plus);
+            cur.mult = mul128(cur.mult, cur.mult);
+        }
+    }
+    return acc;
+}
+
+// ---------------------------------------------------------------------------
+// stepping on the host (state checks, sfc64 warm-up)
+static uint64_t host_next(rp_rng *r)
+{
+    uint64_t *st = r->st;
+    switch (r->engine) {
+    case RP_X256PP: {
+        X256 s{st[0], st[1], st[2], st[3]};
+        uint64_t w = s.next();
+        st[0] = s.s0; st[1] = s.s1; st[2] = s.s2; st[3] = s.s3;
+        return w;
+    }
+    case RP_PCG64: {
+        u128 s{st[0], st[1]}, inc{st[2], st[3]};
+        uint64_t w = pcg_dxsm(s);
+        s = pcg_step(s, inc);
+        st[0] = s.lo;
+        st[1] = s.hi;
+        return w;
+    }
+    case RP_SFC64: {
+        Sfc64 s{st[0], st[1], st[2], st[3]};
+        uint64_t w = s.next();
+        st[0] = s.a; st[1] = s.b; st[2] = s.c; st[3] = s.ctr;
+        return w;
+    }
+    case RP_PHILOX4X32: {
+        uint64_t w0, w1;
+        philox4x32(st[0], st[1], st[2], w0, w1);
+        uint64_t w = r->phase ? w1 : w0;
+        if (++r->phase == 2) {
+            r->phase = 0;
+            st[0] += 1;
+            if (st[0] == 0) st[1] += 1;
+        }
+        return w;
+    }
+    case RP_PHILOX: {
+        uint64_t o[4];
+        philox4x64(st, st[4], st[5], o);
+        uint64_t w = o[r->phase];
+        if (++r->phase == 4) {
+            r->phase = 0;
+            for (int k = 0; k < 4; k++)
+                if (++st[k] != 0) break;
+        }
+        return w;
+    }
+    case RP_RANLUX: {
+        uint64_t y[9];
+        rl_mulmod(st, ranlux_A(), y);
+        uint64_t w = y[r->phase];
+        if (++r->phase == 9) {
+            r->phase = 0;
+            memcpy(st, y, sizeof y);
+        }
+        return w;
+    }
+    }
+    return 0;
+}
+
+static void sfc64_setabc(rp_rng *r, uint64_t a, uint64_t b, uint64_t c)
+{
+    r->st[0] = a;
+    r->st[1] = b;
+    r->st[2] = c;
+    r->st[3] = 1;
+    r->phase = 0;
+    for (int i = 0; i < 18; i++) host_next(r);
+}
+
+static void seed_state(rp_rng *r, uint64_t seed, const uint32_t *key, size_t n_key)
+{
+    std::vector<uint32_t> in = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    if (n_key) {
+        in.resize(4, 0u);  // keep "no key" and "key [0]" distinct
+        in.insert(in.end(), key, key + n_key);
+    }
+    int nw = (r->engine == RP_SFC64) ? 3 : kEngines[r->engine].words;
+    uint32_t o[18];
+    SeedMixer(in).generate(o, (size_t)(2 * nw));
+    uint64_t w[9];
+    for (int i = 0; i < nw; i++) w[i] = (uint64_t)o[2 * i] | ((uint64_t)o[2 * i + 1] << 32);
+    memset(r->st, 0, sizeof r->st);
+    r->phase = 0;
+    switch (r->engine) {
+    case RP_X256PP:
+        memcpy(r->st, w, 32);
+        if (!(w[0] | w[1] | w[2] | w[3])) r->st[0] = 1;
+        break;
+    case RP_PCG64:
+        memcpy(r->st, w, 32);
+        r->st[2] |= 1u;
+        break;
+    case RP_PHILOX4X32:
+    case RP_PHILOX:
+        memcpy(r->st, w, (size_t)nw * 8);
+        break;
+    case RP_SFC64:
+        sfc64_setabc(r, w[0], w[1], w[2]);
+        break;
+    case RP_RANLUX:
+        memcpy(r->st, w, 72);
+        ranlux_fixup(r->st);
+        break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// serial streams
+extern "C" rp_rng *rp_create(const char *engine)
+{
+    int e = RP_X256PP;
+    if (engine && *engine) {
+        e = rp_engine_id(engine);
+        if (e < 0) return nullptr;
+    }
+    rp_rng *r = new (std::nothrow) rp_rng;
+    if (!r) {
+        set_error("rp_create: out of memory");
+        return nullptr;
+    }
+    r->engine = e;
+    seed_state(r, 0, nullptr, 0);
+    return r;
+}
+
+extern "C" void rp_free(rp_rng *rng) { delete rng; }
+
+extern "C" rp_rng *rp_duplicate(const rp_rng *rng)
+{
+    if (!rng) {
+        set_error("rp_duplicate: NULL rng");
+        return nullptr;
+    }
+    rp_rng *r = new (std::nothrow) rp_rng(*rng);
+    if (!r) set_error("rp_duplicate: out of memory");
+    return r;
+}
+
+extern "C" int rp_seed(rp_rng *rng, uint64_t seed, const uint32_t *spawn_key, size_t n_key)
+{
+    if (!rng) return fail(RP_ENULL, "rp_seed: NULL rng");
+    if (n_key && !spawn_key) return fail_rng(rng, RP_ENULL, "rp_seed: NULL spawn key");
+    if (n_key > 1024) return fail_rng(rng, RP_EINVAL, "rp_seed: spawn key longer than 1024 words");
+    rng->seed = seed;
+    rng->key.assign(spawn_key, spawn_key + n_key);
+    seed_state(rng, seed, spawn_key, n_key);
+    return RP_OK;
+}
+
+extern "C" int rp_state_words(const rp_rng *rng)
+{
+    if (!rng) return fail(RP_ENULL, "rp_state_words: NULL rng");
+    return kEngines[rng->engine].words;
+}
+
+extern "C" int rp_get_state(const rp_rng *rng, uint64_t *words, size_t n, uint32_t *phase)
+{
+    if (!rng || !words) return fail(RP_ENULL, "rp_get_state: NULL argument");
+    int nw = kEngines[rng->engine].words;
+    if (n < (size_t)nw) return fail_rng(rng, RP_EINVAL, "rp_get_state: need %d words", nw);
+    memcpy(words, rng->st, (size_t)nw * 8);
+    if (phase) *phase = rng->phase;
+    return RP_OK;
+}
+
+extern "C" int rp_set_state(rp_rng *rng, const uint64_t *words, size_t n, uint32_t phase)
+{
+    if (!rng || !words) return fail(RP_ENULL, "rp_set_state: NULL argument");
+    int nw = kEngines[rng->engine].words;
+    if (n != (size_t)nw) return fail_rng(rng, RP_EINVAL, "rp_set_state: expected %d words", nw);
+    if (phase >= (uint32_t)kEngines[rng->engine].block)
+        return fail_rng(rng, RP_EINVAL, "rp_set_state: phase %u out of range", phase);
+    memset(rng->st, 0, sizeof rng->st);
+    memcpy(rng->st, words, n * 8);
+    rng->phase = phase;
+    return RP_OK;
+}
+
+static int advance_impl(rp_rng *rng, uint64_t lo, uint64_t hi)
+{
+    uint64_t *st = rng->st;
+    switch (rng->engine) {
+    case RP_X256PP:
+        x256_apply(st, poly_xpow(lo, hi, x256_charpoly()));
+        return RP_OK;
+    case RP_PCG64: {
+        PcgAffine m = pcg_power(lo, hi);
+        u128 s{st[0], st[1]}, inc{st[2], st[3]};
+        s = add128(mul128(m.mult, s), mul128(m.plus, inc));
+        st[0] = s.lo;
+        st[1] = s.hi;
+        return RP_OK;
+    }
+    case RP_PHILOX4X32: {
+        u128 c{st[0], st[1]};
+        c = add128(c, u128{lo, hi});
+        st[0] = c.lo;
+        st[1] = c.hi;
+        return RP_OK;
+    }
+    case RP_PHILOX: {
+        uint64_t add[4] = {lo, hi, 0, 0}, carry = 0;
+        for (int k = 0; k < 4; k++) {
+            uint64_t s1 = st[k] + add[k];
+            uint64_t c = s1 < st[k];
+            uint64_t s2 = s1 + carry;
+            c += s2 < s1;
+            st[k] = s2;
+            carry = c;
+        }
+        return RP_OK;
+    }
+    case RP_RANLUX: {
+        uint64_t e[2] = {lo, hi}, An[9];
+        ranlux_pow(ranlux_A(), e, 2, An);
+        rl_mulmod(st, An, st);
+        return RP_OK;
+    }
+    default:
+        return fail_rng(rng, RP_EUNSUPPORTED, "advance: engine '%s' has no jump", kEngines[rng->engine].id);
+    }
+}
+
+extern "C" int rp_advance(rp_rng *rng, uint64_t lo, uint64_t hi)
+{
+    if (!rng) return fail(RP_ENULL, "rp_advance: NULL rng");
+    return advance_impl(rng, lo, hi);
+}
+
+extern "C" int rp_jump(rp_rng *rng, int k)
+{
+    if (!rng) return fail(RP_ENULL, "rp_jump: NULL rng");
+    if (k != 32 && k != 64 && k != 96 && k != 128 && k != 192)
+        return fail_rng(rng, RP_EINVAL, "rp_jump: k must be 32, 64, 96, 128 or 192 (got %d)", k);
+    if (k < 128) return advance_impl(rng, k < 64 ? (1ull << k) : 0, k >= 64 ? (1ull << (k - 64)) : 0);
+    switch (rng->engine) {
+    case RP_X256PP: {
+        Poly x;
+        x.flip(1);
+        const Poly &P = x256_charpoly();
+        for (int i = 0; i < k; i++) x = poly_mulmod(x, x, P);  // x^(2^k)
+        x256_apply(rng->st, x);
+        return RP_OK;
+    }
+    case RP_PHILOX: {  // add 2^k to the 256-bit block counter
+        uint64_t add = 1ull << (k % 64);
+        for (int j = k / 64; j < 4; j++) {
+            uint64_t s1 = rng->st[j] + add;
+            bool c = s1 < rng->st[j];
+            rng->st[j] = s1;
+            if (!c) break;
+            add = 1;
+        }
+        return RP_OK;
+    }
+    case RP_RANLUX: {
+        uint64_t e[4] = {0, 0, 0, 0}, An[9];
+        e[k / 64] = 1ull << (k % 64);
+        ranlux_pow(ranlux_A(), e, 4, An);
+        rl_mulmod(rng->st, An, rng->st);
+        return RP_OK;
+    }
+    case RP_SFC64:
+        return fail_rng(rng, RP_EUNSUPPORTED, "rp_jump: sfc64 has no jump");
+    default:  // pcg64 period and philox4x32 counter are 2^128
+        return fail_rng(rng, RP_EINVAL, "rp_jump: 2^%d is not below the period of '%s'", k,
+                        kEngines[rng->engine].id);
+    }
+}
+
+extern "C" int rp_pcg64_set_inc(rp_rng *rng, uint64_t lo, uint64_t hi)
+{
+    if (!rng) return fail(RP_ENULL, "rp_pcg64_set_inc: NULL rng");
+    if (rng->engine != RP_PCG64) return fail_rng(rng, RP_EUNSUPPORTED, "pcg64_set_inc: engine is not pcg64");
+    rng->st[2] = lo | 1u;
+    rng->st[3] = hi;
+    return RP_OK;
+}
+
+extern "C" int rp_philox_set_key(rp_rng *rng, uint64_t k0, uint64_t k1)
+{
+    if (!rng) return fail(RP_ENULL, "rp_philox_set_key: NULL rng");
+    if (rng->engine == RP_PHILOX4X32) {
+        rng->st[2] = k0;
+    } else if (rng->engine == RP_PHILOX) {
+        rng->st[4] = k0;
+        rng->st[5] = k1;
+    } else {
+        return fail_rng(rng, RP_EUNSUPPORTED, "philox_set_key: engine is not philox");
+    }
+    return RP_OK;
+}
+
+extern "C" int rp_sfc64_set_abc(rp_rng *rng, uint64_t a, uint64_t b, uint64_t c)
+{
+    if (!rng) return fail(RP_ENULL, "rp_sfc64_set_abc: NULL rng");
+    if (rng->engine != RP_SFC64) return fail_rng(rng, RP_EUNSUPPORTED, "sfc64_set_abc: engine is not sfc64");
+    sfc64_setabc(rng, a, b, c);
+    return RP_OK;
+}
+
+// serialized image: magic, engine, phase, 16 state words, seed, key length, key
+static constexpr uint32_t kMagic = 0x52503031u;  // "RP01"
+
+extern "C" int rp_serialize(const rp_rng *rng, void *buf, size_t len, size_t *needed)
+{
+    if (!rng) return fail(RP_ENULL, "rp_serialize: NULL rng");
+    size_t need = 4 * 4 + 16 * 8 + 8 + rng->key.size() * 4;
+    if (needed) *needed = need;
+    if (!buf) return RP_OK;
+    if (len < need) return fail_rng(rng, RP_EINVAL, "rp_serialize: buffer too small (%zu < %zu)", len, need);
+    uint8_t *p = (uint8_t *)buf;
+    uint32_t hdr[4] = {kMagic, (uint32_t)rng->engine, rng->phase, (uint32_t)rng->key.size()};
+    memcpy(p, hdr, 16);
+    memcpy(p + 16, rng->st, 128);
+    memcpy(p + 144, &rng->seed, 8);
+    if (!rng->key.empty()) memcpy(p + 152, rng->key.data(), rng->key.size() * 4);
+    return RP_OK;
+}
+
+extern "C" int rp_deserialize(rp_rng *rng, const void *buf, size_t len)
+{
+    if (!rng || !buf) return fail(RP_ENULL, "rp_deserialize: NULL argument");
+    if (len < 152) return fail_rng(rng, RP_EINVAL, "rp_deserialize: buffer too small");
+    const uint8_t *p = (const uint8_t *)buf;
+    uint32_t hdr[4];
+    memcpy(hdr, p, 16);
+    if (hdr[0] != kMagic || hdr[1] >= RP_NENGINES || hdr[2] >= (uint32_t)kEngines[hdr[1]].block ||
+        len < 152 + (size_t)hdr[3] * 4)
+        return fail_rng(rng, RP_EINVAL, "rp_deserialize: not a serialized stream");
+    rng->engine = (int)hdr[1];
+    rng->phase = hdr[2];
+    memcpy(rng->st, p + 16, 128);
+    memcpy(&rng->seed, p + 144, 8);
+    rng->key.assign((const uint32_t *)(p + 152), (const uint32_t *)(p + 152) + hdr[3]);
+    return RP_OK;
+}
+
+extern "C" int rp_raw_host(rp_rng *rng, uint64_t *out, size_t n)
+{
+    if (!rng || (!out && n)) return fail(RP_ENULL, "rp_raw_host: NULL argument");
+    for (size_t i = 0; i < n; i++) out[i] = host_next(rng);
+    return RP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// device substreams
+static int hip_fail(hipError_t e, const char *what)
+{
+    return fail(RP_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+extern "C" int rp_streams_create(const rp_rng *base, int kind, uint64_t n, int jump_log2, rp_streams **out)
+{
+    if (!base || !out) return fail(RP_ENULL, "rp_streams_create: NULL argument");
+    *out = nullptr;
+    if (n == 0) return fail(RP_EINVAL, "rp_streams_create: n must be positive");
+    if (n > (1ull << 32)) return fail(RP_EINVAL, "rp_streams_create: at most 2^32 substreams");
+    const int e = base->engine;
+    const int nw = kEngines[e].words;
+    switch (kind) {
+    case RP_SUB_KEY:
+        if (e != RP_PHILOX4X32 && e != RP_PHILOX)
+            return fail(RP_EUNSUPPORTED, "RP_SUB_KEY needs a philox engine");
+        break;
+    case RP_SUB_INC:
+        if (e != RP_PCG64) return fail(RP_EUNSUPPORTED, "RP_SUB_INC needs pcg64");
+        break;
+    case RP_SUB_SPAWN:
+        break;
+    case RP_SUB_JUMP:
+        if (e == RP_SFC64) return fail(RP_EUNSUPPORTED, "sfc64 has no jump");
+        if (jump_log2 < 0 || jump_log2 > 192) return fail(RP_EINVAL, "jump_log2 out of range");
+        break;
+    default:
+        return fail(RP_EINVAL, "rp_streams_create: unknown kind %d", kind);
+    }
+    std::vector<uint64_t> words((size_t)nw * n);
+    std::vector<uint32_t> phase(n, 0);
+    rp_rng cur = *base;
+    rp_rng jumped = *base;  // JUMP: running state advanced by 2^jump_log2 per substream
+    uint64_t jl = jump_log2 < 64 ? (1ull << jump_log2) : 0;
+    uint64_t jh = (jump_log2 >= 64 && jump_log2 < 128) ? (1ull << (jump_log2 - 64)) : 0;
+    // precomputed per-step transforms for JUMP
+    Poly jpoly;
+    uint64_t jmul[9];
+    PcgAffine jpcg{};
+    if (kind == RP_SUB_JUMP && n > 1) {
+        if (e == RP_X256PP) {
+            Poly base_x;
+            base_x.flip(1);
+            const Poly &P = x256_charpoly();
+            for (int i = 0; i < jump_log2; i++) base_x = poly_mulmod(base_x, base_x, P);
+            jpoly = base_x;
+        } else if (e == RP_RANLUX) {
+            uint64_t ex[4] = {0, 0, 0, 0};
+            ex[jump_log2 / 64] = 1ull << (jump_log2 % 64);
+            ranlux_pow(ranlux_A(), ex, 4, jmul);
+        } else if (e == RP_PCG64) {
+            if (jump_log2 >= 128) return fail(RP_EINVAL, "pcg64 jump_log2 must be < 128");
+            jpcg = pcg_power(jl, jh);
+        }
+    }
+    for (uint64_t i = 0; i < n; i++) {
+        switch (kind) {
+        case RP_SUB_KEY:
+            cur = *base;
+            if (e == RP_PHILOX4X32) cur.st[2] = i;
+            else {
+                cur.st[4] = i;
+                cur.st[5] = 0;
+            }
+            break;
+        case RP_SUB_INC:
+            cur = *base;
+            cur.st[2] = 2 * i + 1;
+            cur.st[3] = 0;
+            break;
+        case RP_SUB_SPAWN: {
+            cur.engine = e;
+            uint32_t k = (uint32_t)i;
+            seed_state(&cur, base->seed, &k, 1);
+            break;
+        }
+        case RP_SUB_JUMP:
+            if (i > 0) {
+                if (e == RP_X256PP) x256_apply(jumped.st, jpoly);
+                else if (e == RP_RANLUX) rl_mulmod(jumped.st, jmul, jumped.st);
+                else if (e == RP_PCG64) {
+                    u128 s{jumped.st[0], jumped.st[1]}, inc{jumped.st[2], jumped.st[3]};
+                    s = add128(mul128(jpcg.mult, s), mul128(jpcg.plus, inc));
+                    jumped.st[0] = s.lo;
+                    jumped.st[1] = s.hi;
+                } else {
+                    int rc = advance_impl(&jumped, jl, jh);
+                    if (rc) return rc;
+                }
+            }
+            cur = jumped;
+            break;
+        }
+        for (int k = 0; k < nw; k++) words[(size_t)k * n + i] = cur.st[k];
+        phase[i] = cur.phase;
+    }
+    rp_streams *s = new (std::nothrow) rp_streams;
+    if (!s) return fail(RP_ENOMEM, "rp_streams_create: out of memory");
+    s->engine = e;
+    s->n = n;
+    s->nwords = nw;
+    hipError_t err = hipGetDevice(&s->device);
+    if (err != hipSuccess) {
+        delete s;
+        return hip_fail(err, "hipGetDevice");
+    }
+    err = hipMalloc(&s->d_words, words.size() * 8);
+    if (err == hipSuccess) err = hipMalloc(&s->d_phase, n * 4);
+    if (err == hipSuccess) err = hipMemcpy(s->d_words, words.data(), words.size() * 8, hipMemcpyHostToDevice);
+    if (err == hipSuccess) err = hipMemcpy(s->d_phase, phase.data(), n * 4, hipMemcpyHostToDevice);
+    if (err != hipSuccess) {
+        (void)hipFree(s->d_words);
+        (void)hipFree(s->d_phase);
+        delete s;
+        return fail(RP_ENOMEM, "rp_streams_create: device allocation/copy failed: %s", hipGetErrorString(err));
+    }
+    *out = s;
+    return RP_OK;
+}
+
+extern "C" void rp_streams_free(rp_streams *s)
+{
+    if (!s) return;
+    (void)hipFree(s->d_words);
+    (void)hipFree(s->d_phase);
+    delete s;
+}
+
+extern "C" uint64_t rp_streams_count(const rp_streams *s) { return s ? s->n : 0; }
+
+extern "C" int rp_streams_engine(const rp_streams *s)
+{
+    if (!s) return fail(RP_ENULL, "rp_streams_engine: NULL streams");
+    return s->engine;
+}
+
+extern "C" int rp_streams_get(const rp_streams *s, uint64_t *words, uint32_t *phase)
+{
+    if (!s || !words || !phase) return fail(RP_ENULL, "rp_streams_get: NULL argument");
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(words, s->d_words, (size_t)s->nwords * s->n * 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(phase, s->d_phase, s->n * 4, hipMemcpyDeviceToHost);
+    return e == hipSuccess ? RP_OK : hip_fail(e, "rp_streams_get");
+}
+
+extern "C" int rp_streams_set(rp_streams *s, const uint64_t *words, const uint32_t *phase)
+{
+    if (!s || !words || !phase) return fail(RP_ENULL, "rp_streams_set: NULL argument");
+    for (uint64_t i = 0; i < s->n; i++)
+        if (phase[i] >= (uint32_t)kEngines[s->engine].block) return fail(RP_EINVAL, "rp_streams_set: bad phase");
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(s->d_words, words, (size_t)s->nwords * s->n * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->d_phase, phase, s->n * 4, hipMemcpyHostToDevice);
+    return e == hipSuccess ? RP_OK : hip_fail(e, "rp_streams_set");
+}
+
+extern "C" int rp_streams_duplicate(const rp_streams *s, rp_streams **out)
+{
+    if (!s || !out) return fail(RP_ENULL, "rp_streams_duplicate: NULL argument");
+    rp_streams *d = new (std::nothrow) rp_streams(*s);
+    if (!d) return fail(RP_ENOMEM, "rp_streams_duplicate: out of memory");
+    d->d_words = nullptr;
+    d->d_phase = nullptr;
+    hipError_t e = hipMalloc(&d->d_words, (size_t)s->nwords * s->n * 8);
+    if (e == hipSuccess) e = hipMalloc(&d->d_phase, s->n * 4);
+    if (e == hipSuccess) e = hipMemcpy(d->d_words, s->d_words, (size_t)s->nwords * s->n * 8, hipMemcpyDeviceToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d->d_phase, s->d_phase, s->n * 4, hipMemcpyDeviceToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d->d_words);
+        (void)hipFree(d->d_phase);
+        delete d;
+        return hip_fail(e, "rp_streams_duplicate");
+    }
+    *out = d;
+    return RP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// bulk fill dispatch
+extern "C" int rp_fill(rp_streams *s, int dist, int dtype, uint64_t bound, int flags, void *d_out,
+                       uint64_t per_stream, void *hip_stream)
+{
+    if (!s) return fail(RP_ENULL, "rp_fill: NULL streams");
+    if (per_stream == 0) return RP_OK;
+    if (!d_out) return fail(RP_ENULL, "rp_fill: NULL output");
+    bool ok = false;
+    switch (dist) {
+    case RP_RAW: ok = dtype == RP_U64 || dtype == RP_U32; break;
+    case RP_U01: ok = dtype == RP_F64 || dtype == RP_F32; break;
+    case RP_BOUNDED: ok = dtype == RP_U64 || (dtype == RP_U32 && bound <= 0xFFFFFFFFull); break;
+    case RP_NORM:
+    case RP_EXP: ok = dtype == RP_F64; break;
+    default: return fail(RP_EINVAL, "rp_fill: unknown distribution %d", dist);
+    }
+    if (!ok) return fail(RP_EUNSUPPORTED, "rp_fill: distribution %d has no dtype %d form (or bound too large)", dist, dtype);
+    if (flags & ~RP_FLAG_52BIT) return fail(RP_EINVAL, "rp_fill: unknown flags 0x%x", flags);
+    size_t esz = (dtype == RP_U64 || dtype == RP_F64) ? 8 : 4;
+    if ((uintptr_t)d_out % esz) return fail(RP_EINVAL, "rp_fill: output not aligned to %zu bytes", esz);
+    if (s->n > UINT64_MAX / per_stream) return fail(RP_EINVAL, "rp_fill: size overflow");
+    int rc = ensure_device_tables();
+    if (rc) return rc;
+    FillArgs a;
+    a.words = s->d_words;
+    a.phase = s->d_phase;
+    a.n = s->n;
+    a.per_stream = per_stream;
+    a.out = d_out;
+    a.bound = bound;
+    a.thresh = 0;
+    if (dist == RP_BOUNDED && bound) {
+        if (dtype == RP_U64) a.thresh = (0 - bound) % bound;
+        else a.thresh = (uint32_t)(0u - (uint32_t)bound) % (uint32_t)bound;
+    }
+    a.flags = flags;
+    return launch_fill(s->engine, dist, dtype, a, (hipStream_t)hip_stream);
+}

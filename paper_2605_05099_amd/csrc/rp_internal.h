@@ -1,0 +1,64 @@
+// rp_internal.h -- structures shared by the host core and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/rp.h"
+#include "engines.h"
+
+struct rp_rng {
+    int engine = RP_X256PP;
+    uint64_t st[16] = {0};  // state words, Table 3 order
+    uint32_t phase = 0;     // words used from the current block (block engines)
+    uint64_t seed = 0;      // last seed given to rp_seed (base for substreams)
+    std::vector<uint32_t> key;
+    std::string err;
+};
+
+struct rp_streams {
+    int engine = RP_X256PP;
+    uint64_t n = 0;
+    int nwords = 0;            // state words per substream
+    uint64_t *d_words = nullptr;  // SoA: word k of substream i at [k * n + i]
+    uint32_t *d_phase = nullptr;  // n entries
+    int device = 0;
+};
+
+namespace rp {
+
+// ---- host core -------------------------------------------------------------
+int state_words(int engine);
+int block_words(int engine);
+void set_error(const char *fmt, ...);
+void set_error_rng(rp_rng *rng, const char *fmt, ...);
+int fail(int code, const char *fmt, ...);
+
+// ranlux++ multiplier A = a^2048 mod m and its power table (host)
+const uint64_t *ranlux_A();
+
+// PCG64 power tables: A^k and G_k = 1 + A + ... + A^(k-1) (mod 2^128)
+struct PcgAffine {
+    u128 mult, plus;  // s -> mult * s + plus * inc
+};
+
+// device-side constant tables (uploaded once per device)
+int ensure_device_tables();
+
+// ---- kernel launchers (fill.hip) -------------------------------------------
+struct FillArgs {
+    uint64_t *words;   // SoA state
+    uint32_t *phase;
+    uint64_t n;        // substreams
+    uint64_t per_stream;
+    void *out;
+    uint64_t bound;    // Lemire bound (0 = full range)
+    uint64_t thresh;   // Lemire threshold (2^w - b) mod b
+    int flags;
+};
+
+int launch_fill(int engine, int dist, int dtype, const FillArgs &a, hipStream_t stream);
+
+}  // namespace rp

@@ -1,0 +1,134 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+include/rp.h declares, and its host-side stream control (seeding, setters,
+jumps, advance, state get/set, serialization, errors) matches the oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2605_05099_amd as rp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ENGINES = ["x256++", "pcg64", "philox4x32", "philox", "sfc64", "ranlux++"]
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "rp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rp_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 25
+    lib = ctypes.CDLL(rp.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol():
+    assert set(declared_functions()) <= set(rp._SIGS)
+
+
+def test_engine_query_and_ids():
+    txt = rp.rp_engines()
+    for e in ENGINES:
+        assert e + ":" in txt
+    assert rp.rp_engine_id("X256++") == rp.RP_X256PP
+    assert rp.rp_engine_id("RANLUX++") == rp.RP_RANLUX
+    with pytest.raises(rp.RpError) as ei:
+        rp.rp_engine_id("x256")
+    assert ei.value.code == rp.RP_EINVAL
+    with pytest.raises(rp.RpError):
+        rp.rp_create("mt19937")
+    assert rp.rp_create("").get_state()[0] == rp.rp_create("x256++").get_state()[0]
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("seed,key", [(42, ()), (12345, ()), (42, (0,)), (42, (7, 8, 9)), (2**64 - 1, (1,))])
+def test_seeding_matches_oracle(engine, seed, key):
+    r = rp.rp_create(engine).seed(seed, key)
+    o = oracle.Stream.seeded(engine, seed, key)
+    w, ph = r.get_state()
+    assert w == o.state[:len(w)] and ph == o.phase
+    assert (r.raw_host(40) == o.raw(40)).all()
+
+
+@pytest.mark.parametrize("engine", ["x256++", "pcg64", "philox4x32", "philox", "ranlux++"])
+@pytest.mark.parametrize("n", [1, 5, 1000, 2**64 + 17, 3 * 2**70 + 1])
+def test_advance_matches_oracle(engine, n):
+    r = rp.rp_create(engine).seed(7).advance(n)
+    o = oracle.Stream.seeded(engine, 7).advance(n)
+    assert r.get_state()[0] == o.state[:rp.STATE_WORDS[rp.ENGINES[engine]]]
+
+
+@pytest.mark.parametrize("engine", ["x256++", "philox", "ranlux++"])
+@pytest.mark.parametrize("k", [32, 64, 96, 128, 192])
+def test_jump_matches_oracle(engine, k):
+    r = rp.rp_create(engine).seed(9).jump(k)
+    o = oracle.Stream.seeded(engine, 9).advance(2**k)
+    assert r.get_state()[0] == o.state[:rp.STATE_WORDS[rp.ENGINES[engine]]]
+
+
+def test_jump_errors():
+    with pytest.raises(rp.RpError) as ei:
+        rp.rp_create("x256++").jump(5)
+    assert ei.value.code == rp.RP_EINVAL
+    with pytest.raises(rp.RpError) as ei:
+        rp.rp_create("sfc64").jump(64)
+    assert ei.value.code == rp.RP_EUNSUPPORTED
+    with pytest.raises(rp.RpError) as ei:
+        rp.rp_create("pcg64").jump(128)
+    assert ei.value.code == rp.RP_EINVAL
+    with pytest.raises(rp.RpError) as ei:
+        rp.rp_create("sfc64").advance(3)
+    assert ei.value.code == rp.RP_EUNSUPPORTED
+
+
+def test_setters_match_oracle():
+    r = rp.rp_create("pcg64").seed(1).pcg64_set_inc(2**70 + 4)
+    o = oracle.Stream.seeded("pcg64", 1).pcg64_set_inc(2**70 + 4)
+    assert r.get_state()[0] == o.state[:4]
+    r = rp.rp_create("philox").seed(1).philox_set_key(5, 6)
+    o = oracle.Stream.seeded("philox", 1).philox_set_key(5, 6)
+    assert r.get_state()[0] == o.state[:6]
+    r = rp.rp_create("philox4x32").seed(1).philox_set_key(2**40 + 3)
+    o = oracle.Stream.seeded("philox4x32", 1).philox_set_key(2**40 + 3)
+    assert r.get_state()[0] == o.state[:3]
+    r = rp.rp_create("sfc64").sfc64_set_abc(1, 2, 3)
+    o = oracle.Stream("sfc64").sfc64_set_abc(1, 2, 3)
+    assert r.get_state()[0] == o.state[:4]
+    with pytest.raises(rp.RpError) as ei:
+        rp.rp_create("x256++").pcg64_set_inc(3)
+    assert ei.value.code == rp.RP_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_state_roundtrip_phase_and_duplicate(engine):
+    r = rp.rp_create(engine).seed(3)
+    r.raw_host(7)  # leaves a phase for block engines
+    w, ph = r.get_state()
+    o = oracle.Stream.seeded(engine, 3)
+    o.raw(7)
+    assert ph == o.phase and w == o.state[:len(w)]
+    d = r.duplicate()
+    s = rp.rp_create(engine).set_state(w, ph)
+    blob = r.serialize()
+    t = rp.rp_create("x256++").deserialize(blob)
+    ref = r.raw_host(50)
+    assert (d.raw_host(50) == ref).all()
+    assert (s.raw_host(50) == ref).all()
+    assert (t.raw_host(50) == ref).all()
+
+
+def test_set_state_errors():
+    r = rp.rp_create("philox4x32")
+    with pytest.raises(rp.RpError):
+        r.set_state([1, 2, 3], phase=2)
+    with pytest.raises(rp.RpError):
+        r.set_state([1, 2])
+    with pytest.raises(rp.RpError):
+        rp.rp_create("x256++").deserialize(b"\0" * 200)

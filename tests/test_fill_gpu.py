@@ -1,0 +1,127 @@
+"""GPU parity of rp_fill against the oracle (needs an MI355X).
+
+Bit-exact for raw words, uniforms and bounded integers.  For the ziggurat the
+accept/reject decisions must all agree, which shows as the two sequences
+staying aligned; values are then equal except in the tail, where log1p may
+differ by an ulp (tolerance: 4 ulp).  The substream states left behind must
+equal the oracle's after the same draws, so a second call continues exactly.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2605_05099_amd as rp
+from paper_2605_05099_amd import workloads
+from tests.gpu_common import ENGINES, NP_VIEW, TORCH_DTYPE, make_streams, oracle_fill, oracle_stream, ulp_diff
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    (rp.RP_RAW, rp.RP_U64, 0, 0),
+    (rp.RP_RAW, rp.RP_U32, 0, 0),
+    (rp.RP_U01, rp.RP_F64, 0, 0),
+    (rp.RP_U01, rp.RP_F64, 0, rp.RP_FLAG_52BIT),
+    (rp.RP_U01, rp.RP_F32, 0, 0),
+    (rp.RP_U01, rp.RP_F32, 0, rp.RP_FLAG_52BIT),
+    (rp.RP_BOUNDED, rp.RP_U64, 6, 0),
+    (rp.RP_BOUNDED, rp.RP_U64, 6 * 10**18, 0),
+    (rp.RP_BOUNDED, rp.RP_U64, 0, 0),
+    (rp.RP_BOUNDED, rp.RP_U32, 3 * 10**9, 0),
+    (rp.RP_BOUNDED, rp.RP_U32, 2**31, 0),
+    (rp.RP_NORM, rp.RP_F64, 0, 0),
+    (rp.RP_EXP, rp.RP_F64, 0, 0),
+]
+
+
+def _gpu_fill(S, dist, dtype, per, bound, flags):
+    t = torch.empty(len(S) * per, dtype=getattr(torch, TORCH_DTYPE[dtype]), device="cuda")
+    rp.rp_fill(S, dist, dtype, bound, flags, t, per)
+    torch.cuda.synchronize()
+    return t.cpu().numpy().view(NP_VIEW[dtype]).reshape(len(S), per)
+
+
+def _compare(got, ref, dist):
+    if dist in (rp.RP_NORM, rp.RP_EXP):
+        assert got.shape == ref.shape
+        d = ulp_diff(got, ref)
+        assert (np.sign(got) == np.sign(ref)).all()
+        assert d.max() <= 4, d.max()
+        # only tail values (|x| beyond the ziggurat radius) may differ at all
+        r = 3.6541528853610088 if dist == rp.RP_NORM else 7.69711747013105
+        assert (np.abs(ref[d > 0]) >= r).all()
+    else:
+        assert np.array_equal(got, ref)
+
+
+def _states_equal(S, engine, ostreams):
+    words, phase = S.get()
+    nw = rp.STATE_WORDS[rp.ENGINES[engine]]
+    for i, o in ostreams.items():
+        assert [int(words[k, i]) for k in range(nw)] == o.state[:nw], (engine, i)
+        assert int(phase[i]) == o.phase, (engine, i)
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"d{c[0]}t{c[1]}b{c[2]}f{c[3]}")
+def test_fill_matches_oracle(engine, case):
+    dist, dtype, bound, flags = case
+    n = 67 if engine not in ("ranlux++",) else 37   # ragged: not a multiple of 4 or 64
+    S = make_streams(engine, n)
+    ostreams = {i: oracle_stream(engine, i) for i in range(n)}
+    for per in (129, 1, 333):   # successive calls continue each substream
+        got = _gpu_fill(S, dist, dtype, per, bound, flags)
+        for i in range(n):
+            ref = oracle_fill(ostreams[i], dist, dtype, per, bound, flags)
+            _compare(got[i], ref, dist)
+        _states_equal(S, engine, ostreams)
+
+
+@pytest.mark.parametrize("engine", ["philox4x32", "pcg64", "philox"])
+def test_ziggurat_long_run_with_tails(engine):
+    """Enough normals to cross many chunks and hit the tail path in the
+    wavefront kernel (tail probability 2.6e-4 per sample)."""
+    n, per = 20, 20000
+    S = make_streams(engine, n)
+    got = _gpu_fill(S, rp.RP_NORM, rp.RP_F64, per, 0, 0)
+    tails = 0
+    for i in range(n):
+        ref = oracle_stream(engine, i).norm(per)
+        _compare(got[i], ref, rp.RP_NORM)
+        tails += int((np.abs(ref) > 3.6541528853610088).sum())
+    assert tails > 30
+
+
+def test_zero_and_invalid():
+    S = make_streams("philox4x32", 8)
+    before = S.get()[0].copy()
+    t = torch.empty(0, dtype=torch.float64, device="cuda")
+    rp.rp_fill(S, rp.RP_NORM, rp.RP_F64, 0, 0, t, 0)    # per_stream = 0 is a no-op
+    assert (S.get()[0] == before).all()
+    with pytest.raises(rp.RpError) as ei:
+        rp.rp_fill(S, rp.RP_NORM, rp.RP_F32, 0, 0, torch.empty(8, device="cuda"), 1)
+    assert ei.value.code == rp.RP_EUNSUPPORTED
+    with pytest.raises(rp.RpError) as ei:
+        rp.rp_fill(S, rp.RP_NORM, rp.RP_F64, 0, 0, 0, 4)
+    assert ei.value.code == rp.RP_ENULL
+    with pytest.raises(rp.RpError) as ei:
+        rp.rp_fill(S, rp.RP_BOUNDED, rp.RP_U32, 2**40, 0, torch.empty(8, dtype=torch.int32, device="cuda"), 1)
+    assert ei.value.code == rp.RP_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("engine,kind", [("philox4x32", "key"), ("pcg64", "inc")])
+@pytest.mark.parametrize("dist,dtype", [(rp.RP_RAW, rp.RP_U64), (rp.RP_U01, rp.RP_F32), (rp.RP_U01, rp.RP_F64),
+                                        (rp.RP_NORM, rp.RP_F64), (rp.RP_EXP, rp.RP_F64)])
+def test_full_size_substreams_sampled(engine, kind, dist, dtype):
+    """2^16 substreams x 2^14 values (the benchmark's launch); 258 substreams
+    checked in full against the oracle."""
+    n, per = workloads.SUB_N, workloads.SUB_PER
+    S = make_streams(engine, n)
+    t = torch.empty(n * per, dtype=getattr(torch, TORCH_DTYPE[dtype]), device="cuda")
+    rp.rp_fill(S, dist, dtype, 0, 0, t, per)
+    idx = workloads.sampled_substreams(n)
+    rows = t.view(n, per).index_select(0, torch.as_tensor(idx, device="cuda")).cpu().numpy().view(NP_VIEW[dtype])
+    del t
+    for r, i in zip(rows, idx):
+        ref = oracle_fill(oracle_stream(engine, i), dist, dtype, per)
+        _compare(r, ref, dist)
