@@ -33,7 +33,24 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--only", default="", help="comma-separated fill names to run (profiling)")
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="run only plain fill/copy kernels of known size (counter calibration)")
     return p.parse_args()
+
+
+def calibrate_copy(steps):
+    """Known-size reference traffic for the HBM counters: a fill writing
+    8 GiB and a copy reading 2 GiB and writing 2 GiB, per step."""
+    import torch
+    a = torch.empty(2**30, dtype=torch.float64, device="cuda")
+    b = torch.empty(2**28, dtype=torch.float64, device="cuda")
+    c = torch.empty(2**28, dtype=torch.float64, device="cuda")
+    b.fill_(2.0)
+    for _ in range(steps):
+        a.fill_(1.0)
+        c.copy_(b)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "fill 8 GiB write + copy 2 GiB read / 2 GiB write", "steps": steps}))
 
 
 def cpu_baseline(target_cpu_s=12.0):
@@ -85,6 +102,9 @@ def main():
     from paper_2605_05099_amd import workloads
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        calibrate_copy(args.steps)
+        return
     n, per = workloads.SUB_N, workloads.SUB_PER
     total = n * per
     streams = {

@@ -38,7 +38,7 @@ namespace rp {
 struct PcgAffineDev {
     uint64_t mlo, mhi, plo, phi;
 };
-__constant__ PcgAffineDev c_pcg_lane[65];  // A^l, G_l for l = 0..64
+__constant__ PcgAffineDev c_pcg_lane[65];  // A^(8l), G_(8l) for l = 0..64 (8 words per lane)
 __constant__ PcgAffineDev c_pcg_pow2[64];  // A^(2^k), G_(2^k)
 __constant__ uint64_t c_rl_A[9];           // ranlux++ step multiplier a^2048 mod m
 
@@ -62,10 +62,12 @@ int ensure_device_tables()
     if (done[dev]) return RP_OK;
     PcgAffineDev lane[65], pow2[64];
     const PcgAffine step{{kPcgMult, 0}, {1, 0}};
+    PcgAffine step8{{1, 0}, {0, 0}};
+    for (int k = 0; k < 8; k++) step8 = compose(step, step8);
     PcgAffine cur{{1, 0}, {0, 0}};
     for (int l = 0; l <= 64; l++) {
         lane[l] = to_dev(cur);
-        cur = compose(step, cur);
+        cur = compose(step8, cur);
     }
     PcgAffine p = step;
     for (int k = 0; k < 64; k++) {
@@ -190,30 +192,51 @@ __device__ __forceinline__ int zig_classify(const ZigLds *t, uint64_t w, uint64_
 }
 
 // ---------------------------------------------------------------------------
-// wavefront-per-substream engines.  Word positions are counted from the
-// start of the block (or state) the substream pointed at when the call began.
+// wavefront-per-substream engines.  A chunk is 64 * R consecutive words of
+// one substream; lane l holds words R l .. R l + R - 1 of the chunk.  Word
+// positions are counted from the start of the block (or state) the substream
+// pointed at when the call began.  Per-substream values (keys, increments) are
+// wave-uniform and live in scalar registers.
+static constexpr int kWaveR = 8;
+
+__device__ __forceinline__ uint64_t uni64(uint64_t v)
+{
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
 struct WavePhilox32 {
-    static constexpr int R = 2;  // words per lane per chunk (one block)
-    uint64_t key, clo, chi, b0lo, b0hi;
+    static constexpr int R = kWaveR;  // 4 blocks of 2 words per lane
+    uint64_t key, b0lo, b0hi;         // uniform: key, counter of the first block
+    uint64_t clo, chi;                // this lane's first block in the chunk
     uint32_t phase0;
 
     __device__ void load(const FillArgs &a, uint64_t i, int lane)
     {
-        b0lo = a.words[i];
-        b0hi = a.words[a.n + i];
-        key = a.words[2 * a.n + i];
-        phase0 = a.phase[i];
-        clo = b0lo + (uint64_t)lane;
+        b0lo = uni64(a.words[i]);
+        b0hi = uni64(a.words[a.n + i]);
+        key = uni64(a.words[2 * a.n + i]);
+        phase0 = __builtin_amdgcn_readfirstlane(a.phase[i]);
+        clo = b0lo + (uint64_t)(lane * (R / 2));
         chi = b0hi + (clo < b0lo ? 1u : 0u);
     }
-    __device__ void gen(uint64_t w[R]) { philox4x32(clo, chi, key, w[0], w[1]); }
+    __device__ void gen(uint64_t w[R]) const
+    {
+#pragma unroll
+        for (int k = 0; k < R / 2; k++) {
+            uint64_t lo = clo + (uint64_t)k;
+            uint64_t hi = chi + (lo < clo ? 1u : 0u);
+            philox4x32(lo, hi, key, w[2 * k], w[2 * k + 1]);
+        }
+    }
     __device__ void next_chunk()
     {
         uint64_t o = clo;
-        clo += 64;
+        clo += 64 * (R / 2);
         chi += (clo < o) ? 1u : 0u;
     }
-    __device__ uint64_t far_word(uint64_t pos) const  // pos: words from the start
+    __device__ uint64_t far_word(uint64_t pos) const
     {
         uint64_t lo = b0lo + pos / 2, hi = b0hi + (lo < b0lo ? 1u : 0u);
         uint64_t w0, w1;
@@ -230,8 +253,9 @@ struct WavePhilox32 {
 };
 
 struct WavePhilox64 {
-    static constexpr int R = 4;
-    uint64_t c[4], b0[4], k0, k1;
+    static constexpr int R = kWaveR;  // 2 blocks of 4 words per lane
+    uint64_t b0[4], k0, k1;          // uniform
+    uint64_t c[4];                   // this lane's first block in the chunk
     uint32_t phase0;
 
     __device__ static void add256(const uint64_t in[4], uint64_t add, uint64_t out[4])
@@ -239,22 +263,30 @@ struct WavePhilox64 {
         uint64_t carry = add;
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            uint64_t s = in[k] + carry;
-            carry = (s < carry) ? 1u : 0u;
-            out[k] = s;
+            uint64_t v = in[k] + carry;
+            carry = (v < carry) ? 1u : 0u;
+            out[k] = v;
         }
     }
     __device__ void load(const FillArgs &a, uint64_t i, int lane)
     {
 #pragma unroll
-        for (int k = 0; k < 4; k++) b0[k] = a.words[(uint64_t)k * a.n + i];
-        k0 = a.words[4 * a.n + i];
-        k1 = a.words[5 * a.n + i];
-        phase0 = a.phase[i];
-        add256(b0, (uint64_t)lane, c);
+        for (int k = 0; k < 4; k++) b0[k] = uni64(a.words[(uint64_t)k * a.n + i]);
+        k0 = uni64(a.words[4 * a.n + i]);
+        k1 = uni64(a.words[5 * a.n + i]);
+        phase0 = __builtin_amdgcn_readfirstlane(a.phase[i]);
+        add256(b0, (uint64_t)(lane * (R / 4)), c);
     }
-    __device__ void gen(uint64_t w[R]) { philox4x64(c, k0, k1, w); }
-    __device__ void next_chunk() { add256(c, 64, c); }
+    __device__ void gen(uint64_t w[R]) const
+    {
+#pragma unroll
+        for (int k = 0; k < R / 4; k++) {
+            uint64_t blk[4];
+            add256(c, (uint64_t)k, blk);
+            philox4x64(blk, k0, k1, &w[4 * k]);
+        }
+    }
+    __device__ void next_chunk() { add256(c, 64 * (R / 4), c); }
     __device__ uint64_t far_word(uint64_t pos) const
     {
         uint64_t blk[4], w[4];
@@ -276,19 +308,31 @@ struct WavePhilox64 {
     }
 };
 
+// PCG64: lane l starts each chunk at word R l (state A^(R l) s + G_(R l) inc),
+// takes R - 1 ordinary steps inside the chunk, and moves to the next chunk
+// with the stride-64R map from the constant table.
 struct WavePcg {
-    static constexpr int R = 1;
-    u128 s, inc, s0;
+    static constexpr int R = kWaveR;
+    u128 s;        // this lane's state at its first word of the chunk
+    u128 inc, s0;  // uniform
     uint32_t phase0;
 
     __device__ void load(const FillArgs &a, uint64_t i, int lane)
     {
-        s0 = u128{a.words[i], a.words[a.n + i]};
-        inc = u128{a.words[2 * a.n + i], a.words[3 * a.n + i]};
+        s0 = u128{uni64(a.words[i]), uni64(a.words[a.n + i])};
+        inc = u128{uni64(a.words[2 * a.n + i]), uni64(a.words[3 * a.n + i])};
         phase0 = 0;
         s = pcg_apply(c_pcg_lane[lane], s0, inc);
     }
-    __device__ void gen(uint64_t w[R]) { w[0] = pcg_dxsm(s); }
+    __device__ void gen(uint64_t w[R]) const
+    {
+        u128 t = s;
+#pragma unroll
+        for (int k = 0; k < R; k++) {
+            w[k] = pcg_dxsm(t);
+            if (k + 1 < R) t = pcg_step(t, inc);
+        }
+    }
     __device__ void next_chunk() { s = pcg_apply(c_pcg_lane[64], s, inc); }
     __device__ uint64_t far_word(uint64_t pos) const { return pcg_dxsm(pcg_jump(s0, inc, pos)); }
     __device__ void store(const FillArgs &a, uint64_t i, uint64_t pos) const
@@ -340,216 +384,513 @@ __device__ __forceinline__ bool item_value(uint64_t it, const FillArgs &a, typen
     }
 }
 
+// number of set bits of mask in lanes below this one
+__device__ __forceinline__ uint32_t mbcnt64(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Fast ziggurat test of one word as the first word of a sample.  Returns true
+// when the sample is accepted from this word alone (value in val); otherwise
+// the word starts a wedge test or the tail and needs the next word(s).
+template <int DIST>
+__device__ __forceinline__ bool zig_fast(const ZigLds *t, uint64_t w, double &val)
+{
+    const int j = (int)(w & 0xff);
+    if (DIST == RP_NORM) {
+        const uint64_t m = (w >> 9) & ((1ull << 52) - 1);
+        // m < 2^52: (2^52 + m) - 2^52 is exact; the sign comes from bit 8
+        const double md = __longlong_as_double((long long)(m | 0x4330000000000000ull)) - 0x1.0p52;
+        const double x = md * t->W[j];
+        const uint64_t sgn = (w & 0x100) << 55;
+        val = __longlong_as_double(__double_as_longlong(x) ^ (long long)sgn);
+        return m < t->K[j];
+    } else {
+        const uint64_t m = (w >> 8) & ((1ull << 53) - 1);
+        // m < 2^53: hi 2^32 + lo formed exactly with one fused operation
+        const double md = __fma_rn((double)(uint32_t)(m >> 32), 0x1.0p32, (double)(uint32_t)m);
+        val = md * t->W[j];
+        return m < t->K[j];
+    }
+}
+
+// Slow part of a sample that started at word w with next word u, for a word
+// that failed the fast test: wedge test (strips j >= 1) or exponential tail
+// (strip 0).  Returns 1 accept (value in val), 2 reject; for the normal tail
+// returns 3 (resolved by the serial walk, which may need more words).
+template <int DIST>
+__device__ __forceinline__ int zig_slow(const ZigLds *t, uint64_t w, uint64_t u, double &val)
+{
+    const int j = (int)(w & 0xff);
+    double x;
+    zig_fast<DIST>(t, w, x);
+    if (j == 0) {
+        if (DIST == RP_NORM) return 3;
+        val = RP_ZE_R - log1p(-u01_53(u));
+        return 1;
+    }
+    const double ax = (DIST == RP_NORM) ? fabs(x) : x;
+    val = x;
+    return wedge_accept<DIST>(t, j, ax, u) ? 1 : 2;
+}
+
+struct SlowSlot {
+    uint64_t w, u;
+};
+
+// Orders a wavefront's LDS accesses: writes before the barrier are visible
+// to reads after it (all lanes of one wavefront).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Copies n staged values to dst with coalesced stores: consecutive lanes
+// write consecutive 16-byte pieces when dst is 16-byte aligned, consecutive
+// elements otherwise.
+template <typename T>
+__device__ __forceinline__ void flush_stage(const T *stage, T *dst, int n, int lane)
+{
+    constexpr int V = 16 / sizeof(T);
+    int done = 0;
+    if (((uintptr_t)dst & 15) == 0) {
+        const int nvec = n / V;
+        for (int m = lane; m < nvec; m += 64) *(uint4 *)(dst + m * V) = *(const uint4 *)(stage + m * V);
+        done = nvec * V;
+    }
+    for (int t = done + lane; t < n; t += 64) dst[t] = stage[t];
+}
+
+// Slow part of a sample whose first word w0 failed the fast test.  The
+// following words are word(1), word(2), ...; only `avail` of them exist in
+// the current chunk.  Returns the words used including w0 (2 for a wedge test
+// or the exponential tail, 3 + 2 t for the normal tail), or 0 if the sample
+// needs words past the chunk; then, for the normal tail, *u1 receives an
+// unused first word of a pair when one is left (has_u1).
+template <int DIST, class Word>
+__device__ __forceinline__ int zig_resolve(const ZigLds *t, uint64_t w0, Word word, int avail, bool &accepted,
+                                           double &val, bool &has_u1, uint64_t &u1)
+{
+    const int j = (int)(w0 & 0xff);
+    accepted = false;
+    has_u1 = false;
+    if (j != 0 || DIST == RP_EXP) {
+        if (avail < 1) return 0;
+        const uint64_t u = word(1);
+        if (j != 0) {
+            double x;
+            zig_fast<DIST>(t, w0, x);
+            val = x;
+            accepted = wedge_accept<DIST>(t, j, DIST == RP_NORM ? fabs(x) : x, u);
+        } else {
+            val = RP_ZE_R - log1p(-u01_53(u));
+            accepted = true;
+        }
+        return 2;
+    }
+    // normal tail (Marsaglia 1964): pairs of uniforms until e2 + e2 > e1 e1
+    for (int it = 0; it < kMaxTailIters; it++) {
+        if (2 + 2 * it > avail) {
+            if (1 + 2 * it <= avail) {
+                has_u1 = true;
+                u1 = word(1 + 2 * it);
+            }
+            return 0;
+        }
+        const double e1 = -log1p(-u01_53(word(1 + 2 * it))) / RP_ZN_R;
+        const double e2 = -log1p(-u01_53(word(2 + 2 * it)));
+        if (e2 + e2 > e1 * e1) {
+            const double tt = RP_ZN_R + e1;
+            val = ((w0 >> 8) & 1) ? -tt : tt;
+            accepted = true;
+            return 3 + 2 * it;
+        }
+    }
+    return 2;  // unreachable in practice (see kMaxTailIters)
+}
+
+// Marks positions [from, to) of the chunk (position 64 r + lane) in skip[].
+template <int R>
+__device__ __forceinline__ void mark_range(uint64_t skip[R], int from, int to)
+{
+    to = to < 64 * R ? to : 64 * R;
+    for (int p = from; p < to; p++) {
+#pragma unroll
+        for (int r = 0; r < R; r++)
+            if ((p >> 6) == r) skip[r] |= 1ull << (p & 63);
+    }
+}
+
 template <class E, int DIST, int OT>
 __global__ __launch_bounds__(256) void k_fill_wave(FillArgs a)
 {
     using T = typename OutType<DIST, OT>::T;
-    constexpr int R = E::R;
+    constexpr int R = E::R;          // words per lane per chunk
+    constexpr int CHW = 64 * R;      // words per chunk
     constexpr bool ZIG = DIST == RP_NORM || DIST == RP_EXP;
     constexpr bool FIXED = DIST == RP_RAW || DIST == RP_U01;
     constexpr int IPW = (OT == RP_U32 || OT == RP_F32) ? 2 : 1;  // items per word
-    constexpr int RI = R * IPW;                                  // items per lane
-    constexpr int CH = 64 * RI;                                  // items per chunk
-    constexpr int CHW = 64 * R;                                  // words per chunk
 
+    const int wib = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    // chunk words in stream order, for the lane-to-position transpose and for
+    // reading the words after a sample start
+    __shared__ __align__(16) uint64_t wbuf_all[4][CHW];
+    uint64_t *const wbuf = wbuf_all[wib];
     ZigLds *zt = nullptr;
+    uint32_t *slot_pos = nullptr;
+    double *slot_val = nullptr;
+    int *slot_len = nullptr;
+    int *slot_flag = nullptr;
     if constexpr (ZIG) {
         __shared__ ZigLds zbuf;
+        __shared__ uint32_t spos[4][64];
+        __shared__ double sval[4][64];
+        __shared__ int slen[4][64];
+        __shared__ int sflag[4][64];
         load_zig<DIST>(&zbuf);
         __syncthreads();
         zt = &zbuf;
+        slot_pos = spos[wib];
+        slot_val = sval[wib];
+        slot_len = slen[wib];
+        slot_flag = sflag[wib];
     }
-    const int lane = threadIdx.x & 63;
-    const uint64_t sub = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint64_t sub = (uint64_t)__builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + wib);
     if (sub >= a.n) return;
     const uint64_t P = a.per_stream;
-    T *out = (T *)a.out + sub * P;
-    const uint64_t ltmask = (1ull << lane) - 1;
+    T *const out = (T *)a.out + sub * P;
 
     E eng;
     eng.load(a, sub, lane);
-    int e = (int)eng.phase0 * IPW;  // items of chunk 0 already used
+    int e = (int)eng.phase0 * IPW;  // items of this chunk already used
     uint64_t produced = 0;
-    uint64_t cur[R], nxt[R];
-    eng.gen(cur);
-    if constexpr (ZIG) {
-        eng.next_chunk();
-        eng.gen(nxt);
-    }
-    uint64_t final_pos = 0;  // words from the start, after the last value
-    // Every chunk yields about CH values (at least half of them for the
-    // samplers here), so this bound is never reached by a correct kernel; it
-    // only guarantees that the wavefront exits.
-    const uint64_t max_chunks = 2 * (P / CH) + 1024;
+    uint64_t final_pos = 0;         // words from the start, after the last value
+    bool pending = false;           // a sample that started in the previous chunk still needs words
+    uint64_t pend_w = 0;            // its first word
+    bool pend_hu = false;           // it holds an unused first word of a tail pair:
+    uint64_t pend_u1 = 0;           //   this one
+    // Each chunk yields well over half of CHW values, so this bound is never
+    // reached; it only guarantees that the wavefront exits.
+    const uint64_t max_chunks = 2 * (P / CHW) + 1024;
     for (uint64_t chunk = 0; chunk < max_chunks; chunk++) {
-        const uint64_t need = P - produced;
-        if constexpr (FIXED) {
-            // every item is a value: item q -> value produced + q - e
+        // ---- generate R consecutive words per lane, transpose through LDS:
+        //      afterwards w[r] is the word at chunk position 64 r + lane ----
+        {
+            uint64_t g[R];
+            eng.gen(g);
 #pragma unroll
-            for (int r = 0; r < RI; r++) {
-                const int q = RI * lane + r;
-                const uint64_t w = cur[r / IPW];
-                const uint64_t it = (IPW == 2) ? ((r & 1) ? (w >> 32) : (w & 0xffffffffull)) : w;
-                T v;
-                item_value<DIST, OT>(it, a, v);
-                const uint64_t idx = (uint64_t)(q - e);
-                if (q >= e && idx < need) out[produced + idx] = v;
+            for (int k = 0; k < R; k += 2) {
+                ulonglong2 q;
+                q.x = g[k];
+                q.y = g[k + 1];
+                *(ulonglong2 *)(wbuf + R * lane + k) = q;
             }
-            const uint64_t got = (uint64_t)(CH - e);
+            eng.next_chunk();
+        }
+        wave_sync();
+        uint64_t w[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) w[r] = wbuf[64 * r + lane];
+        const uint64_t base_pos = chunk * CHW;
+
+        if constexpr (FIXED) {
+            const uint64_t need = P - produced;
+            const uint64_t got = (uint64_t)(IPW * CHW - e);
+            T *dst = out + produced - e;  // item q of the chunk goes to dst[q]
+            if constexpr (IPW == 1) {
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    T v;
+                    item_value<DIST, OT>(w[r], a, v);
+                    const int q = 64 * r + lane;
+                    if (q >= e && (uint64_t)(q - e) < need) dst[q] = v;
+                }
+            } else {
+                const bool al8 = (((uintptr_t)dst) & 7) == 0;
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    T v0, v1;
+                    item_value<DIST, OT>(w[r] & 0xffffffffull, a, v0);
+                    item_value<DIST, OT>(w[r] >> 32, a, v1);
+                    const int q = 2 * (64 * r + lane);
+                    const bool ok0 = q >= e && (uint64_t)(q - e) < need;
+                    const bool ok1 = q + 1 >= e && (uint64_t)(q + 1 - e) < need;
+                    if (al8 && ok0 && ok1) {
+                        uint2 pr;
+                        pr.x = __builtin_bit_cast(uint32_t, v0);
+                        pr.y = __builtin_bit_cast(uint32_t, v1);
+                        *(uint2 *)(dst + q) = pr;
+                    } else {
+                        if (ok0) dst[q] = v0;
+                        if (ok1) dst[q + 1] = v1;
+                    }
+                }
+            }
             if (got >= need) {
                 const uint64_t items = (uint64_t)e + need;
-                final_pos = chunk * CHW + (items + IPW - 1) / IPW;
+                final_pos = base_pos + (items + IPW - 1) / IPW;
                 break;
             }
             produced += got;
             e = 0;
+        } else if constexpr (!ZIG) {
+            // Lemire: every item is a candidate of its own; items in stream
+            // order are (r, lane, half)
+            constexpr int H = IPW;
+            T val[R][H];
+            uint64_t okm[R][H];
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+#pragma unroll
+                for (int h = 0; h < H; h++) {
+                    const uint64_t it = (H == 2) ? (h ? (w[r] >> 32) : (w[r] & 0xffffffffull)) : w[r];
+                    const bool ok = item_value<DIST, OT>(it, a, val[r][h]);
+                    const int q = H * (64 * r + lane) + h;
+                    okm[r][h] = __ballot(ok && q >= e);
+                }
+            }
+            const uint64_t need = P - produced;
+            uint64_t basec = 0;
+            int endq = -1;
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                uint32_t idx = (uint32_t)basec;
+#pragma unroll
+                for (int h = 0; h < H; h++) idx += mbcnt64(okm[r][h]);
+#pragma unroll
+                for (int h = 0; h < H; h++) {
+                    if ((okm[r][h] >> lane) & 1) {
+                        if (idx < need) out[produced + idx] = val[r][h];
+                        if (idx == need - 1) endq = H * (64 * r + lane) + h + 1;
+                        idx++;
+                    }
+                }
+#pragma unroll
+                for (int h = 0; h < H; h++) basec += (uint64_t)__popcll(okm[r][h]);
+            }
+            if (basec >= need) {
+                const uint64_t who = __ballot(endq >= 0);
+                const int src = __ffsll((long long)who) - 1;
+                const int eq = __shfl(endq, src);
+                final_pos = base_pos + (uint64_t)((eq + H - 1) / H);
+                break;
+            }
+            produced += basec;
+            e = 0;
         } else {
-            T val[RI];
-            bool acc[RI];
-            int len[RI];
-            uint64_t lmask[RI], tmask[RI];
+            // ---- ziggurat: lane l parses its own words S l .. S l + S - 1
+            //      (S = R) in stream order; wedge / tail tests of all items that
+            //      fail the fast test run first, compacted into one pass ----
+            constexpr int S = R;
+            uint64_t g[S];
 #pragma unroll
-            for (int r = 0; r < RI; r++) {
-                len[r] = 1;
-                lmask[r] = 0;
-                tmask[r] = 0;
+            for (int k = 0; k < S; k++) g[k] = wbuf[S * lane + k];
+            double val[S];
+            int len[S];        // words used by a sample starting at item k (0: past the chunk)
+            uint32_t accb = 0; // bit k: such a sample is accepted
+            uint32_t longb = 0;
+#pragma unroll
+            for (int k = 0; k < S; k++) {
+                const bool f = zig_fast<DIST>(zt, g[k], val[k]);
+                len[k] = 1;
+                accb |= (f ? 1u : 0u) << k;
+                longb |= (f ? 0u : 1u) << k;
             }
-            if constexpr (ZIG) {
-                // the word after item q: same lane, next lane, or next chunk
-                const uint64_t up = __shfl(cur[0], (lane + 1) & 63);
-                const uint64_t nx0 = __shfl(nxt[0], 0);
-                const uint64_t after_last = (lane == 63) ? nx0 : up;
+            // rank of this lane's first long item among all long items
+            const int nlong = __popc(longb);
+            int lbase = 0;
 #pragma unroll
-                for (int r = 0; r < R; r++) {
-                    const uint64_t nw = (r + 1 < R) ? cur[(r + 1) % R] : after_last;
-                    double v;
-                    const int kind = zig_classify<DIST>(zt, cur[r], nw, v);
-                    val[r] = v;
-                    acc[r] = kind <= 1;
-                    len[r] = kind == 0 ? 1 : 2;
-                    lmask[r] = __ballot(kind != 0);
-                    tmask[r] = __ballot(kind == 3);
-                }
-            } else {
+            for (int bit = 0; bit < 4; bit++) lbase += (int)mbcnt64(__ballot((nlong >> bit) & 1)) << bit;
+            int K = 0;
 #pragma unroll
-                for (int r = 0; r < RI; r++) {
-                    const uint64_t w = cur[r / IPW];
-                    const uint64_t it = (IPW == 2) ? ((r & 1) ? (w >> 32) : (w & 0xffffffffull)) : w;
-                    acc[r] = item_value<DIST, OT>(it, a, val[r]);
-                }
-            }
-            // items before the entry point e belong to the previous sample
-            uint64_t skip[RI];
+            for (int bit = 0; bit < 4; bit++) K += __popcll(__ballot((nlong >> bit) & 1)) << bit;
+            const int npre = pending ? 1 : 0;
+            K += npre;
+            lbase += npre;
+            bool pre_acc = false;
+            double pre_val = 0.0;
+            int pre_len = 1;
+            bool pre_hu = false;
+            uint64_t pre_u1 = 0;
+            for (int base = 0; base < K; base += 64) {
+                {
+                    int rk = lbase;
 #pragma unroll
-            for (int r = 0; r < RI; r++) {
-                const int lim = (e - r + RI - 1) / RI;  // lanes l with RI l + r < e
-                skip[r] = lim <= 0 ? 0ull : (lim >= 64 ? ~0ull : ((1ull << lim) - 1));
-            }
-            int c = e;  // next sample start (relative to this chunk)
-            if constexpr (ZIG) {
-                uint64_t cand = 0;
-#pragma unroll
-                for (int r = 0; r < R; r++) cand |= lmask[r];
-                while (cand) {
-                    const int l = __ffsll((long long)cand) - 1;
-                    cand &= cand - 1;
-#pragma unroll
-                    for (int r = 0; r < R; r++) {
-                        if (!((lmask[r] >> l) & 1)) continue;
-                        const int q = R * l + r;
-                        if (q < c) continue;  // used by an earlier sample
-                        int L = 2;
-                        if constexpr (DIST == RP_NORM) {
-                            if ((tmask[r] >> l) & 1) {
-                                // Marsaglia's tail: pairs of uniforms from the
-                                // words after q until e2 + e2 > e1 e1
-                                const uint64_t w0 = readlane64(cur[r], l);
-                                auto word_at = [&](int p) -> uint64_t {
-                                    if (p < CHW) {
-                                        uint64_t v = cur[0];
-#pragma unroll
-                                        for (int rr = 1; rr < R; rr++) v = (p % R == rr) ? cur[rr] : v;
-                                        return readlane64(v, p / R);
-                                    }
-                                    if (p < 2 * CHW) {
-                                        const int pp = p - CHW;
-                                        uint64_t v = nxt[0];
-#pragma unroll
-                                        for (int rr = 1; rr < R; rr++) v = (pp % R == rr) ? nxt[rr] : v;
-                                        return readlane64(v, pp / R);
-                                    }
-                                    return eng.far_word(chunk * CHW + (uint64_t)p);
-                                };
-                                double tv = 0.0;
-                                for (int it = 0; it < kMaxTailIters; it++) {
-                                    const double U1 = u01_53(word_at(q + 1 + 2 * it));
-                                    const double U2 = u01_53(word_at(q + 2 + 2 * it));
-                                    const double e1 = -log1p(-U1) / RP_ZN_R;
-                                    const double e2 = -log1p(-U2);
-                                    if (e2 + e2 > e1 * e1) {
-                                        const double tt = RP_ZN_R + e1;
-                                        tv = ((w0 >> 8) & 1) ? -tt : tt;
-                                        L = 3 + 2 * it;
-                                        break;
-                                    }
-                                }
-                                if (lane == l) {
-                                    val[r] = tv;
-                                    acc[r] = true;
-                                    len[r] = L;
-                                }
-                            }
+                    for (int k = 0; k < S; k++) {
+                        if ((longb >> k) & 1) {
+                            if (rk >= base && rk < base + 64) slot_pos[rk - base] = (uint32_t)(S * lane + k);
+                            rk++;
                         }
-                        c = q + L;
-                        for (int p = q + 1; p < c && p < CH; p++) {
+                    }
+                    if (npre && base == 0 && lane == 0) slot_pos[0] = 0xffffffffu;
+                }
+                wave_sync();
+                if (base + lane < K) {
+                    const uint32_t sp = slot_pos[lane];
+                    const bool pend = sp == 0xffffffffu;
+                    // the pending sample's words: [its spare uniform,] then this
+                    // chunk from position 0
+                    const int q = pend ? -1 : (int)sp;
+                    const int hu = (pend && pend_hu) ? 1 : 0;
+                    const uint64_t w0 = pend ? pend_w : wbuf[q];
+                    const uint64_t pu1 = pend_u1;
+                    bool acd, hu_out;
+                    double v = 0.0;
+                    uint64_t u1o = 0;
+                    const int L = zig_resolve<DIST>(
+                        zt, w0, [&](int kk) { return (kk == 1 && hu) ? pu1 : wbuf[q + kk - hu]; },
+                        CHW - 1 - q + hu, acd, v, hu_out, u1o);
+                    // length 0: runs past the chunk (-1: keeping a spare uniform)
+                    slot_len[lane] = (L == 0 && hu_out) ? -1 : L;
+                    slot_val[lane] = hu_out ? __longlong_as_double((long long)u1o) : v;
+                    slot_flag[lane] = acd ? 1 : 0;
+                }
+                wave_sync();
+                if (npre && base == 0) {
+                    pre_len = slot_len[0];
+                    pre_acc = slot_flag[0] != 0;
+                    pre_val = slot_val[0];
+                    pre_hu = pre_len < 0;
+                    pre_u1 = (uint64_t)__double_as_longlong(pre_val);
+                }
+                {
+                    int rk = lbase;
 #pragma unroll
-                            for (int rr = 0; rr < R; rr++)
-                                if (p % R == rr) skip[rr] |= 1ull << (p / R);
+                    for (int k = 0; k < S; k++) {
+                        if ((longb >> k) & 1) {
+                            if (rk >= base && rk < base + 64) {
+                                const int L = slot_len[rk - base];
+                                len[k] = L;  // <= 0: runs past the chunk
+                                if (slot_flag[rk - base]) {
+                                    accb |= 1u << k;
+                                    val[k] = slot_val[rk - base];
+                                }
+                                if (L < 0) val[k] = slot_val[rk - base];  // spare uniform bits
+                            }
+                            rk++;
                         }
                     }
                 }
+                wave_sync();
             }
-            // compaction: prefix count of accepted starts in stream order
-            bool outp[RI];
-            uint64_t bal[RI];
-            uint64_t before = 0, total = 0;
-#pragma unroll
-            for (int r = 0; r < RI; r++) {
-                outp[r] = acc[r] && !((skip[r] >> lane) & 1);
-                bal[r] = __ballot(outp[r]);
-                before += (uint64_t)__popcll(bal[r] & ltmask);
-                total += (uint64_t)__popcll(bal[r]);
-            }
-            uint64_t idx = before;
-            int endp = -1;
-#pragma unroll
-            for (int r = 0; r < RI; r++) {
-                if (outp[r]) {
-                    if (idx < need) out[produced + idx] = val[r];
-                    if (idx == need - 1) endp = RI * lane + r + len[r];
-                    idx++;
+            // ---- the previous chunk's pending sample ----
+            int e0 = e;  // words of this chunk used before the first start
+            bool pre_out = false;
+            bool still_pending = false;
+            if (pending) {
+                if (pre_len <= 0) {
+                    // runs past this chunk as well: it uses the whole chunk
+                    pend_hu = pre_len < 0;
+                    pend_u1 = pre_u1;
+                    still_pending = true;
+                    e0 = CHW;
+                } else {
+                    e0 = pre_len - 1 - (pend_hu ? 1 : 0);
+                    pending = false;
+                    pre_out = pre_acc;
                 }
             }
-            if (total >= need) {
-                const uint64_t who = __ballot(endp >= 0);
+            (void)pre_hu;
+            if (pre_out) {
+                if (lane == 0) out[produced] = pre_val;
+                produced++;
+                if (produced == P) {
+                    final_pos = base_pos + (uint64_t)e0;
+                    break;
+                }
+            }
+            const uint64_t need = P - produced;
+            // ---- per-lane parse with the entry fixed point: a lane's entry
+            //      (words already used) is the previous lane's exit ----
+            int entry = lane == 0 ? e0 : 0;
+            uint32_t outb = 0;  // bit k: item k starts an accepted sample
+            uint32_t pendb = 0; // bit k: item k starts a sample that runs past the chunk
+            int exitw = 0;
+            for (int it = 0; it < 66; it++) {
+                int skp = entry;
+                outb = 0;
+                pendb = 0;
+                bool past = false;
+#pragma unroll
+                for (int k = 0; k < S; k++) {
+                    const bool start = skp == 0 && !past;
+                    const int L = len[k];
+                    outb |= (start && ((accb >> k) & 1) && L > 0 ? 1u : 0u) << k;
+                    pendb |= (start && L <= 0 ? 1u : 0u) << k;
+                    past = past || (start && L <= 0);
+                    skp = start ? (L > 0 ? L - 1 : 0) : (skp > 0 ? skp - 1 : 0);
+                }
+                // words still owed after this lane's segment
+                exitw = past ? (1 << 20) : skp;
+                int prev = __shfl_up(exitw, 1);
+                const int ne = lane == 0 ? e0 : prev;
+                const bool changed = __ballot(ne != entry) != 0;
+                entry = ne;
+                if (!changed) break;
+            }
+            // a sample running past the chunk (at most one: it uses the rest)
+            const uint64_t pl = __ballot(pendb != 0);
+            if (pl && !still_pending) {
+                const int lp = __ffsll((long long)pl) - 1;
+                const int kp = __ffs((int)__shfl((int)pendb, lp)) - 1;
+                const int q = S * lp + kp;
+                pending = true;
+                pend_w = wbuf[q];
+                int lq = 0;
+                uint64_t vb = 0;
+#pragma unroll
+                for (int k = 0; k < S; k++)
+                    if (k == kp) {
+                        lq = len[k];
+                        vb = (uint64_t)__double_as_longlong(val[k]);
+                    }
+                pend_hu = __shfl(lq, lp) < 0;
+                pend_u1 = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)vb, lp)) |
+                          ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(vb >> 32), lp) << 32);
+            }
+            if (still_pending) outb = 0;
+            // ---- compaction: prefix of per-lane counts, values staged in LDS
+            //      in stream order, then coalesced stores ----
+            const int cnt = __popc(outb);
+            int obase = 0, total = 0;
+#pragma unroll
+            for (int bit = 0; bit < 4; bit++) {
+                const uint64_t bb = __ballot((cnt >> bit) & 1);
+                obase += (int)mbcnt64(bb) << bit;
+                total += __popcll(bb) << bit;
+            }
+            double *stage = (double *)wbuf;  // the chunk's words are no longer needed
+            wave_sync();
+            int endq = -1;
+            {
+                int o = obase;
+#pragma unroll
+                for (int k = 0; k < S; k++) {
+                    if ((outb >> k) & 1) {
+                        stage[o] = val[k];
+                        if ((uint64_t)o == need - 1) endq = S * lane + k + len[k];
+                        o++;
+                    }
+                }
+            }
+            wave_sync();
+            const int nv = (uint64_t)total < need ? total : (int)need;
+            flush_stage<double>(stage, (double *)out + produced, nv, lane);
+            if ((uint64_t)total >= need) {
+                const uint64_t who = __ballot(endq >= 0);
                 const int src = __ffsll((long long)who) - 1;
-                const int endq = __shfl(endp, src);
-                final_pos = chunk * CHW + (uint64_t)((endq + IPW - 1) / IPW);
+                final_pos = base_pos + (uint64_t)__shfl(endq, src);
                 break;
             }
-            produced += total;
-            if constexpr (ZIG) e = c > CH ? c - CH : 0;
-            else e = 0;
+            produced += (uint64_t)total;
+            // words of the next chunk already used by the last lane's sample
+            const int last_exit = __shfl(exitw, 63);
+            e = pending ? 0 : last_exit;
         }
-        if constexpr (ZIG) {
-#pragma unroll
-            for (int r = 0; r < R; r++) cur[r] = nxt[r];
-            eng.next_chunk();
-            eng.gen(nxt);
-        } else {
-            eng.next_chunk();
-            eng.gen(cur);
-        }
+        wave_sync();  // the next chunk overwrites wbuf
     }
     if (lane == 0) eng.store(a, sub, final_pos);
 }
