@@ -154,6 +154,29 @@ enum { RP_FLAG_52BIT = 1 }; /* uniform method 2 (mantissa fill, 52/23 bits) */
 int rp_fill(rp_streams *s, int dist, int dtype, uint64_t bound, int flags, void *d_out,
             uint64_t per_stream, void *hip_stream);
 
+/* ---- fused generate-and-reduce (Section 3.1 normals) -------------------- */
+/* For every substream i draws per_stream standard normals (the same values
+ * rp_fill(RP_NORM) would return) and stores only their sum and sum of
+ * squares, accumulated in draw order in binary64: d_sum[i], d_sumsq[i].
+ * The substreams are advanced as by that fill.  per_stream = 0 stores
+ * zeros.  Device buffers of n doubles each, owned by the caller. */
+int rp_norm_moments(rp_streams *s, uint64_t per_stream, double *d_sum, double *d_sumsq, void *hip_stream);
+
+/* ---- gamma and beta, one draw per element (Section 3.1, "Gamma and ------ */
+/* related distributions"; Table 4) ----------------------------------------- */
+/* Element e (0 <= e < n <= number of substreams) draws one Gamma(alpha[e], 1)
+ * value from substream e by Marsaglia and Tsang's method; shape < 1 draws
+ * Gamma(alpha + 1) and then a uniform U and scales by U^(1/alpha).  The draw
+ * is computed in binary64 from the binary32 shape and rounded once to
+ * binary32 into z[e].  A shape that is not > 0 (or NaN) gives NaN and uses
+ * no words.  Substreams e >= n are untouched.  All pointers are device
+ * memory owned by the caller; n = 0 does nothing. */
+int rp_gamma_elem(rp_streams *s, const float *d_alpha, float *d_z, uint64_t n, void *hip_stream);
+/* Beta(a[e], b[e]) = X / (X + Y), X ~ Gamma(a) drawn before Y ~ Gamma(b) on
+ * substream e; X + Y = 0 (both underflow) gives a / (a + b).  Invalid
+ * parameters as for rp_gamma_elem. */
+int rp_beta_elem(rp_streams *s, const float *d_a, const float *d_b, float *d_z, uint64_t n, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1101,4 +1101,6 @@ int launch_fill(int engine, int dist, int dtype, const FillArgs &a, hipStream_t 
     return fail(RP_EINVAL, "unknown engine");
 }
 
+#include "k_samplers.h"
+
 }  // namespace rp

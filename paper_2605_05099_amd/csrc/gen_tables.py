@@ -1,4 +1,4 @@
-"""Generate csrc/zig_tables.inc: ziggurat and squeeze tables for the kernels.
+"""Generate csrc/zig_tables.inc: ziggurat, squeeze and log tables for the kernels.
 
 Geometry (Section 3.1 and the ziggurat figure): 256 strips of equal area v
 under f (normal: exp(-x^2/2), exponential: exp(-x)); edges
@@ -29,6 +29,10 @@ rounding of l_j and of exp) makes a squeeze decision agree with the plain
 test y < f(x) evaluated in binary64.
 
 B = 52 for the normal (52-bit magnitude), 53 for the exponential.
+
+The log table (c_i, 1/c_i, log c_i as hi + lo) lets the gamma boost form
+log(U) to about 2^-70 absolute, so that U^(1/alpha) = exp(log(U)/alpha) stays
+within an ulp even when |log(U)/alpha| is in the hundreds.
 Run: python paper_2605_05099_amd/csrc/gen_tables.py
 """
 import os
@@ -157,6 +161,25 @@ def _arr(ctype, name, vals, fmt):
     return f"RP_TBL {ctype} {name}[256] = {{\n{body}\n}};"
 
 
+def log_table():
+    """Table for an accurate log on [1, 2): c_i = 1 + (i + 1/2)/256, with
+    1/c_i rounded and log(c_i) as a pair of doubles (hi + lo)."""
+    C, INV, HI, LO = [], [], [], []
+    for i in range(256):
+        c = 1 + (mp.mpf(i) + mp.mpf(1) / 2) / 256
+        C.append(float(c))
+        INV.append(float(1 / c))
+        lg = mp.log(c)
+        hi = float(lg)
+        HI.append(hi)
+        LO.append(float(lg - mp.mpf(hi)))
+    ln2 = mp.log(2)
+    # ln2 split so that e * LN2_HI is exact for |e| < 2^11
+    ln2_hi = float(mp.floor(ln2 * 2**42) / 2**42)
+    ln2_lo = float(ln2 - mp.mpf(ln2_hi))
+    return C, INV, HI, LO, ln2_hi, ln2_lo
+
+
 def main():
     out = ["// Generated by csrc/gen_tables.py (mpmath, 60 digits, top-down solve). Do not edit.",
            "// Define RP_TBL (e.g. as `__device__ const`) before including.",
@@ -174,6 +197,14 @@ def main():
         out.append(_arr("double", p + "_S", t["S"], hx))
         out.append(_arr("double", p + "_DP", t["DP"], hx))
         out.append(_arr("double", p + "_DM", t["DM"], hx))
+    C, INV, HI, LO, l2h, l2l = log_table()
+    hx = lambda v: float.hex(v)
+    out.append(f"static constexpr double RP_LN2_HI = {hx(l2h)};")
+    out.append(f"static constexpr double RP_LN2_LO = {hx(l2l)};")
+    out.append(_arr("double", "RP_LOG_C", C, hx))
+    out.append(_arr("double", "RP_LOG_INV", INV, hx))
+    out.append(_arr("double", "RP_LOG_HI", HI, hx))
+    out.append(_arr("double", "RP_LOG_LO", LO, hx))
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "zig_tables.inc")
     with open(path, "w") as fh:
         fh.write("\n".join(out) + "\n")

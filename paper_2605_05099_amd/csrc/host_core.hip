@@ -946,3 +946,65 @@ extern "C" int rp_fill(rp_streams *s, int dist, int dtype, uint64_t bound, int f
     a.flags = flags;
     return launch_fill(s->engine, dist, dtype, a, (hipStream_t)hip_stream);
 }
+
+// ---------------------------------------------------------------------------
+// lane-per-substream samplers
+static FillArgs state_args(rp_streams *s, uint64_t per_stream)
+{
+    FillArgs a{};
+    a.words = s->d_words;
+    a.phase = s->d_phase;
+    a.n = s->n;
+    a.per_stream = per_stream;
+    return a;
+}
+
+extern "C" int rp_norm_moments(rp_streams *s, uint64_t per_stream, double *d_sum, double *d_sumsq,
+                               void *hip_stream)
+{
+    if (!s) return fail(RP_ENULL, "rp_norm_moments: NULL streams");
+    if (s->n == 0) return RP_OK;
+    if (!d_sum || !d_sumsq) return fail(RP_ENULL, "rp_norm_moments: NULL output");
+    if ((uintptr_t)d_sum % 8 || (uintptr_t)d_sumsq % 8)
+        return fail(RP_EINVAL, "rp_norm_moments: outputs not aligned to 8 bytes");
+    int rc = ensure_device_tables();
+    if (rc) return rc;
+    SampArgs a{};
+    a.f = state_args(s, per_stream);
+    a.count = s->n;
+    a.sum = d_sum;
+    a.sumsq = d_sumsq;
+    return launch_moments(s->engine, a, (hipStream_t)hip_stream);
+}
+
+static int elem_common(const char *who, rp_streams *s, const float *pa, const float *pb, bool beta, float *z,
+                       uint64_t n, void *hip_stream)
+{
+    if (!s) return fail(RP_ENULL, "%s: NULL streams", who);
+    if (n == 0) return RP_OK;
+    if (!pa || !z || (beta && !pb)) return fail(RP_ENULL, "%s: NULL device pointer", who);
+    if (n > s->n) return fail(RP_EINVAL, "%s: %llu elements but only %llu substreams", who,
+                              (unsigned long long)n, (unsigned long long)s->n);
+    if ((uintptr_t)pa % 4 || (uintptr_t)z % 4 || (beta && (uintptr_t)pb % 4))
+        return fail(RP_EINVAL, "%s: pointers not aligned to 4 bytes", who);
+    int rc = ensure_device_tables();
+    if (rc) return rc;
+    SampArgs a{};
+    a.f = state_args(s, 1);
+    a.count = n;
+    a.pa = pa;
+    a.pb = pb;
+    a.z = z;
+    return launch_gamma_elem(s->engine, a, beta, (hipStream_t)hip_stream);
+}
+
+extern "C" int rp_gamma_elem(rp_streams *s, const float *d_alpha, float *d_z, uint64_t n, void *hip_stream)
+{
+    return elem_common("rp_gamma_elem", s, d_alpha, nullptr, false, d_z, n, hip_stream);
+}
+
+extern "C" int rp_beta_elem(rp_streams *s, const float *d_a, const float *d_b, float *d_z, uint64_t n,
+                            void *hip_stream)
+{
+    return elem_common("rp_beta_elem", s, d_a, d_b, true, d_z, n, hip_stream);
+}

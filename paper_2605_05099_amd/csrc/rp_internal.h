@@ -61,4 +61,16 @@ struct FillArgs {
 
 int launch_fill(int engine, int dist, int dtype, const FillArgs &a, hipStream_t stream);
 
+// lane-per-substream samplers (k_samplers.h)
+struct SampArgs {
+    FillArgs f;           // substream states (f.n = substreams, f.per_stream for moments)
+    uint64_t count;       // lanes: substreams (moments) or elements
+    const float *pa;      // per-element shape (gamma) or a (beta)
+    const float *pb;      // per-element b (beta)
+    float *z;             // per-element result
+    double *sum, *sumsq;  // per-substream moments
+};
+int launch_moments(int engine, const SampArgs &s, hipStream_t stream);
+int launch_gamma_elem(int engine, const SampArgs &s, bool beta, hipStream_t stream);
+
 }  // namespace rp
