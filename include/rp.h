@@ -177,6 +177,21 @@ int rp_gamma_elem(rp_streams *s, const float *d_alpha, float *d_z, uint64_t n, v
  * parameters as for rp_gamma_elem. */
 int rp_beta_elem(rp_streams *s, const float *d_a, const float *d_b, float *d_z, uint64_t n, void *hip_stream);
 
+/* ---- implicit-reparameterization backward (gamma and beta draws) -------- */
+/* A draw z = F^{-1}(u; theta) is differentiated with u held fixed:
+ * dz/dtheta = -(dF/dtheta)(z; theta) / f(z; theta), F the distribution
+ * function and f the density of the Gamma(alpha, 1) or Beta(a, b) law
+ * sampled by rp_gamma_elem / rp_beta_elem (Section 3.1 defines the laws; the
+ * paper has no derivatives).  Each element returns g_theta = g_z dz/dtheta.
+ * Inputs and outputs are binary32 device arrays of n elements owned by the
+ * caller; the derivative is evaluated in binary64 at the binary32 values.
+ * z = 0 (or z = 1 for beta) gives 0; a parameter not > 0 or z outside the
+ * support gives NaN.  Stateless; n = 0 does nothing. */
+int rp_gamma_grad(const float *d_z, const float *d_alpha, const float *d_gz, float *d_galpha, uint64_t n,
+                  void *hip_stream);
+int rp_beta_grad(const float *d_z, const float *d_a, const float *d_b, const float *d_gz, float *d_ga, float *d_gb,
+                 uint64_t n, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

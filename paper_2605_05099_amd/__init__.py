@@ -61,6 +61,8 @@ _SIGS = {
     "rp_norm_moments": ([_vp, _u64, _vp, _vp, _vp], _int),
     "rp_gamma_elem": ([_vp, _vp, _vp, _u64, _vp], _int),
     "rp_beta_elem": ([_vp, _vp, _vp, _vp, _u64, _vp], _int),
+    "rp_gamma_grad": ([_vp, _vp, _vp, _vp, _u64, _vp], _int),
+    "rp_beta_grad": ([_vp, _vp, _vp, _vp, _vp, _vp, _u64, _vp], _int),
 }
 
 
@@ -157,6 +159,16 @@ def rp_gamma_elem(streams, alpha, z, n, stream=None):
 
 def rp_beta_elem(streams, a, b, z, n, stream=None):
     _check(lib().rp_beta_elem(streams.h, _dev_ptr(a), _dev_ptr(b), _dev_ptr(z), n, _stream_ptr(stream)))
+
+
+def rp_gamma_grad(z, alpha, gz, galpha, n, stream=None):
+    _check(lib().rp_gamma_grad(_dev_ptr(z), _dev_ptr(alpha), _dev_ptr(gz), _dev_ptr(galpha), n,
+                               _stream_ptr(stream)))
+
+
+def rp_beta_grad(z, a, b, gz, ga, gb, n, stream=None):
+    _check(lib().rp_beta_grad(_dev_ptr(z), _dev_ptr(a), _dev_ptr(b), _dev_ptr(gz), _dev_ptr(ga), _dev_ptr(gb), n,
+                              _stream_ptr(stream)))
 
 
 # ---- object wrappers ----------------------------------------------------------------
