@@ -177,6 +177,46 @@ int rp_gamma_elem(rp_streams *s, const float *d_alpha, float *d_z, uint64_t n, v
  * parameters as for rp_gamma_elem. */
 int rp_beta_elem(rp_streams *s, const float *d_a, const float *d_b, float *d_z, uint64_t n, void *hip_stream);
 
+/* ---- batched gamma and beta (Section 3.1; Table 4) ---------------------- */
+/* Set j (0 <= j < n_sets <= number of substreams) draws count[j] values from
+ * substream j: Gamma(alpha[j], 1) by Marsaglia and Tsang's method (shape < 1:
+ * Gamma(alpha + 1) then the U^(1/alpha) boost), or Beta(a[j], b[j]) as
+ * X / (X + Y) with X ~ Gamma(a) drawn before Y ~ Gamma(b).  The values go to
+ * d_out[offset_j ...], offset_j = count[0] + ... + count[j-1] (set-major), in
+ * binary64, each set's values in its stream's serial order; the substreams
+ * are advanced as by those serial draws.  Negative counts count as 0.  A set
+ * whose parameter is not > 0 (or NaN) gets NaN values and its substream is
+ * untouched.  d_out must hold sum(count) doubles; all arrays are device
+ * memory owned by the caller.
+ *
+ * The plan holds scratch memory (about 12 bytes per set), the generator's
+ * launch configuration, and a HIP graph recording the whole sequence (count
+ * scan, sort of the sets longest first, persistent generator fed by an
+ * atomic work queue).  A call with the same streams, pointers, n_sets and
+ * configuration as the previous call on the plan replays that graph; other
+ * calls record it again (and may allocate scratch).  A plan serves one call
+ * at a time: calls on different HIP streams that may overlap need separate
+ * plans.  n_sets = 0 does nothing. */
+typedef struct rp_plan rp_plan;
+int rp_plan_create(rp_plan **out);
+void rp_plan_free(rp_plan *p);
+/* block: threads per block (64, 128, 192 or 256); blocks_per_cu: resident
+ * blocks asked for per compute unit (grid = CUs x blocks_per_cu, 1..64);
+ * sets_per_lane: sets each lane takes from one popped group (1..16). */
+int rp_plan_set_config(rp_plan *p, int block, int blocks_per_cu, int sets_per_lane);
+/* Returns 1 if the configuration came from rp_plan_autotune, else 0. */
+int rp_plan_get_config(const rp_plan *p, int *block, int *blocks_per_cu, int *sets_per_lane);
+/* Times the generator over a grid of configurations on a copy of the
+ * substreams (the caller's are not advanced) with the given inputs and keeps
+ * the fastest.  beta = 0: gamma with d_pa = alpha (d_pb unused); beta = 1:
+ * Beta(d_pa, d_pb).  d_out is overwritten.  Synchronizes the device. */
+int rp_plan_autotune(rp_plan *p, rp_streams *s, int beta, const double *d_pa, const double *d_pb,
+                     const int64_t *d_count, uint64_t n_sets, double *d_out);
+int rp_gamma_batched(rp_streams *s, const double *d_alpha, const int64_t *d_count, uint64_t n_sets, double *d_out,
+                     rp_plan *plan, void *hip_stream);
+int rp_beta_batched(rp_streams *s, const double *d_a, const double *d_b, const int64_t *d_count, uint64_t n_sets,
+                    double *d_out, rp_plan *plan, void *hip_stream);
+
 /* ---- implicit-reparameterization backward (gamma and beta draws) -------- */
 /* A draw z = F^{-1}(u; theta) is differentiated with u held fixed:
  * dz/dtheta = -(dF/dtheta)(z; theta) / f(z; theta), F the distribution

@@ -61,6 +61,13 @@ _SIGS = {
     "rp_norm_moments": ([_vp, _u64, _vp, _vp, _vp], _int),
     "rp_gamma_elem": ([_vp, _vp, _vp, _u64, _vp], _int),
     "rp_beta_elem": ([_vp, _vp, _vp, _vp, _u64, _vp], _int),
+    "rp_plan_create": ([_vp], _int),
+    "rp_plan_free": ([_vp], None),
+    "rp_plan_set_config": ([_vp, _int, _int, _int], _int),
+    "rp_plan_get_config": ([_vp, _vp, _vp, _vp], _int),
+    "rp_plan_autotune": ([_vp, _vp, _int, _vp, _vp, _vp, _u64, _vp], _int),
+    "rp_gamma_batched": ([_vp, _vp, _vp, _u64, _vp, _vp, _vp], _int),
+    "rp_beta_batched": ([_vp, _vp, _vp, _vp, _u64, _vp, _vp, _vp], _int),
     "rp_gamma_grad": ([_vp, _vp, _vp, _vp, _u64, _vp], _int),
     "rp_beta_grad": ([_vp, _vp, _vp, _vp, _vp, _vp, _u64, _vp], _int),
 }
@@ -159,6 +166,48 @@ def rp_gamma_elem(streams, alpha, z, n, stream=None):
 
 def rp_beta_elem(streams, a, b, z, n, stream=None):
     _check(lib().rp_beta_elem(streams.h, _dev_ptr(a), _dev_ptr(b), _dev_ptr(z), n, _stream_ptr(stream)))
+
+
+class Plan:
+    """rp_plan*: scratch, launch configuration and recorded graph of the
+    batched gamma / beta sequence."""
+
+    def __init__(self):
+        out = ctypes.c_void_p()
+        _check(lib().rp_plan_create(ctypes.byref(out)))
+        self.h = ctypes.c_void_p(out.value)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.rp_plan_free(self.h)
+            self.h = None
+
+    def set_config(self, block, blocks_per_cu, sets_per_lane):
+        _check(lib().rp_plan_set_config(self.h, block, blocks_per_cu, sets_per_lane))
+
+    def get_config(self):
+        b, p, s = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        tuned = _check(lib().rp_plan_get_config(self.h, ctypes.byref(b), ctypes.byref(p), ctypes.byref(s)))
+        return {"block": b.value, "blocks_per_cu": p.value, "sets_per_lane": s.value, "tuned": bool(tuned)}
+
+
+def rp_plan_create():
+    return Plan()
+
+
+def rp_plan_autotune(plan, streams, beta, pa, pb, count, n_sets, out):
+    _check(lib().rp_plan_autotune(plan.h, streams.h, int(beta), _dev_ptr(pa), _dev_ptr(pb) if pb is not None else None,
+                                  _dev_ptr(count), n_sets, _dev_ptr(out)))
+
+
+def rp_gamma_batched(streams, alpha, count, n_sets, out, plan, stream=None):
+    _check(lib().rp_gamma_batched(streams.h, _dev_ptr(alpha), _dev_ptr(count), n_sets, _dev_ptr(out), plan.h,
+                                  _stream_ptr(stream)))
+
+
+def rp_beta_batched(streams, a, b, count, n_sets, out, plan, stream=None):
+    _check(lib().rp_beta_batched(streams.h, _dev_ptr(a), _dev_ptr(b), _dev_ptr(count), n_sets, _dev_ptr(out), plan.h,
+                                 _stream_ptr(stream)))
 
 
 def rp_gamma_grad(z, alpha, gz, galpha, n, stream=None):

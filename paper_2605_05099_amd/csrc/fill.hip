@@ -1102,5 +1102,6 @@ int launch_fill(int engine, int dist, int dtype, const FillArgs &a, hipStream_t 
 }
 
 #include "k_samplers.h"
+#include "k_batched.h"
 
 }  // namespace rp

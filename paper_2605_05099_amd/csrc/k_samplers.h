@@ -145,6 +145,7 @@ __device__ double boost_pow(double u, double a)
     const double th = lh / a;
     const double tl = (__fma_rn(-th, a, lh) + ll) / a;
     const double eh = exp(th);
+    if (eh == 0.0) return 0.0;  // also keeps 0 * inf away when a is tiny
     return eh + eh * tl;
 }
 

@@ -70,6 +70,26 @@ struct SampArgs {
     float *z;             // per-element result
     double *sum, *sumsq;  // per-substream moments
 };
+// batched gamma / beta (k_batched.h)
+struct BatchArgs {
+    FillArgs f;              // substream states (set j uses substream j)
+    const double *pa, *pb;   // per-set shape (gamma) or a, b (beta)
+    const int64_t *count;    // per-set counts (negative counts as 0)
+    uint64_t n_sets;
+    double *out;             // sum of counts values, set-major
+    int64_t *offsets;        // scratch: n_sets exclusive prefix sums
+    uint32_t *order;         // scratch: n_sets sorted set indices
+    uint32_t *hist;          // scratch: sort-key histogram / bucket cursors
+    int64_t *block_sums;     // scratch: one per scan block
+    uint32_t *queue;         // scratch: work-queue head
+    int spl;                 // sets per lane per popped group
+};
+int launch_batched_setup(const BatchArgs &a, bool beta, hipStream_t stream);
+int launch_batched_gen(int engine, const BatchArgs &a, bool beta, unsigned grid, unsigned block, hipStream_t stream);
+int launch_queue_reset(const BatchArgs &a, hipStream_t stream);
+int batched_blocks_for_scan(uint64_t n_sets);
+int batched_buckets();
+
 int launch_moments(int engine, const SampArgs &s, hipStream_t stream);
 int launch_gamma_elem(int engine, const SampArgs &s, bool beta, hipStream_t stream);
 
