@@ -232,6 +232,31 @@ int rp_gamma_grad(const float *d_z, const float *d_alpha, const float *d_gz, flo
 int rp_beta_grad(const float *d_z, const float *d_a, const float *d_b, const float *d_gz, float *d_ga, float *d_gb,
                  uint64_t n, void *hip_stream);
 
+/* ---- multivariate normal (Section 3.1, "Multivariate normal distribution") */
+/* Cholesky factor of a covariance matrix, on the host in binary64: reads the
+ * lower triangle of Sigma (row-major d x d, host memory), writes L (row-major,
+ * zeros above the diagonal) with Sigma = L L^T.  RP_ENOTSPD when a leading
+ * minor is not positive definite (or not finite); L is then incomplete. */
+int rp_cholesky(const double *Sigma, int d, double *L);
+/* Row i < n of X (n x d, row-major, binary32) is mu + L z_i, where z_i is the
+ * next d standard normals of substream i (ziggurat in binary64, rounded to
+ * binary32); that is X = mu + Z L^T.  The contraction runs on the matrix
+ * cores in binary32 with binary32 accumulation.  L is the d x d lower
+ * factor (row-major binary32; the entries above the diagonal are read, so
+ * they must be zero), mu has d entries.  Substreams i < n are advanced by
+ * their d normals.  Device pointers owned by the caller; a workspace of
+ * n x d floats is taken from the device's stream-ordered pool. */
+int rp_mvn(rp_streams *s, const float *d_mu, const float *d_L, int d, uint64_t n, float *d_X, void *hip_stream);
+/* Backward of rp_mvn for upstream gradient G (n x d): gmu = sum of the rows
+ * of G, gL = tril(G^T Z) (d x d row-major, zeros above the diagonal).  Z is
+ * regenerated from s, which must hold the substream states the forward
+ * started from (for example an rp_streams_duplicate taken before it); s is
+ * not advanced.  Partial sums over row slices are binary32 (matrix cores),
+ * combined in binary64.  Uses a workspace of n x d floats plus the slice
+ * partials from the stream-ordered pool. */
+int rp_mvn_backward(rp_streams *s, const float *d_G, int d, uint64_t n, float *d_gmu, float *d_gL,
+                    void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -235,6 +235,21 @@ class StreamArray:
         for i, s in enumerate(streams):
             self.buf[i] = s.buf
 
+    @classmethod
+    def key_family(cls, engine, seed, n):
+        """Substreams 0..n-1 of the Philox key family (key := i over the
+        seeded counter), built as one array; equal to substream(engine, seed,
+        "key", i) for every i (spot-checked here)."""
+        base = substream(engine, seed, "key", 0)
+        arr = cls.__new__(cls)
+        arr.n = n
+        arr.buf = np.tile(base.buf, (n, 1))
+        key_word = {"philox4x32": 2, "philox": 4}[engine]
+        arr.buf[:, 2 + key_word] = np.arange(n, dtype=np.uint64)
+        for i in {0, 1, n // 2, n - 1}:
+            assert (arr.buf[i] == substream(engine, seed, "key", i).buf).all()
+        return arr
+
     def stream(self, i):
         s = Stream(int(self.buf[i, 0]))
         s.buf[:] = self.buf[i]

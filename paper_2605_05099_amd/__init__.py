@@ -68,6 +68,9 @@ _SIGS = {
     "rp_plan_autotune": ([_vp, _vp, _int, _vp, _vp, _vp, _u64, _vp], _int),
     "rp_gamma_batched": ([_vp, _vp, _vp, _u64, _vp, _vp, _vp], _int),
     "rp_beta_batched": ([_vp, _vp, _vp, _vp, _u64, _vp, _vp, _vp], _int),
+    "rp_cholesky": ([_vp, _int, _vp], _int),
+    "rp_mvn": ([_vp, _vp, _vp, _int, _u64, _vp, _vp], _int),
+    "rp_mvn_backward": ([_vp, _vp, _int, _u64, _vp, _vp, _vp], _int),
     "rp_gamma_grad": ([_vp, _vp, _vp, _vp, _u64, _vp], _int),
     "rp_beta_grad": ([_vp, _vp, _vp, _vp, _vp, _vp, _u64, _vp], _int),
 }
@@ -208,6 +211,25 @@ def rp_gamma_batched(streams, alpha, count, n_sets, out, plan, stream=None):
 def rp_beta_batched(streams, a, b, count, n_sets, out, plan, stream=None):
     _check(lib().rp_beta_batched(streams.h, _dev_ptr(a), _dev_ptr(b), _dev_ptr(count), n_sets, _dev_ptr(out), plan.h,
                                  _stream_ptr(stream)))
+
+
+def rp_cholesky(sigma):
+    """Binary64 Cholesky factor on the host (numpy in, numpy out)."""
+    a = np.ascontiguousarray(sigma, dtype=np.float64)
+    d = a.shape[0]
+    if a.shape != (d, d):
+        raise ValueError("sigma must be square")
+    out = np.zeros((d, d), dtype=np.float64)
+    _check(lib().rp_cholesky(_ptr(a), d, _ptr(out)))
+    return out
+
+
+def rp_mvn(streams, mu, L, d, n, X, stream=None):
+    _check(lib().rp_mvn(streams.h, _dev_ptr(mu), _dev_ptr(L), d, n, _dev_ptr(X), _stream_ptr(stream)))
+
+
+def rp_mvn_backward(streams, G, d, n, gmu, gL, stream=None):
+    _check(lib().rp_mvn_backward(streams.h, _dev_ptr(G), d, n, _dev_ptr(gmu), _dev_ptr(gL), _stream_ptr(stream)))
 
 
 def rp_gamma_grad(z, alpha, gz, galpha, n, stream=None):

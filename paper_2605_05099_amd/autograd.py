@@ -1,4 +1,5 @@
-"""torch.autograd wrappers over the per-element samplers and their
+"""torch.autograd wrappers over the per-element samplers, multivariate
+normal rows, and their
 implicit-reparameterization backward kernels.
 
     z = sample_gamma(alpha, streams)     # element e draws from substream e
@@ -10,7 +11,7 @@ saved binary32 draws.  Parameters must be contiguous float32 CUDA tensors.
 """
 import torch
 
-from . import rp_beta_elem, rp_beta_grad, rp_gamma_elem, rp_gamma_grad
+from . import rp_beta_elem, rp_beta_grad, rp_gamma_elem, rp_gamma_grad, rp_mvn, rp_mvn_backward
 
 
 def _check_param(t, name):
@@ -65,3 +66,36 @@ def sample_gamma(alpha, streams):
 
 def sample_beta(a, b, streams):
     return BetaFn.apply(a, b, streams)
+
+
+class MvnFn(torch.autograd.Function):
+    """X = mu + Z L^T for n rows (row i from substream i).  The forward keeps
+    a device copy of the substream states it started from; the backward
+    regenerates Z from that copy."""
+
+    @staticmethod
+    def forward(ctx, mu, L, streams, n):
+        mu = _check_param(mu, "mu")
+        L = _check_param(L, "L")
+        d = mu.numel()
+        if L.shape != (d, d):
+            raise ValueError("L must be d x d")
+        start = streams.duplicate()
+        X = torch.empty((n, d), dtype=torch.float32, device=mu.device)
+        rp_mvn(streams, mu, L, d, n, X)
+        ctx.start = start
+        ctx.dims = (d, n)
+        return X
+
+    @staticmethod
+    def backward(ctx, G):
+        d, n = ctx.dims
+        G = G.to(torch.float32).contiguous()
+        gmu = torch.empty(d, dtype=torch.float32, device=G.device)
+        gL = torch.empty((d, d), dtype=torch.float32, device=G.device)
+        rp_mvn_backward(ctx.start, G, d, n, gmu, gL)
+        return gmu, gL, None, None
+
+
+def sample_mvn(mu, L, streams, n):
+    return MvnFn.apply(mu, L, streams, n)

@@ -1,0 +1,421 @@
+// k_mvn.hip -- multivariate normal rows (Section 3.1, "Multivariate normal
+// distribution"): X = mu + Z L^T for n rows of d standard normals Z, with L
+// the lower-triangular Cholesky factor of the covariance, and its backward
+// grad_mu = sum_rows G, grad_L = tril(G^T Z).
+//
+// Row i of Z is the next d normals of substream i (binary64 ziggurat draws
+// rounded to binary32).  Z is generated into a stream-ordered workspace by
+// the lane-per-row kernel, then contracted on the matrix cores with
+// v_mfma_f32_32x32x2f32 (binary32 in, binary32 accumulate).  The backward
+// regenerates the same Z from the substream states the forward started from,
+// so nothing of size n x d is kept between the two.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "rp_internal.h"
+
+namespace rp {
+
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kKT = 32;         // k per LDS stage
+constexpr int kLdK = kKT + 4;   // forward LDS row stride (floats), rows indexed by m / n
+constexpr int kTile = 128;      // rows of a block tile
+constexpr int kLdT = kTile + 4; // backward LDS row stride (floats), rows indexed by k
+
+__device__ __forceinline__ float4 load4(const float *M, uint64_t rows, uint64_t cols, uint64_t r, uint64_t c,
+                                        bool vec)
+{
+    float4 v = {0.f, 0.f, 0.f, 0.f};
+    if (r >= rows) return v;
+    const float *p = M + r * cols + c;
+    if (vec && c + 3 < cols) return *(const float4 *)p;
+    if (c < cols) v.x = p[0];
+    if (c + 1 < cols) v.y = p[1];
+    if (c + 2 < cols) v.z = p[2];
+    if (c + 3 < cols) v.w = p[3];
+    return v;
+}
+
+// Blocks are dealt round-robin to the 8 XCDs; renumber them so that each XCD
+// works through a contiguous range of tiles (tiles that share operand rows
+// then share that XCD's L2).
+__device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb)
+{
+    return (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+}
+
+// One 32x32 output tile of C += A B per lane-pair of operands, lane l giving
+// A[l % 32][k] and B[k][l % 32] for the k of its half (l / 32); the result
+// element v of lane l is C[8 (v / 4) + 4 (l / 32) + v % 4][l % 32].
+__device__ __forceinline__ int acc_row(int v, int h) { return 8 * (v >> 2) + 4 * h + (v & 3); }
+
+// ---------------------------------------------------------------------------
+// forward: block tile 128 rows x BN columns, 4 waves as 2 x 2, wave tile
+// 64 x BN/2 (2 x BN/64 MFMA tiles).  Each lane half takes four consecutive k
+// of an eight-k step, so operand fragments are single 16-byte LDS reads.
+template <int BN>
+__global__ __launch_bounds__(256) void k_mvn_fwd(const float *Z, const float *L, const float *mu, float *X,
+                                                 uint64_t n, int d, unsigned ncol_tiles, int vec)
+{
+    constexpr int TN = BN / 64;
+    __shared__ __align__(16) float As[kTile * kLdK];
+    __shared__ __align__(16) float Bs[BN * kLdK];
+    const unsigned w = xcd_tile(blockIdx.x, gridDim.x);
+    const uint64_t row0 = (uint64_t)(w / ncol_tiles) * kTile;
+    const int col0 = (int)(w % ncol_tiles) * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, l32 = lane & 31;
+    const int wr = wave >> 1, wc = wave & 1;
+    f32x16 acc[2][TN];
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int b = 0; b < TN; b++)
+#pragma unroll
+            for (int v = 0; v < 16; v++) acc[a][b][v] = 0.f;
+    float4 ra[4], rb[BN / 32];
+    const int nk = (d + kKT - 1) / kKT;
+    const uint64_t dd = (uint64_t)d;
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        const int u = tid + 256 * r;
+        ra[r] = load4(Z, n, dd, row0 + (u >> 3), 4 * (u & 7), vec);
+    }
+#pragma unroll
+    for (int r = 0; r < BN / 32; r++) {
+        const int u = tid + 256 * r;
+        rb[r] = load4(L, dd, dd, (uint64_t)(col0 + (u >> 3)), 4 * (u & 7), vec);
+    }
+    for (int kt = 0; kt < nk; kt++) {
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int u = tid + 256 * r;
+            *(float4 *)&As[(u >> 3) * kLdK + 4 * (u & 7)] = ra[r];
+        }
+#pragma unroll
+        for (int r = 0; r < BN / 32; r++) {
+            const int u = tid + 256 * r;
+            *(float4 *)&Bs[(u >> 3) * kLdK + 4 * (u & 7)] = rb[r];
+        }
+        __syncthreads();
+        if (kt + 1 < nk) {
+            const uint64_t k0 = (uint64_t)(kt + 1) * kKT;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int u = tid + 256 * r;
+                ra[r] = load4(Z, n, dd, row0 + (u >> 3), k0 + 4 * (u & 7), vec);
+            }
+#pragma unroll
+            for (int r = 0; r < BN / 32; r++) {
+                const int u = tid + 256 * r;
+                rb[r] = load4(L, dd, dd, (uint64_t)(col0 + (u >> 3)), k0 + 4 * (u & 7), vec);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < kKT / 8; s++) {
+            float4 af[2], bf[TN];
+#pragma unroll
+            for (int a = 0; a < 2; a++) af[a] = *(const float4 *)&As[(wr * 64 + a * 32 + l32) * kLdK + 8 * s + 4 * h];
+#pragma unroll
+            for (int b = 0; b < TN; b++)
+                bf[b] = *(const float4 *)&Bs[(wc * (BN / 2) + b * 32 + l32) * kLdK + 8 * s + 4 * h];
+#pragma unroll
+            for (int a = 0; a < 2; a++)
+#pragma unroll
+                for (int b = 0; b < TN; b++) {
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a].x, bf[b].x, acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a].y, bf[b].y, acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a].z, bf[b].z, acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a].w, bf[b].w, acc[a][b], 0, 0, 0);
+                }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < TN; b++) {
+        const int j = col0 + wc * (BN / 2) + b * 32 + l32;
+        if (j >= d) continue;
+        const float m = mu[j];
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int v = 0; v < 16; v++) {
+                const uint64_t i = row0 + (uint64_t)(wr * 64 + a * 32 + acc_row(v, h));
+                if (i < n) X[i * dd + j] = acc[a][b][v] + m;
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// backward, split over the rows: block (tile t, slice s) accumulates
+// sum_{i in slice s} G[i][a] Z[i][b] for the 128 x 128 tile t of the lower
+// triangle (tiles with ta >= tb), and, in the tiles with tb = 0, the column
+// sums of G over the slice.
+__global__ __launch_bounds__(256) void k_mvn_bwd(const float *G, const float *Z, uint64_t n, int d, uint64_t slice,
+                                                 float *part, float *gmu_part, int vec)
+{
+    __shared__ __align__(16) float Gs[kKT * kLdT];
+    __shared__ __align__(16) float Zs[kKT * kLdT];
+    unsigned t = blockIdx.x, ta = 0;
+    while (t > ta) {
+        t -= ta + 1;
+        ta++;
+    }
+    const unsigned tb = t;
+    const int a0 = (int)ta * kTile, b0 = (int)tb * kTile;
+    const uint64_t i0 = (uint64_t)blockIdx.y * slice;
+    uint64_t i1 = i0 + slice;
+    if (i1 > n) i1 = n;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, l32 = lane & 31;
+    const int wr = wave >> 1, wc = wave & 1;
+    const uint64_t dd = (uint64_t)d;
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++)
+#pragma unroll
+            for (int v = 0; v < 16; v++) acc[a][b][v] = 0.f;
+    float colsum = 0.f;
+    float4 rg[4], rz[4];
+    const uint64_t nk = (i1 > i0) ? (i1 - i0 + kKT - 1) / kKT : 0;
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        const int u = tid + 256 * r;
+        rg[r] = load4(G, i1, dd, i0 + (u >> 5), a0 + 4 * (u & 31), vec);
+        rz[r] = load4(Z, i1, dd, i0 + (u >> 5), b0 + 4 * (u & 31), vec);
+    }
+    for (uint64_t kt = 0; kt < nk; kt++) {
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int u = tid + 256 * r;
+            *(float4 *)&Gs[(u >> 5) * kLdT + 4 * (u & 31)] = rg[r];
+            *(float4 *)&Zs[(u >> 5) * kLdT + 4 * (u & 31)] = rz[r];
+        }
+        __syncthreads();
+        if (kt + 1 < nk) {
+            const uint64_t k0 = i0 + (kt + 1) * kKT;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int u = tid + 256 * r;
+                rg[r] = load4(G, i1, dd, k0 + (u >> 5), a0 + 4 * (u & 31), vec);
+                rz[r] = load4(Z, i1, dd, k0 + (u >> 5), b0 + 4 * (u & 31), vec);
+            }
+        }
+        if (tb == 0 && tid < kTile) {
+#pragma unroll 8
+            for (int k = 0; k < kKT; k++) colsum += Gs[k * kLdT + tid];
+        }
+#pragma unroll
+        for (int k = 0; k < kKT; k += 2) {
+            float af[2], bf[2];
+#pragma unroll
+            for (int a = 0; a < 2; a++) af[a] = Gs[(k + h) * kLdT + wr * 64 + a * 32 + l32];
+#pragma unroll
+            for (int b = 0; b < 2; b++) bf[b] = Zs[(k + h) * kLdT + wc * 64 + b * 32 + l32];
+#pragma unroll
+            for (int a = 0; a < 2; a++)
+#pragma unroll
+                for (int b = 0; b < 2; b++)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a], bf[b], acc[a][b], 0, 0, 0);
+        }
+    }
+    float *P = part + (uint64_t)blockIdx.y * dd * dd;
+#pragma unroll
+    for (int b = 0; b < 2; b++) {
+        const int j = b0 + wc * 64 + b * 32 + l32;
+        if (j >= d) continue;
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int v = 0; v < 16; v++) {
+                const int i = a0 + wr * 64 + a * 32 + acc_row(v, h);
+                if (i < d) P[(uint64_t)i * dd + j] = acc[a][b][v];
+            }
+    }
+    if (tb == 0 && tid < kTile && a0 + tid < d) gmu_part[(uint64_t)blockIdx.y * dd + a0 + tid] = colsum;
+}
+
+// Sums the per-slice partials in slice order (binary64), lower triangle only.
+__global__ __launch_bounds__(256) void k_mvn_reduce(const float *part, const float *gmu_part, int nslices, int d,
+                                                    float *gL, float *gmu)
+{
+    const uint64_t dd = (uint64_t)d, total = dd * dd;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t a = e / dd, b = e % dd;
+        double s = 0.0;
+        if (a >= b)
+            for (int k = 0; k < nslices; k++) s += (double)part[(uint64_t)k * total + e];
+        gL[e] = (float)s;
+        if (e < dd) {
+            double g = 0.0;
+            for (int k = 0; k < nslices; k++) g += (double)gmu_part[(uint64_t)k * dd + e];
+            gmu[e] = (float)g;
+        }
+    }
+}
+
+int hip_fail(hipError_t e, const char *what) { return fail(RP_EDEVICE, "%s: %s", what, hipGetErrorString(e)); }
+
+bool al16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+bool al4(const void *p) { return ((uintptr_t)p & 3) == 0; }
+
+// Keep freed stream-ordered allocations cached in the device's default pool.
+int keep_pool(hipStream_t)
+{
+    static bool done[64] = {false};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return RP_OK;
+    if (done[dev]) return RP_OK;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    done[dev] = true;
+    return RP_OK;
+}
+
+int gen_rows(rp_streams *s, float *z, int d, uint64_t n, bool advance, hipStream_t st)
+{
+    SampArgs a{};
+    a.f.words = s->d_words;
+    a.f.phase = s->d_phase;
+    a.f.n = s->n;
+    a.f.per_stream = (uint64_t)d;
+    a.count = n;
+    a.z = z;
+    a.advance = advance ? 1 : 0;
+    return launch_norm_rows(s->engine, a, st);
+}
+
+int check_common(const char *who, rp_streams *s, int d, uint64_t n)
+{
+    if (!s) return fail(RP_ENULL, "%s: NULL streams", who);
+    if (d < 1 || d > 65536) return fail(RP_EINVAL, "%s: d = %d (1..65536)", who, d);
+    if (n > s->n) return fail(RP_EINVAL, "%s: %llu rows but only %llu substreams", who, (unsigned long long)n,
+                              (unsigned long long)s->n);
+    return RP_OK;
+}
+
+}  // namespace
+
+}  // namespace rp
+
+using namespace rp;
+
+extern "C" int rp_mvn(rp_streams *s, const float *d_mu, const float *d_L, int d, uint64_t n, float *d_X,
+                      void *hip_stream)
+{
+    int rc = check_common("rp_mvn", s, d, n);
+    if (rc) return rc;
+    if (n == 0) return RP_OK;
+    if (!d_mu || !d_L || !d_X) return fail(RP_ENULL, "rp_mvn: NULL device pointer");
+    if (!al4(d_mu) || !al4(d_L) || !al4(d_X)) return fail(RP_EINVAL, "rp_mvn: pointers not aligned to 4 bytes");
+    rc = ensure_device_tables();
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    keep_pool(st);
+    float *z = nullptr;
+    hipError_t e = hipMallocAsync((void **)&z, n * (uint64_t)d * sizeof(float), st);
+    if (e != hipSuccess) return fail(RP_ENOMEM, "rp_mvn: workspace of %llu floats: %s",
+                                     (unsigned long long)(n * (uint64_t)d), hipGetErrorString(e));
+    rc = gen_rows(s, z, d, n, true, st);
+    if (rc == RP_OK) {
+        const int vec = (d % 4 == 0) && al16(d_L) && al16(z) ? 1 : 0;
+        const uint64_t nrt = (n + kTile - 1) / kTile;
+        if (d <= 64) {
+            const unsigned nct = 1;
+            hipLaunchKernelGGL(k_mvn_fwd<64>, dim3((unsigned)(nrt * nct)), dim3(256), 0, st, z, d_L, d_mu, d_X, n, d,
+                               nct, vec);
+        } else {
+            const unsigned nct = (unsigned)((d + 127) / 128);
+            hipLaunchKernelGGL(k_mvn_fwd<128>, dim3((unsigned)(nrt * nct)), dim3(256), 0, st, z, d_L, d_mu, d_X, n,
+                               d, nct, vec);
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) rc = hip_fail(e, "rp_mvn launch");
+    }
+    (void)hipFreeAsync(z, st);
+    return rc;
+}
+
+extern "C" int rp_mvn_backward(rp_streams *s, const float *d_G, int d, uint64_t n, float *d_gmu, float *d_gL,
+                               void *hip_stream)
+{
+    int rc = check_common("rp_mvn_backward", s, d, n);
+    if (rc) return rc;
+    if (!d_G || !d_gmu || !d_gL) return fail(RP_ENULL, "rp_mvn_backward: NULL device pointer");
+    if (!al4(d_G) || !al4(d_gmu) || !al4(d_gL)) return fail(RP_EINVAL, "rp_mvn_backward: pointers not aligned");
+    rc = ensure_device_tables();
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    keep_pool(st);
+    // split the rows so that the lower-triangle tiles times the slices give
+    // about 2048 blocks
+    const uint64_t nt = (uint64_t)(d + kTile - 1) / kTile;
+    const uint64_t ntl = nt * (nt + 1) / 2;
+    uint64_t nsl = (2048 + ntl - 1) / ntl;
+    const uint64_t max_sl = (n + kKT - 1) / kKT;
+    if (nsl > max_sl) nsl = max_sl;
+    if (nsl < 1) nsl = 1;
+    uint64_t slice = (n + nsl - 1) / nsl;
+    slice = (slice + kKT - 1) / kKT * kKT;
+    if (slice == 0) slice = kKT;
+    nsl = (n + slice - 1) / slice;
+    if (nsl == 0) nsl = 1;
+    const uint64_t dd = (uint64_t)d;
+    const uint64_t zf = n * dd, pf = nsl * dd * dd, gf = nsl * dd;
+    float *ws = nullptr;
+    hipError_t e = hipMallocAsync((void **)&ws, (zf + pf + gf + 64) * sizeof(float), st);
+    if (e != hipSuccess) return fail(RP_ENOMEM, "rp_mvn_backward: workspace: %s", hipGetErrorString(e));
+    float *z = ws;
+    float *part = ws + ((zf + 3) & ~3ull);
+    float *gpart = part + pf;
+    rc = n ? gen_rows(s, z, d, n, false, st) : RP_OK;
+    if (rc == RP_OK) {
+        const int vec = (d % 4 == 0) && al16(d_G) && al16(z) ? 1 : 0;
+        if (n) hipLaunchKernelGGL(k_mvn_bwd, dim3((unsigned)ntl, (unsigned)nsl), dim3(256), 0, st, d_G, z, n, d,
+                                  slice, part, gpart, vec);
+        const int nsl_used = n ? (int)nsl : 0;
+        uint64_t blocks = (dd * dd + 255) / 256;
+        if (blocks > 4096) blocks = 4096;
+        hipLaunchKernelGGL(k_mvn_reduce, dim3((unsigned)blocks), dim3(256), 0, st, part, gpart, nsl_used, d, d_gL,
+                           d_gmu);
+        e = hipGetLastError();
+        if (e != hipSuccess) rc = hip_fail(e, "rp_mvn_backward launch");
+    }
+    (void)hipFreeAsync(ws, st);
+    return rc;
+}
+
+// Cholesky-Banachiewicz in binary64 on the host, reading the lower triangle
+// of Sigma (row-major d x d) and writing L with zeros above the diagonal.
+extern "C" int rp_cholesky(const double *Sigma, int d, double *L)
+{
+    if (!Sigma || !L) return fail(RP_ENULL, "rp_cholesky: NULL pointer");
+    if (d < 1) return fail(RP_EINVAL, "rp_cholesky: d = %d", d);
+    const size_t D = (size_t)d;
+    for (size_t i = 0; i < D; i++) {
+        for (size_t j = 0; j <= i; j++) {
+            double s = Sigma[i * D + j];
+            for (size_t k = 0; k < j; k++) s -= L[i * D + k] * L[j * D + k];
+            if (i == j) {
+                if (!(s > 0.0) || !std::isfinite(s))
+                    return fail(RP_ENOTSPD, "rp_cholesky: leading minor %zu is not positive definite", i + 1);
+                L[i * D + i] = std::sqrt(s);
+            } else {
+                L[i * D + j] = s / L[j * D + j];
+            }
+        }
+        for (size_t j = i + 1; j < D; j++) L[i * D + j] = 0.0;
+    }
+    return RP_OK;
+}

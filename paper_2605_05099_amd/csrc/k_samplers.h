@@ -240,6 +240,36 @@ __global__ __launch_bounds__(256) void k_gamma_elem(SampArgs s)
 }
 
 
+// Row i of z (count rows of per_stream = d values) holds the next d normals
+// of substream i rounded to binary32.  With d a multiple of 4 each lane
+// writes its row as 16-byte pieces.
+template <class E>
+__global__ __launch_bounds__(256) void k_norm_rows(SampArgs s)
+{
+    __shared__ ZigLds zt;
+    load_zig<RP_NORM>(&zt);
+    __syncthreads();
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= s.count) return;
+    E eng;
+    eng.load(s.f, i);
+    const uint64_t d = s.f.per_stream;
+    float *row = s.z + i * d;
+    if ((d & 3) == 0) {
+        for (uint64_t t = 0; t < d; t += 4) {
+            float4 v;
+            v.x = (float)zig_serial<RP_NORM>(&zt, eng);
+            v.y = (float)zig_serial<RP_NORM>(&zt, eng);
+            v.z = (float)zig_serial<RP_NORM>(&zt, eng);
+            v.w = (float)zig_serial<RP_NORM>(&zt, eng);
+            *(float4 *)(row + t) = v;
+        }
+    } else {
+        for (uint64_t t = 0; t < d; t++) row[t] = (float)zig_serial<RP_NORM>(&zt, eng);
+    }
+    if (s.advance) eng.store(s.f, i);
+}
+
 template <class E>
 static int launch_moments_e(const SampArgs &s, hipStream_t st)
 {
@@ -272,6 +302,22 @@ int launch_moments(int engine, const SampArgs &s, hipStream_t st)
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? RP_OK : fail(RP_EDEVICE, "moments launch: %s", hipGetErrorString(e));
+}
+
+int launch_norm_rows(int engine, const SampArgs &s, hipStream_t st)
+{
+    const dim3 grid((unsigned)((s.count + 255) / 256)), block(256);
+    switch (engine) {
+    case RP_X256PP: hipLaunchKernelGGL(k_norm_rows<LaneX256>, grid, block, 0, st, s); break;
+    case RP_PCG64: hipLaunchKernelGGL(k_norm_rows<LanePcg>, grid, block, 0, st, s); break;
+    case RP_PHILOX4X32: hipLaunchKernelGGL(k_norm_rows<LanePhilox32>, grid, block, 0, st, s); break;
+    case RP_PHILOX: hipLaunchKernelGGL(k_norm_rows<LanePhilox64>, grid, block, 0, st, s); break;
+    case RP_SFC64: hipLaunchKernelGGL(k_norm_rows<LaneSfc64>, grid, block, 0, st, s); break;
+    case RP_RANLUX: hipLaunchKernelGGL(k_norm_rows<LaneRanlux>, grid, block, 0, st, s); break;
+    default: return fail(RP_EINVAL, "unknown engine");
+    }
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RP_OK : fail(RP_EDEVICE, "normal rows launch: %s", hipGetErrorString(e));
 }
 
 int launch_gamma_elem(int engine, const SampArgs &s, bool beta, hipStream_t st)

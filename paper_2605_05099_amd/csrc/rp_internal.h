@@ -69,6 +69,7 @@ struct SampArgs {
     const float *pb;      // per-element b (beta)
     float *z;             // per-element result
     double *sum, *sumsq;  // per-substream moments
+    int advance;          // rows of normals: store the advanced states
 };
 // batched gamma / beta (k_batched.h)
 struct BatchArgs {
@@ -92,5 +93,7 @@ int batched_buckets();
 
 int launch_moments(int engine, const SampArgs &s, hipStream_t stream);
 int launch_gamma_elem(int engine, const SampArgs &s, bool beta, hipStream_t stream);
+// rows of normals: z[i * d + t] = t-th normal of substream i, binary32
+int launch_norm_rows(int engine, const SampArgs &s, hipStream_t stream);
 
 }  // namespace rp

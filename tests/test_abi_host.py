@@ -132,3 +132,25 @@ def test_set_state_errors():
         r.set_state([1, 2])
     with pytest.raises(rp.RpError):
         rp.rp_create("x256++").deserialize(b"\0" * 200)
+
+
+@pytest.mark.parametrize("d", [1, 5, 64, 200])
+def test_cholesky_matches_library(d):
+    """rp_cholesky (host, binary64) against LAPACK via numpy; only the lower
+    triangle of Sigma is read."""
+    from paper_2605_05099_amd import workloads
+    sigma = workloads.mvn(d)["sigma"] if d > 1 else np.array([[2.5]])
+    L = rp.rp_cholesky(sigma)
+    ref = np.linalg.cholesky(sigma)
+    np.testing.assert_allclose(L, ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
+    assert (np.triu(L, 1) == 0).all()
+    garbage = sigma + np.triu(np.full_like(sigma, 7.0), 1)
+    assert np.array_equal(rp.rp_cholesky(garbage), L)
+
+
+def test_cholesky_errors():
+    for bad in (np.array([[1.0, 0.0], [3.0, 1.0]]), np.array([[0.0]]), np.array([[np.nan]]),
+                -np.eye(3)):
+        with pytest.raises(rp.RpError) as ei:
+            rp.rp_cholesky(bad)
+        assert ei.value.code == rp.RP_ENOTSPD
