@@ -154,6 +154,22 @@ enum { RP_FLAG_52BIT = 1 }; /* uniform method 2 (mantissa fill, 52/23 bits) */
 int rp_fill(rp_streams *s, int dist, int dtype, uint64_t bound, int flags, void *d_out,
             uint64_t per_stream, void *hip_stream);
 
+/* ---- one stream split over many lanes (Section 4.4 jumps) -------------- */
+/* Fills d_out[0 .. n-1] with the next n values of the single stream `rng`,
+ * exactly as n serial calls would (same values, same order), and advances
+ * rng past the words those values used (a 32-bit half left over at the end
+ * is dropped, as in rp_fill).  The work is split over GPU lanes that start
+ * at word offsets l C found by jump-ahead: the characteristic-polynomial
+ * jump for x256++, affine powers for pcg64, counter arithmetic for Philox,
+ * A^k for ranlux++.  Rejection samplers (normal, exponential, bounded) are
+ * put back in serial order from per-chunk entry/exit maps; these forms wait
+ * for the device (the consumed word count decides the new state), the
+ * fixed-consumption forms (raw, uniform, bound 0) do not.  sfc64 has no
+ * jump and runs on one lane.  dist, dtype, bound and flags as for rp_fill;
+ * d_out is device memory of n elements owned by the caller. */
+int rp_fill_serial(rp_rng *rng, int dist, int dtype, uint64_t bound, int flags, void *d_out, uint64_t n,
+                   void *hip_stream);
+
 /* ---- fused generate-and-reduce (Section 3.1 normals) -------------------- */
 /* For every substream i draws per_stream standard normals (the same values
  * rp_fill(RP_NORM) would return) and stores only their sum and sum of

@@ -58,6 +58,7 @@ _SIGS = {
     "rp_streams_set": ([_vp, _vp, _vp], _int),
     "rp_streams_duplicate": ([_vp, _vp], _int),
     "rp_fill": ([_vp, _int, _int, _u64, _int, _vp, _u64, _vp], _int),
+    "rp_fill_serial": ([_vp, _int, _int, _u64, _int, _vp, _u64, _vp], _int),
     "rp_norm_moments": ([_vp, _u64, _vp, _vp, _vp], _int),
     "rp_gamma_elem": ([_vp, _vp, _vp, _u64, _vp], _int),
     "rp_beta_elem": ([_vp, _vp, _vp, _vp, _u64, _vp], _int),
@@ -157,6 +158,10 @@ def rp_streams_create(base, kind, n, jump_log2=0):
 
 def rp_fill(streams, dist, dtype, bound, flags, out, per_stream, stream=None):
     _check(lib().rp_fill(streams.h, dist, dtype, bound, flags, _dev_ptr(out), per_stream, _stream_ptr(stream)))
+
+
+def rp_fill_serial(rng, dist, dtype, bound, flags, out, n, stream=None):
+    _check(lib().rp_fill_serial(rng.h, dist, dtype, bound, flags, _dev_ptr(out), n, _stream_ptr(stream)))
 
 
 def rp_norm_moments(streams, per_stream, d_sum, d_sumsq, stream=None):

@@ -1,6 +1,6 @@
-"""torch.autograd wrappers over the per-element samplers, multivariate
-normal rows, and their
-implicit-reparameterization backward kernels.
+"""torch.autograd wrappers: per-element gamma and beta draws with their
+implicit-reparameterization backward kernels, and multivariate normal rows
+with their backward to mu and L.
 
     z = sample_gamma(alpha, streams)     # element e draws from substream e
     z = sample_beta(a, b, streams)

@@ -1103,5 +1103,6 @@ int launch_fill(int engine, int dist, int dtype, const FillArgs &a, hipStream_t 
 
 #include "k_samplers.h"
 #include "k_batched.h"
+#include "k_serial.h"
 
 }  // namespace rp

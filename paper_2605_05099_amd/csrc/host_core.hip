@@ -1008,3 +1008,230 @@ extern "C" int rp_beta_elem(rp_streams *s, const float *d_a, const float *d_b, f
 {
     return elem_common("rp_beta_elem", s, d_a, d_b, true, d_z, n, hip_stream);
 }
+
+// ---------------------------------------------------------------------------
+// serial split of one stream
+namespace {
+
+// Words consumed from (state, phase): block engines move the counter by whole
+// blocks and keep the remainder as the phase.
+int advance_words(rp_rng *r, uint64_t w)
+{
+    const int B = block_words(r->engine);
+    if (B <= 1) return advance_impl(r, w, 0);
+    const uint64_t p = (uint64_t)r->phase + w;
+    r->phase = (uint32_t)(p % (uint64_t)B);
+    return advance_impl(r, p / (uint64_t)B, 0);
+}
+
+// Jump data for lanes C words apart (cached for the last C of each engine).
+struct SerialTables {
+    std::mutex mu;
+    uint64_t c_x256 = 0, c_pcg = 0, c_rl = 0;
+    uint64_t x256[280], pcg[48], rl[108];
+} g_ser;
+
+void serial_tables(int engine, uint64_t C, uint64_t *jt)
+{
+    std::lock_guard<std::mutex> lock(g_ser.mu);
+    switch (engine) {
+    case RP_X256PP:
+        if (g_ser.c_x256 != C) {
+            // lanes l < 64: x^(l C) mod P; waves: x^(64 C 2^k), k < 6
+            const Poly &P = x256_charpoly();
+            const Poly q = poly_xpow(C, 0, P);
+            Poly cur;
+            cur.flip(0);
+            for (int l = 0; l < 64; l++) {
+                memcpy(&g_ser.x256[4 * l], cur.w, 32);
+                cur = poly_mulmod(cur, q, P);
+            }
+            for (int k = 0; k < 6; k++) {
+                memcpy(&g_ser.x256[256 + 4 * k], cur.w, 32);
+                cur = poly_mulmod(cur, cur, P);
+            }
+            g_ser.c_x256 = C;
+        }
+        memcpy(jt, g_ser.x256, sizeof g_ser.x256);
+        break;
+    case RP_PCG64:
+        if (g_ser.c_pcg != C) {
+            for (int k = 0; k < 12; k++) {
+                const PcgAffine m = pcg_power(C << k, k ? C >> (64 - k) : 0);
+                g_ser.pcg[4 * k] = m.mult.lo;
+                g_ser.pcg[4 * k + 1] = m.mult.hi;
+                g_ser.pcg[4 * k + 2] = m.plus.lo;
+                g_ser.pcg[4 * k + 3] = m.plus.hi;
+            }
+            g_ser.c_pcg = C;
+        }
+        memcpy(jt, g_ser.pcg, sizeof g_ser.pcg);
+        break;
+    case RP_RANLUX:
+        if (g_ser.c_rl != C) {
+            uint64_t e = C / 9, a[9];
+            ranlux_pow(ranlux_A(), &e, 1, a);
+            for (int k = 0; k < 12; k++) {
+                memcpy(&g_ser.rl[9 * k], a, 72);
+                rl_mulmod(a, a, a);
+            }
+            g_ser.c_rl = C;
+        }
+        memcpy(jt, g_ser.rl, sizeof g_ser.rl);
+        break;
+    default: break;
+    }
+}
+
+void plan_lanes(SerialArgs &a, uint64_t words, int B)
+{
+    uint64_t L = (words + 255) / 256;
+    if (L < 1) L = 1;
+    if (L > 4096) L = 4096;
+    uint64_t C = (words + L - 1) / L;
+    C = (C + B - 1) / B * B;
+    if (C == 0) C = B;
+    a.C = C;
+    a.lanes = (uint32_t)((words + C - 1) / C);
+    a.words = words;
+}
+
+int serial_family(int engine)
+{
+    switch (engine) {
+    case RP_PHILOX4X32:
+    case RP_PHILOX: return RP_SUB_KEY;
+    case RP_PCG64: return RP_SUB_INC;
+    case RP_SFC64: return RP_SUB_SPAWN;
+    default: return RP_SUB_JUMP;
+    }
+}
+
+// The whole request on one substream holding the stream's state (one lane
+// or one wavefront), then the state copied back.
+int serial_fallback(rp_rng *rng, int dist, int dtype, uint64_t bound, int flags, void *d_out, uint64_t n,
+                    hipStream_t st)
+{
+    rp_streams *s = nullptr;
+    int rc = rp_streams_create(rng, serial_family(rng->engine), 1, 64, &s);
+    if (rc) return rc;
+    uint64_t words[16];
+    uint32_t ph = rng->phase;
+    memcpy(words, rng->st, sizeof words);
+    rc = rp_streams_set(s, words, &ph);
+    if (rc == RP_OK) rc = rp_fill(s, dist, dtype, bound, flags, d_out, n, st);
+    if (rc == RP_OK) {
+        const hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = hip_fail(e, "rp_fill_serial");
+    }
+    if (rc == RP_OK) rc = rp_streams_get(s, words, &ph);
+    if (rc == RP_OK) {
+        memcpy(rng->st, words, (size_t)state_words(rng->engine) * 8);
+        rng->phase = ph;
+    }
+    rp_streams_free(s);
+    return rc;
+}
+
+}  // namespace
+
+extern "C" int rp_fill_serial(rp_rng *rng, int dist, int dtype, uint64_t bound, int flags, void *d_out, uint64_t n,
+                              void *hip_stream)
+{
+    if (!rng) return fail(RP_ENULL, "rp_fill_serial: NULL rng");
+    if (n == 0) return RP_OK;
+    if (!d_out) return fail(RP_ENULL, "rp_fill_serial: NULL output");
+    bool ok = false;
+    switch (dist) {
+    case RP_RAW: ok = dtype == RP_U64 || dtype == RP_U32; break;
+    case RP_U01: ok = dtype == RP_F64 || dtype == RP_F32; break;
+    case RP_BOUNDED: ok = dtype == RP_U64 || (dtype == RP_U32 && bound <= 0xFFFFFFFFull); break;
+    case RP_NORM:
+    case RP_EXP: ok = dtype == RP_F64; break;
+    default: return fail(RP_EINVAL, "rp_fill_serial: unknown distribution %d", dist);
+    }
+    if (!ok) return fail(RP_EUNSUPPORTED, "rp_fill_serial: distribution %d has no dtype %d form", dist, dtype);
+    if (flags & ~RP_FLAG_52BIT) return fail(RP_EINVAL, "rp_fill_serial: unknown flags 0x%x", flags);
+    const bool half = dtype == RP_U32 || dtype == RP_F32;
+    if ((uintptr_t)d_out % (half ? 4 : 8)) return fail(RP_EINVAL, "rp_fill_serial: output not aligned");
+    if (n > (1ull << 40)) return fail(RP_EINVAL, "rp_fill_serial: n above 2^40");
+    int rc = ensure_device_tables();
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (rng->engine == RP_SFC64)  // no jump: one lane
+        return serial_fallback(rng, dist, dtype, bound, flags, d_out, n, st);
+    SerialArgs a{};
+    memcpy(a.base, rng->st, sizeof a.base);
+    a.phase = rng->phase;
+    a.fa.out = d_out;
+    a.fa.bound = bound;
+    a.fa.flags = flags;
+    if (dist == RP_BOUNDED && bound) {
+        if (dtype == RP_U64) a.fa.thresh = (0 - bound) % bound;
+        else a.fa.thresh = (uint32_t)(0u - (uint32_t)bound) % (uint32_t)bound;
+    }
+    a.n = n;
+    const int B = block_words(rng->engine);
+    const bool fixed = dist == RP_RAW || dist == RP_U01 || (dist == RP_BOUNDED && bound == 0);
+    if (fixed) {
+        const uint64_t words = half ? (n + 1) / 2 : n;
+        plan_lanes(a, words, B);
+        serial_tables(rng->engine, a.C, a.jt);
+        rc = launch_serial_fixed(rng->engine, dist, dtype, a, st);
+        if (rc) return rc;
+        return advance_words(rng, words);
+    }
+    // rejection samplers: enough units that n samples are found in all but
+    // astronomically rare cases (then the one-lane fill takes over)
+    uint64_t units;
+    if (dist == RP_BOUNDED) {
+        const double rej = dtype == RP_U64 ? (double)a.fa.thresh * 0x1.0p-64 : (double)a.fa.thresh * 0x1.0p-32;
+        units = (uint64_t)((double)n / (1.0 - rej) * 1.03) + 64;
+    } else {
+        units = n + n / 16 + 64;
+    }
+    const uint64_t margin = 2 * (uint64_t)8192 + 16;  // longest attempt: a normal tail at its iteration cap
+    const uint64_t gen_units = units + margin;
+    plan_lanes(a, half ? (gen_units + 1) / 2 : gen_units, B);
+    serial_tables(rng->engine, a.C, a.jt);
+    a.units = units;
+    const int S = serial_chunk_units(), E = serial_entries(), CB = serial_chunks_per_block();
+    a.nchunks = (units + S - 1) / S;
+    a.nblocks = (a.nchunks + CB - 1) / CB;
+    auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
+    const uint64_t o_wbuf = 0, o_cexit = al(o_wbuf + a.words * 8), o_ccount = al(o_cexit + a.nchunks * E),
+                   o_bexit = al(o_ccount + a.nchunks * E * 4), o_bcount = al(o_bexit + a.nblocks * E),
+                   o_bentry = al(o_bcount + a.nblocks * E * 4), o_bbase = al(o_bentry + a.nblocks),
+                   o_res = al(o_bbase + a.nblocks * 8), total = al(o_res + 64);
+    char *ws = nullptr;
+    hipError_t e = hipMallocAsync((void **)&ws, total, st);
+    if (e != hipSuccess) return fail(RP_ENOMEM, "rp_fill_serial: workspace: %s", hipGetErrorString(e));
+    a.wbuf = (uint64_t *)(ws + o_wbuf);
+    a.cexit = (uint8_t *)(ws + o_cexit);
+    a.ccount = (uint32_t *)(ws + o_ccount);
+    a.bexit = (uint8_t *)(ws + o_bexit);
+    a.bcount = (uint32_t *)(ws + o_bcount);
+    a.bentry = (uint8_t *)(ws + o_bentry);
+    a.bbase = (uint64_t *)(ws + o_bbase);
+    a.result = (uint64_t *)(ws + o_res);
+    static thread_local uint64_t *h_res = nullptr;
+    if (!h_res) {
+        e = hipHostMalloc((void **)&h_res, 64, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            h_res = nullptr;
+            (void)hipFreeAsync(ws, st);
+            return fail(RP_ENOMEM, "rp_fill_serial: pinned result buffer: %s", hipGetErrorString(e));
+        }
+    }
+    rc = launch_serial_stitch(rng->engine, dist, dtype, a, st);
+    if (rc == RP_OK) {
+        e = hipMemcpyAsync(h_res, a.result, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = hip_fail(e, "rp_fill_serial");
+    }
+    (void)hipFreeAsync(ws, st);
+    if (rc) return rc;
+    if (h_res[2] != 0 || h_res[1] < n) return serial_fallback(rng, dist, dtype, bound, flags, d_out, n, st);
+    const uint64_t end = h_res[0];
+    return advance_words(rng, half ? (end + 1) / 2 : end);
+}

@@ -91,6 +91,34 @@ int launch_queue_reset(const BatchArgs &a, hipStream_t stream);
 int batched_blocks_for_scan(uint64_t n_sets);
 int batched_buckets();
 
+// serial split of one stream (k_serial.h)
+constexpr int kSerJt = 320;
+struct SerialArgs {
+    uint64_t base[9];      // engine state words at the start (Table 3 order)
+    uint32_t phase;        // words used from the current block
+    uint32_t lanes;        // generator lanes
+    uint64_t C;            // words per lane (a multiple of the block size)
+    uint64_t words;        // words generated: positions 0 .. words-1
+    uint64_t jt[kSerJt];   // jump data, engine specific
+    FillArgs fa;           // out, bound, thresh, flags
+    uint64_t n;            // outputs wanted
+    uint64_t units;        // attempts start at units 0 .. units-1 (words or halves)
+    uint64_t *wbuf;        // generated words (rejection samplers)
+    uint8_t *cexit;        // per chunk: exclusive prefix map within its block
+    uint32_t *ccount;
+    uint8_t *bexit;        // per block: the block's map
+    uint32_t *bcount;
+    uint8_t *bentry;       // per block: entry offset and output base
+    uint64_t *bbase;
+    uint64_t *result;      // end unit of the n-th output, outputs available, overflow
+    uint64_t nchunks, nblocks;
+};
+int launch_serial_fixed(int engine, int dist, int dtype, const SerialArgs &a, hipStream_t stream);
+int launch_serial_stitch(int engine, int dist, int dtype, const SerialArgs &a, hipStream_t stream);
+int serial_chunk_units();
+int serial_entries();
+int serial_chunks_per_block();
+
 int launch_moments(int engine, const SampArgs &s, hipStream_t stream);
 int launch_gamma_elem(int engine, const SampArgs &s, bool beta, hipStream_t stream);
 // rows of normals: z[i * d + t] = t-th normal of substream i, binary32

@@ -1,0 +1,102 @@
+"""GPU split of one stream over many lanes against the serial oracle (MI355X).
+
+rp_fill_serial must return exactly what n serial calls on the stream return
+(bit-exact for raw bits, uniforms and bounded integers; ziggurat values
+within 4 ulp, tails only) and leave the stream where those calls leave it.
+The x256++ case at 10^6 values per output is the one-stream workload of the
+plain method (seed 12345, each output from a freshly seeded stream).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2605_05099_amd as rp
+from tests.gpu_common import NP_VIEW, TORCH_DTYPE, oracle_fill, ulp_diff
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ENGINES = ["x256++", "pcg64", "philox4x32", "philox", "ranlux++", "sfc64"]
+CASES = [
+    (rp.RP_RAW, rp.RP_U64, 0, 0),
+    (rp.RP_RAW, rp.RP_U32, 0, 0),
+    (rp.RP_U01, rp.RP_F64, 0, 0),
+    (rp.RP_U01, rp.RP_F32, 0, rp.RP_FLAG_52BIT),
+    (rp.RP_BOUNDED, rp.RP_U64, 6, 0),
+    (rp.RP_BOUNDED, rp.RP_U64, 6 * 10**18, 0),
+    (rp.RP_BOUNDED, rp.RP_U32, 3 * 10**9, 0),
+    (rp.RP_BOUNDED, rp.RP_U64, 0, 0),
+    (rp.RP_NORM, rp.RP_F64, 0, 0),
+    (rp.RP_EXP, rp.RP_F64, 0, 0),
+]
+
+
+def _gpu(rng, dist, dtype, bound, flags, n):
+    t = torch.empty(max(n, 1), dtype=getattr(torch, TORCH_DTYPE[dtype]), device="cuda")
+    rp.rp_fill_serial(rng, dist, dtype, bound, flags, t, n)
+    torch.cuda.synchronize()
+    return t.cpu().numpy().view(NP_VIEW[dtype])[:n]
+
+
+def _compare(got, ref, dist):
+    assert got.shape == ref.shape
+    if dist in (rp.RP_NORM, rp.RP_EXP):
+        d = ulp_diff(got, ref)
+        assert d.max() <= 4, int(d.max())
+        r = 3.6541528853610088 if dist == rp.RP_NORM else 7.69711747013105
+        assert (np.abs(ref[d > 0]) >= r).all()
+    else:
+        assert np.array_equal(got, ref)
+
+
+def _same_state(rng, o):
+    words, phase = rng.get_state()
+    assert words == o.state[: len(words)] and phase == o.phase
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"d{c[0]}t{c[1]}b{c[2]}f{c[3]}")
+def test_serial_matches_oracle(engine, case):
+    dist, dtype, bound, flags = case
+    rng = rp.rp_create(engine).seed(7)
+    o = oracle.Stream.seeded(engine, 7)
+    if engine == "sfc64":               # no jump: move on by drawing
+        rng.raw_host(3)
+        o.raw(3)
+    else:
+        rng.advance(3)
+        o.advance(3)
+    if engine in ("philox4x32", "philox", "ranlux++"):
+        rng.raw_host(1)                 # and with a partly used block
+        o.raw(1)
+    for n in (1, 777, 40001):           # successive calls continue the stream
+        got = _gpu(rng, dist, dtype, bound, flags, n)
+        _compare(got, oracle_fill(o, dist, dtype, n, bound, flags), dist)
+        _same_state(rng, o)
+
+
+@pytest.mark.parametrize("what", ["raw", "u01", "norm", "exp"])
+def test_one_stream_workload(what):
+    """x256++ from seed 12345, 10^6 values; each output from a fresh stream."""
+    n = 10**6
+    dist, dtype = {"raw": (rp.RP_RAW, rp.RP_U64), "u01": (rp.RP_U01, rp.RP_F64),
+                   "norm": (rp.RP_NORM, rp.RP_F64), "exp": (rp.RP_EXP, rp.RP_F64)}[what]
+    rng = rp.rp_create("x256++").seed(12345)
+    got = _gpu(rng, dist, dtype, 0, 0, n)
+    o = oracle.Stream.seeded("x256++", 12345)
+    _compare(got, oracle_fill(o, dist, dtype, n), dist)
+    _same_state(rng, o)
+
+
+def test_serial_errors():
+    rng = rp.rp_create("x256++").seed(1)
+    t = torch.empty(4, dtype=torch.float64, device="cuda")
+    with pytest.raises(rp.RpError) as ei:
+        rp.rp_fill_serial(rng, rp.RP_NORM, rp.RP_F32, 0, 0, t, 4)
+    assert ei.value.code == rp.RP_EUNSUPPORTED
+    with pytest.raises(rp.RpError) as ei:
+        rp.rp_fill_serial(rng, rp.RP_RAW, rp.RP_U64, 0, 0, 0, 4)
+    assert ei.value.code == rp.RP_ENULL
+    before = rng.get_state()
+    rp.rp_fill_serial(rng, rp.RP_RAW, rp.RP_U64, 0, 0, t, 0)
+    assert rng.get_state() == before
