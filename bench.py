@@ -1,21 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark of the bulk substream-generation hot path on one MI355X.
 
-Workload (one "step"): Philox4x32-10 substreams (key = substream index) and
-PCG64 substreams (increment 2 i + 1), base seed 42, 2^16 substreams x 2^14
+Step (the figure in `value`): Philox4x32-10 substreams (key = substream index)
+and PCG64 substreams (increment 2 i + 1), base seed 42, 2^16 substreams x 2^14
 values each (2^30 values per fill), filled as raw uint64, uniform float32,
 uniform float64, standard normal float64 and standard exponential float64:
-ten fills, 10 x 2^30 values per step.  Inputs (the substream states) are
-resident in HBM before timing; the fills run back to back on one HIP stream.
+ten fills, 10 x 2^30 values per step.  The substream states are resident in
+HBM before timing; the fills run back to back on one HIP stream.
 
-Prints one JSON line: whole-step throughput in Gsamples/s, the roofline of the
-dominant kernel (its average duration measured with HIP events on the launch
-stream), per-fill figures, and the CPU oracle timed on a bounded sample of the
-same workload on the host cores.
+The same run also times the other parts of the path, each on its own
+workload (`parts`): one x256++ stream split over lanes (10^6 values), batched
+gamma and beta (10^6 sets, about 2.6e8 values, recorded graph, tuned plan),
+per-element gamma / beta forward and backward ([4096, 1024]), multivariate
+normal forward and backward (2^20 rows, d = 64, 256, 512), and the fused
+per-substream moments (2^18 substreams x 2^16 normals, ranlux++ and sfc64).
+
+Prints one JSON line: the step's throughput in Gsamples/s, the roofline of
+its dominant kernel (average duration from HIP events on the launch stream;
+HBM traffic from the committed counter summary when it still matches the
+kernel sources), per-fill and per-part figures, and the CPU oracle timed on a
+bounded sample of the step's workload on the host cores.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -23,7 +33,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
 METRIC = "Gsamples/s per engine x distribution, % HBM-write roofline; gamma grad/s"
+# counter summaries: profiles/pmc_fill_<engine>_<output>.md
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_fill_{}.md")
+KERNEL_SOURCES = ["fill.hip", "engines.h", "rp_internal.h", "zig_tables.inc"]
 
 
 def parse():
@@ -32,10 +46,36 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-parts", action="store_true", help="time only the ten-fill step")
+    p.add_argument("--parts", default=None,
+                   help="comma-separated parts to time after the step: serial, batched, elem, mvn, "
+                        "moments (default all; none with --only)")
     p.add_argument("--only", default="", help="comma-separated fill names to run (profiling)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="run only plain fill/copy kernels of known size (counter calibration)")
     return p.parse_args()
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2605_05099_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(fill):
+    """HBM bytes per launch of a fill kernel from its counter summary, or
+    None when that summary is missing or was taken on other sources."""
+    try:
+        text = open(TRAFFIC_SUMMARY.format(fill.replace("/", "_").replace("+", "p"))).read()
+    except OSError:
+        return None
+    src = re.search(r"^source_sha256_16:\s*([0-9a-f]+)", text, re.M)
+    tot = re.search(r"^hbm_bytes_per_launch:\s*([0-9.eE+]+)", text, re.M)
+    if not src or not tot or src.group(1) != kernel_source_hash():
+        return None
+    return float(tot.group(1))
 
 
 def calibrate_copy(steps):
@@ -54,11 +94,9 @@ def calibrate_copy(steps):
 
 
 def cpu_baseline(target_cpu_s=12.0):
-    """The oracle on the host cores, on a bounded sample of the workload:
-    whole substreams of 2^14 values, both engines, all five outputs."""
+    """The oracle on the host cores, on a bounded sample of the step's
+    workload: whole substreams of 2^14 values, both engines, all five fills."""
     import concurrent.futures as cf
-
-    import numpy as np
 
     import oracle
     from paper_2605_05099_amd import workloads
@@ -74,20 +112,169 @@ def cpu_baseline(target_cpu_s=12.0):
         getattr(s, what)(per)
         return time.perf_counter() - t0
 
-    # calibrate: one substream per (engine, output)
     cal = [one((e, k, 0, w)) for e, k in kinds for w in outs]
-    per_round = sum(cal)  # CPU seconds for one substream of every fill
+    per_round = sum(cal)
     rounds = max(1, int(target_cpu_s / per_round))
     threads = min(os.cpu_count() or 1, 16)
     tasks = [(e, k, i, w) for i in range(1, rounds + 1) for e, k in kinds for w in outs]
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(max_workers=threads) as ex:
-        cpu_s = sum(ex.map(one, tasks))
+        list(ex.map(one, tasks))
     wall = time.perf_counter() - t0
     n_values = len(tasks) * per
-    return {"value": n_values / wall / 1e9, "unit": "Gsamples/s", "cores": threads, "kind": "oracle",
-            "sample": f"{rounds} substreams x 2^14 values for each of the 10 fills "
-                      f"({n_values} values, {cpu_s:.1f} CPU-s on {threads} threads)"}
+    return {"value": round(n_values / wall / 1e9, 4), "unit": "Gsamples/s", "cores": threads, "kind": "oracle",
+            "sample": f"{rounds} substreams x 2^14 values for each of the 10 fills ({n_values} values, "
+                      f"{wall:.1f} s wall on {threads} threads; single-substream estimate "
+                      f"{per_round:.3f} s per 10 x 2^14 values)"}
+
+
+class Timer:
+    """HIP events on one stream; ms per repetition of fn."""
+
+    def __init__(self, torch, stream):
+        self.torch, self.stream = torch, stream
+
+    def __call__(self, fn, reps=3, warmup=1):
+        t = self.torch
+        for _ in range(warmup):
+            fn()
+        t.cuda.synchronize()
+        a, b = t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)
+        a.record(self.stream)
+        for _ in range(reps):
+            fn()
+        b.record(self.stream)
+        t.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+
+def parts(torch, rp, workloads, stream, only):
+    """Every other row of the path on its own workload (see module doc)."""
+    import numpy as np
+    tm = Timer(torch, stream)
+    sp = stream.cuda_stream
+    out = {}
+    if "serial" in only:
+        out.update(part_serial(torch, rp, workloads, tm, sp))
+    if "batched" in only:
+        out.update(part_batched(torch, rp, workloads, tm, sp))
+    if "elem" in only:
+        out.update(part_elem(torch, rp, workloads, tm, sp, np))
+    if "mvn" in only:
+        out.update(part_mvn(torch, rp, workloads, tm, sp, np))
+    if "moments" in only:
+        out.update(part_moments(torch, rp, workloads, tm, sp))
+    return out
+
+
+def part_serial(torch, rp, workloads, tm, sp):
+    out = {}
+
+    # one stream split over lanes: x256++ seed 12345, 10^6 values each
+    n = workloads.SERIAL_N
+    buf = torch.empty(n, dtype=torch.float64, device="cuda")
+    ser = {}
+    for name, dist, dtype in (("raw_u64", rp.RP_RAW, rp.RP_U64), ("u01_f64", rp.RP_U01, rp.RP_F64),
+                              ("normal_f64", rp.RP_NORM, rp.RP_F64), ("exp_f64", rp.RP_EXP, rp.RP_F64)):
+        rng = rp.rp_create("x256++").seed(workloads.SERIAL_SEED)
+        ms = tm(lambda: rp.rp_fill_serial(rng, dist, dtype, 0, 0, buf, n, sp), reps=5)
+        ser[name] = {"ms": round(ms, 4), "gsamples_s": round(n / ms / 1e6, 3)}
+    out["serial_x256pp_1e6"] = ser
+    return out
+
+
+def part_batched(torch, rp, workloads, tm, sp):
+    out = {}
+    w = workloads.batched_sets()
+    nsets = len(w["alpha"])
+    bat = {}
+    for kind, params, count in (("gamma", (w["alpha"],), w["count"]), ("beta", (w["a"], w["b"]), w["count_beta"])):
+        total = int(count.sum())
+        o = torch.empty(total, dtype=torch.float64, device="cuda")
+        dp = [torch.as_tensor(p, device="cuda") for p in params]
+        dc = torch.as_tensor(count, device="cuda")
+        S = rp.rp_streams_create(rp.rp_create("philox4x32").seed(workloads.BASE_SEED), rp.RP_SUB_KEY, nsets)
+        plan = rp.rp_plan_create()
+        rp.rp_plan_autotune(plan, S, kind == "beta", dp[0], dp[1] if kind == "beta" else None, dc, nsets, o)
+        if kind == "gamma":
+            fn = lambda: rp.rp_gamma_batched(S, dp[0], dc, nsets, o, plan, sp)  # noqa: E731
+        else:
+            fn = lambda: rp.rp_beta_batched(S, dp[0], dp[1], dc, nsets, o, plan, sp)  # noqa: E731
+        ms = tm(fn, reps=5)
+        bat[kind] = {"ms": round(ms, 4), "samples": total, "gsamples_s": round(total / ms / 1e6, 3),
+                     "write_gb_s": round(total * 8 / ms / 1e6, 1),
+                     "hbm_write_frac": round(total * 8 / ms / 1e6 / HBM_PEAK_GBS, 4), "plan": plan.get_config()}
+        del o, S, plan
+    out["batched_1e6_sets"] = bat
+    return out
+
+
+def part_elem(torch, rp, workloads, tm, sp, np):
+    out = {}
+    pe = workloads.per_element()
+    ne = int(np.prod(workloads.PER_ELEMENT_SHAPE))
+    S = rp.rp_streams_create(rp.rp_create("philox4x32").seed(workloads.BASE_SEED), rp.RP_SUB_KEY, ne)
+    al = torch.as_tensor(pe["alpha"].reshape(-1), device="cuda")
+    a = torch.as_tensor(pe["a"].reshape(-1), device="cuda")
+    b = torch.as_tensor(pe["b"].reshape(-1), device="cuda")
+    gz = torch.as_tensor(pe["gz"].reshape(-1), device="cuda")
+    z = torch.empty(ne, dtype=torch.float32, device="cuda")
+    zb = torch.empty(ne, dtype=torch.float32, device="cuda")
+    g1 = torch.empty(ne, dtype=torch.float32, device="cuda")
+    g2 = torch.empty(ne, dtype=torch.float32, device="cuda")
+    el = {}
+    ms = tm(lambda: rp.rp_gamma_elem(S, al, z, ne, sp))
+    el["gamma_fwd"] = {"ms": round(ms, 4), "gsamples_s": round(ne / ms / 1e6, 3)}
+    ms = tm(lambda: rp.rp_gamma_grad(z, al, gz, g1, ne, sp))
+    el["gamma_bwd"] = {"ms": round(ms, 4), "ggrad_s": round(ne / ms / 1e6, 3),
+                       "hbm_gb_s": round(ne * 16 / ms / 1e6, 1)}
+    ms = tm(lambda: rp.rp_beta_elem(S, a, b, zb, ne, sp))
+    el["beta_fwd"] = {"ms": round(ms, 4), "gsamples_s": round(ne / ms / 1e6, 3)}
+    ms = tm(lambda: rp.rp_beta_grad(zb, a, b, gz, g1, g2, ne, sp))
+    el["beta_bwd"] = {"ms": round(ms, 4), "ggrad_s": round(ne / ms / 1e6, 3),
+                      "hbm_gb_s": round(ne * 24 / ms / 1e6, 1)}
+    out["per_element_4096x1024"] = el
+    return out
+
+
+def part_mvn(torch, rp, workloads, tm, sp, np):
+    out = {}
+    mv = {}
+    nr = workloads.MVN_N
+    for d in workloads.MVN_DIMS:
+        wm = workloads.mvn(d)
+        L = torch.as_tensor(rp.rp_cholesky(wm["sigma"]).astype(np.float32), device="cuda")
+        mu = torch.as_tensor(wm["mu"].astype(np.float32), device="cuda")
+        S = rp.rp_streams_create(rp.rp_create("philox4x32").seed(workloads.BASE_SEED), rp.RP_SUB_KEY, nr)
+        X = torch.empty((nr, d), dtype=torch.float32, device="cuda")
+        ms_f = tm(lambda: rp.rp_mvn(S, mu, L, d, nr, X, sp))
+        G = torch.ones((nr, d), dtype=torch.float32, device="cuda")
+        gm = torch.empty(d, dtype=torch.float32, device="cuda")
+        gL = torch.empty((d, d), dtype=torch.float32, device="cuda")
+        ms_b = tm(lambda: rp.rp_mvn_backward(S, G, d, nr, gm, gL, sp))
+        fl = 2.0 * nr * d * d
+        mv[f"d{d}"] = {"fwd_ms": round(ms_f, 4), "fwd_tflops": round(fl / ms_f / 1e9, 2),
+                       "fwd_mfma_frac": round(fl / ms_f / 1e9 / FP32_MFMA_PEAK_TFLOPS, 4),
+                       "bwd_ms": round(ms_b, 4), "bwd_tflops": round(fl / 2 / ms_b / 1e9, 2),
+                       "rows_per_s_g": round(nr / ms_f / 1e6, 3)}
+        del S, X, G
+    out["mvn_2p20_rows"] = mv
+    return out
+
+
+def part_moments(torch, rp, workloads, tm, sp):
+    out = {}
+    mo = {}
+    nm, pm = workloads.MOM_N, workloads.MOM_PER
+    s1 = torch.empty(nm, dtype=torch.float64, device="cuda")
+    s2 = torch.empty(nm, dtype=torch.float64, device="cuda")
+    for eng, kind in (("ranlux++", rp.RP_SUB_JUMP), ("sfc64", rp.RP_SUB_SPAWN)):
+        S = rp.rp_streams_create(rp.rp_create(eng).seed(workloads.BASE_SEED), kind, nm, 64)
+        ms = tm(lambda: rp.rp_norm_moments(S, pm, s1, s2, sp), reps=2)
+        mo[eng] = {"ms": round(ms, 3), "gsamples_s": round(nm * pm / ms / 1e6, 3)}
+        del S
+    out["moments_2p18x2p16"] = mo
+    return out
 
 
 def main():
@@ -134,7 +321,7 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    # timed region: K steps, no per-kernel events (whole-job wall clock on the GPU)
+    # timed region: K steps, no per-kernel events (whole-job time on the GPU)
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -143,8 +330,7 @@ def main():
         step()
     t1.record(stream)
     torch.cuda.synchronize()
-    ms_total = t0.elapsed_time(t1)
-    ms_step = ms_total / args.steps
+    ms_step = t0.elapsed_time(t1) / args.steps
     # per-kernel durations: a separate pass of K steps with events around each launch
     per_kernel = {f[0]: 0.0 for f in fills}
     for _ in range(args.steps):
@@ -162,7 +348,9 @@ def main():
     dom = max(fills, key=lambda f: per_kernel[f[0]])
     dom_ms = per_kernel[dom[0]]
     achieved = total * dom[4] / dom_ms / 1e6
+    traffic = measured_traffic(dom[0])
     samples_step = total * len(fills)
+    del buf
     result = {
         "metric": METRIC,
         "value": round(samples_step / ms_step / 1e6, 3),
@@ -181,10 +369,14 @@ def main():
                                "exponential f64 (10 fills of 2^30 values per step)",
                    "substreams": n, "per_substream": per, "fills": [f[0] for f in fills]},
         "roofline": {"bound": "hbm", "kernel": dom[0], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
                      "algorithmic_bytes_per_launch": total * dom[4], "avg_launch_ms": round(dom_ms, 4)},
         "rows": rows,
     }
+    want = args.parts if args.parts is not None else ("" if args.only else "serial,batched,elem,mvn,moments")
+    if not args.no_parts and want:
+        result["parts"] = parts(torch, rp, workloads, stream, set(want.split(",")))
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline()
     print(json.dumps(result), flush=True)

@@ -929,44 +929,68 @@ struct LaneSfc64 {
     }
 };
 
-// ranlux++: state (x, phase); the current block is the nine limbs of y = A x,
-// of which `phase` words are used.  When the block is used up, x <- y.
+// Lanes of a wavefront that run serial streams drift apart in how many words
+// they have used, so a per-lane "make a block when the current one is used
+// up" branch would run the block computation for the whole wavefront on
+// almost every word.  Block engines therefore keep a second block: when some
+// lane has used both, every lane without a next block makes one, so the
+// wavefront computes about one block per block's worth of words.
+__device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0; }
+
+// ranlux++: state (x, phase); the current block is the nine limbs of A x, of
+// which `phase` words are used.  Here: cur = A xp, nxt = A cur when hn.
 struct LaneRanlux {
-    uint64_t x[9], y[9];
-    int used;     // words of y already returned (0..9)
-    bool have;    // y holds A x
+    uint64_t xp[9], cur[9], nxt[9];
+    int used;  // words of cur already returned (0..9)
+    bool hn;   // nxt holds A cur
+    __device__ static void mul_A(const uint64_t *in, uint64_t *out)
+    {
+        uint64_t A[9];
+#pragma unroll
+        for (int k = 0; k < 9; k++) A[k] = c_rl_A[k];
+        rl_mulmod(in, A, out);
+    }
+    __device__ void start(int phase)
+    {
+        mul_A(xp, cur);
+        used = phase;
+        hn = false;
+    }
     __device__ void load(const FillArgs &a, uint64_t i)
     {
 #pragma unroll
-        for (int k = 0; k < 9; k++) x[k] = a.words[(uint64_t)k * a.n + i];
-        used = (int)a.phase[i];
-        have = false;
+        for (int k = 0; k < 9; k++) xp[k] = a.words[(uint64_t)k * a.n + i];
+        start((int)a.phase[i]);
     }
     __device__ uint64_t next()
     {
-        if (!have) {
-            uint64_t A[9];
-#pragma unroll
-            for (int k = 0; k < 9; k++) A[k] = c_rl_A[k];
-            rl_mulmod(x, A, y);
-            have = true;
+        if (wave_any(used == 9 && !hn)) {
+            if (!hn) {
+                mul_A(cur, nxt);
+                hn = true;
+            }
         }
-        uint64_t w = y[0];
+        if (used == 9) {
 #pragma unroll
-        for (int k = 1; k < 9; k++) w = (used == k) ? y[k] : w;
-        if (++used == 9) {
-#pragma unroll
-            for (int k = 0; k < 9; k++) x[k] = y[k];
+            for (int k = 0; k < 9; k++) {
+                xp[k] = cur[k];
+                cur[k] = nxt[k];
+            }
+            hn = false;
             used = 0;
-            have = false;
         }
+        uint64_t w = cur[0];
+#pragma unroll
+        for (int k = 1; k < 9; k++) w = (used == k) ? cur[k] : w;
+        used++;
         return w;
     }
     __device__ void store(const FillArgs &a, uint64_t i) const
     {
+        const bool done = used == 9;
 #pragma unroll
-        for (int k = 0; k < 9; k++) a.words[(uint64_t)k * a.n + i] = x[k];
-        a.phase[i] = (uint32_t)used;
+        for (int k = 0; k < 9; k++) a.words[(uint64_t)k * a.n + i] = done ? cur[k] : xp[k];
+        a.phase[i] = done ? 0u : (uint32_t)used;
     }
 };
 

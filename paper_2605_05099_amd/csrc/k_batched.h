@@ -175,8 +175,8 @@ __global__ __launch_bounds__(256) void k_batched(BatchArgs a)
         uint32_t j = 0;
         int64_t cnt = 0, t = 0;
         double *out = nullptr;
-        double pa = 1.0, pb = 1.0;
         E eng;
+        GamMachine<BETA> gm;
         for (;;) {
             if (s < a.spl && !valid) {
                 // open the next set of this lane (or skip past the end)
@@ -185,10 +185,13 @@ __global__ __launch_bounds__(256) void k_batched(BatchArgs a)
                     j = a.order[idx];
                     cnt = bat::clamp_count(a.count[j]);
                     out = a.out + a.offsets[j];
-                    pa = a.pa[j];
-                    pb = BETA ? a.pb[j] : 1.0;
+                    const double pa = a.pa[j];
+                    const double pb = BETA ? a.pb[j] : 1.0;
                     bad = !(pa > 0.0) || !(pb > 0.0);
-                    eng.load(a.f, j);
+                    if (!bad) {
+                        eng.load(a.f, j);
+                        gm.set(pa, pb);
+                    }
                     valid = true;
                     t = 0;
                 } else {
@@ -197,11 +200,12 @@ __global__ __launch_bounds__(256) void k_batched(BatchArgs a)
             }
             if (!valid) break;
             if (t < cnt) {
-                double v;
-                if (bad) v = __builtin_nan("");
-                else v = BETA ? beta_one(eng, &zt, pa, pb) : gamma_one(eng, &zt, pa);
-                out[t] = v;
-                t++;
+                if (bad) {
+                    out[t++] = __builtin_nan("");
+                } else {
+                    double v;
+                    if (gm.step(eng, &zt, v)) out[t++] = v;
+                }
             } else {
                 if (!bad) eng.store(a.f, j);
                 valid = false;

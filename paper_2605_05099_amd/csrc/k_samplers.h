@@ -11,81 +11,118 @@
 
 // ---------------------------------------------------------------------------
 // serial word streams for the counter / LCG engines (lane-per-substream use)
+// Philox4x32-10: counter of the current block, its two words, and the next
+// block (counter + 1) when hn (the two-block scheme of wave_any in fill.hip).
 struct LanePhilox32 {
-    uint64_t clo, chi, key, b0, b1;
-    uint32_t ph;
-    bool have;
+    uint64_t clo, chi, key;
+    uint64_t c0, c1, n0, n1;
+    uint32_t ph;  // words of the current block used (0..2)
+    bool hn;
+    __device__ void start(uint64_t lo, uint64_t hi, uint64_t k, uint32_t phase)
+    {
+        clo = lo;
+        chi = hi;
+        key = k;
+        ph = phase;
+        philox4x32(clo, chi, key, c0, c1);
+        hn = false;
+    }
     __device__ void load(const FillArgs &a, uint64_t i)
     {
-        clo = a.words[i];
-        chi = a.words[a.n + i];
-        key = a.words[2 * a.n + i];
-        ph = a.phase[i];
-        have = false;
+        start(a.words[i], a.words[a.n + i], a.words[2 * a.n + i], a.phase[i]);
     }
     __device__ uint64_t next()
     {
-        if (!have) {
-            philox4x32(clo, chi, key, b0, b1);
-            have = true;
+        if (wave_any(ph == 2 && !hn)) {
+            if (!hn) {
+                const uint64_t lo = clo + 1;
+                philox4x32(lo, chi + (lo == 0 ? 1u : 0u), key, n0, n1);
+                hn = true;
+            }
         }
-        const uint64_t w = ph ? b1 : b0;
-        if (++ph == 2) {
-            ph = 0;
+        if (ph == 2) {
             clo += 1;
             chi += (clo == 0) ? 1u : 0u;
-            have = false;
+            c0 = n0;
+            c1 = n1;
+            hn = false;
+            ph = 0;
         }
+        const uint64_t w = ph ? c1 : c0;
+        ph++;
         return w;
     }
     __device__ void store(const FillArgs &a, uint64_t i) const
     {
-        a.words[i] = clo;
-        a.words[a.n + i] = chi;
-        a.phase[i] = ph;
+        const bool done = ph == 2;
+        const uint64_t lo = clo + (done ? 1u : 0u);
+        a.words[i] = lo;
+        a.words[a.n + i] = chi + ((done && lo == 0) ? 1u : 0u);
+        a.phase[i] = done ? 0u : ph;
     }
 };
 
+// Philox-4x64-10: 256-bit counter of the current block, its four words, and
+// the next block when hn.
 struct LanePhilox64 {
-    uint64_t c[4], k0, k1, b[4];
-    uint32_t ph;
-    bool have;
+    uint64_t c[4], k0, k1, b[4], nb[4];
+    uint32_t ph;  // 0..4
+    bool hn;
+    __device__ static void inc(const uint64_t *in, uint64_t *out)
+    {
+        uint64_t carry = 1;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            out[k] = in[k] + carry;
+            carry = (carry && out[k] == 0) ? 1u : 0u;
+        }
+    }
+    __device__ void start(uint32_t phase)
+    {
+        ph = phase;
+        philox4x64(c, k0, k1, b);
+        hn = false;
+    }
     __device__ void load(const FillArgs &a, uint64_t i)
     {
 #pragma unroll
         for (int k = 0; k < 4; k++) c[k] = a.words[(uint64_t)k * a.n + i];
         k0 = a.words[4 * a.n + i];
         k1 = a.words[5 * a.n + i];
-        ph = a.phase[i];
-        have = false;
+        start(a.phase[i]);
     }
     __device__ uint64_t next()
     {
-        if (!have) {
-            philox4x64(c, k0, k1, b);
-            have = true;
+        if (wave_any(ph == 4 && !hn)) {
+            if (!hn) {
+                uint64_t cn[4];
+                inc(c, cn);
+                philox4x64(cn, k0, k1, nb);
+                hn = true;
+            }
+        }
+        if (ph == 4) {
+            inc(c, c);
+#pragma unroll
+            for (int k = 0; k < 4; k++) b[k] = nb[k];
+            hn = false;
+            ph = 0;
         }
         uint64_t w = b[0];
         w = (ph == 1) ? b[1] : w;
         w = (ph == 2) ? b[2] : w;
         w = (ph == 3) ? b[3] : w;
-        if (++ph == 4) {
-            ph = 0;
-            uint64_t carry = 1;
-#pragma unroll
-            for (int k = 0; k < 4; k++) {
-                c[k] += carry;
-                carry = (carry && c[k] == 0) ? 1u : 0u;
-            }
-            have = false;
-        }
+        ph++;
         return w;
     }
     __device__ void store(const FillArgs &a, uint64_t i) const
     {
+        uint64_t cn[4];
+        inc(c, cn);
+        const bool done = ph == 4;
 #pragma unroll
-        for (int k = 0; k < 4; k++) a.words[(uint64_t)k * a.n + i] = c[k];
-        a.phase[i] = ph;
+        for (int k = 0; k < 4; k++) a.words[(uint64_t)k * a.n + i] = done ? cn[k] : c[k];
+        a.phase[i] = done ? 0u : ph;
     }
 };
 
@@ -123,7 +160,7 @@ __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e
     e = (a - (s - bb)) + (b - bb);
 }
 
-__device__ double boost_pow(double u, double a)
+__device__ double boost_pow(double u, double a, double ia)
 {
     if (u == 0.0) return 0.0;
     int ex;
@@ -142,60 +179,120 @@ __device__ double boost_pow(double u, double a)
     sl = sl + t + (((double)ex * RP_LN2_LO + RP_LOG_LO[i]) + (rl + p));
     const double lh = sh + sl;
     const double ll = sl - (lh - sh);
-    const double th = lh / a;
-    const double tl = (__fma_rn(-th, a, lh) + ll) / a;
+    // t = log(u) / a as th + tl; th need not be the rounded quotient
+    const double th = lh * ia;
+    const double tl = (__fma_rn(-th, a, lh) + ll) * ia;
     const double eh = exp(th);
     if (eh == 0.0) return 0.0;  // also keeps 0 * inf away when a is tiny
     return eh + eh * tl;
 }
 
-// The rejection loops accept with probability above 0.95 (Marsaglia-Tsang)
-// per attempt; the bound only guarantees that a lane exits.
-static constexpr int kMaxAttempts = 1 << 20;
-
+// One ziggurat normal candidate (the serial ziggurat's decisions): true with
+// the value when it is accepted, false when rejected (the caller starts a
+// new candidate, exactly where the serial sampler would).
 template <class E>
-__device__ double mt_gamma(E &eng, const ZigLds *zt, double a)
+__device__ __forceinline__ bool zig_candidate(E &eng, const ZigLds *zt, double &x)
 {
-    const double d = a - 1.0 / 3.0;
-    const double c = 1.0 / sqrt(9.0 * d);
-    for (int it = 0; it < kMaxAttempts; it++) {
-        double x, v;
-        int guard = 0;
-        do {
-            x = zig_serial<RP_NORM>(zt, eng);
-            v = 1.0 + c * x;
-        } while (v <= 0.0 && ++guard < kMaxAttempts);
+    const uint64_t w = eng.next();
+    const int j = (int)(w & 0xff);
+    const uint64_t m = (w >> 9) & ((1ull << 52) - 1);
+    const bool neg = (w >> 8) & 1;
+    const double xx = (double)m * zt->W[j];
+    if (m < zt->K[j]) {
+        x = neg ? -xx : xx;
+        return true;
+    }
+    if (j == 0) {
+        for (int it = 0; it < kMaxTailIters; it++) {
+            const double e1 = -log1p(-u01_53(eng.next())) / RP_ZN_R;
+            const double e2 = -log1p(-u01_53(eng.next()));
+            if (e2 + e2 > e1 * e1) {
+                const double t = RP_ZN_R + e1;
+                x = neg ? -t : t;
+                return true;
+            }
+        }
+        return false;
+    }
+    if (wedge_accept<RP_NORM>(zt, j, xx, eng.next())) {
+        x = neg ? -xx : xx;
+        return true;
+    }
+    return false;
+}
+
+// Marsaglia-Tsang constants of one shape: d = s - 1/3, c = 1/sqrt(9 d) for
+// s = a (a >= 1) or s = a + 1 followed by the boost U^(1/a) (a < 1).
+struct GamParam {
+    double a, d, c, ia;
+    bool boost;
+};
+
+__device__ __forceinline__ GamParam gam_param(double a)
+{
+    GamParam p;
+    p.a = a;
+    p.boost = a < 1.0;
+    const double s = p.boost ? a + 1.0 : a;
+    p.d = s - 1.0 / 3.0;
+    p.c = 1.0 / sqrt(9.0 * p.d);
+    p.ia = 1.0 / a;
+    return p;
+}
+
+// Gamma or beta draws as a sequence of single attempts, so the lanes of a
+// wavefront move on independently: each step() takes one ziggurat candidate
+// and, if it is accepted and v > 0, one uniform for the squeeze / log test
+// (and one more for the boost when the attempt is accepted and a < 1).  The
+// words used and the decisions are those of the serial sampler: a rejected
+// candidate or attempt is followed by a fresh one, as in its loops.  Beta
+// draws X ~ Gamma(a), then Y ~ Gamma(b), then returns X / (X + Y).
+template <bool BETA>
+struct GamMachine {
+    GamParam pa, pb;
+    bool second;
+    double X;
+    __device__ void set(double a, double b)
+    {
+        pa = gam_param(a);
+        if (BETA) pb = gam_param(b);
+        second = false;
+    }
+    template <class E>
+    __device__ __forceinline__ bool step(E &eng, const ZigLds *zt, double &val)
+    {
+        const bool sb = BETA && second;
+        const double d = sb ? pb.d : pa.d, c = sb ? pb.c : pa.c;
+        double x;
+        if (!zig_candidate(eng, zt, x)) return false;
+        double v = 1.0 + c * x;
+        if (v <= 0.0) return false;
         v = v * v * v;
         const double u = u01_53(eng.next());
         const double x2 = x * x;
-        if (u < 1.0 - 0.0331 * (x2 * x2)) return d * v;
-        if (log(u) < 0.5 * x2 + d * ((1.0 - v) + log(v))) return d * v;
+        bool acc = u < 1.0 - 0.0331 * (x2 * x2);
+        if (!acc) acc = log(u) < 0.5 * x2 + d * ((1.0 - v) + log(v));
+        if (!acc) return false;
+        double g = d * v;
+        if (sb ? pb.boost : pa.boost) {
+            const double a = sb ? pb.a : pa.a, ia = sb ? pb.ia : pa.ia;
+            g = g * boost_pow(u01_53(eng.next()), a, ia);
+        }
+        if (!BETA) {
+            val = g;
+            return true;
+        }
+        if (!second) {
+            X = g;
+            second = true;
+            return false;
+        }
+        second = false;
+        const double t = X + g;
+        val = (t == 0.0) ? pa.a / (pa.a + pb.a) : X / t;
+        return true;
     }
-    return d;
-}
-
-template <class E>
-__device__ double gamma_one(E &eng, const ZigLds *zt, double a)
-{
-    if (a < 1.0) {
-        const double g = mt_gamma(eng, zt, a + 1.0);
-        const double u = u01_53(eng.next());
-        return g * boost_pow(u, a);
-    }
-    return mt_gamma(eng, zt, a);
-}
-
-template <class E>
-__device__ double beta_one(E &eng, const ZigLds *zt, double a, double b)
-{
-    const double x = gamma_one(eng, zt, a);
-    const double y = gamma_one(eng, zt, b);
-    const double t = x + y;
-    if (t == 0.0) return a / (a + b);
-    return x / t;
-}
-
-// ---------------------------------------------------------------------------
+};
 
 template <class E>
 __global__ __launch_bounds__(256) void k_norm_moments(SampArgs s)
@@ -218,27 +315,42 @@ __global__ __launch_bounds__(256) void k_norm_moments(SampArgs s)
     eng.store(s.f, i);
 }
 
+// Element e draws from substream e.  Lanes take elements e, e + stride, ...
+// and move to their next element as soon as the current one is accepted.
 template <class E, bool BETA>
 __global__ __launch_bounds__(256) void k_gamma_elem(SampArgs s)
 {
     __shared__ ZigLds zt;
     load_zig<RP_NORM>(&zt);
     __syncthreads();
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= s.count) return;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     E eng;
-    eng.load(s.f, i);
-    const double pa = (double)s.pa[i];
-    const double pb = BETA ? (double)s.pb[i] : 1.0;
-    if (!(pa > 0.0) || !(pb > 0.0)) {
-        s.z[i] = __builtin_nanf("");
-        return;
+    GamMachine<BETA> gm;
+    bool open = false;
+    for (;;) {
+        if (!open) {
+            if (i >= s.count) break;
+            const double pa = (double)s.pa[i];
+            const double pb = BETA ? (double)s.pb[i] : 1.0;
+            if (!(pa > 0.0) || !(pb > 0.0)) {
+                s.z[i] = __builtin_nanf("");
+                i += stride;
+                continue;
+            }
+            eng.load(s.f, i);
+            gm.set(pa, pb);
+            open = true;
+        }
+        double v;
+        if (gm.step(eng, &zt, v)) {
+            s.z[i] = (float)v;
+            eng.store(s.f, i);
+            open = false;
+            i += stride;
+        }
     }
-    const double v = BETA ? beta_one(eng, &zt, pa, pb) : gamma_one(eng, &zt, pa);
-    s.z[i] = (float)v;
-    eng.store(s.f, i);
 }
-
 
 // Row i of z (count rows of per_stream = d values) holds the next d normals
 // of substream i rounded to binary32.  With d a multiple of 4 each lane
@@ -281,7 +393,8 @@ static int launch_moments_e(const SampArgs &s, hipStream_t st)
 template <class E>
 static int launch_elem_e(const SampArgs &s, bool beta, hipStream_t st)
 {
-    const uint64_t blocks = (s.count + 255) / 256;
+    uint64_t blocks = (s.count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;  // lanes then take several elements each
     if (beta)
         hipLaunchKernelGGL((k_gamma_elem<E, true>), dim3((unsigned)blocks), dim3(256), 0, st, s);
     else

@@ -89,11 +89,8 @@ struct SerLane<RP_PHILOX4X32> : LanePhilox32 {
     __device__ void init(const SerialArgs &a, uint64_t id)
     {
         const uint64_t add = id * (a.C / 2);
-        clo = a.base[0] + add;
-        chi = a.base[1] + (clo < add ? 1u : 0u);
-        key = a.base[2];
-        ph = a.phase;
-        have = false;
+        const uint64_t lo = a.base[0] + add;
+        start(lo, a.base[1] + (lo < add ? 1u : 0u), a.base[2], a.phase);
     }
 };
 
@@ -113,8 +110,7 @@ struct SerLane<RP_PHILOX> : LanePhilox64 {
         }
         k0 = a.base[4];
         k1 = a.base[5];
-        ph = a.phase;
-        have = false;
+        start(a.phase);
     }
 };
 
@@ -124,16 +120,15 @@ struct SerLane<RP_RANLUX> : LaneRanlux {
     __device__ void init(const SerialArgs &a, uint64_t id)
     {
 #pragma unroll
-        for (int k = 0; k < 9; k++) x[k] = a.base[k];
+        for (int k = 0; k < 9; k++) xp[k] = a.base[k];
         for (int k = 0; k < 12; k++)
             if ((id >> k) & 1) {
                 uint64_t m[9];
 #pragma unroll
                 for (int t = 0; t < 9; t++) m[t] = a.jt[9 * k + t];
-                rl_mulmod(x, m, x);
+                rl_mulmod(xp, m, xp);
             }
-        used = (int)a.phase;
-        have = false;
+        start((int)a.phase);
     }
 };
 

@@ -26,6 +26,11 @@ BASE_SEED = 42
 SERIAL_N = 10**6
 SUB_N = 2**16
 SUB_PER = 2**14
+MVN_N = 2**20
+MVN_DIMS = (64, 256, 512)
+MOM_N = 2**18
+MOM_PER = 2**16
+PER_ELEMENT_SHAPE = (4096, 1024)
 
 
 def sampled_substreams(n=SUB_N, k=256, seed=2):
