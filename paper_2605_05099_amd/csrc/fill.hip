@@ -120,9 +120,12 @@ static constexpr int kMaxTailIters = 4096;
 
 // ---------------------------------------------------------------------------
 // ziggurat tables in LDS
+struct WKe {
+    double w;    // strip width factor W[j]
+    uint64_t k;  // fast-accept bound K[j]
+};
 struct ZigLds {
-    double W[256];
-    uint64_t K[256];
+    __align__(16) WKe WK[256];  // W and K of a strip in one 16-byte read
     double F[256];
     double X[256];
     double S[256];
@@ -135,8 +138,8 @@ __device__ __forceinline__ void load_zig(ZigLds *t)
 {
     const bool nrm = DIST == RP_NORM;
     for (int k = threadIdx.x; k < 256; k += blockDim.x) {
-        t->W[k] = nrm ? RP_ZN_W[k] : RP_ZE_W[k];
-        t->K[k] = nrm ? RP_ZN_K[k] : RP_ZE_K[k];
+        t->WK[k].w = nrm ? RP_ZN_W[k] : RP_ZE_W[k];
+        t->WK[k].k = nrm ? RP_ZN_K[k] : RP_ZE_K[k];
         t->F[k] = nrm ? RP_ZN_F[k] : RP_ZE_F[k];
         t->X[k] = nrm ? RP_ZN_X[k] : RP_ZE_X[k];
         t->S[k] = nrm ? RP_ZN_S[k] : RP_ZE_S[k];
@@ -161,34 +164,6 @@ __device__ __forceinline__ bool wedge_accept(const ZigLds *t, int j, double x, u
     if (y > l + t->DP[j]) return false;
     if (DIST == RP_NORM) return y < exp(-0.5 * x * x);
     return y < exp(-x);
-}
-
-// Classify a word as the first word of a sample.
-//   kind 0: fast accept (1 word), 1: accept using the next word (2 words),
-//   2: reject after the wedge test (2 words), 3: normal tail (resolved later)
-template <int DIST>
-__device__ __forceinline__ int zig_classify(const ZigLds *t, uint64_t w, uint64_t next_w, double &val)
-{
-    const int j = (int)(w & 0xff);
-    if (DIST == RP_NORM) {
-        const uint64_t m = (w >> 9) & ((1ull << 52) - 1);
-        const bool neg = (w >> 8) & 1;
-        const double x = (double)m * t->W[j];
-        val = neg ? -x : x;
-        if (m < t->K[j]) return 0;
-        if (j == 0) return 3;
-        return wedge_accept<DIST>(t, j, x, next_w) ? 1 : 2;
-    } else {
-        const uint64_t m = (w >> 8) & ((1ull << 53) - 1);
-        const double x = (double)m * t->W[j];
-        val = x;
-        if (m < t->K[j]) return 0;
-        if (j == 0) {
-            val = RP_ZE_R - log1p(-u01_53(next_w));
-            return 1;
-        }
-        return wedge_accept<DIST>(t, j, x, next_w) ? 1 : 2;
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -397,46 +372,23 @@ template <int DIST>
 __device__ __forceinline__ bool zig_fast(const ZigLds *t, uint64_t w, double &val)
 {
     const int j = (int)(w & 0xff);
+    const WKe e = t->WK[j];
     if (DIST == RP_NORM) {
         const uint64_t m = (w >> 9) & ((1ull << 52) - 1);
         // m < 2^52: (2^52 + m) - 2^52 is exact; the sign comes from bit 8
         const double md = __longlong_as_double((long long)(m | 0x4330000000000000ull)) - 0x1.0p52;
-        const double x = md * t->W[j];
+        const double x = md * e.w;
         const uint64_t sgn = (w & 0x100) << 55;
         val = __longlong_as_double(__double_as_longlong(x) ^ (long long)sgn);
-        return m < t->K[j];
+        return m < e.k;
     } else {
         const uint64_t m = (w >> 8) & ((1ull << 53) - 1);
         // m < 2^53: hi 2^32 + lo formed exactly with one fused operation
         const double md = __fma_rn((double)(uint32_t)(m >> 32), 0x1.0p32, (double)(uint32_t)m);
-        val = md * t->W[j];
-        return m < t->K[j];
+        val = md * e.w;
+        return m < e.k;
     }
 }
-
-// Slow part of a sample that started at word w with next word u, for a word
-// that failed the fast test: wedge test (strips j >= 1) or exponential tail
-// (strip 0).  Returns 1 accept (value in val), 2 reject; for the normal tail
-// returns 3 (resolved by the serial walk, which may need more words).
-template <int DIST>
-__device__ __forceinline__ int zig_slow(const ZigLds *t, uint64_t w, uint64_t u, double &val)
-{
-    const int j = (int)(w & 0xff);
-    double x;
-    zig_fast<DIST>(t, w, x);
-    if (j == 0) {
-        if (DIST == RP_NORM) return 3;
-        val = RP_ZE_R - log1p(-u01_53(u));
-        return 1;
-    }
-    const double ax = (DIST == RP_NORM) ? fabs(x) : x;
-    val = x;
-    return wedge_accept<DIST>(t, j, ax, u) ? 1 : 2;
-}
-
-struct SlowSlot {
-    uint64_t w, u;
-};
 
 // Orders a wavefront's LDS accesses: writes before the barrier are visible
 // to reads after it (all lanes of one wavefront).
@@ -447,28 +399,17 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Copies n staged values to dst with coalesced stores: consecutive lanes
-// write consecutive 16-byte pieces when dst is 16-byte aligned, consecutive
-// elements otherwise.
-template <typename T>
-__device__ __forceinline__ void flush_stage(const T *stage, T *dst, int n, int lane)
-{
-    constexpr int V = 16 / sizeof(T);
-    int done = 0;
-    if (((uintptr_t)dst & 15) == 0) {
-        const int nvec = n / V;
-        for (int m = lane; m < nvec; m += 64) *(uint4 *)(dst + m * V) = *(const uint4 *)(stage + m * V);
-        done = nvec * V;
-    }
-    for (int t = done + lane; t < n; t += 64) dst[t] = stage[t];
-}
-
 // Slow part of a sample whose first word w0 failed the fast test.  The
 // following words are word(1), word(2), ...; only `avail` of them exist in
 // the current chunk.  Returns the words used including w0 (2 for a wedge test
 // or the exponential tail, 3 + 2 t for the normal tail), or 0 if the sample
 // needs words past the chunk; then, for the normal tail, *u1 receives an
 // unused first word of a pair when one is left (has_u1).
+// exp and log1p kept out of line on the rare paths of the wavefront kernel,
+// so that their constants do not occupy registers across its chunk loop
+__device__ __noinline__ double exp_ool(double x) { return exp(x); }
+__device__ __noinline__ double log1p_ool(double x) { return log1p(x); }
+
 template <int DIST, class Word>
 __device__ __forceinline__ int zig_resolve(const ZigLds *t, uint64_t w0, Word word, int avail, bool &accepted,
                                            double &val, bool &has_u1, uint64_t &u1)
@@ -483,9 +424,17 @@ __device__ __forceinline__ int zig_resolve(const ZigLds *t, uint64_t w0, Word wo
             double x;
             zig_fast<DIST>(t, w0, x);
             val = x;
-            accepted = wedge_accept<DIST>(t, j, DIST == RP_NORM ? fabs(x) : x, u);
+            // the wedge test of wedge_accept, with the exp out of line
+            const double ax = DIST == RP_NORM ? fabs(x) : x;
+            const double U = u01_53(u);
+            const double fj = t->F[j], fj1 = t->F[j - 1];
+            const double y = fj + U * (fj1 - fj);
+            const double l = fj1 + t->S[j] * (ax - t->X[j - 1]);
+            if (y < l - t->DM[j]) accepted = true;
+            else if (y > l + t->DP[j]) accepted = false;
+            else accepted = y < exp_ool(DIST == RP_NORM ? -0.5 * ax * ax : -ax);
         } else {
-            val = RP_ZE_R - log1p(-u01_53(u));
+            val = RP_ZE_R - log1p_ool(-u01_53(u));
             accepted = true;
         }
         return 2;
@@ -499,8 +448,8 @@ __device__ __forceinline__ int zig_resolve(const ZigLds *t, uint64_t w0, Word wo
             }
             return 0;
         }
-        const double e1 = -log1p(-u01_53(word(1 + 2 * it))) / RP_ZN_R;
-        const double e2 = -log1p(-u01_53(word(2 + 2 * it)));
+        const double e1 = -log1p_ool(-u01_53(word(1 + 2 * it))) / RP_ZN_R;
+        const double e2 = -log1p_ool(-u01_53(word(2 + 2 * it)));
         if (e2 + e2 > e1 * e1) {
             const double tt = RP_ZN_R + e1;
             val = ((w0 >> 8) & 1) ? -tt : tt;
@@ -511,52 +460,60 @@ __device__ __forceinline__ int zig_resolve(const ZigLds *t, uint64_t w0, Word wo
     return 2;  // unreachable in practice (see kMaxTailIters)
 }
 
-// Marks positions [from, to) of the chunk (position 64 r + lane) in skip[].
-template <int R>
-__device__ __forceinline__ void mark_range(uint64_t skip[R], int from, int to)
+// A chunk's words live in LDS in stream order with two spare words after
+// every eight: the generating lanes' 16-byte writes (eight consecutive words
+// per lane) and the transposed reads (consecutive positions on consecutive
+// lanes) then spread over the banks.
+__device__ __forceinline__ int wpos(int p) { return p + 2 * (p >> 3); }
+
+// Mask of the chunk positions [lo, hi) that fall in ballot word r
+// (positions 64 r .. 64 r + 63).
+__device__ __forceinline__ uint64_t range_mask(int r, int lo, int hi)
 {
-    to = to < 64 * R ? to : 64 * R;
-    for (int p = from; p < to; p++) {
-#pragma unroll
-        for (int r = 0; r < R; r++)
-            if ((p >> 6) == r) skip[r] |= 1ull << (p & 63);
-    }
+    const int a = lo > 64 * r ? lo - 64 * r : 0;
+    const int b = hi < 64 * r + 64 ? hi - 64 * r : 64;
+    if (a >= b) return 0;
+    const uint64_t top = b == 64 ? ~0ull : ((1ull << b) - 1);
+    return top & ~((1ull << a) - 1);
 }
 
 template <class E, int DIST, int OT>
 __global__ __launch_bounds__(256) void k_fill_wave(FillArgs a)
 {
     using T = typename OutType<DIST, OT>::T;
-    constexpr int R = E::R;          // words per lane per chunk
-    constexpr int CHW = 64 * R;      // words per chunk
+    constexpr int R = E::R;              // words per lane per chunk
+    constexpr int CHW = 64 * R;          // words per chunk
+    constexpr int CHWP = CHW + CHW / 4;  // with the spare words
     constexpr bool ZIG = DIST == RP_NORM || DIST == RP_EXP;
     constexpr bool FIXED = DIST == RP_RAW || DIST == RP_U01;
     constexpr int IPW = (OT == RP_U32 || OT == RP_F32) ? 2 : 1;  // items per word
 
     const int wib = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    // chunk words in stream order, for the lane-to-position transpose and for
-    // reading the words after a sample start
-    __shared__ __align__(16) uint64_t wbuf_all[4][CHW];
+    __shared__ __align__(16) uint64_t wbuf_all[4][CHWP];
     uint64_t *const wbuf = wbuf_all[wib];
     ZigLds *zt = nullptr;
     uint32_t *slot_pos = nullptr;
-    double *slot_val = nullptr;
-    int *slot_len = nullptr;
-    int *slot_flag = nullptr;
+    uint16_t *linfo = nullptr;             // long item at a position: length | 0x8000 if it yields a value
+    unsigned long long *covl = nullptr;    // per ballot word r: [2r] positions inside other samples,
+                                           // [2r + 1] accepted long starts
+    unsigned long long *omem = nullptr;    // per ballot word r: positions that yield a value
+    uint32_t *pmem = nullptr;              //   and the values before word r
     if constexpr (ZIG) {
         __shared__ ZigLds zbuf;
         __shared__ uint32_t spos[4][64];
-        __shared__ double sval[4][64];
-        __shared__ int slen[4][64];
-        __shared__ int sflag[4][64];
+        __shared__ uint16_t linf[4][CHW];
+        __shared__ __align__(16) unsigned long long cov[4][2 * R];
+        __shared__ unsigned long long omv[4][R];
+        __shared__ uint32_t pcv[4][R];
         load_zig<DIST>(&zbuf);
         __syncthreads();
         zt = &zbuf;
         slot_pos = spos[wib];
-        slot_val = sval[wib];
-        slot_len = slen[wib];
-        slot_flag = sflag[wib];
+        linfo = linf[wib];
+        covl = cov[wib];
+        omem = omv[wib];
+        pmem = pcv[wib];
     }
     const uint64_t sub = (uint64_t)__builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + wib);
     if (sub >= a.n) return;
@@ -586,14 +543,14 @@ __global__ __launch_bounds__(256) void k_fill_wave(FillArgs a)
                 ulonglong2 q;
                 q.x = g[k];
                 q.y = g[k + 1];
-                *(ulonglong2 *)(wbuf + R * lane + k) = q;
+                *(ulonglong2 *)(wbuf + wpos(R * lane + k)) = q;
             }
             eng.next_chunk();
         }
         wave_sync();
         uint64_t w[R];
 #pragma unroll
-        for (int r = 0; r < R; r++) w[r] = wbuf[64 * r + lane];
+        for (int r = 0; r < R; r++) w[r] = wbuf[wpos(64 * r + lane)];
         const uint64_t base_pos = chunk * CHW;
 
         if constexpr (FIXED) {
@@ -681,214 +638,226 @@ __global__ __launch_bounds__(256) void k_fill_wave(FillArgs a)
             produced += basec;
             e = 0;
         } else {
-            // ---- ziggurat: lane l parses its own words S l .. S l + S - 1
-            //      (S = R) in stream order; wedge / tail tests of all items that
-            //      fail the fast test run first, compacted into one pass ----
-            constexpr int S = R;
-            uint64_t g[S];
+            // ---- ziggurat.  (1) A sample carried over from the previous
+            //      chunk: its words are [a spare tail uniform,] then this
+            //      chunk from position 0. ----
+            bool whole = false;  // the carried sample uses the whole chunk
+            {
+                double val[R];
+                uint32_t fb = 0, lb = 0;  // per lane: bit r set if position 64 r + lane is a fast / long start
 #pragma unroll
-            for (int k = 0; k < S; k++) g[k] = wbuf[S * lane + k];
-            double val[S];
-            int len[S];        // words used by a sample starting at item k (0: past the chunk)
-            uint32_t accb = 0; // bit k: such a sample is accepted
-            uint32_t longb = 0;
-#pragma unroll
-            for (int k = 0; k < S; k++) {
-                const bool f = zig_fast<DIST>(zt, g[k], val[k]);
-                len[k] = 1;
-                accb |= (f ? 1u : 0u) << k;
-                longb |= (f ? 0u : 1u) << k;
-            }
-            // rank of this lane's first long item among all long items
-            const int nlong = __popc(longb);
-            int lbase = 0;
-#pragma unroll
-            for (int bit = 0; bit < 4; bit++) lbase += (int)mbcnt64(__ballot((nlong >> bit) & 1)) << bit;
-            int K = 0;
-#pragma unroll
-            for (int bit = 0; bit < 4; bit++) K += __popcll(__ballot((nlong >> bit) & 1)) << bit;
-            const int npre = pending ? 1 : 0;
-            K += npre;
-            lbase += npre;
-            bool pre_acc = false;
-            double pre_val = 0.0;
-            int pre_len = 1;
-            bool pre_hu = false;
-            uint64_t pre_u1 = 0;
-            for (int base = 0; base < K; base += 64) {
+                for (int r = 0; r < R; r++) {
+                    const bool f = zig_fast<DIST>(zt, w[r], val[r]);
+                    fb |= (f ? 1u : 0u) << r;
+                    lb |= (f ? 0u : 1u) << r;
+                }
+                // number of long items (plus the carried sample as slot 0):
+                // each lane's count (<= R < 16) summed bitwise
+                const int npre = pending ? 1 : 0;
+                int K = npre;
                 {
-                    int rk = lbase;
+                    const int cnt = __popc(lb);
 #pragma unroll
-                    for (int k = 0; k < S; k++) {
-                        if ((longb >> k) & 1) {
-                            if (rk >= base && rk < base + 64) slot_pos[rk - base] = (uint32_t)(S * lane + k);
-                            rk++;
+                    for (int bit = 0; bit < 4; bit++) K += __popcll(__ballot((cnt >> bit) & 1)) << bit;
+                }
+                if (lane < 2 * R) covl[lane] = 0;
+                if (e > 0 && lane < R) {  // words of the chunk used before its first start
+                    const uint64_t m = range_mask(lane, 0, e);
+                    if (m) atomicOr(&covl[2 * lane], (unsigned long long)m);
+                }
+                // ---- (3) long items, 64 at a time in position order: one
+                //      lane each resolves its wedge / tail test, then a scalar
+                //      walk decides which of them start a sample (one inside
+                //      an earlier long sample does not) ----
+                int cover_end = e;
+                int pend_slot = -1;
+                uint64_t pw = 0, pu1 = 0;
+                int phu = 0;
+                // the resolving lane of a long value keeps it for the store
+                int yq = -1;
+                double yv = 0.0;
+                uint32_t first = 0;    // values before position 0 (the carried sample's)
+                for (int base = 0; base < K; base += 64) {
+                    int rk0 = npre;  // slots before ballot word r
+#pragma unroll
+                    for (int r = 0; r < R; r++) {
+                        const uint64_t lm = __ballot((lb >> r) & 1);
+                        if ((lb >> r) & 1) {
+                            const int rk = rk0 + (int)mbcnt64(lm) - base;
+                            if (rk >= 0 && rk < 64) slot_pos[rk] = (uint32_t)(64 * r + lane);
                         }
+                        rk0 += __popcll(lm);
                     }
                     if (npre && base == 0 && lane == 0) slot_pos[0] = 0xffffffffu;
-                }
-                wave_sync();
-                if (base + lane < K) {
-                    const uint32_t sp = slot_pos[lane];
-                    const bool pend = sp == 0xffffffffu;
-                    // the pending sample's words: [its spare uniform,] then this
-                    // chunk from position 0
-                    const int q = pend ? -1 : (int)sp;
-                    const int hu = (pend && pend_hu) ? 1 : 0;
-                    const uint64_t w0 = pend ? pend_w : wbuf[q];
-                    const uint64_t pu1 = pend_u1;
-                    bool acd, hu_out;
+                    wave_sync();
+                    const int ns = K - base < 64 ? K - base : 64;
+                    int q = 0, L = 0;
+                    bool acc = false, hu_out = false;
                     double v = 0.0;
-                    uint64_t u1o = 0;
-                    const int L = zig_resolve<DIST>(
-                        zt, w0, [&](int kk) { return (kk == 1 && hu) ? pu1 : wbuf[q + kk - hu]; },
-                        CHW - 1 - q + hu, acd, v, hu_out, u1o);
-                    // length 0: runs past the chunk (-1: keeping a spare uniform)
-                    slot_len[lane] = (L == 0 && hu_out) ? -1 : L;
-                    slot_val[lane] = hu_out ? __longlong_as_double((long long)u1o) : v;
-                    slot_flag[lane] = acd ? 1 : 0;
-                }
-                wave_sync();
-                if (npre && base == 0) {
-                    pre_len = slot_len[0];
-                    pre_acc = slot_flag[0] != 0;
-                    pre_val = slot_val[0];
-                    pre_hu = pre_len < 0;
-                    pre_u1 = (uint64_t)__double_as_longlong(pre_val);
-                }
-                {
-                    int rk = lbase;
-#pragma unroll
-                    for (int k = 0; k < S; k++) {
-                        if ((longb >> k) & 1) {
-                            if (rk >= base && rk < base + 64) {
-                                const int L = slot_len[rk - base];
-                                len[k] = L;  // <= 0: runs past the chunk
-                                if (slot_flag[rk - base]) {
-                                    accb |= 1u << k;
-                                    val[k] = slot_val[rk - base];
-                                }
-                                if (L < 0) val[k] = slot_val[rk - base];  // spare uniform bits
+                    uint64_t u1o = 0, w0 = 0;
+                    if (lane < ns) {
+                        const uint32_t sp = slot_pos[lane];
+                        const bool cp = sp == 0xffffffffu;  // the carried sample: its words are
+                        const int hu = (cp && pend_hu) ? 1 : 0;  // [spare,] then position 0 on
+                        q = cp ? -1 : (int)sp;
+                        const int off = cp ? -1 - hu : q;
+                        w0 = cp ? pend_w : wbuf[wpos(q)];
+                        L = zig_resolve<DIST>(
+                            zt, w0, [&](int kk) { return (hu && kk == 1) ? pend_u1 : wbuf[wpos(off + kk)]; },
+                            cp ? CHW + hu : CHW - 1 - q, acc, v, hu_out, u1o);
+                    }
+                    int i0 = 0;
+                    if (npre && base == 0) {
+                        // the carried sample decides where this chunk's first start is
+                        i0 = 1;
+                        const int L0 = __builtin_amdgcn_readlane(L, 0);
+                        if (L0 <= 0) {
+                            pend_hu = __builtin_amdgcn_readlane(hu_out ? 1 : 0, 0) != 0;
+                            pend_u1 = readlane64(u1o, 0);
+                            whole = true;
+                            break;
+                        }
+                        e = L0 - 1 - (pend_hu ? 1 : 0);
+                        cover_end = e;
+                        pending = false;
+                        if (lane < R) {
+                            const uint64_t m = range_mask(lane, 0, e);
+                            if (m) atomicOr(&covl[2 * lane], (unsigned long long)m);
+                        }
+                        if (__builtin_amdgcn_readlane(acc ? 1 : 0, 0)) {
+                            first = 1;
+                            if (lane == 0) {
+                                yq = -2;  // stored first, before every position
+                                yv = v;
                             }
-                            rk++;
                         }
                     }
+                    uint64_t stm = 0;
+                    for (int i = i0; i < ns; i++) {
+                        const int qi = __builtin_amdgcn_readlane(q, i);
+                        if (qi < cover_end) continue;
+                        const int Li = __builtin_amdgcn_readlane(L, i);
+                        stm |= 1ull << i;
+                        if (Li <= 0) {
+                            pend_slot = i;
+                            cover_end = CHW;
+                            break;
+                        }
+                        cover_end = qi + Li;
+                    }
+                    if (pend_slot >= 0) {
+                        pw = readlane64(w0, pend_slot);
+                        pu1 = readlane64(u1o, pend_slot);
+                        phu = __builtin_amdgcn_readlane(hu_out ? 1 : 0, pend_slot);
+                    }
+                    if (lane < ns && q >= 0) {
+                        const bool st = (stm >> lane) & 1;
+                        const bool yields = st && L > 0 && acc;
+                        if (st && L == 2) {
+                            const int c = q + 1;  // c < CHW: the sample fits in the chunk
+                            atomicOr(&covl[2 * (c >> 6)], 1ull << (c & 63));
+                        } else if (st) {
+                            const int end = L > 0 ? q + L : CHW;
+#pragma unroll
+                            for (int r = 0; r < R; r++) {
+                                const uint64_t m = range_mask(r, q + 1, end);
+                                if (m) atomicOr(&covl[2 * r], (unsigned long long)m);
+                            }
+                        }
+                        if (yields) {
+                            atomicOr(&covl[2 * (q >> 6) + 1], 1ull << (q & 63));
+                            linfo[q] = (uint16_t)L;
+                            yq = q;
+                            yv = v;
+                        }
+                    }
+                    wave_sync();
+                    if (pend_slot >= 0) break;
                 }
-                wave_sync();
-            }
-            // ---- the previous chunk's pending sample ----
-            int e0 = e;  // words of this chunk used before the first start
-            bool pre_out = false;
-            bool still_pending = false;
-            if (pending) {
-                if (pre_len <= 0) {
-                    // runs past this chunk as well: it uses the whole chunk
-                    pend_hu = pre_len < 0;
-                    pend_u1 = pre_u1;
-                    still_pending = true;
-                    e0 = CHW;
+                if (whole) {
+                    wave_sync();
                 } else {
-                    e0 = pre_len - 1 - (pend_hu ? 1 : 0);
-                    pending = false;
-                    pre_out = pre_acc;
-                }
-            }
-            (void)pre_hu;
-            if (pre_out) {
-                if (lane == 0) out[produced] = pre_val;
-                produced++;
-                if (produced == P) {
-                    final_pos = base_pos + (uint64_t)e0;
+                wave_sync();
+                // ---- (4) values in stream order: position p yields a value
+                //      if it is a fast start not inside another sample, or a
+                //      long start that was accepted.  Fast values are stored
+                //      by their own lanes, one ballot word at a time; the
+                //      resolving lanes store the long ones. ----
+                const uint64_t need = P - produced;
+                T *const dst = out + produced;
+                uint32_t total = first;
+                if (yq == -2) dst[0] = yv;  // need >= 1 here
+                if (first && need == 1) {
+                    final_pos = base_pos + (uint64_t)e;
                     break;
                 }
-            }
-            const uint64_t need = P - produced;
-            // ---- per-lane parse with the entry fixed point: a lane's entry
-            //      (words already used) is the previous lane's exit ----
-            int entry = lane == 0 ? e0 : 0;
-            uint32_t outb = 0;  // bit k: item k starts an accepted sample
-            uint32_t pendb = 0; // bit k: item k starts a sample that runs past the chunk
-            int exitw = 0;
-            for (int it = 0; it < 66; it++) {
-                int skp = entry;
-                outb = 0;
-                pendb = 0;
-                bool past = false;
+                if (need >= (uint64_t)CHW + 1) {
 #pragma unroll
-                for (int k = 0; k < S; k++) {
-                    const bool start = skp == 0 && !past;
-                    const int L = len[k];
-                    outb |= (start && ((accb >> k) & 1) && L > 0 ? 1u : 0u) << k;
-                    pendb |= (start && L <= 0 ? 1u : 0u) << k;
-                    past = past || (start && L <= 0);
-                    skp = start ? (L > 0 ? L - 1 : 0) : (skp > 0 ? skp - 1 : 0);
+                    for (int r = 0; r < R; r++) {
+                        const ulonglong2 c = *(const ulonglong2 *)&covl[2 * r];
+                        const uint64_t cv = uni64(c.x), ol = uni64(c.y);
+                        const uint64_t fo = __ballot((fb >> r) & 1) & ~cv;
+                        const uint64_t om = fo | ol;
+                        if ((fo >> lane) & 1) dst[total + mbcnt64(om)] = val[r];
+                        if (lane == 0) {
+                            omem[r] = om;
+                            pmem[r] = total;
+                        }
+                        total += (uint32_t)__popcll(om);
+                    }
+                    wave_sync();
+                    if (yq >= 0) {
+                        const int r = yq >> 6, b = yq & 63;
+                        dst[pmem[r] + (uint32_t)__popcll(omem[r] & ((1ull << b) - 1))] = yv;
+                    }
+                } else {
+                    // the last chunk of this call: only need values, and the
+                    // position after the last one
+                    bool done = false;
+#pragma unroll
+                    for (int r = 0; r < R; r++) {
+                        const ulonglong2 c = *(const ulonglong2 *)&covl[2 * r];
+                        const uint64_t cv = uni64(c.x), ol = uni64(c.y);
+                        const uint64_t fo = __ballot((fb >> r) & 1) & ~cv;
+                        const uint64_t om = fo | ol;
+                        if ((fo >> lane) & 1) {
+                            const uint32_t idx = total + mbcnt64(om);
+                            if (idx < need) dst[idx] = val[r];
+                        }
+                        if (lane == 0) {
+                            omem[r] = om;
+                            pmem[r] = total;
+                        }
+                        const uint32_t cnt = (uint32_t)__popcll(om);
+                        if (!done && (uint64_t)(total + cnt) >= need) {
+                            uint64_t m = om;
+                            for (uint64_t k = need - 1 - total; k > 0; k--) m &= m - 1;
+                            const int bit = __ffsll((long long)m) - 1;
+                            const int qe = 64 * r + bit;
+                            const int len = ((ol >> bit) & 1) ? (int)linfo[qe] : 1;
+                            final_pos = base_pos + (uint64_t)(qe + len);
+                            done = true;
+                        }
+                        total += cnt;
+                    }
+                    wave_sync();
+                    if (yq >= 0) {
+                        const int r = yq >> 6, b = yq & 63;
+                        const uint32_t idx = pmem[r] + (uint32_t)__popcll(omem[r] & ((1ull << b) - 1));
+                        if (idx < need) dst[idx] = yv;
+                    }
+                    if (done) break;
                 }
-                // words still owed after this lane's segment
-                exitw = past ? (1 << 20) : skp;
-                int prev = __shfl_up(exitw, 1);
-                const int ne = lane == 0 ? e0 : prev;
-                const bool changed = __ballot(ne != entry) != 0;
-                entry = ne;
-                if (!changed) break;
-            }
-            // a sample running past the chunk (at most one: it uses the rest)
-            const uint64_t pl = __ballot(pendb != 0);
-            if (pl && !still_pending) {
-                const int lp = __ffsll((long long)pl) - 1;
-                const int kp = __ffs((int)__shfl((int)pendb, lp)) - 1;
-                const int q = S * lp + kp;
-                pending = true;
-                pend_w = wbuf[q];
-                int lq = 0;
-                uint64_t vb = 0;
-#pragma unroll
-                for (int k = 0; k < S; k++)
-                    if (k == kp) {
-                        lq = len[k];
-                        vb = (uint64_t)__double_as_longlong(val[k]);
-                    }
-                pend_hu = __shfl(lq, lp) < 0;
-                pend_u1 = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)vb, lp)) |
-                          ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(vb >> 32), lp) << 32);
-            }
-            if (still_pending) outb = 0;
-            // ---- compaction: prefix of per-lane counts, values staged in LDS
-            //      in stream order, then coalesced stores ----
-            const int cnt = __popc(outb);
-            int obase = 0, total = 0;
-#pragma unroll
-            for (int bit = 0; bit < 4; bit++) {
-                const uint64_t bb = __ballot((cnt >> bit) & 1);
-                obase += (int)mbcnt64(bb) << bit;
-                total += __popcll(bb) << bit;
-            }
-            double *stage = (double *)wbuf;  // the chunk's words are no longer needed
-            wave_sync();
-            int endq = -1;
-            {
-                int o = obase;
-#pragma unroll
-                for (int k = 0; k < S; k++) {
-                    if ((outb >> k) & 1) {
-                        stage[o] = val[k];
-                        if ((uint64_t)o == need - 1) endq = S * lane + k + len[k];
-                        o++;
-                    }
+                produced += (uint64_t)total;
+                e = 0;
+                if (pend_slot >= 0) {
+                    pending = true;
+                    pend_w = pw;
+                    pend_hu = phu != 0;
+                    pend_u1 = pu1;
+                }
                 }
             }
-            wave_sync();
-            const int nv = (uint64_t)total < need ? total : (int)need;
-            flush_stage<double>(stage, (double *)out + produced, nv, lane);
-            if ((uint64_t)total >= need) {
-                const uint64_t who = __ballot(endq >= 0);
-                const int src = __ffsll((long long)who) - 1;
-                final_pos = base_pos + (uint64_t)__shfl(endq, src);
-                break;
-            }
-            produced += (uint64_t)total;
-            // words of the next chunk already used by the last lane's sample
-            const int last_exit = __shfl(exitw, 63);
-            e = pending ? 0 : last_exit;
         }
         wave_sync();  // the next chunk overwrites wbuf
     }
@@ -1004,8 +973,9 @@ __device__ double zig_serial(const ZigLds *t, E &eng)
         if (DIST == RP_NORM) {
             const uint64_t m = (w >> 9) & ((1ull << 52) - 1);
             const bool neg = (w >> 8) & 1;
-            const double x = (double)m * t->W[j];
-            if (m < t->K[j]) return neg ? -x : x;
+            const WKe e = t->WK[j];
+            const double x = (double)m * e.w;
+            if (m < e.k) return neg ? -x : x;
             if (j == 0) {
                 for (int it = 0; it < kMaxTailIters; it++) {
                     const double e1 = -log1p(-u01_53(eng.next())) / RP_ZN_R;
@@ -1020,8 +990,9 @@ __device__ double zig_serial(const ZigLds *t, E &eng)
             if (wedge_accept<DIST>(t, j, x, eng.next())) return neg ? -x : x;
         } else {
             const uint64_t m = (w >> 8) & ((1ull << 53) - 1);
-            const double x = (double)m * t->W[j];
-            if (m < t->K[j]) return x;
+            const WKe e = t->WK[j];
+            const double x = (double)m * e.w;
+            if (m < e.k) return x;
             if (j == 0) return RP_ZE_R - log1p(-u01_53(eng.next()));
             if (wedge_accept<DIST>(t, j, x, eng.next())) return x;
         }

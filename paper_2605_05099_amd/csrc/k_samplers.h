@@ -197,8 +197,9 @@ __device__ __forceinline__ bool zig_candidate(E &eng, const ZigLds *zt, double &
     const int j = (int)(w & 0xff);
     const uint64_t m = (w >> 9) & ((1ull << 52) - 1);
     const bool neg = (w >> 8) & 1;
-    const double xx = (double)m * zt->W[j];
-    if (m < zt->K[j]) {
+    const WKe e = zt->WK[j];
+    const double xx = (double)m * e.w;
+    if (m < e.k) {
         x = neg ? -xx : xx;
         return true;
     }

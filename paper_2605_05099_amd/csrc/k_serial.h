@@ -185,8 +185,9 @@ __device__ __forceinline__ uint32_t ser_attempt(const SerialArgs &a, const ZigLd
         if constexpr (DIST == RP_NORM) {
             const uint64_t m = (w >> 9) & ((1ull << 52) - 1);
             const bool neg = (w >> 8) & 1;
-            const double x = (double)m * zt->W[j];
-            if (m < zt->K[j]) {
+            const WKe e = zt->WK[j];
+            const double x = (double)m * e.w;
+            if (m < e.k) {
                 acc = true;
                 val = neg ? -x : x;
                 return 1;
@@ -210,8 +211,9 @@ __device__ __forceinline__ uint32_t ser_attempt(const SerialArgs &a, const ZigLd
             return 2;
         } else {
             const uint64_t m = (w >> 8) & ((1ull << 53) - 1);
-            const double x = (double)m * zt->W[j];
-            if (m < zt->K[j]) {
+            const WKe e = zt->WK[j];
+            const double x = (double)m * e.w;
+            if (m < e.k) {
                 acc = true;
                 val = x;
                 return 1;
