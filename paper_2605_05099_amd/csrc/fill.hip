@@ -369,10 +369,10 @@ __device__ __forceinline__ uint32_t mbcnt64(uint64_t mask)
 // when the sample is accepted from this word alone (value in val); otherwise
 // the word starts a wedge test or the tail and needs the next word(s).
 template <int DIST>
-__device__ __forceinline__ bool zig_fast(const ZigLds *t, uint64_t w, double &val)
+__device__ __forceinline__ bool zig_fast(const WKe *wk, uint64_t w, double &val)
 {
     const int j = (int)(w & 0xff);
-    const WKe e = t->WK[j];
+    const WKe e = wk[j];
     if (DIST == RP_NORM) {
         const uint64_t m = (w >> 9) & ((1ull << 52) - 1);
         // m < 2^52: (2^52 + m) - 2^52 is exact; the sign comes from bit 8
@@ -409,9 +409,27 @@ __device__ __forceinline__ void wave_sync()
 // so that their constants do not occupy registers across its chunk loop
 __device__ __noinline__ double exp_ool(double x) { return exp(x); }
 __device__ __noinline__ double log1p_ool(double x) { return log1p(x); }
+// one pair of the normal tail test: accepted iff e2 + e2 > e1 e1; t = r + e1
+__device__ __noinline__ bool normal_tail_pair(uint64_t a, uint64_t b, double &t)
+{
+    const double e1 = -log1p(-u01_53(a)) / RP_ZN_R;
+    const double e2 = -log1p(-u01_53(b));
+    t = RP_ZN_R + e1;
+    return e2 + e2 > e1 * e1;
+}
+
+// wedge-test tables in global memory (read only on the rare wedge path)
+template <int DIST>
+struct ZigG {
+    static __device__ __forceinline__ double F(int j) { return DIST == RP_NORM ? RP_ZN_F[j] : RP_ZE_F[j]; }
+    static __device__ __forceinline__ double X(int j) { return DIST == RP_NORM ? RP_ZN_X[j] : RP_ZE_X[j]; }
+    static __device__ __forceinline__ double S(int j) { return DIST == RP_NORM ? RP_ZN_S[j] : RP_ZE_S[j]; }
+    static __device__ __forceinline__ double DP(int j) { return DIST == RP_NORM ? RP_ZN_DP[j] : RP_ZE_DP[j]; }
+    static __device__ __forceinline__ double DM(int j) { return DIST == RP_NORM ? RP_ZN_DM[j] : RP_ZE_DM[j]; }
+};
 
 template <int DIST, class Word>
-__device__ __forceinline__ int zig_resolve(const ZigLds *t, uint64_t w0, Word word, int avail, bool &accepted,
+__device__ __forceinline__ int zig_resolve(const WKe *t, uint64_t w0, Word word, int avail, bool &accepted,
                                            double &val, bool &has_u1, uint64_t &u1)
 {
     const int j = (int)(w0 & 0xff);
@@ -427,11 +445,12 @@ __device__ __forceinline__ int zig_resolve(const ZigLds *t, uint64_t w0, Word wo
             // the wedge test of wedge_accept, with the exp out of line
             const double ax = DIST == RP_NORM ? fabs(x) : x;
             const double U = u01_53(u);
-            const double fj = t->F[j], fj1 = t->F[j - 1];
+            using G = ZigG<DIST>;
+            const double fj = G::F(j), fj1 = G::F(j - 1);
             const double y = fj + U * (fj1 - fj);
-            const double l = fj1 + t->S[j] * (ax - t->X[j - 1]);
-            if (y < l - t->DM[j]) accepted = true;
-            else if (y > l + t->DP[j]) accepted = false;
+            const double l = fj1 + G::S(j) * (ax - G::X(j - 1));
+            if (y < l - G::DM(j)) accepted = true;
+            else if (y > l + G::DP(j)) accepted = false;
             else accepted = y < exp_ool(DIST == RP_NORM ? -0.5 * ax * ax : -ax);
         } else {
             val = RP_ZE_R - log1p_ool(-u01_53(u));
@@ -448,10 +467,8 @@ __device__ __forceinline__ int zig_resolve(const ZigLds *t, uint64_t w0, Word wo
             }
             return 0;
         }
-        const double e1 = -log1p_ool(-u01_53(word(1 + 2 * it))) / RP_ZN_R;
-        const double e2 = -log1p_ool(-u01_53(word(2 + 2 * it)));
-        if (e2 + e2 > e1 * e1) {
-            const double tt = RP_ZN_R + e1;
+        double tt;
+        if (normal_tail_pair(word(1 + 2 * it), word(2 + 2 * it), tt)) {
             val = ((w0 >> 8) & 1) ? -tt : tt;
             accepted = true;
             return 3 + 2 * it;
@@ -492,7 +509,7 @@ __global__ __launch_bounds__(256) void k_fill_wave(FillArgs a)
     const int lane = threadIdx.x & 63;
     __shared__ __align__(16) uint64_t wbuf_all[4][CHWP];
     uint64_t *const wbuf = wbuf_all[wib];
-    ZigLds *zt = nullptr;
+    const WKe *zt = nullptr;
     uint32_t *slot_pos = nullptr;
     uint16_t *linfo = nullptr;             // long item at a position: length | 0x8000 if it yields a value
     unsigned long long *covl = nullptr;    // per ballot word r: [2r] positions inside other samples,
@@ -500,15 +517,18 @@ __global__ __launch_bounds__(256) void k_fill_wave(FillArgs a)
     unsigned long long *omem = nullptr;    // per ballot word r: positions that yield a value
     uint32_t *pmem = nullptr;              //   and the values before word r
     if constexpr (ZIG) {
-        __shared__ ZigLds zbuf;
+        __shared__ __align__(16) WKe zbuf[256];
         __shared__ uint32_t spos[4][64];
         __shared__ uint16_t linf[4][CHW];
         __shared__ __align__(16) unsigned long long cov[4][2 * R];
         __shared__ unsigned long long omv[4][R];
         __shared__ uint32_t pcv[4][R];
-        load_zig<DIST>(&zbuf);
+        for (int k = threadIdx.x; k < 256; k += blockDim.x) {
+            zbuf[k].w = DIST == RP_NORM ? RP_ZN_W[k] : RP_ZE_W[k];
+            zbuf[k].k = DIST == RP_NORM ? RP_ZN_K[k] : RP_ZE_K[k];
+        }
         __syncthreads();
-        zt = &zbuf;
+        zt = zbuf;
         slot_pos = spos[wib];
         linfo = linf[wib];
         covl = cov[wib];
@@ -643,11 +663,11 @@ __global__ __launch_bounds__(256) void k_fill_wave(FillArgs a)
             //      chunk from position 0. ----
             bool whole = false;  // the carried sample uses the whole chunk
             {
-                double val[R];
                 uint32_t fb = 0, lb = 0;  // per lane: bit r set if position 64 r + lane is a fast / long start
 #pragma unroll
                 for (int r = 0; r < R; r++) {
-                    const bool f = zig_fast<DIST>(zt, w[r], val[r]);
+                    double v0;
+                    const bool f = zig_fast<DIST>(zt, w[r], v0);
                     fb |= (f ? 1u : 0u) << r;
                     lb |= (f ? 0u : 1u) << r;
                 }
@@ -798,7 +818,12 @@ __global__ __launch_bounds__(256) void k_fill_wave(FillArgs a)
                         const uint64_t cv = uni64(c.x), ol = uni64(c.y);
                         const uint64_t fo = __ballot((fb >> r) & 1) & ~cv;
                         const uint64_t om = fo | ol;
-                        if ((fo >> lane) & 1) dst[total + mbcnt64(om)] = val[r];
+                        if ((fo >> lane) & 1) {
+                            // the value again from the word (cheaper than keeping R values live)
+                            double v0;
+                            zig_fast<DIST>(zt, wbuf[wpos(64 * r + lane)], v0);
+                            dst[total + mbcnt64(om)] = v0;
+                        }
                         if (lane == 0) {
                             omem[r] = om;
                             pmem[r] = total;
@@ -822,7 +847,9 @@ __global__ __launch_bounds__(256) void k_fill_wave(FillArgs a)
                         const uint64_t om = fo | ol;
                         if ((fo >> lane) & 1) {
                             const uint32_t idx = total + mbcnt64(om);
-                            if (idx < need) dst[idx] = val[r];
+                            double v0;
+                            zig_fast<DIST>(zt, wbuf[wpos(64 * r + lane)], v0);
+                            if (idx < need) dst[idx] = v0;
                         }
                         if (lane == 0) {
                             omem[r] = om;
