@@ -30,6 +30,22 @@ namespace rp {
 
 namespace {
 
+// 1/a to full binary64 precision without the correctly rounded division
+// sequence: the hardware reciprocal (about 23 good bits) and two Newton
+// steps r <- r + r (1 - a r).  a is finite, nonzero and not subnormal here.
+RP_HD double rcp(double a)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(a);
+    double e = __fma_rn(-a, r, 1.0);
+    r = __fma_rn(r, e, r);
+    e = __fma_rn(-a, r, 1.0);
+    return __fma_rn(r, e, r);
+#else
+    return 1.0 / a;
+#endif
+}
+
 // psi(x), x > 0: shift to x >= 10 by psi(x) = psi(x+1) - 1/x, then the
 // asymptotic series ln x - 1/(2x) - sum_k B_2k / (2k x^2k) (Bernoulli numbers
 // 1/6, -1/30, 1/42, -1/30, 5/66, -691/2730); truncation error below 1e-15.
@@ -37,10 +53,10 @@ RP_HD double digamma(double x)
 {
     double r = 0.0;
     while (x < 10.0) {
-        r -= 1.0 / x;
+        r -= rcp(x);
         x += 1.0;
     }
-    const double i1 = 1.0 / x, i2 = i1 * i1;
+    const double i1 = rcp(x), i2 = i1 * i1;
     const double s = i2 * (1.0 / 12.0 - i2 * (1.0 / 120.0 - i2 * (1.0 / 252.0 - i2 * (1.0 / 240.0 - i2 * (1.0 / 132.0 - i2 * (691.0 / 32760.0))))));
     return r + log(x) - 0.5 * i1 - s;
 }
@@ -53,13 +69,13 @@ RP_HD Dual dmul(Dual x, Dual y) { return {x.v * y.v, x.a * y.v + x.v * y.a, x.b 
 RP_HD Dual dadd(Dual x, Dual y) { return {x.v + y.v, x.a + y.a, x.b + y.b}; }
 RP_HD Dual dinv(Dual x)
 {
-    const double r = 1.0 / x.v, r2 = -r * r;
+    const double r = rcp(x.v), r2 = -r * r;
     return {r, x.a * r2, x.b * r2};
 }
 RP_HD Dual dconst(double v) { return {v, 0.0, 0.0}; }
 
 constexpr double kTiny = 1e-300;
-constexpr double kEps = 1e-16;
+constexpr double kEps = 4e-16;  // a few ulps of 1: the stopping tolerance
 constexpr int kMaxIter = 1 << 16;
 
 RP_HD Dual guard(Dual x)
@@ -95,13 +111,14 @@ RP_HD double gamma_dz_dalpha(double z, double al)
     if (z == 0.0) return 0.0;
     const double lz = log(z);
     if (z < al + 1.0) {
-        double t = 1.0 / al;
+        double t = rcp(al);
         double psi = digamma(al + 1.0);
         double s = t * (lz - psi), sabs = fabs(s);
         for (int n = 1; n < kMaxIter; n++) {
             const double an = al + (double)n;
-            t = t * z / an;
-            psi = psi + 1.0 / an;
+            const double ia = rcp(an);
+            t = t * z * ia;
+            psi = psi + ia;
             const double term = t * (lz - psi);
             s += term;
             sabs += fabs(term);

@@ -160,9 +160,11 @@ __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e
     e = (a - (s - bb)) + (b - bb);
 }
 
-__device__ double boost_pow(double u, double a, double ia)
+// log u as a pair (lh, ll), u > 0 finite, from the 256-entry table: u = 2^e m,
+// m in [1, 2), c the table point of m's top fraction bits, log u =
+// e ln2 + log c + log1p((m - c)/c) with a degree-7 series.
+__device__ __forceinline__ void log_dd(double u, double &lh, double &ll)
 {
-    if (u == 0.0) return 0.0;
     int ex;
     double m = frexp(u, &ex);  // u = m 2^ex, m in [0.5, 1)
     m = m * 2.0;
@@ -177,8 +179,15 @@ __device__ double boost_pow(double u, double a, double ia)
     two_sum((double)ex * RP_LN2_HI, RP_LOG_HI[i], sh, sl);
     two_sum(sh, rh, sh, t);
     sl = sl + t + (((double)ex * RP_LN2_LO + RP_LOG_LO[i]) + (rl + p));
-    const double lh = sh + sl;
-    const double ll = sl - (lh - sh);
+    lh = sh + sl;
+    ll = sl - (lh - sh);
+}
+
+__device__ double boost_pow(double u, double a, double ia)
+{
+    if (u == 0.0) return 0.0;
+    double lh, ll;
+    log_dd(u, lh, ll);
     // t = log(u) / a as th + tl; th need not be the rounded quotient
     const double th = lh * ia;
     const double tl = (__fma_rn(-th, a, lh) + ll) * ia;
