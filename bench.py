@@ -180,6 +180,15 @@ def part_serial(torch, rp, workloads, tm, sp):
         ms = tm(lambda: rp.rp_fill_serial(rng, dist, dtype, 0, 0, buf, n, sp), reps=5)
         ser[name] = {"ms": round(ms, 4), "gsamples_s": round(n / ms / 1e6, 3)}
     out["serial_x256pp_1e6"] = ser
+    # throughput form: the same stream, 2^30 raw words over 2^16 lanes
+    n30 = 2**30
+    big = torch.empty(n30, dtype=torch.int64, device="cuda")
+    rng = rp.rp_create("x256++").seed(workloads.SERIAL_SEED)
+    ms = tm(lambda: rp.rp_fill_serial(rng, rp.RP_RAW, rp.RP_U64, 0, 0, big, n30, sp), reps=3)
+    out["serial_x256pp_2p30_raw"] = {"ms": round(ms, 4), "gsamples_s": round(n30 / ms / 1e6, 2),
+                                     "write_gb_s": round(n30 * 8 / ms / 1e6, 1),
+                                     "hbm_frac": round(n30 * 8 / ms / 1e6 / HBM_PEAK_GBS, 4)}
+    del big
     return out
 
 

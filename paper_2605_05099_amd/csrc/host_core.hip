@@ -1028,7 +1028,7 @@ int advance_words(rp_rng *r, uint64_t w)
 struct SerialTables {
     std::mutex mu;
     uint64_t c_x256 = 0, c_pcg = 0, c_rl = 0;
-    uint64_t x256[280], pcg[48], rl[108];
+    uint64_t x256[304], pcg[72], rl[162];
 } g_ser;
 
 void serial_tables(int engine, uint64_t C, uint64_t *jt)
@@ -1037,7 +1037,7 @@ void serial_tables(int engine, uint64_t C, uint64_t *jt)
     switch (engine) {
     case RP_X256PP:
         if (g_ser.c_x256 != C) {
-            // lanes l < 64: x^(l C) mod P; waves: x^(64 C 2^k), k < 6
+            // lanes l < 64: x^(l C) mod P; waves: x^(64 C 2^k), k < 12
             const Poly &P = x256_charpoly();
             const Poly q = poly_xpow(C, 0, P);
             Poly cur;
@@ -1046,7 +1046,7 @@ void serial_tables(int engine, uint64_t C, uint64_t *jt)
                 memcpy(&g_ser.x256[4 * l], cur.w, 32);
                 cur = poly_mulmod(cur, q, P);
             }
-            for (int k = 0; k < 6; k++) {
+            for (int k = 0; k < 12; k++) {
                 memcpy(&g_ser.x256[256 + 4 * k], cur.w, 32);
                 cur = poly_mulmod(cur, cur, P);
             }
@@ -1056,7 +1056,7 @@ void serial_tables(int engine, uint64_t C, uint64_t *jt)
         break;
     case RP_PCG64:
         if (g_ser.c_pcg != C) {
-            for (int k = 0; k < 12; k++) {
+            for (int k = 0; k < 18; k++) {
                 const PcgAffine m = pcg_power(C << k, k ? C >> (64 - k) : 0);
                 g_ser.pcg[4 * k] = m.mult.lo;
                 g_ser.pcg[4 * k + 1] = m.mult.hi;
@@ -1071,7 +1071,7 @@ void serial_tables(int engine, uint64_t C, uint64_t *jt)
         if (g_ser.c_rl != C) {
             uint64_t e = C / 9, a[9];
             ranlux_pow(ranlux_A(), &e, 1, a);
-            for (int k = 0; k < 12; k++) {
+            for (int k = 0; k < 18; k++) {
                 memcpy(&g_ser.rl[9 * k], a, 72);
                 rl_mulmod(a, a, a);
             }
@@ -1085,9 +1085,12 @@ void serial_tables(int engine, uint64_t C, uint64_t *jt)
 
 void plan_lanes(SerialArgs &a, uint64_t words, int B)
 {
+    // about 256 words per lane for short requests; at most 2^16 lanes (1024
+    // wavefronts) for long ones: each lane writes its own run of the output,
+    // and more concurrent runs cost more in HBM efficiency than they gain
     uint64_t L = (words + 255) / 256;
     if (L < 1) L = 1;
-    if (L > 4096) L = 4096;
+    if (L > (1u << 16)) L = 1u << 16;
     uint64_t C = (words + L - 1) / L;
     C = (C + B - 1) / B * B;
     if (C == 0) C = B;

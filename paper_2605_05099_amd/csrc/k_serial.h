@@ -58,7 +58,7 @@ struct SerLane<RP_X256PP> : LaneX256 {
     {
         X256 b{a.base[0], a.base[1], a.base[2], a.base[3]};
         const uint64_t w = id >> 6;
-        for (int k = 0; k < 6; k++)
+        for (int k = 0; k < 12; k++)
             if ((w >> k) & 1) {
                 const uint64_t *q = &a.jt[256 + 4 * k];
                 b = jump(b, q[0], q[1], q[2], q[3]);
@@ -75,7 +75,7 @@ struct SerLane<RP_PCG64> : LanePcg {
     {
         s = u128{a.base[0], a.base[1]};
         inc = u128{a.base[2], a.base[3]};
-        for (int k = 0; k < 12; k++)
+        for (int k = 0; k < 18; k++)
             if ((id >> k) & 1) {
                 const uint64_t *m = &a.jt[4 * k];
                 s = add128(mul128(u128{m[0], m[1]}, s), mul128(u128{m[2], m[3]}, inc));
@@ -121,7 +121,7 @@ struct SerLane<RP_RANLUX> : LaneRanlux {
     {
 #pragma unroll
         for (int k = 0; k < 9; k++) xp[k] = a.base[k];
-        for (int k = 0; k < 12; k++)
+        for (int k = 0; k < 18; k++)
             if ((id >> k) & 1) {
                 uint64_t m[9];
 #pragma unroll
@@ -147,7 +147,25 @@ __global__ __launch_bounds__(256) void k_ser_gen(SerialArgs a)
     uint64_t w1 = w0 + a.C;
     if (w1 > a.words) w1 = a.words;
     T *out = (T *)a.fa.out;
-    for (uint64_t w = w0; w < w1; w++) {
+    uint64_t w = w0;
+    if constexpr (FIXED && !HALF) {
+        // whole 128-byte runs (16 values) per store burst where they fit
+        if ((((uintptr_t)(out + w)) & 15) == 0) {
+            for (; w + 16 <= w1 && w + 16 <= a.n; w += 16) {
+                T v[16];
+#pragma unroll
+                for (int k = 0; k < 16; k++) item_value<DIST, OT>(g.next(), a.fa, v[k]);
+#pragma unroll
+                for (int k = 0; k < 16; k += 2) {
+                    ulonglong2 q;
+                    q.x = __builtin_bit_cast(uint64_t, v[k]);
+                    q.y = __builtin_bit_cast(uint64_t, v[k + 1]);
+                    *(ulonglong2 *)(out + w + k) = q;
+                }
+            }
+        }
+    }
+    for (; w < w1; w++) {
         const uint64_t word = g.next();
         if constexpr (!FIXED) {
             a.wbuf[w] = word;

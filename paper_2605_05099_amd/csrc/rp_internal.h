@@ -92,7 +92,7 @@ int batched_blocks_for_scan(uint64_t n_sets);
 int batched_buckets();
 
 // serial split of one stream (k_serial.h)
-constexpr int kSerJt = 320;
+constexpr int kSerJt = 304;
 struct SerialArgs {
     uint64_t base[9];      // engine state words at the start (Table 3 order)
     uint32_t phase;        // words used from the current block

@@ -100,3 +100,20 @@ def test_serial_errors():
     before = rng.get_state()
     rp.rp_fill_serial(rng, rp.RP_RAW, rp.RP_U64, 0, 0, t, 0)
     assert rng.get_state() == before
+
+
+@pytest.mark.parametrize("engine", ["x256++", "pcg64", "ranlux++"])
+def test_serial_many_lanes(engine):
+    """2^27 raw words (2^16 lanes, 1024 wavefronts of jump levels) and 2^24
+    normals (about 2^15 chunks of stitching) against the serial stream."""
+    rng = rp.rp_create(engine).seed(5)
+    o = oracle.Stream.seeded(engine, 5)
+    n = 2**27 if engine != "ranlux++" else 2**24
+    got = _gpu(rng, rp.RP_RAW, rp.RP_U64, 0, 0, n)
+    assert np.array_equal(got, o.raw(n))
+    del got
+    _same_state(rng, o)
+    m = 2**24 if engine != "ranlux++" else 2**21
+    got = _gpu(rng, rp.RP_NORM, rp.RP_F64, 0, 0, m)
+    _compare(got, o.norm(m), rp.RP_NORM)
+    _same_state(rng, o)
