@@ -205,15 +205,10 @@ RP_HD void rl_fold(const uint64_t *in, uint64_t *out)
     }
 }
 
-// x = p mod m for an 18-limb product p
-RP_HD void rl_reduce(const uint64_t p[18], uint64_t x[9])
+// out[0..9) = r3 mod m for r3 < 2^576: subtract m once if r3 >= m, tested as
+// "r3 + 2^240 - 1 carries out of 2^576".
+RP_HD void rl_final(const uint64_t r3[9], uint64_t x[9])
 {
-    uint64_t r1[13], r2[10], r3[9];
-    rl_fold<9, 13>(p, r1);
-    rl_fold<4, 10>(r1, r2);
-    rl_fold<1, 9>(r2, r3);
-    // t = r3 + 2^240 - 1; if it carries out of 2^576 then r3 >= m and the
-    // reduced value is t mod 2^576 = r3 - m.
     uint64_t t[9];
     uint64_t carry = 0;
 #pragma unroll
@@ -228,6 +223,16 @@ RP_HD void rl_reduce(const uint64_t p[18], uint64_t x[9])
     }
 #pragma unroll
     for (int k = 0; k < 9; k++) x[k] = carry ? t[k] : r3[k];
+}
+
+// x = p mod m for an 18-limb product p
+RP_HD void rl_reduce(const uint64_t p[18], uint64_t x[9])
+{
+    uint64_t r1[13], r2[10], r3[9];
+    rl_fold<9, 13>(p, r1);
+    rl_fold<4, 10>(r1, r2);
+    rl_fold<1, 9>(r2, r3);
+    rl_final(r3, x);
 }
 
 RP_HD void rl_mul_full(const uint64_t a[9], const uint64_t b[9], uint64_t p[18])
@@ -257,6 +262,67 @@ RP_HD void rl_mulmod(const uint64_t a[9], const uint64_t b[9], uint64_t x[9])
     uint64_t p[18];
     rl_mul_full(a, b, p);
     rl_reduce(p, x);
+}
+
+// ---------------------------------------------------------------------------
+// The generator step x <- A x mod m with the reduction folded into a table.
+// Write x = sum_i x_i 2^(29 i) with 20 limbs x_i of 29 bits (580 >= 576) and
+// let B_i = 2^(29 i) A mod m, itself in 29-bit limbs B_i,j.  Then
+//     A x = sum_j y_j 2^(29 j)  (mod m),   y_j = sum_i x_i B_i,j,
+// and each column sum y_j of 20 products below 2^58 stays below 2^64, so a
+// column is a chain of 32x32->64 multiply-adds with no carry handling.
+// After the carries are propagated the value is below 20 2^29 m < 2^610;
+// one fold of its top word and one of the 0/1 overflow bring it below 2^576
+// and a conditional subtraction of m finishes.  B is stored row-major by
+// output limb: B[j * 20 + i] = B_i,j.
+static constexpr int kRlL = 20;
+static constexpr uint32_t kRlM29 = (1u << 29) - 1;
+
+template <class TAB>
+RP_HD void rl_mul_tab(const uint64_t in[9], TAB *B, uint64_t out[9])
+{
+    uint32_t d[18];
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        d[2 * k] = (uint32_t)in[k];
+        d[2 * k + 1] = (uint32_t)(in[k] >> 32);
+    }
+    uint32_t x[kRlL];
+#pragma unroll
+    for (int i = 0; i < kRlL; i++) {
+        const int p = 29 * i, k = p >> 5, off = p & 31;
+        uint32_t v = d[k] >> off;
+        if (off > 3 && k + 1 < 18) v |= d[k + 1] << (32 - off);
+        x[i] = v & kRlM29;
+    }
+    uint32_t D[20];
+#pragma unroll
+    for (int k = 0; k < 20; k++) D[k] = 0;
+    uint64_t carry = 0;
+#pragma unroll
+    for (int j = 0; j < kRlL; j++) {
+        uint64_t s0 = 0, s1 = 0;
+#pragma unroll
+        for (int i = 0; i < kRlL; i += 2) {
+            s0 += (uint64_t)x[i] * B[j * kRlL + i];
+            s1 += (uint64_t)x[i + 1] * B[j * kRlL + i + 1];
+        }
+        const uint64_t z = s0 + s1 + carry;
+        const uint32_t limb = (uint32_t)z & kRlM29;
+        carry = z >> 29;
+        const int p = 29 * j, k = p >> 5, off = p & 31;
+        D[k] |= limb << off;
+        if (off > 3) D[k + 1] |= limb >> (32 - off);
+    }
+    // carry has weight 2^580 = bit 4 of dword 18
+    D[18] |= (uint32_t)carry << 4;
+    D[19] |= (uint32_t)(carry >> 28);
+    uint64_t p[10], r2[10], r3[9];
+#pragma unroll
+    for (int q = 0; q < 10; q++) p[q] = D[2 * q] | ((uint64_t)D[2 * q + 1] << 32);
+    rl_fold<1, 10>(p, r2);
+    rl_fold<1, 9>(r2, r3);
+    rl_final(r3, out);
 }
 
 }  // namespace rp

@@ -40,7 +40,7 @@ struct PcgAffineDev {
 };
 __constant__ PcgAffineDev c_pcg_lane[65];  // A^(8l), G_(8l) for l = 0..64 (8 words per lane)
 __constant__ PcgAffineDev c_pcg_pow2[64];  // A^(2^k), G_(2^k)
-__constant__ uint64_t c_rl_A[9];           // ranlux++ step multiplier a^2048 mod m
+__constant__ uint32_t c_rl_B[kRlL * kRlL];  // ranlux++ folded step table (rl_mul_tab)
 
 static PcgAffineDev to_dev(const PcgAffine &p) { return {p.mult.lo, p.mult.hi, p.plus.lo, p.plus.hi}; }
 
@@ -76,7 +76,7 @@ int ensure_device_tables()
     }
     e = hipMemcpyToSymbol(HIP_SYMBOL(c_pcg_lane), lane, sizeof lane);
     if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_pcg_pow2), pow2, sizeof pow2);
-    if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_rl_A), ranlux_A(), 9 * 8);
+    if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_rl_B), ranlux_B(), sizeof c_rl_B);
     if (e != hipSuccess) return fail(RP_EDEVICE, "uploading constant tables: %s", hipGetErrorString(e));
     done[dev] = true;
     return RP_OK;
@@ -900,6 +900,7 @@ struct LaneX256 {
         s = X256{a.words[i], a.words[a.n + i], a.words[2 * a.n + i], a.words[3 * a.n + i]};
     }
     __device__ uint64_t next() { return s.next(); }
+    __device__ void reserve(int) {}
     __device__ void store(const FillArgs &a, uint64_t i) const
     {
         a.words[i] = s.s0;
@@ -916,6 +917,7 @@ struct LaneSfc64 {
         s = Sfc64{a.words[i], a.words[a.n + i], a.words[2 * a.n + i], a.words[3 * a.n + i]};
     }
     __device__ uint64_t next() { return s.next(); }
+    __device__ void reserve(int) {}
     __device__ void store(const FillArgs &a, uint64_t i) const
     {
         a.words[i] = s.a;
@@ -935,20 +937,46 @@ __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0; }
 
 // ranlux++: state (x, phase); the current block is the nine limbs of A x, of
 // which `phase` words are used.  Here: cur = A xp, nxt = A cur when hn.
+//
+// The step is computed in two places.  reserve(k), called by the kernels at
+// points every active lane reaches, gives each lane at least k words: as
+// soon as one lane is short, every lane without a next block computes it
+// (inline, one copy per call site), so a wavefront pays about one step per
+// nine words.  next() only falls back to an out-of-line step when a caller
+// took more words than it reserved (rejection loops that run long).
+typedef const __attribute__((address_space(4))) uint32_t RlTab;
+
+__device__ __forceinline__ void rl_step_inline(const uint64_t *in, uint64_t *out)
+{
+    // an opaque copy of the table address keeps its scalar loads here
+    // instead of hoisted (and spilled) across the kernel's loops
+    RlTab *B = (RlTab *)c_rl_B;
+    asm volatile("" : "+s"(B));
+    rl_mul_tab(in, B, out);
+}
+
+struct Rl9 {
+    uint64_t w[9];
+};
+__device__ __noinline__ Rl9 rl_step_call(Rl9 x)
+{
+    Rl9 y;
+    rl_step_inline(x.w, y.w);
+    return y;
+}
+
 struct LaneRanlux {
     uint64_t xp[9], cur[9], nxt[9];
     int used;  // words of cur already returned (0..9)
     bool hn;   // nxt holds A cur
-    __device__ static void mul_A(const uint64_t *in, uint64_t *out)
-    {
-        uint64_t A[9];
-#pragma unroll
-        for (int k = 0; k < 9; k++) A[k] = c_rl_A[k];
-        rl_mulmod(in, A, out);
-    }
     __device__ void start(int phase)
     {
-        mul_A(xp, cur);
+        Rl9 x;
+#pragma unroll
+        for (int k = 0; k < 9; k++) x.w[k] = xp[k];
+        const Rl9 y = rl_step_call(x);
+#pragma unroll
+        for (int k = 0; k < 9; k++) cur[k] = y.w[k];
         used = phase;
         hn = false;
     }
@@ -958,15 +986,26 @@ struct LaneRanlux {
         for (int k = 0; k < 9; k++) xp[k] = a.words[(uint64_t)k * a.n + i];
         start((int)a.phase[i]);
     }
-    __device__ uint64_t next()
+    __device__ void reserve(int k)
     {
-        if (wave_any(used == 9 && !hn)) {
+        if (wave_any(!hn && used > 9 - k)) {
             if (!hn) {
-                mul_A(cur, nxt);
+                rl_step_inline(cur, nxt);
                 hn = true;
             }
         }
+    }
+    __device__ uint64_t next()
+    {
         if (used == 9) {
+            if (!hn) {
+                Rl9 x;
+#pragma unroll
+                for (int k = 0; k < 9; k++) x.w[k] = cur[k];
+                const Rl9 y = rl_step_call(x);
+#pragma unroll
+                for (int k = 0; k < 9; k++) nxt[k] = y.w[k];
+            }
 #pragma unroll
             for (int k = 0; k < 9; k++) {
                 xp[k] = cur[k];
@@ -1049,8 +1088,10 @@ __global__ __launch_bounds__(256) void k_fill_lane(FillArgs a)
     uint32_t hi = 0;
     for (uint64_t t = 0; t < P;) {
         if constexpr (ZIG) {
+            eng.reserve(3);
             out[t++] = zig_serial<DIST>(zt, eng);
         } else {
+            eng.reserve(1);
             uint64_t it;
             if constexpr (HALF) {
                 if (have) {

@@ -220,6 +220,29 @@ const uint64_t *ranlux_A()
     });
     return g_rl_A;
 }
+
+// B[j * 20 + i] = limb j (29 bits) of 2^(29 i) A mod m, the table of the
+// folded generator step (engines.h)
+const uint32_t *ranlux_B()
+{
+    static uint32_t B[kRlL * kRlL];
+    static std::once_flag once;
+    std::call_once(once, [] {
+        const uint64_t *A = ranlux_A();
+        for (int i = 0; i < kRlL; i++) {
+            uint64_t t[9] = {0}, y[9];
+            t[(29 * i) / 64] = 1ull << ((29 * i) % 64);
+            rl_mulmod(A, t, y);
+            for (int j = 0; j < kRlL; j++) {
+                const int p = 29 * j, w = p / 64, off = p % 64;
+                uint64_t v = y[w] >> off;
+                if (off > 35 && w + 1 < 9) v |= y[w + 1] << (64 - off);
+                B[j * kRlL + i] = (uint32_t)(v & kRlM29);
+            }
+        }
+    });
+    return B;
+}
 }  // namespace rp
 
 // base^e (e given as 64-bit limbs, little-endian) mod m
@@ -429,7 +452,7 @@ static uint64_t host_next(rp_rng *r)
     }
     case RP_RANLUX: {
         uint64_t y[9];
-        rl_mulmod(st, ranlux_A(), y);
+        rl_mul_tab(st, ranlux_B(), y);
         uint64_t w = y[r->phase];
         if (++r->phase == 9) {
             r->phase = 0;

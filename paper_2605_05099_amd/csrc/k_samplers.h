@@ -27,6 +27,7 @@ struct LanePhilox32 {
         philox4x32(clo, chi, key, c0, c1);
         hn = false;
     }
+    __device__ void reserve(int) {}
     __device__ void load(const FillArgs &a, uint64_t i)
     {
         start(a.words[i], a.words[a.n + i], a.words[2 * a.n + i], a.phase[i]);
@@ -83,6 +84,7 @@ struct LanePhilox64 {
         philox4x64(c, k0, k1, b);
         hn = false;
     }
+    __device__ void reserve(int) {}
     __device__ void load(const FillArgs &a, uint64_t i)
     {
 #pragma unroll
@@ -128,6 +130,7 @@ struct LanePhilox64 {
 
 struct LanePcg {
     u128 s, inc;
+    __device__ void reserve(int) {}
     __device__ void load(const FillArgs &a, uint64_t i)
     {
         s = u128{a.words[i], a.words[a.n + i]};
@@ -231,6 +234,51 @@ __device__ __forceinline__ bool zig_candidate(E &eng, const ZigLds *zt, double &
     return false;
 }
 
+// The normal ziggurat as a step machine: a step takes at most two words (a
+// candidate and its wedge word, or one tail pair) and either yields a value
+// or leaves the machine where the serial sampler would continue.  Kernels
+// that loop over steps can therefore reserve two words per step.
+struct NormMachine {
+    int tail;  // tail pairs taken for the current candidate, -1 outside the tail
+    bool neg;
+    __device__ void reset() { tail = -1; }
+    template <class E>
+    __device__ __forceinline__ bool step(E &eng, const ZigLds *zt, double &x)
+    {
+        if (tail >= 0) {
+            const double e1 = -log1p(-u01_53(eng.next())) / RP_ZN_R;
+            const double e2 = -log1p(-u01_53(eng.next()));
+            if (e2 + e2 > e1 * e1) {
+                tail = -1;
+                const double t = RP_ZN_R + e1;
+                x = neg ? -t : t;
+                return true;
+            }
+            if (++tail == kMaxTailIters) tail = -1;
+            return false;
+        }
+        const uint64_t w = eng.next();
+        const int j = (int)(w & 0xff);
+        const uint64_t m = (w >> 9) & ((1ull << 52) - 1);
+        neg = (w >> 8) & 1;
+        const WKe e = zt->WK[j];
+        const double xx = (double)m * e.w;
+        if (m < e.k) {
+            x = neg ? -xx : xx;
+            return true;
+        }
+        if (j == 0) {
+            tail = 0;
+            return false;
+        }
+        if (wedge_accept<RP_NORM>(zt, j, xx, eng.next())) {
+            x = neg ? -xx : xx;
+            return true;
+        }
+        return false;
+    }
+};
+
 // Marsaglia-Tsang constants of one shape: d = s - 1/3, c = 1/sqrt(9 d) for
 // s = a (a >= 1) or s = a + 1 followed by the boost U^(1/a) (a < 1).
 struct GamParam {
@@ -271,6 +319,7 @@ struct GamMachine {
     template <class E>
     __device__ __forceinline__ bool step(E &eng, const ZigLds *zt, double &val)
     {
+        eng.reserve(4);  // candidate, wedge word, uniform, boost uniform
         const bool sb = BETA && second;
         const double d = sb ? pb.d : pa.d, c = sb ? pb.c : pa.c;
         double x;
@@ -314,11 +363,17 @@ __global__ __launch_bounds__(256) void k_norm_moments(SampArgs s)
     if (i >= s.count) return;
     E eng;
     eng.load(s.f, i);
+    NormMachine nm;
+    nm.reset();
     double a = 0.0, q = 0.0;
-    for (uint64_t t = 0; t < s.f.per_stream; t++) {
-        const double x = zig_serial<RP_NORM>(&zt, eng);
-        a = a + x;
-        q = q + x * x;
+    for (uint64_t t = 0; t < s.f.per_stream;) {
+        eng.reserve(2);
+        double x;
+        if (nm.step(eng, &zt, x)) {
+            a = a + x;
+            q = q + x * x;
+            t++;
+        }
     }
     s.sum[i] = a;
     s.sumsq[i] = q;
@@ -380,6 +435,7 @@ __global__ __launch_bounds__(256) void k_norm_rows(SampArgs s)
     if ((d & 3) == 0) {
         for (uint64_t t = 0; t < d; t += 4) {
             float4 v;
+            eng.reserve(9);  // four normals rarely take more than nine words
             v.x = (float)zig_serial<RP_NORM>(&zt, eng);
             v.y = (float)zig_serial<RP_NORM>(&zt, eng);
             v.z = (float)zig_serial<RP_NORM>(&zt, eng);
@@ -387,7 +443,10 @@ __global__ __launch_bounds__(256) void k_norm_rows(SampArgs s)
             *(float4 *)(row + t) = v;
         }
     } else {
-        for (uint64_t t = 0; t < d; t++) row[t] = (float)zig_serial<RP_NORM>(&zt, eng);
+        for (uint64_t t = 0; t < d; t++) {
+            eng.reserve(3);
+            row[t] = (float)zig_serial<RP_NORM>(&zt, eng);
+        }
     }
     if (s.advance) eng.store(s.f, i);
 }

@@ -154,7 +154,10 @@ __global__ __launch_bounds__(256) void k_ser_gen(SerialArgs a)
             for (; w + 16 <= w1 && w + 16 <= a.n; w += 16) {
                 T v[16];
 #pragma unroll
-                for (int k = 0; k < 16; k++) item_value<DIST, OT>(g.next(), a.fa, v[k]);
+                for (int k = 0; k < 16; k++) {
+                    if (k % 8 == 0) g.reserve(8);
+                    item_value<DIST, OT>(g.next(), a.fa, v[k]);
+                }
 #pragma unroll
                 for (int k = 0; k < 16; k += 2) {
                     ulonglong2 q;
@@ -166,6 +169,7 @@ __global__ __launch_bounds__(256) void k_ser_gen(SerialArgs a)
         }
     }
     for (; w < w1; w++) {
+        g.reserve(1);
         const uint64_t word = g.next();
         if constexpr (!FIXED) {
             a.wbuf[w] = word;

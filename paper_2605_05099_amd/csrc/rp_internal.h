@@ -38,6 +38,7 @@ int fail(int code, const char *fmt, ...);
 
 // ranlux++ multiplier A = a^2048 mod m and its power table (host)
 const uint64_t *ranlux_A();
+const uint32_t *ranlux_B();
 
 // PCG64 power tables: A^k and G_k = 1 + A + ... + A^(k-1) (mod 2^128)
 struct PcgAffine {

@@ -154,3 +154,40 @@ def test_cholesky_errors():
         with pytest.raises(rp.RpError) as ei:
             rp.rp_cholesky(bad)
         assert ei.value.code == rp.RP_ENOTSPD
+
+
+RL_M = 2**576 - 2**240 + 1
+
+
+def _rl_words(x):
+    return [(x >> (64 * k)) & (2**64 - 1) for k in range(9)]
+
+
+def _rl_value(words):
+    return sum(int(w) << (64 * k) for k, w in enumerate(words))
+
+
+@pytest.mark.parametrize("x", [1, 2, RL_M - 1, RL_M - 2, 2**575, 2**551 - 1, 2**551, 2**240 - 1, 2**240,
+                               (RL_M - 1) // 3, 2**576 - 2**241])
+def test_ranlux_step_edge_states(x):
+    """The folded-table step (29-bit limbs) against the oracle on states that
+    stress the folds: near m, powers of two at limb and fold boundaries."""
+    r = rp.rp_create("ranlux++").set_state(_rl_words(x))
+    o = oracle.Stream.from_state("ranlux++", _rl_words(x))
+    assert (r.raw_host(9 * 30) == o.raw(9 * 30)).all()
+
+
+def test_ranlux_step_is_power_of_the_lcg_multiplier():
+    """From state 1 block k is A^k mod m with A = a^2048, a = m - (m - 1)/2^24
+    (ranlux++ as the LCG equivalent of RANLUX, b = 2^24, r = 24)."""
+    a = RL_M - (RL_M - 1) // 2**24
+    A = pow(a, 2048, RL_M)
+    w = rp.rp_create("ranlux++").set_state(_rl_words(1)).raw_host(9 * 50)
+    for k in range(50):
+        assert _rl_value(w[9 * k: 9 * k + 9]) == pow(A, k + 1, RL_M)
+
+
+def test_ranlux_long_host_draw_matches_oracle():
+    r = rp.rp_create("ranlux++").seed(2024)
+    o = oracle.Stream.seeded("ranlux++", 2024)
+    assert (r.raw_host(9 * 3000 + 5) == o.raw(9 * 3000 + 5)).all()
