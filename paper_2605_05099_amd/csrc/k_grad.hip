@@ -190,35 +190,173 @@ RP_HD void beta_dz_dab(double z, double a, double b, double &ga, double &gb)
     }
 }
 
-__global__ __launch_bounds__(256) void k_gamma_grad(const float *z, const float *al, const float *gz, float *ga,
-                                                     uint64_t n)
+// ---------------------------------------------------------------------------
+// Work keys.  The cost of an element is the length of its series or
+// continued fraction, which varies by more than an order of magnitude over
+// the parameter range; a wavefront runs as long as its slowest lane.  Each
+// block therefore loads a tile of elements, orders it by a 6-bit key that
+// predicts the loop length, and gives every wavefront 64 consecutive
+// elements in that order.  The key only changes which lanes evaluate which
+// elements together, never a result.
+
+// Gamma: the series (z < alpha + 1) needs about n terms where the term ratio
+// product falls below 1e-16, n ln((alpha + n/2) / z) = 36, solved by a few
+// fixed-point steps; the continued fraction (z >= alpha + 1 > 1) converges
+// more slowly the smaller z is.
+// a / b from the hardware reciprocal: keys need no correctly rounded quotient
+__device__ __forceinline__ float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
+__device__ __forceinline__ int gamma_key(float zf, float af)
 {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const double d = gamma_dz_dalpha((double)z[i], (double)al[i]);
-        ga[i] = (float)((double)gz[i] * d);
+    if (!(af > 0.f) || !(zf > 0.f) || !(zf < INFINITY)) return 0;
+    if (zf < af + 1.f) {
+        float nn = 8.f;
+#pragma unroll
+        for (int k = 0; k < 4; k++) nn = fminf(qdiv(36.f, fmaxf(__logf(qdiv(af + 0.5f * nn, zf)), 1e-3f)), 4096.f);
+        return min(31, (int)(4.f * __log2f(nn + 1.f)));
+    }
+    return 32 + min(31, max(0, (int)(4.f * __log2f(zf))));
+}
+
+// Beta: after the symmetry switch the continued fraction runs at x < (p+1) /
+// (p+q+2).  Its partial numerators tend to -x/4, and with them the error
+// ratio per step to rho(x) = (1 - sqrt(1-x)) / (1 + sqrt(1-x)); the first
+// numerator is about r = x (p+q+2) / (p+1), so the pair count is predicted
+// from rho(r): ln(1e-16) / (2 ln rho).
+__device__ __forceinline__ int beta_key(float zf, float af, float bf)
+{
+    if (!(af > 0.f) || !(bf > 0.f) || !(zf > 0.f) || !(zf < 1.f)) return 0;
+    const bool sw = !(zf < qdiv(af + 1.f, af + bf + 2.f));
+    const float p = sw ? bf : af, q = sw ? af : bf, x = sw ? 1.f - zf : zf;
+    const float r = fminf(qdiv(x * (p + q + 2.f), p + 1.f), 0.999999f);
+    const float sq = sqrtf(1.f - r);
+    const float rho = qdiv(1.f - sq, 1.f + sq);
+    const float nn = 1.f + qdiv(18.42f, fmaxf(-__logf(fmaxf(rho, 1e-30f)), 1e-6f));
+    return min(63, max(0, (int)(8.f * __log2f(nn))));
+}
+
+constexpr int kGradBlock = 256;
+
+// The per-element evaluations out of line, so the tile bookkeeping and the
+// series/continued-fraction loops do not share one register allocation.
+struct D2 {
+    double a, b;
+};
+__device__ __noinline__ double gamma_elem(double z, double al) { return gamma_dz_dalpha(z, al); }
+__device__ __noinline__ D2 beta_elem(double z, double a, double b)
+{
+    D2 r;
+    beta_dz_dab(z, a, b, r.a, r.b);
+    return r;
+}
+
+// One tile of TILE elements per iteration: coalesced loads into LDS, a
+// counting sort of the element indices by key, evaluation in key order
+// (results back into LDS at the element's own slot), coalesced stores.
+// Inputs are read in full before any output of the tile is written, so the
+// outputs may alias the inputs.
+template <bool BETA, int TILE>
+__global__ __launch_bounds__(kGradBlock) void k_grad_sorted(const float *z, const float *pa, const float *pb,
+                                                            const float *gz, float *ga, float *gb, uint64_t n)
+{
+    constexpr int K = TILE / kGradBlock;
+    __shared__ float s_z[TILE], s_a[TILE], s_b[BETA ? TILE : 1], s_g[TILE];
+    __shared__ uint16_t s_perm[TILE];
+    __shared__ uint32_t s_cnt[64];
+    const int tid = threadIdx.x;
+    for (uint64_t base = (uint64_t)blockIdx.x * TILE; base < n; base += (uint64_t)gridDim.x * TILE) {
+        const int cnt = (int)((n - base) < (uint64_t)TILE ? (n - base) : (uint64_t)TILE);
+        if (tid < 64) s_cnt[tid] = 0;
+        __syncthreads();
+        float zf[K], af[K], bf[K], gf[K];
+        if (cnt == TILE) {  // all loads of a full tile in flight together
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                const uint64_t i = base + k * kGradBlock + tid;
+                zf[k] = z[i];
+                af[k] = pa[i];
+                bf[k] = BETA ? pb[i] : 0.f;
+                gf[k] = gz[i];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                const int e = k * kGradBlock + tid;
+                const uint64_t i = base + (e < cnt ? e : 0);
+                zf[k] = z[i];
+                af[k] = pa[i];
+                bf[k] = BETA ? pb[i] : 0.f;
+                gf[k] = gz[i];
+            }
+        }
+        int key[K];
+        uint32_t rank[K];
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            const int e = k * kGradBlock + tid;
+            if (e < cnt) {
+                s_z[e] = zf[k];
+                s_a[e] = af[k];
+                if (BETA) s_b[e] = bf[k];
+                s_g[e] = gf[k];
+                key[k] = BETA ? beta_key(zf[k], af[k], bf[k]) : gamma_key(zf[k], af[k]);
+                rank[k] = atomicAdd(&s_cnt[key[k]], 1u);
+            }
+        }
+        __syncthreads();
+        if (tid < 64) {  // exclusive scan of the 64 bucket sizes (one wavefront)
+            const uint32_t c = s_cnt[tid];
+            uint32_t v = c;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t u = __shfl_up(v, d, 64);
+                if (tid >= d) v += u;
+            }
+            s_cnt[tid] = v - c;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            const int e = k * kGradBlock + tid;
+            if (e < cnt) s_perm[s_cnt[key[k]] + rank[k]] = (uint16_t)e;
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int k = 0; k < K; k++) {
+            const int q = k * kGradBlock + tid;
+            if (q < cnt) {
+                const int e = s_perm[q];
+                const double g = (double)s_g[e];
+                if (BETA) {
+                    const D2 d = beta_elem((double)s_z[e], (double)s_a[e], (double)s_b[e]);
+                    s_a[e] = (float)(g * d.a);
+                    s_b[e] = (float)(g * d.b);
+                } else {
+                    const double d = gamma_elem((double)s_z[e], (double)s_a[e]);
+                    s_a[e] = (float)(g * d);
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            const int e = k * kGradBlock + tid;
+            if (e < cnt) {
+                ga[base + e] = s_a[e];
+                if (BETA) gb[base + e] = s_b[e];
+            }
+        }
+        __syncthreads();
     }
 }
 
-__global__ __launch_bounds__(256) void k_beta_grad(const float *z, const float *pa, const float *pb, const float *gz,
-                                                    float *ga, float *gb, uint64_t n)
-{
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        double da, db;
-        beta_dz_dab((double)z[i], (double)pa[i], (double)pb[i], da, db);
-        const double g = (double)gz[i];
-        ga[i] = (float)(g * da);
-        gb[i] = (float)(g * db);
-    }
-}
+constexpr int kGammaTile = 2048, kBetaTile = 1024;
 
-unsigned grid_for(uint64_t n)
+unsigned grid_for(uint64_t n, int tile)
 {
-    const uint64_t b = (n + 255) / 256;
-    return (unsigned)(b < (1u << 20) ? b : (1u << 20));
+    const uint64_t b = (n + tile - 1) / tile;
+    return (unsigned)(b < 4096 ? b : 4096);
 }
-
 bool aligned4(const void *p) { return ((uintptr_t)p & 3) == 0; }
 
 }  // namespace
@@ -234,8 +372,8 @@ extern "C" int rp_gamma_grad(const float *d_z, const float *d_alpha, const float
     if (!d_z || !d_alpha || !d_gz || !d_galpha) return fail(RP_ENULL, "rp_gamma_grad: NULL device pointer");
     if (!aligned4(d_z) || !aligned4(d_alpha) || !aligned4(d_gz) || !aligned4(d_galpha))
         return fail(RP_EINVAL, "rp_gamma_grad: pointers not aligned to 4 bytes");
-    hipLaunchKernelGGL(k_gamma_grad, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)hip_stream, d_z, d_alpha, d_gz,
-                       d_galpha, n);
+    hipLaunchKernelGGL((k_grad_sorted<false, kGammaTile>), dim3(grid_for(n, kGammaTile)), dim3(kGradBlock), 0,
+                       (hipStream_t)hip_stream, d_z, d_alpha, (const float *)nullptr, d_gz, d_galpha, (float *)nullptr, n);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? RP_OK : fail(RP_EDEVICE, "rp_gamma_grad launch: %s", hipGetErrorString(e));
 }
@@ -247,8 +385,8 @@ extern "C" int rp_beta_grad(const float *d_z, const float *d_a, const float *d_b
     if (!d_z || !d_a || !d_b || !d_gz || !d_ga || !d_gb) return fail(RP_ENULL, "rp_beta_grad: NULL device pointer");
     if (!aligned4(d_z) || !aligned4(d_a) || !aligned4(d_b) || !aligned4(d_gz) || !aligned4(d_ga) || !aligned4(d_gb))
         return fail(RP_EINVAL, "rp_beta_grad: pointers not aligned to 4 bytes");
-    hipLaunchKernelGGL(k_beta_grad, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)hip_stream, d_z, d_a, d_b, d_gz,
-                       d_ga, d_gb, n);
+    hipLaunchKernelGGL((k_grad_sorted<true, kBetaTile>), dim3(grid_for(n, kBetaTile)), dim3(kGradBlock), 0,
+                       (hipStream_t)hip_stream, d_z, d_a, d_b, d_gz, d_ga, d_gb, n);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? RP_OK : fail(RP_EDEVICE, "rp_beta_grad launch: %s", hipGetErrorString(e));
 }
