@@ -75,7 +75,11 @@ RP_HD Dual dinv(Dual x)
 RP_HD Dual dconst(double v) { return {v, 0.0, 0.0}; }
 
 constexpr double kTiny = 1e-300;
-constexpr double kEps = 4e-16;  // a few ulps of 1: the stopping tolerance
+// Stopping tolerance 2^-36: the result is rounded to binary32 (relative
+// spacing 2^-23), so a relative truncation error of a few times 2^-36, even
+// after the slowest geometric tails, stays three orders below the output
+// rounding.  Tighter stopping only adds iterations.
+constexpr double kEps = 0x1p-36;
 constexpr int kMaxIter = 1 << 16;
 
 RP_HD Dual guard(Dual x)
@@ -200,7 +204,7 @@ RP_HD void beta_dz_dab(double z, double a, double b, double &ga, double &gb)
 // elements together, never a result.
 
 // Gamma: the series (z < alpha + 1) needs about n terms where the term ratio
-// product falls below 1e-16, n ln((alpha + n/2) / z) = 36, solved by a few
+// product falls below 2^-38, n ln((alpha + n/2) / z) = 26, solved by a few
 // fixed-point steps; the continued fraction (z >= alpha + 1 > 1) converges
 // more slowly the smaller z is.
 // a / b from the hardware reciprocal: keys need no correctly rounded quotient
@@ -212,7 +216,7 @@ __device__ __forceinline__ int gamma_key(float zf, float af)
     if (zf < af + 1.f) {
         float nn = 8.f;
 #pragma unroll
-        for (int k = 0; k < 4; k++) nn = fminf(qdiv(36.f, fmaxf(__logf(qdiv(af + 0.5f * nn, zf)), 1e-3f)), 4096.f);
+        for (int k = 0; k < 4; k++) nn = fminf(qdiv(26.f, fmaxf(__logf(qdiv(af + 0.5f * nn, zf)), 1e-3f)), 4096.f);
         return min(31, (int)(4.f * __log2f(nn + 1.f)));
     }
     return 32 + min(31, max(0, (int)(4.f * __log2f(zf))));
@@ -222,7 +226,7 @@ __device__ __forceinline__ int gamma_key(float zf, float af)
 // (p+q+2).  Its partial numerators tend to -x/4, and with them the error
 // ratio per step to rho(x) = (1 - sqrt(1-x)) / (1 + sqrt(1-x)); the first
 // numerator is about r = x (p+q+2) / (p+1), so the pair count is predicted
-// from rho(r): ln(1e-16) / (2 ln rho).
+// from rho(r): ln(2^-36) / (2 ln rho).
 __device__ __forceinline__ int beta_key(float zf, float af, float bf)
 {
     if (!(af > 0.f) || !(bf > 0.f) || !(zf > 0.f) || !(zf < 1.f)) return 0;
@@ -231,7 +235,7 @@ __device__ __forceinline__ int beta_key(float zf, float af, float bf)
     const float r = fminf(qdiv(x * (p + q + 2.f), p + 1.f), 0.999999f);
     const float sq = sqrtf(1.f - r);
     const float rho = qdiv(1.f - sq, 1.f + sq);
-    const float nn = 1.f + qdiv(18.42f, fmaxf(-__logf(fmaxf(rho, 1e-30f)), 1e-6f));
+    const float nn = 1.f + qdiv(12.5f, fmaxf(-__logf(fmaxf(rho, 1e-30f)), 1e-6f));
     return min(63, max(0, (int)(8.f * __log2f(nn))));
 }
 
@@ -243,7 +247,7 @@ struct D2 {
     double a, b;
 };
 __device__ __noinline__ double gamma_elem(double z, double al) { return gamma_dz_dalpha(z, al); }
-__device__ __noinline__ D2 beta_elem(double z, double a, double b)
+__device__ __forceinline__ D2 beta_elem(double z, double a, double b)
 {
     D2 r;
     beta_dz_dab(z, a, b, r.a, r.b);
@@ -256,7 +260,7 @@ __device__ __noinline__ D2 beta_elem(double z, double a, double b)
 // Inputs are read in full before any output of the tile is written, so the
 // outputs may alias the inputs.
 template <bool BETA, int TILE>
-__global__ __launch_bounds__(kGradBlock) void k_grad_sorted(const float *z, const float *pa, const float *pb,
+__global__ __launch_bounds__(kGradBlock, BETA ? 4 : 5) void k_grad_sorted(const float *z, const float *pa, const float *pb,
                                                             const float *gz, float *ga, float *gb, uint64_t n)
 {
     constexpr int K = TILE / kGradBlock;
