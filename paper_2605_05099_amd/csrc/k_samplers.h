@@ -279,6 +279,28 @@ struct NormMachine {
     }
 };
 
+// The Marsaglia-Tsang test log u < x^2/2 + d (1 - v + log v), decided first
+// with the binary32 hardware logarithm (log2, an ulp or two) of u and v.  Its
+// error, with that of rounding u and v to binary32, is below 2^-16 (1 + |log|)
+// for either logarithm, and the binary64 evaluation of the right-hand side
+// errs by far less than 1e-13 (x^2 + d (1 + v)).  When the two sides are
+// further apart than the sum of these bounds the binary64 test can only
+// agree; otherwise (a few attempts in 10^5) the binary64 logarithms decide,
+// exactly as written.  About one attempt in twelve reaches this test, so a
+// wavefront meets it at almost every step: the bound saves the two binary64
+// logarithms there.
+__device__ __forceinline__ bool mt_log_test(double u, double x2, double v, double d)
+{
+    constexpr double kLn2 = 0x1.62e42fefa39efp-1;
+    const double lu = (double)__builtin_amdgcn_logf((float)u) * kLn2;
+    const double lv = (double)__builtin_amdgcn_logf((float)v) * kLn2;
+    const double r = 0.5 * x2 + d * ((1.0 - v) + lv);
+    const double e = 0x1p-16 * (1.0 + fabs(lu) + d * (1.0 + fabs(lv))) + 1e-13 * (x2 + d * (1.0 + v));
+    if (lu < r - e) return true;
+    if (lu > r + e) return false;
+    return log(u) < 0.5 * x2 + d * ((1.0 - v) + log(v));
+}
+
 // Marsaglia-Tsang constants of one shape: d = s - 1/3, c = 1/sqrt(9 d) for
 // s = a (a >= 1) or s = a + 1 followed by the boost U^(1/a) (a < 1).
 struct GamParam {
@@ -330,7 +352,7 @@ struct GamMachine {
         const double u = u01_53(eng.next());
         const double x2 = x * x;
         bool acc = u < 1.0 - 0.0331 * (x2 * x2);
-        if (!acc) acc = log(u) < 0.5 * x2 + d * ((1.0 - v) + log(v));
+        if (!acc) acc = mt_log_test(u, x2, v, d);
         if (!acc) return false;
         double g = d * v;
         if (sb ? pb.boost : pa.boost) {
