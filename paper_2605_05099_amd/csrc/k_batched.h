@@ -158,7 +158,9 @@ template <class E, bool BETA>
 __global__ __launch_bounds__(256) void k_batched(BatchArgs a)
 {
     __shared__ ZigLds zt;
+    __shared__ LogLds lt;
     load_zig<RP_NORM>(&zt);
+    load_logt(&lt);
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const uint64_t n = a.n_sets;
@@ -204,7 +206,7 @@ __global__ __launch_bounds__(256) void k_batched(BatchArgs a)
                     out[t++] = __builtin_nan("");
                 } else {
                     double v;
-                    if (gm.step(eng, &zt, v)) out[t++] = v;
+                    if (gm.step(eng, &zt, &lt, v)) out[t++] = v;
                 }
             } else {
                 if (!bad) eng.store(a.f, j);

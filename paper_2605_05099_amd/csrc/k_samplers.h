@@ -163,34 +163,49 @@ __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e
     e = (a - (s - bb)) + (b - bb);
 }
 
+// The log table of log_dd, one 32-byte entry per point, staged in LDS by the
+// kernels that draw boosted gammas: the lookup sits on every boosted draw,
+// where a global-memory load stalls the whole wavefront.
+struct LogE {
+    double c, inv, hi, lo;
+};
+struct LogLds {
+    LogE e[256];
+};
+__device__ __forceinline__ void load_logt(LogLds *t)
+{
+    for (int k = threadIdx.x; k < 256; k += blockDim.x) t->e[k] = LogE{RP_LOG_C[k], RP_LOG_INV[k], RP_LOG_HI[k], RP_LOG_LO[k]};
+}
+
 // log u as a pair (lh, ll), u > 0 finite, from the 256-entry table: u = 2^e m,
 // m in [1, 2), c the table point of m's top fraction bits, log u =
 // e ln2 + log c + log1p((m - c)/c) with a degree-7 series.
-__device__ __forceinline__ void log_dd(double u, double &lh, double &ll)
+__device__ __forceinline__ void log_dd(double u, double &lh, double &ll, const LogLds *lt)
 {
     int ex;
     double m = frexp(u, &ex);  // u = m 2^ex, m in [0.5, 1)
     m = m * 2.0;
     ex -= 1;
     const int i = (int)(((uint64_t)__double_as_longlong(m) >> 44) & 0xff);
-    const double c = RP_LOG_C[i], ic = RP_LOG_INV[i];
+    const LogE te = lt->e[i];
+    const double c = te.c, ic = te.inv;
     const double num = m - c;  // exact: m and c are within a factor of 2
     const double rh = num * ic;
     const double rl = __fma_rn(-rh, c, num) * ic;
     const double p = (rh * rh) * (-0.5 + rh * (1.0 / 3.0 + rh * (-0.25 + rh * (0.2 + rh * (-1.0 / 6.0 + rh * (1.0 / 7.0))))));
     double sh, sl, t;
-    two_sum((double)ex * RP_LN2_HI, RP_LOG_HI[i], sh, sl);
+    two_sum((double)ex * RP_LN2_HI, te.hi, sh, sl);
     two_sum(sh, rh, sh, t);
-    sl = sl + t + (((double)ex * RP_LN2_LO + RP_LOG_LO[i]) + (rl + p));
+    sl = sl + t + (((double)ex * RP_LN2_LO + te.lo) + (rl + p));
     lh = sh + sl;
     ll = sl - (lh - sh);
 }
 
-__device__ double boost_pow(double u, double a, double ia)
+__device__ double boost_pow(double u, double a, double ia, const LogLds *lt)
 {
     if (u == 0.0) return 0.0;
     double lh, ll;
-    log_dd(u, lh, ll);
+    log_dd(u, lh, ll, lt);
     // t = log(u) / a as th + tl; th need not be the rounded quotient
     const double th = lh * ia;
     const double tl = (__fma_rn(-th, a, lh) + ll) * ia;
@@ -339,7 +354,7 @@ struct GamMachine {
         second = false;
     }
     template <class E>
-    __device__ __forceinline__ bool step(E &eng, const ZigLds *zt, double &val)
+    __device__ __forceinline__ bool step(E &eng, const ZigLds *zt, const LogLds *lt, double &val)
     {
         eng.reserve(4);  // candidate, wedge word, uniform, boost uniform
         const bool sb = BETA && second;
@@ -357,7 +372,7 @@ struct GamMachine {
         double g = d * v;
         if (sb ? pb.boost : pa.boost) {
             const double a = sb ? pb.a : pa.a, ia = sb ? pb.ia : pa.ia;
-            g = g * boost_pow(u01_53(eng.next()), a, ia);
+            g = g * boost_pow(u01_53(eng.next()), a, ia, lt);
         }
         if (!BETA) {
             val = g;
@@ -408,7 +423,9 @@ template <class E, bool BETA>
 __global__ __launch_bounds__(256) void k_gamma_elem(SampArgs s)
 {
     __shared__ ZigLds zt;
+    __shared__ LogLds lt;
     load_zig<RP_NORM>(&zt);
+    load_logt(&lt);
     __syncthreads();
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -430,7 +447,7 @@ __global__ __launch_bounds__(256) void k_gamma_elem(SampArgs s)
             open = true;
         }
         double v;
-        if (gm.step(eng, &zt, v)) {
+        if (gm.step(eng, &zt, &lt, v)) {
             s.z[i] = (float)v;
             eng.store(s.f, i);
             open = false;
