@@ -148,6 +148,55 @@ __global__ __launch_bounds__(256) void k_ser_gen(SerialArgs a)
     if (w1 > a.words) w1 = a.words;
     T *out = (T *)a.fa.out;
     uint64_t w = w0;
+    if constexpr (!HALF) {
+        // Wavefront-cooperative runs.  A lane's chunk is contiguous in the
+        // output, so per-lane stores touch 64 cache lines per instruction and
+        // leave lines half written.  When every lane of the wavefront has a
+        // whole chunk of C words inside the output, each lane stages its next
+        // 16 values in LDS and the wavefront writes them as 4 runs of 16
+        // consecutive values (4 whole 128-byte lines) per store instruction.
+        constexpr int kRow = 18;  // 16 values + padding, 16-byte aligned rows
+        __shared__ __align__(16) uint64_t stage_all[4][64 * kRow];
+        uint64_t *const stage = stage_all[(threadIdx.x >> 6) & 3];
+        const int lane = (int)(threadIdx.x & 63);
+        const uint64_t id0 = id - (uint64_t)lane;
+        const uint64_t lim = FIXED ? (a.words < a.n ? a.words : a.n) : a.words;
+        if (blockDim.x <= 256 && id0 + 64 <= (uint64_t)a.lanes && (id0 + 64) * a.C <= lim) {
+            uint64_t *const dst = FIXED ? (uint64_t *)out : a.wbuf;
+            const uint64_t nrun = a.C / 16;
+            for (uint64_t it = 0; it < nrun; it++) {
+                uint64_t v[16];
+#pragma unroll
+                for (int k = 0; k < 16; k++) {
+                    if (k % 8 == 0) g.reserve(8);
+                    const uint64_t word = g.next();
+                    if constexpr (FIXED) {
+                        T t;
+                        item_value<DIST, OT>(word, a.fa, t);
+                        v[k] = __builtin_bit_cast(uint64_t, t);
+                    } else {
+                        v[k] = word;
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 16; k += 2) {
+                    ulonglong2 q;
+                    q.x = v[k];
+                    q.y = v[k + 1];
+                    *(ulonglong2 *)(stage + lane * kRow + k) = q;
+                }
+                wave_sync();
+                const int e = lane & 15;
+#pragma unroll
+                for (int k = 0; k < 16; k++) {
+                    const int r = 4 * k + (lane >> 4);
+                    dst[(id0 + (uint64_t)r) * a.C + it * 16 + (uint64_t)e] = stage[r * kRow + e];
+                }
+                wave_sync();
+            }
+            w = w0 + nrun * 16;
+        }
+    }
     if constexpr (FIXED && !HALF) {
         // whole 128-byte runs (16 values) per store burst where they fit
         if ((((uintptr_t)(out + w)) & 15) == 0) {
