@@ -103,6 +103,72 @@ def test_grad_special_values():
     assert ei.value.code == rp.RP_ENULL
 
 
+def _grad_inputs(n, seed):
+    rng = np.random.default_rng(seed)
+    al = np.exp(rng.uniform(np.log(0.05), np.log(50), n)).astype(np.float32)
+    b = np.exp(rng.uniform(np.log(0.05), np.log(50), n)).astype(np.float32)
+    z = rng.gamma(al).astype(np.float32)
+    zb = np.clip(rng.beta(al, b), 1e-6, 1 - 1e-6).astype(np.float32)
+    gz = rng.standard_normal(n).astype(np.float32)
+    return al, b, z, zb, gz
+
+
+def _gamma_grad(z, al, gz):
+    ga = torch.empty(len(z), dtype=torch.float32, device="cuda")
+    rp.rp_gamma_grad(_dev(z), _dev(al), _dev(gz), ga, len(z))
+    torch.cuda.synchronize()
+    return ga.cpu().numpy()
+
+
+def _beta_grad(z, a, b, gz):
+    ga = torch.empty(len(z), dtype=torch.float32, device="cuda")
+    gb = torch.empty(len(z), dtype=torch.float32, device="cuda")
+    rp.rp_beta_grad(_dev(z), _dev(a), _dev(b), _dev(gz), ga, gb, len(z))
+    torch.cuda.synchronize()
+    return ga.cpu().numpy(), gb.cpu().numpy()
+
+
+def test_grad_independent_of_order_and_tiling():
+    """The kernels reorder each tile by predicted loop length; a result may
+    not depend on which elements share a tile or a wavefront.  A ragged size
+    (several tiles and a partial one), a permutation, and a prefix must give
+    the same bits per element."""
+    n = 3 * 2048 + 1000 + 37
+    al, b, z, zb, gz = _grad_inputs(n, 11)
+    g0 = _gamma_grad(z, al, gz)
+    a0, b0 = _beta_grad(zb, al, b, gz)
+    perm = np.random.default_rng(12).permutation(n)
+    g1 = _gamma_grad(z[perm], al[perm], gz[perm])
+    a1, b1 = _beta_grad(zb[perm], al[perm], b[perm], gz[perm])
+    assert np.array_equal(g1.view(np.uint32), g0[perm].view(np.uint32))
+    assert np.array_equal(a1.view(np.uint32), a0[perm].view(np.uint32))
+    assert np.array_equal(b1.view(np.uint32), b0[perm].view(np.uint32))
+    k = 777
+    assert np.array_equal(_gamma_grad(z[:k], al[:k], gz[:k]).view(np.uint32), g0[:k].view(np.uint32))
+    # one shape for a whole tile: every element in the same key bucket
+    one = np.full(2048, 7.5, dtype=np.float32)
+    g2 = _gamma_grad(np.full(2048, 6.0, dtype=np.float32), one, np.ones(2048, dtype=np.float32))
+    assert np.isfinite(g2).all() and (g2 == g2[0]).all()
+
+
+def test_grad_outputs_may_alias_inputs():
+    """A tile is read in full before any of its outputs is written, so the
+    gradient may overwrite its own inputs."""
+    n = 2 * 2048 + 501
+    al, b, z, zb, gz = _grad_inputs(n, 13)
+    ref = _gamma_grad(z, al, gz)
+    zt, at, gt = _dev(z), _dev(al), _dev(gz)
+    rp.rp_gamma_grad(zt, at, gt, gt, n)      # into gz
+    torch.cuda.synchronize()
+    assert np.array_equal(gt.cpu().numpy().view(np.uint32), ref.view(np.uint32))
+    ra, rb = _beta_grad(zb, al, b, gz)
+    zt, at, bt, gt = _dev(zb), _dev(al), _dev(b), _dev(gz)
+    rp.rp_beta_grad(zt, at, bt, gt, at, bt, n)   # into a and b
+    torch.cuda.synchronize()
+    assert np.array_equal(at.cpu().numpy().view(np.uint32), ra.view(np.uint32))
+    assert np.array_equal(bt.cpu().numpy().view(np.uint32), rb.view(np.uint32))
+
+
 def test_closed_forms():
     """Beta(a, 1): z = u^(1/a), dz/da = -z ln z / a; Beta(1, b): dz/db =
     (1 - z) ln(1 - z) / b."""

@@ -117,3 +117,18 @@ def test_serial_many_lanes(engine):
     got = _gpu(rng, rp.RP_NORM, rp.RP_F64, 0, 0, m)
     _compare(got, o.norm(m), rp.RP_NORM)
     _same_state(rng, o)
+
+
+@pytest.mark.parametrize("dist,dtype", [(rp.RP_RAW, rp.RP_U64), (rp.RP_U01, rp.RP_F64)])
+def test_serial_wavefront_runs_ragged(dist, dtype):
+    """2^16 lanes of 1001 words (not a multiple of the 16-value runs the
+    wavefront writes together) with a partial last wavefront: the staged runs,
+    the per-lane remainders and the per-lane path must all land in place."""
+    n = 2**16 * 1000 + 12345
+    rng = rp.rp_create("x256++").seed(77)
+    o = oracle.Stream.seeded("x256++", 77)
+    got = _gpu(rng, dist, dtype, 0, 0, n)
+    ref = o.raw(n) if dist == rp.RP_RAW else o.u01(n)
+    assert np.array_equal(got, ref)
+    del got, ref
+    _same_state(rng, o)
