@@ -49,7 +49,7 @@ def parse():
     p.add_argument("--no-parts", action="store_true", help="time only the ten-fill step")
     p.add_argument("--parts", default=None,
                    help="comma-separated parts to time after the step: serial, batched, elem, mvn, "
-                        "moments (default all; none with --only)")
+                        "moments, setup (default all; none with --only)")
     p.add_argument("--only", default="", help="comma-separated fill names to run (profiling)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="run only plain fill/copy kernels of known size (counter calibration)")
@@ -164,6 +164,8 @@ def parts(torch, rp, workloads, stream, only):
         out.update(part_mvn(torch, rp, workloads, tm, sp, np))
     if "moments" in only:
         out.update(part_moments(torch, rp, workloads, tm, sp))
+    if "setup" in only:
+        out.update(part_setup(torch, rp, workloads))
     return out
 
 
@@ -286,6 +288,32 @@ def part_moments(torch, rp, workloads, tm, sp):
     return out
 
 
+def part_setup(torch, rp, workloads):
+    """Substream construction (host seeding and per-substream keys, increments,
+    spawn keys or jumps, then the copy to device), timed on its own: it is
+    outside every timed region above."""
+    import time
+    cases = (("philox4x32_key_2p16", "philox4x32", rp.RP_SUB_KEY, workloads.SUB_N, 0),
+             ("pcg64_inc_2p16", "pcg64", rp.RP_SUB_INC, workloads.SUB_N, 0),
+             ("philox4x32_key_1e6", "philox4x32", rp.RP_SUB_KEY, 10**6, 0),
+             ("ranlux_jump64_2p18", "ranlux++", rp.RP_SUB_JUMP, workloads.MOM_N, 64),
+             ("sfc64_spawn_2p18", "sfc64", rp.RP_SUB_SPAWN, workloads.MOM_N, 0))
+    res = {}
+    for name, eng, kind, n, stride in cases:
+        base = rp.rp_create(eng).seed(workloads.BASE_SEED)
+        best = None
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            S = rp.rp_streams_create(base, kind, n, stride)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) * 1e3
+            best = dt if best is None else min(best, dt)
+            del S
+        res[name] = {"ms": round(best, 3), "substreams": n}
+    return {"substream_setup": res}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -383,7 +411,7 @@ def main():
                      "algorithmic_bytes_per_launch": total * dom[4], "avg_launch_ms": round(dom_ms, 4)},
         "rows": rows,
     }
-    want = args.parts if args.parts is not None else ("" if args.only else "serial,batched,elem,mvn,moments")
+    want = args.parts if args.parts is not None else ("" if args.only else "serial,batched,elem,mvn,moments,setup")
     if not args.no_parts and want:
         result["parts"] = parts(torch, rp, workloads, stream, set(want.split(",")))
     if not args.no_cpu_baseline:
