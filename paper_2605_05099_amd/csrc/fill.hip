@@ -198,11 +198,16 @@ struct WavePhilox32 {
     }
     __device__ void gen(uint64_t w[R]) const
     {
+        // an opaque copy of the key: its ten round keys are then formed here,
+        // once per chunk, instead of hoisted out of the chunk loop where they
+        // would hold twenty scalar registers for the whole kernel
+        uint64_t kk = key;
+        asm volatile("" : "+s"(kk));
 #pragma unroll
         for (int k = 0; k < R / 2; k++) {
             uint64_t lo = clo + (uint64_t)k;
             uint64_t hi = chi + (lo < clo ? 1u : 0u);
-            philox4x32(lo, hi, key, w[2 * k], w[2 * k + 1]);
+            philox4x32(lo, hi, kk, w[2 * k], w[2 * k + 1]);
         }
     }
     __device__ void next_chunk()
@@ -421,11 +426,19 @@ __device__ __noinline__ bool normal_tail_pair(uint64_t a, uint64_t b, double &t)
 // wedge-test tables in global memory (read only on the rare wedge path)
 template <int DIST>
 struct ZigG {
-    static __device__ __forceinline__ double F(int j) { return DIST == RP_NORM ? RP_ZN_F[j] : RP_ZE_F[j]; }
-    static __device__ __forceinline__ double X(int j) { return DIST == RP_NORM ? RP_ZN_X[j] : RP_ZE_X[j]; }
-    static __device__ __forceinline__ double S(int j) { return DIST == RP_NORM ? RP_ZN_S[j] : RP_ZE_S[j]; }
-    static __device__ __forceinline__ double DP(int j) { return DIST == RP_NORM ? RP_ZN_DP[j] : RP_ZE_DP[j]; }
-    static __device__ __forceinline__ double DM(int j) { return DIST == RP_NORM ? RP_ZN_DM[j] : RP_ZE_DM[j]; }
+    // Each table address passes through an opaque copy where it is used: the
+    // wedge test is a rare path, and five table addresses hoisted out of the
+    // chunk loop would hold ten scalar registers for the whole kernel.
+    static __device__ __forceinline__ const double *opaque(const double *p)
+    {
+        asm volatile("" : "+s"(p));
+        return p;
+    }
+    static __device__ __forceinline__ double F(int j) { return opaque(DIST == RP_NORM ? RP_ZN_F : RP_ZE_F)[j]; }
+    static __device__ __forceinline__ double X(int j) { return opaque(DIST == RP_NORM ? RP_ZN_X : RP_ZE_X)[j]; }
+    static __device__ __forceinline__ double S(int j) { return opaque(DIST == RP_NORM ? RP_ZN_S : RP_ZE_S)[j]; }
+    static __device__ __forceinline__ double DP(int j) { return opaque(DIST == RP_NORM ? RP_ZN_DP : RP_ZE_DP)[j]; }
+    static __device__ __forceinline__ double DM(int j) { return opaque(DIST == RP_NORM ? RP_ZN_DM : RP_ZE_DM)[j]; }
 };
 
 template <int DIST, class Word>
@@ -671,6 +684,10 @@ __global__ __launch_bounds__(256) void k_fill_wave(FillArgs a)
                     fb |= (f ? 1u : 0u) << r;
                     lb |= (f ? 0u : 1u) << r;
                 }
+                // keep the flags as bits of a vector register: otherwise each
+                // row's compare result stays live as a scalar lane mask (two
+                // scalar registers per row) until the stores
+                asm volatile("" : "+v"(fb), "+v"(lb));
                 // number of long items (plus the carried sample as slot 0):
                 // each lane's count (<= R < 16) summed bitwise
                 const int npre = pending ? 1 : 0;
