@@ -242,7 +242,10 @@ int rp_beta_batched(rp_streams *s, const double *d_a, const double *d_b, const i
  * Inputs and outputs are binary32 device arrays of n elements owned by the
  * caller; the derivative is evaluated in binary64 at the binary32 values.
  * z = 0 (or z = 1 for beta) gives 0; a parameter not > 0 or z outside the
- * support gives NaN.  Stateless; n = 0 does nothing. */
+ * support gives NaN.  Each result depends only on its own element, and an
+ * output array may be the same as an input array (results overwrite their
+ * inputs in place).  Stateless; n = 0 does nothing; pointers must be 4-byte
+ * aligned (RP_EINVAL otherwise). */
 int rp_gamma_grad(const float *d_z, const float *d_alpha, const float *d_gz, float *d_galpha, uint64_t n,
                   void *hip_stream);
 int rp_beta_grad(const float *d_z, const float *d_a, const float *d_b, const float *d_gz, float *d_ga, float *d_gb,
