@@ -242,23 +242,46 @@ __global__ __launch_bounds__(256) void k_mvn_bwd(const float *G, const float *Z,
     if (tb == 0 && tid < kTile && a0 + tid < d) gmu_part[(uint64_t)blockIdx.y * dd + a0 + tid] = colsum;
 }
 
-// Sums the per-slice partials in slice order (binary64), lower triangle only.
-__global__ __launch_bounds__(256) void k_mvn_reduce(const float *part, const float *gmu_part, int nslices, int d,
-                                                    float *gL, float *gmu)
+// The per-slice partials are summed in binary64 in two passes, so that the
+// reduction has parallelism even when there are few elements (d = 64: 4096
+// elements, 2048 slices).  Elements of the combined array are the d x d
+// entries of the grad_L partials followed by the d entries of the grad_mu
+// partials.  Pass 1: block (x, y) sums slices 64 y .. 64 y + 63 of elements
+// 64 x .. 64 x + 63, four threads per element.  Pass 2: the group sums of an
+// element, in group order.  Entries above the diagonal of grad_L are 0.
+constexpr int kRedGroup = 64;
+
+__global__ __launch_bounds__(256) void k_mvn_reduce1(const float *part, const float *gmu_part, int nslices, int d,
+                                                     double *sums)
 {
-    const uint64_t dd = (uint64_t)d, total = dd * dd;
-    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+    __shared__ double red[4][64];
+    const uint64_t dd = (uint64_t)d, total = dd * dd, all = total + dd;
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const uint64_t e = (uint64_t)blockIdx.x * 64 + lane;
+    const int k0 = (int)blockIdx.y * kRedGroup;
+    const int k1 = nslices < k0 + kRedGroup ? nslices : k0 + kRedGroup;
+    double acc = 0.0;
+    const bool gmu = e >= total;
+    if (e < all && (gmu || e / dd >= e % dd)) {
+        const float *src = gmu ? gmu_part + (e - total) : part + e;
+        const uint64_t stride = gmu ? dd : total;
+        for (int k = k0 + q; k < k1; k += 4) acc += (double)src[(uint64_t)k * stride];
+    }
+    red[q][lane] = acc;
+    __syncthreads();
+    if (q == 0 && e < all) sums[(uint64_t)blockIdx.y * all + e] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
+__global__ __launch_bounds__(256) void k_mvn_reduce2(const double *sums, int ngroups, int d, float *gL, float *gmu)
+{
+    const uint64_t dd = (uint64_t)d, total = dd * dd, all = total + dd;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < all;
          e += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t a = e / dd, b = e % dd;
         double s = 0.0;
-        if (a >= b)
-            for (int k = 0; k < nslices; k++) s += (double)part[(uint64_t)k * total + e];
-        gL[e] = (float)s;
-        if (e < dd) {
-            double g = 0.0;
-            for (int k = 0; k < nslices; k++) g += (double)gmu_part[(uint64_t)k * dd + e];
-            gmu[e] = (float)g;
-        }
+        if (e >= total || e / dd >= e % dd)
+            for (int g = 0; g < ngroups; g++) s += sums[(uint64_t)g * all + e];
+        if (e < total) gL[e] = (float)s;
+        else gmu[e - total] = (float)s;
     }
 }
 
@@ -373,21 +396,28 @@ extern "C" int rp_mvn_backward(rp_streams *s, const float *d_G, int d, uint64_t 
     if (nsl == 0) nsl = 1;
     const uint64_t dd = (uint64_t)d;
     const uint64_t zf = n * dd, pf = nsl * dd * dd, gf = nsl * dd;
+    const uint64_t ngroups = n ? (nsl + kRedGroup - 1) / kRedGroup : 0, all = dd * dd + dd;
+    // floats: Z, the slice partials of grad_L and grad_mu; then the group sums (binary64)
+    const uint64_t fl = (zf + 3) / 4 * 4 + pf + gf;
+    const uint64_t sum_off = (fl * sizeof(float) + 255) / 256 * 256;
     float *ws = nullptr;
-    hipError_t e = hipMallocAsync((void **)&ws, (zf + pf + gf + 64) * sizeof(float), st);
+    hipError_t e = hipMallocAsync((void **)&ws, sum_off + ngroups * all * sizeof(double) + 256, st);
     if (e != hipSuccess) return fail(RP_ENOMEM, "rp_mvn_backward: workspace: %s", hipGetErrorString(e));
     float *z = ws;
     float *part = ws + ((zf + 3) & ~3ull);
     float *gpart = part + pf;
+    double *sums = (double *)((char *)ws + sum_off);
     rc = n ? gen_rows(s, z, d, n, false, st) : RP_OK;
     if (rc == RP_OK) {
         const int vec = (d % 4 == 0) && al16(d_G) && al16(z) ? 1 : 0;
         if (n) hipLaunchKernelGGL(k_mvn_bwd, dim3((unsigned)ntl, (unsigned)nsl), dim3(256), 0, st, d_G, z, n, d,
                                   slice, part, gpart, vec);
-        const int nsl_used = n ? (int)nsl : 0;
-        uint64_t blocks = (dd * dd + 255) / 256;
+        if (ngroups)
+            hipLaunchKernelGGL(k_mvn_reduce1, dim3((unsigned)((all + 63) / 64), (unsigned)ngroups), dim3(256), 0, st,
+                               part, gpart, (int)nsl, d, sums);
+        uint64_t blocks = (all + 255) / 256;
         if (blocks > 4096) blocks = 4096;
-        hipLaunchKernelGGL(k_mvn_reduce, dim3((unsigned)blocks), dim3(256), 0, st, part, gpart, nsl_used, d, d_gL,
+        hipLaunchKernelGGL(k_mvn_reduce2, dim3((unsigned)blocks), dim3(256), 0, st, sums, (int)ngroups, d, d_gL,
                            d_gmu);
         e = hipGetLastError();
         if (e != hipSuccess) rc = hip_fail(e, "rp_mvn_backward launch");
