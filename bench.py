@@ -317,8 +317,8 @@ def part_setup(torch, rp, workloads):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (single-GPU box); "
-              "run with --gpus 1", file=sys.stderr)
+        print("bench.py: only single-GPU runs are supported (every workload runs on one GPU; "
+              "the multi-GPU split is described, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
 
