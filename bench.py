@@ -49,7 +49,7 @@ def parse():
     p.add_argument("--no-parts", action="store_true", help="time only the ten-fill step")
     p.add_argument("--parts", default=None,
                    help="comma-separated parts to time after the step: serial, batched, elem, mvn, "
-                        "moments, setup (default all; none with --only)")
+                        "moments, laws, setup (default all; none with --only)")
     p.add_argument("--only", default="", help="comma-separated fill names to run (profiling)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="run only plain fill/copy kernels of known size (counter calibration)")
@@ -164,6 +164,8 @@ def parts(torch, rp, workloads, stream, only):
         out.update(part_mvn(torch, rp, workloads, tm, sp, np))
     if "moments" in only:
         out.update(part_moments(torch, rp, workloads, tm, sp))
+    if "laws" in only:
+        out.update(part_laws(torch, rp, workloads, tm, sp))
     if "setup" in only:
         out.update(part_setup(torch, rp, workloads))
     return out
@@ -286,6 +288,24 @@ def part_moments(torch, rp, workloads, tm, sp):
         del S
     out["moments_2p18x2p16"] = mo
     return out
+
+
+def part_laws(torch, rp, workloads, tm, sp):
+    """Derived laws (one transform fused into the base fill's store) on the
+    substream workload: Philox4x32-10, 2^16 substreams x 2^14 values."""
+    n, per = workloads.SUB_N, workloads.SUB_PER
+    S = rp.rp_streams_create(rp.rp_create("philox4x32").seed(workloads.BASE_SEED), rp.RP_SUB_KEY, n)
+    buf = torch.empty(n * per, dtype=torch.float64, device="cuda")
+    res = {}
+    for name, law, p in (("unif", rp.RP_LAW_UNIF, (-2.0, 5.0)), ("normal", rp.RP_LAW_NORMAL, (3.0, 5.0)),
+                         ("lognormal", rp.RP_LAW_LOGNORMAL, (0.5, 0.75)), ("exp", rp.RP_LAW_EXP, (2.5,)),
+                         ("gumbel", rp.RP_LAW_GUMBEL, (1.0, 2.0)), ("pareto", rp.RP_LAW_PARETO, (1.5, 3.0)),
+                         ("gpareto", rp.RP_LAW_GPARETO, (0.5, 2.0, 0.3)), ("weibull", rp.RP_LAW_WEIBULL, (1.7, 4.0))):
+        ms = tm(lambda: rp.rp_fill_law(S, law, p, buf, per, sp), reps=3)
+        res[name] = {"ms": round(ms, 4), "gsamples_s": round(n * per / ms / 1e6, 2),
+                     "hbm_frac": round(8.0 * n * per / ms / 1e6 / HBM_PEAK_GBS, 4)}
+    del buf, S
+    return {"laws_philox4x32_2p16x2p14": res}
 
 
 def part_setup(torch, rp, workloads):
@@ -411,7 +431,7 @@ def main():
                      "algorithmic_bytes_per_launch": total * dom[4], "avg_launch_ms": round(dom_ms, 4)},
         "rows": rows,
     }
-    want = args.parts if args.parts is not None else ("" if args.only else "serial,batched,elem,mvn,moments,setup")
+    want = args.parts if args.parts is not None else ("" if args.only else "serial,batched,elem,mvn,moments,laws,setup")
     if not args.no_parts and want:
         result["parts"] = parts(torch, rp, workloads, stream, set(want.split(",")))
     if not args.no_cpu_baseline:

@@ -154,6 +154,41 @@ enum { RP_FLAG_52BIT = 1 }; /* uniform method 2 (mantissa fill, 52/23 bits) */
 int rp_fill(rp_streams *s, int dist, int dtype, uint64_t bound, int flags, void *d_out,
             uint64_t per_stream, void *hip_stream);
 
+/* ---- derived continuous laws by transform (Table 4, Section 3.1) ------- */
+/* rp_fill_law fills d_out[i * per_stream + t] (binary64, substream-major) with
+ * per_stream draws of a derived law per substream, each draw one transform of
+ * one base draw, the base draws being exactly those rp_fill would return
+ * (U(0,1) with 53 bits, or the ziggurat N(0,1) or Exp(1)), so the streams
+ * advance exactly as rp_fill advances them.  The transforms are evaluated in
+ * binary64 in the order written (no contraction); "inv" values are formed
+ * once on the host.  Parameters p[] (host memory):
+ *   RP_LAW_UNIF      U(a,b),        p = {a, b}, a < b:       a + (b - a) U
+ *   RP_LAW_NORMAL    N(mu,sigma^2), p = {mu, sigma}, s >= 0: mu + sigma Z
+ *   RP_LAW_LOGNORMAL log N,         p = {mu, sigma}, s >= 0: exp(mu + sigma Z)
+ *   RP_LAW_EXP       Exp(beta),     p = {beta}, beta > 0 (the scale): beta E
+ *   RP_LAW_GUMBEL    Gumbel(mu,b),  p = {mu, b}, b > 0:      mu - b log(-log U)
+ *   RP_LAW_PARETO    Pareto(xm,a),  p = {xm, a}, both > 0:   xm exp(E / a)
+ *   RP_LAW_GPARETO   GPD(mu,s,xi),  p = {mu, s, xi}, s > 0:  with P =
+ *                    exp(E / inv), inv = 1/|xi| (P is Pareto(1, 1/|xi|)):
+ *                    xi > 0: mu + s (P - 1) / xi; xi < 0: mu - s (1 - 1/P) / xi;
+ *                    xi = 0: mu + s E
+ *   RP_LAW_WEIBULL   Weibull(k,l),  p = {k, l}, both > 0:    l pow(E, inv), inv = 1/k
+ * Parameters must be finite; others give RP_EINVAL.  d_out must be 8-byte
+ * aligned device memory of n * per_stream doubles owned by the caller.
+ * Asynchronous on hip_stream; per_stream = 0 does nothing. */
+enum {
+    RP_LAW_UNIF = 1,
+    RP_LAW_NORMAL = 2,
+    RP_LAW_LOGNORMAL = 3,
+    RP_LAW_EXP = 4,
+    RP_LAW_GUMBEL = 5,
+    RP_LAW_PARETO = 6,
+    RP_LAW_GPARETO = 7,
+    RP_LAW_WEIBULL = 8
+};
+int rp_fill_law(rp_streams *s, int law, const double *p, int np, double *d_out, uint64_t per_stream,
+                void *hip_stream);
+
 /* ---- one stream split over many lanes (Section 4.4 jumps) -------------- */
 /* Fills d_out[0 .. n-1] with the next n values of the single stream `rng`,
  * exactly as n serial calls would (same values, same order), and advances

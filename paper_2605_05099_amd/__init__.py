@@ -24,6 +24,8 @@ RP_SUB_KEY, RP_SUB_INC, RP_SUB_SPAWN, RP_SUB_JUMP = range(4)
 RP_RAW, RP_U01, RP_BOUNDED, RP_NORM, RP_EXP = range(5)
 RP_U64, RP_U32, RP_F64, RP_F32 = range(4)
 RP_FLAG_52BIT = 1
+(RP_LAW_UNIF, RP_LAW_NORMAL, RP_LAW_LOGNORMAL, RP_LAW_EXP, RP_LAW_GUMBEL, RP_LAW_PARETO, RP_LAW_GPARETO,
+ RP_LAW_WEIBULL) = range(1, 9)
 
 ENGINES = {"x256++": RP_X256PP, "pcg64": RP_PCG64, "philox4x32": RP_PHILOX4X32, "philox": RP_PHILOX,
            "sfc64": RP_SFC64, "ranlux++": RP_RANLUX}
@@ -58,6 +60,7 @@ _SIGS = {
     "rp_streams_set": ([_vp, _vp, _vp], _int),
     "rp_streams_duplicate": ([_vp, _vp], _int),
     "rp_fill": ([_vp, _int, _int, _u64, _int, _vp, _u64, _vp], _int),
+    "rp_fill_law": ([_vp, _int, _vp, _int, _vp, _u64, _vp], _int),
     "rp_fill_serial": ([_vp, _int, _int, _u64, _int, _vp, _u64, _vp], _int),
     "rp_norm_moments": ([_vp, _u64, _vp, _vp, _vp], _int),
     "rp_gamma_elem": ([_vp, _vp, _vp, _u64, _vp], _int),
@@ -158,6 +161,12 @@ def rp_streams_create(base, kind, n, jump_log2=0):
 
 def rp_fill(streams, dist, dtype, bound, flags, out, per_stream, stream=None):
     _check(lib().rp_fill(streams.h, dist, dtype, bound, flags, _dev_ptr(out), per_stream, _stream_ptr(stream)))
+
+
+def rp_fill_law(streams, law, params, out, per_stream, stream=None):
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(-1))
+    _check(lib().rp_fill_law(streams.h, law, _ptr(p) if len(p) else None, len(p), _dev_ptr(out), per_stream,
+                             _stream_ptr(stream)))
 
 
 def rp_fill_serial(rng, dist, dtype, bound, flags, out, n, stream=None):

@@ -507,7 +507,38 @@ __device__ __forceinline__ uint64_t range_mask(int r, int lo, int hi)
     return top & ~((1ull << a) - 1);
 }
 
-template <class E, int DIST, int OT>
+// The derived laws of rp_fill_law: one transform of one base draw (U, Z or
+// E), in binary64, in the order the boundary documents, fused into the store
+// of the base fill.  XF = 0 is the base value itself.
+template <int XF>
+__device__ __forceinline__ double xform(double v, const FillArgs &a)
+{
+    if constexpr (XF == RP_LAW_UNIF) {
+        return a.xp[0] + a.xp[1] * v;  // a + (b - a) U, b - a formed on the host
+    } else if constexpr (XF == RP_LAW_NORMAL) {
+        return a.xp[0] + a.xp[1] * v;
+    } else if constexpr (XF == RP_LAW_LOGNORMAL) {
+        return exp(a.xp[0] + a.xp[1] * v);
+    } else if constexpr (XF == RP_LAW_EXP) {
+        return a.xp[0] * v;
+    } else if constexpr (XF == RP_LAW_GUMBEL) {
+        return a.xp[0] - a.xp[1] * log(-log(v));
+    } else if constexpr (XF == RP_LAW_PARETO) {
+        return a.xp[0] * exp(v / a.xp[1]);
+    } else if constexpr (XF == RP_LAW_GPARETO) {
+        const double mu = a.xp[0], sg = a.xp[1], xi = a.xp[2];
+        if (xi == 0.0) return mu + sg * v;
+        const double P = exp(v / a.xp[3]);
+        if (xi > 0.0) return mu + (sg * (P - 1.0)) / xi;
+        return mu - (sg * (1.0 - 1.0 / P)) / xi;
+    } else if constexpr (XF == RP_LAW_WEIBULL) {
+        return a.xp[1] * pow(v, a.xp[2]);
+    } else {
+        return v;
+    }
+}
+
+template <class E, int DIST, int OT, int XF = 0>
 __global__ __launch_bounds__(256) void k_fill_wave(FillArgs a)
 {
     using T = typename OutType<DIST, OT>::T;
@@ -595,6 +626,7 @@ __global__ __launch_bounds__(256) void k_fill_wave(FillArgs a)
                 for (int r = 0; r < R; r++) {
                     T v;
                     item_value<DIST, OT>(w[r], a, v);
+                    if constexpr (XF != 0) v = xform<XF>(v, a);
                     const int q = 64 * r + lane;
                     if (q >= e && (uint64_t)(q - e) < need) dst[q] = v;
                 }
@@ -823,7 +855,7 @@ __global__ __launch_bounds__(256) void k_fill_wave(FillArgs a)
                 const uint64_t need = P - produced;
                 T *const dst = out + produced;
                 uint32_t total = first;
-                if (yq == -2) dst[0] = yv;  // need >= 1 here
+                if (yq == -2) dst[0] = xform<XF>(yv, a);  // need >= 1 here
                 if (first && need == 1) {
                     final_pos = base_pos + (uint64_t)e;
                     break;
@@ -839,7 +871,7 @@ __global__ __launch_bounds__(256) void k_fill_wave(FillArgs a)
                             // the value again from the word (cheaper than keeping R values live)
                             double v0;
                             zig_fast<DIST>(zt, wbuf[wpos(64 * r + lane)], v0);
-                            dst[total + mbcnt64(om)] = v0;
+                            dst[total + mbcnt64(om)] = xform<XF>(v0, a);
                         }
                         if (lane == 0) {
                             omem[r] = om;
@@ -850,7 +882,7 @@ __global__ __launch_bounds__(256) void k_fill_wave(FillArgs a)
                     wave_sync();
                     if (yq >= 0) {
                         const int r = yq >> 6, b = yq & 63;
-                        dst[pmem[r] + (uint32_t)__popcll(omem[r] & ((1ull << b) - 1))] = yv;
+                        dst[pmem[r] + (uint32_t)__popcll(omem[r] & ((1ull << b) - 1))] = xform<XF>(yv, a);
                     }
                 } else {
                     // the last chunk of this call: only need values, and the
@@ -866,7 +898,7 @@ __global__ __launch_bounds__(256) void k_fill_wave(FillArgs a)
                             const uint32_t idx = total + mbcnt64(om);
                             double v0;
                             zig_fast<DIST>(zt, wbuf[wpos(64 * r + lane)], v0);
-                            if (idx < need) dst[idx] = v0;
+                            if (idx < need) dst[idx] = xform<XF>(v0, a);
                         }
                         if (lane == 0) {
                             omem[r] = om;
@@ -888,7 +920,7 @@ __global__ __launch_bounds__(256) void k_fill_wave(FillArgs a)
                     if (yq >= 0) {
                         const int r = yq >> 6, b = yq & 63;
                         const uint32_t idx = pmem[r] + (uint32_t)__popcll(omem[r] & ((1ull << b) - 1));
-                        if (idx < need) dst[idx] = yv;
+                        if (idx < need) dst[idx] = xform<XF>(yv, a);
                     }
                     if (done) break;
                 }
@@ -1082,7 +1114,7 @@ __device__ double zig_serial(const ZigLds *t, E &eng)
     }
 }
 
-template <class E, int DIST, int OT>
+template <class E, int DIST, int OT, int XF = 0>
 __global__ __launch_bounds__(256) void k_fill_lane(FillArgs a)
 {
     using T = typename OutType<DIST, OT>::T;
@@ -1106,7 +1138,7 @@ __global__ __launch_bounds__(256) void k_fill_lane(FillArgs a)
     for (uint64_t t = 0; t < P;) {
         if constexpr (ZIG) {
             eng.reserve(3);
-            out[t++] = zig_serial<DIST>(zt, eng);
+            out[t++] = (T)xform<XF>(zig_serial<DIST>(zt, eng), a);
         } else {
             eng.reserve(1);
             uint64_t it;
@@ -1124,23 +1156,26 @@ __global__ __launch_bounds__(256) void k_fill_lane(FillArgs a)
                 it = eng.next();
             }
             T v;
-            if (item_value<DIST, OT>(it, a, v)) out[t++] = v;
+            if (item_value<DIST, OT>(it, a, v)) {
+                if constexpr (XF != 0) v = xform<XF>(v, a);
+                out[t++] = v;
+            }
         }
     }
     eng.store(a, i);
 }
 
 // ---------------------------------------------------------------------------
-template <bool WAVE, class E, int DIST, int OT>
+template <bool WAVE, class E, int DIST, int OT, int XF = 0>
 static int launch_one(const FillArgs &a, hipStream_t st)
 {
     const unsigned threads = 256;
     const unsigned per_block = WAVE ? threads / 64 : threads;
     const uint64_t blocks = (a.n + per_block - 1) / per_block;
     if constexpr (WAVE)
-        hipLaunchKernelGGL((k_fill_wave<E, DIST, OT>), dim3((unsigned)blocks), dim3(threads), 0, st, a);
+        hipLaunchKernelGGL((k_fill_wave<E, DIST, OT, XF>), dim3((unsigned)blocks), dim3(threads), 0, st, a);
     else
-        hipLaunchKernelGGL((k_fill_lane<E, DIST, OT>), dim3((unsigned)blocks), dim3(threads), 0, st, a);
+        hipLaunchKernelGGL((k_fill_lane<E, DIST, OT, XF>), dim3((unsigned)blocks), dim3(threads), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(RP_EDEVICE, "fill kernel launch: %s", hipGetErrorString(e));
     return RP_OK;
@@ -1177,6 +1212,36 @@ int launch_fill(int engine, int dist, int dtype, const FillArgs &a, hipStream_t 
     case RP_X256PP: return dispatch_dist<false, LaneX256>(dist, dtype, a, st);
     case RP_SFC64: return dispatch_dist<false, LaneSfc64>(dist, dtype, a, st);
     case RP_RANLUX: return dispatch_dist<false, LaneRanlux>(dist, dtype, a, st);
+    }
+    return fail(RP_EINVAL, "unknown engine");
+}
+
+template <bool WAVE, class E>
+static int dispatch_law(int law, const FillArgs &a, hipStream_t st)
+{
+    switch (law) {
+    case RP_LAW_UNIF: return launch_one<WAVE, E, RP_U01, RP_F64, RP_LAW_UNIF>(a, st);
+    case RP_LAW_NORMAL: return launch_one<WAVE, E, RP_NORM, RP_F64, RP_LAW_NORMAL>(a, st);
+    case RP_LAW_LOGNORMAL: return launch_one<WAVE, E, RP_NORM, RP_F64, RP_LAW_LOGNORMAL>(a, st);
+    case RP_LAW_EXP: return launch_one<WAVE, E, RP_EXP, RP_F64, RP_LAW_EXP>(a, st);
+    case RP_LAW_GUMBEL: return launch_one<WAVE, E, RP_U01, RP_F64, RP_LAW_GUMBEL>(a, st);
+    case RP_LAW_PARETO: return launch_one<WAVE, E, RP_EXP, RP_F64, RP_LAW_PARETO>(a, st);
+    case RP_LAW_GPARETO: return launch_one<WAVE, E, RP_EXP, RP_F64, RP_LAW_GPARETO>(a, st);
+    case RP_LAW_WEIBULL: return launch_one<WAVE, E, RP_EXP, RP_F64, RP_LAW_WEIBULL>(a, st);
+    }
+    return fail(RP_EINVAL, "unknown law");
+}
+
+int launch_fill_law(int engine, int law, const FillArgs &a, hipStream_t st)
+{
+    if (a.n > (uint64_t)UINT32_MAX * 4) return fail(RP_EINVAL, "too many substreams for one launch");
+    switch (engine) {
+    case RP_PHILOX4X32: return dispatch_law<true, WavePhilox32>(law, a, st);
+    case RP_PHILOX: return dispatch_law<true, WavePhilox64>(law, a, st);
+    case RP_PCG64: return dispatch_law<true, WavePcg>(law, a, st);
+    case RP_X256PP: return dispatch_law<false, LaneX256>(law, a, st);
+    case RP_SFC64: return dispatch_law<false, LaneSfc64>(law, a, st);
+    case RP_RANLUX: return dispatch_law<false, LaneRanlux>(law, a, st);
     }
     return fail(RP_EINVAL, "unknown engine");
 }

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cctype>
 #include <cstdarg>
 #include <cstdio>
@@ -954,7 +955,7 @@ extern "C" int rp_fill(rp_streams *s, int dist, int dtype, uint64_t bound, int f
     if (s->n > UINT64_MAX / per_stream) return fail(RP_EINVAL, "rp_fill: size overflow");
     int rc = ensure_device_tables();
     if (rc) return rc;
-    FillArgs a;
+    FillArgs a{};
     a.words = s->d_words;
     a.phase = s->d_phase;
     a.n = s->n;
@@ -968,6 +969,76 @@ extern "C" int rp_fill(rp_streams *s, int dist, int dtype, uint64_t bound, int f
     }
     a.flags = flags;
     return launch_fill(s->engine, dist, dtype, a, (hipStream_t)hip_stream);
+}
+
+extern "C" int rp_fill_law(rp_streams *s, int law, const double *p, int np, double *d_out, uint64_t per_stream,
+                           void *hip_stream)
+{
+    if (!s) return fail(RP_ENULL, "rp_fill_law: NULL streams");
+    static const int kParams[9] = {0, 2, 2, 2, 1, 2, 2, 3, 2};
+    if (law < RP_LAW_UNIF || law > RP_LAW_WEIBULL) return fail(RP_EINVAL, "rp_fill_law: unknown law %d", law);
+    if (np != kParams[law]) return fail(RP_EINVAL, "rp_fill_law: law %d takes %d parameters, not %d", law, kParams[law], np);
+    if (!p) return fail(RP_ENULL, "rp_fill_law: NULL parameters");
+    for (int k = 0; k < np; k++)
+        if (!std::isfinite(p[k])) return fail(RP_EINVAL, "rp_fill_law: parameter %d is not finite", k);
+    FillArgs a{};
+    bool ok = true;
+    switch (law) {
+    case RP_LAW_UNIF:
+        ok = p[0] < p[1];
+        a.xp[0] = p[0];
+        a.xp[1] = p[1] - p[0];
+        ok = ok && std::isfinite(a.xp[1]);
+        break;
+    case RP_LAW_NORMAL:
+    case RP_LAW_LOGNORMAL:
+        ok = p[1] >= 0.0;
+        a.xp[0] = p[0];
+        a.xp[1] = p[1];
+        break;
+    case RP_LAW_EXP:
+        ok = p[0] > 0.0;
+        a.xp[0] = p[0];
+        break;
+    case RP_LAW_GUMBEL:
+        ok = p[1] > 0.0;
+        a.xp[0] = p[0];
+        a.xp[1] = p[1];
+        break;
+    case RP_LAW_PARETO:
+        ok = p[0] > 0.0 && p[1] > 0.0;
+        a.xp[0] = p[0];
+        a.xp[1] = p[1];
+        break;
+    case RP_LAW_GPARETO:
+        ok = p[1] > 0.0;
+        a.xp[0] = p[0];
+        a.xp[1] = p[1];
+        a.xp[2] = p[2];
+        a.xp[3] = p[2] != 0.0 ? 1.0 / std::fabs(p[2]) : 0.0;
+        ok = ok && std::isfinite(a.xp[3]);
+        break;
+    case RP_LAW_WEIBULL:
+        ok = p[0] > 0.0 && p[1] > 0.0;
+        a.xp[0] = p[0];
+        a.xp[1] = p[1];
+        a.xp[2] = 1.0 / p[0];
+        ok = ok && std::isfinite(a.xp[2]);
+        break;
+    }
+    if (!ok) return fail(RP_EINVAL, "rp_fill_law: parameters outside the law's domain");
+    if (per_stream == 0) return RP_OK;
+    if (!d_out) return fail(RP_ENULL, "rp_fill_law: NULL output");
+    if ((uintptr_t)d_out % 8) return fail(RP_EINVAL, "rp_fill_law: output not aligned to 8 bytes");
+    if (s->n > UINT64_MAX / per_stream) return fail(RP_EINVAL, "rp_fill_law: size overflow");
+    int rc = ensure_device_tables();
+    if (rc) return rc;
+    a.words = s->d_words;
+    a.phase = s->d_phase;
+    a.n = s->n;
+    a.per_stream = per_stream;
+    a.out = d_out;
+    return launch_fill_law(s->engine, law, a, (hipStream_t)hip_stream);
 }
 
 // ---------------------------------------------------------------------------

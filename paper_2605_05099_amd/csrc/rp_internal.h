@@ -58,9 +58,12 @@ struct FillArgs {
     uint64_t bound;    // Lemire bound (0 = full range)
     uint64_t thresh;   // Lemire threshold (2^w - b) mod b
     int flags;
+    double xp[4];      // transform parameters of rp_fill_law (host-formed)
 };
 
 int launch_fill(int engine, int dist, int dtype, const FillArgs &a, hipStream_t stream);
+// rp_fill_law: the base fill of the law with its transform fused at the store
+int launch_fill_law(int engine, int law, const FillArgs &a, hipStream_t stream);
 
 // lane-per-substream samplers (k_samplers.h)
 struct SampArgs {

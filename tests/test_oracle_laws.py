@@ -1,0 +1,58 @@
+"""Pins of the derived laws' oracle (CPU only): each transform of Table 4,
+applied to the oracle's own base draws, must give the law it names -- a
+Kolmogorov-Smirnov test against SciPy's distribution with the paper's
+parameterization (a swapped parameter, a wrong sign or a scale taken as a
+rate fails it) -- and the special cases that reduce to another law must."""
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle
+from oracle import laws
+
+N = 20000
+
+CASES = [
+    (laws.UNIF, (-2.0, 5.0), stats.uniform(loc=-2.0, scale=7.0)),
+    (laws.NORMAL, (3.0, 5.0), stats.norm(loc=3.0, scale=5.0)),
+    (laws.LOGNORMAL, (0.5, 0.75), stats.lognorm(s=0.75, scale=np.exp(0.5))),
+    (laws.EXP, (2.5,), stats.expon(scale=2.5)),
+    (laws.GUMBEL, (1.0, 2.0), stats.gumbel_r(loc=1.0, scale=2.0)),
+    (laws.PARETO, (1.5, 3.0), stats.pareto(b=3.0, scale=1.5)),
+    (laws.GPARETO, (0.5, 2.0, 0.3), stats.genpareto(c=0.3, loc=0.5, scale=2.0)),
+    (laws.GPARETO, (0.5, 2.0, -0.4), stats.genpareto(c=-0.4, loc=0.5, scale=2.0)),
+    (laws.GPARETO, (0.5, 2.0, 0.0), stats.genpareto(c=0.0, loc=0.5, scale=2.0)),
+    (laws.WEIBULL, (1.7, 4.0), stats.weibull_min(c=1.7, scale=4.0)),
+]
+
+
+@pytest.mark.parametrize("law,p,dist", CASES, ids=lambda c: str(c) if not hasattr(c, "cdf") else "")
+def test_law_matches_its_distribution(law, p, dist):
+    s = oracle.Stream.seeded("x256++", 1000 + law)
+    x = laws.draw(s, law, p, N)
+    assert np.isfinite(x).all()
+    assert stats.kstest(x, dist.cdf).pvalue > 1e-3
+
+
+def test_special_cases():
+    s = oracle.Stream.seeded("pcg64", 5)
+    base = s.copy().exp(1000)
+    # Weibull with k = 1 and Exp(beta) are beta E; Pareto(1, alpha) is exp(E / alpha)
+    assert np.array_equal(laws.transform(laws.WEIBULL, base, (1.0, 2.5)), 2.5 * base ** 1.0)
+    assert np.array_equal(laws.transform(laws.EXP, base, (2.5,)), 2.5 * base)
+    # generalized Pareto with xi > 0 at mu = 0, s = xi: P - 1
+    P = laws.transform(laws.PARETO, base, (1.0, 1.0 / 0.5))
+    np.testing.assert_allclose(laws.transform(laws.GPARETO, base, (0.0, 0.5, 0.5)), P - 1.0, rtol=1e-12)
+    # Gumbel at u = exp(-1) is mu; normal and lognormal are exp-related
+    assert laws.transform(laws.GUMBEL, [np.exp(-1.0)], (3.0, 2.0))[0] == pytest.approx(3.0, abs=1e-15)
+    z = oracle.Stream.seeded("x256++", 9).norm(1000)
+    np.testing.assert_allclose(np.log(laws.transform(laws.LOGNORMAL, z, (0.3, 1.2))),
+                               laws.transform(laws.NORMAL, z, (0.3, 1.2)), rtol=1e-13, atol=1e-13)
+
+
+def test_draw_advances_like_the_base_fill():
+    a = oracle.Stream.seeded("philox4x32", 3)
+    b = a.copy()
+    laws.draw(a, laws.PARETO, (1.0, 2.0), 777)
+    b.exp(777)
+    assert a.state == b.state and a.phase == b.phase
