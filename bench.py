@@ -291,8 +291,10 @@ def part_moments(torch, rp, workloads, tm, sp):
 
 
 def part_laws(torch, rp, workloads, tm, sp):
-    """Derived laws (one transform fused into the base fill's store) on the
-    substream workload: Philox4x32-10, 2^16 substreams x 2^14 values."""
+    """Derived laws on the substream workload: Philox4x32-10, 2^16 substreams
+    x 2^14 values.  Transform laws fuse one transform into the base fill's
+    store; the laws of several draws per value (gamma, beta, chi-square, t,
+    F, skew-normal) run one lane per substream."""
     n, per = workloads.SUB_N, workloads.SUB_PER
     S = rp.rp_streams_create(rp.rp_create("philox4x32").seed(workloads.BASE_SEED), rp.RP_SUB_KEY, n)
     buf = torch.empty(n * per, dtype=torch.float64, device="cuda")
@@ -300,7 +302,11 @@ def part_laws(torch, rp, workloads, tm, sp):
     for name, law, p in (("unif", rp.RP_LAW_UNIF, (-2.0, 5.0)), ("normal", rp.RP_LAW_NORMAL, (3.0, 5.0)),
                          ("lognormal", rp.RP_LAW_LOGNORMAL, (0.5, 0.75)), ("exp", rp.RP_LAW_EXP, (2.5,)),
                          ("gumbel", rp.RP_LAW_GUMBEL, (1.0, 2.0)), ("pareto", rp.RP_LAW_PARETO, (1.5, 3.0)),
-                         ("gpareto", rp.RP_LAW_GPARETO, (0.5, 2.0, 0.3)), ("weibull", rp.RP_LAW_WEIBULL, (1.7, 4.0))):
+                         ("gpareto", rp.RP_LAW_GPARETO, (0.5, 2.0, 0.3)), ("weibull", rp.RP_LAW_WEIBULL, (1.7, 4.0)),
+                         ("gamma", rp.RP_LAW_GAMMA, (2.5, 1.5)), ("gamma_0.4", rp.RP_LAW_GAMMA, (0.4, 1.0)),
+                         ("beta", rp.RP_LAW_BETA, (2.0, 5.0)), ("chi2", rp.RP_LAW_CHI2, (3.0,)),
+                         ("t", rp.RP_LAW_T, (4.5,)), ("F", rp.RP_LAW_F, (5.0, 7.0)),
+                         ("skewnormal", rp.RP_LAW_SKEWNORMAL, (1.0, 2.0, 3.0))):
         ms = tm(lambda: rp.rp_fill_law(S, law, p, buf, per, sp), reps=3)
         res[name] = {"ms": round(ms, 4), "gsamples_s": round(n * per / ms / 1e6, 2),
                      "hbm_frac": round(8.0 * n * per / ms / 1e6 / HBM_PEAK_GBS, 4)}

@@ -173,9 +173,20 @@ int rp_fill(rp_streams *s, int dist, int dtype, uint64_t bound, int flags, void 
  *                    xi > 0: mu + s (P - 1) / xi; xi < 0: mu - s (1 - 1/P) / xi;
  *                    xi = 0: mu + s E
  *   RP_LAW_WEIBULL   Weibull(k,l),  p = {k, l}, both > 0:    l pow(E, inv), inv = 1/k
- * Parameters must be finite; others give RP_EINVAL.  d_out must be 8-byte
- * aligned device memory of n * per_stream doubles owned by the caller.
- * Asynchronous on hip_stream; per_stream = 0 does nothing. */
+ * Laws of several base draws per value (Marsaglia-Tsang gamma draws G with
+ * the shape < 1 boost, ziggurat normals Z, drawn in the order listed):
+ *   RP_LAW_GAMMA     Gamma(al,th),  p = {alpha, theta}, both > 0: theta G(alpha)
+ *   RP_LAW_BETA      Beta(a,b),     p = {a, b}, both > 0: X / (X + Y), X = G(a) then Y = G(b)
+ *   RP_LAW_CHI2      chi2(nu),      p = {nu}, nu > 0:   2 G(nu / 2)
+ *   RP_LAW_T         t(nu),         p = {nu}, nu > 0:   Z / sqrt(V / nu), Z then V = 2 G(nu / 2)
+ *   RP_LAW_F         F(nu1,nu2),    p = {nu1, nu2} > 0: (X / nu1) / (Y / nu2), X = G(nu1 / 2) then
+ *                                                      Y = G(nu2 / 2)
+ *   RP_LAW_SKEWNORMAL SN(mu,s,al),  p = {mu, s, alpha}, s >= 0: mu + s (d |Z0| + c Z1), Z0 then Z1,
+ *                    d = alpha / sqrt(1 + alpha^2), c = sqrt(1 - d^2) (Azzalini's construction)
+ * These run one lane per substream.  Parameters must be finite; others give
+ * RP_EINVAL.  d_out must be 8-byte aligned device memory of n * per_stream
+ * doubles owned by the caller.  Asynchronous on hip_stream; per_stream = 0
+ * does nothing. */
 enum {
     RP_LAW_UNIF = 1,
     RP_LAW_NORMAL = 2,
@@ -184,7 +195,13 @@ enum {
     RP_LAW_GUMBEL = 5,
     RP_LAW_PARETO = 6,
     RP_LAW_GPARETO = 7,
-    RP_LAW_WEIBULL = 8
+    RP_LAW_WEIBULL = 8,
+    RP_LAW_GAMMA = 9,
+    RP_LAW_BETA = 10,
+    RP_LAW_CHI2 = 11,
+    RP_LAW_T = 12,
+    RP_LAW_F = 13,
+    RP_LAW_SKEWNORMAL = 14
 };
 int rp_fill_law(rp_streams *s, int law, const double *p, int np, double *d_out, uint64_t per_stream,
                 void *hip_stream);

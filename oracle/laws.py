@@ -17,13 +17,28 @@ out as the paper gives it, in binary64 and in the order written:
   weibull(k, lam)     lam E^(1/k)
 
 U is the 53-bit uniform, Z and E the ziggurat normal and exponential of the
-same stream (Stream.u01 / norm / exp).  Pinned against the laws themselves in
-tests/test_oracle_laws.py.
+same stream (Stream.u01 / norm / exp).
+
+Laws of several base draws per value, G(a) the Marsaglia-Tsang gamma draw of
+the stream (Stream.gamma), drawn in the order written:
+
+  gamma(alpha, theta)  theta G(alpha)
+  beta(a, b)           X / (X + Y), X = G(a) then Y = G(b)    (Stream.beta)
+  chi2(nu)             2 G(nu / 2)                (gamma, alpha = nu/2, theta = 2)
+  t(nu)                Z / sqrt(V / nu), Z then V = 2 G(nu / 2)
+  f(nu1, nu2)          (X / nu1) / (Y / nu2), X = G(nu1 / 2) then Y = G(nu2 / 2)
+  skew_normal(mu, s, alpha)
+                       mu + s (d |Z0| + c Z1), Z0 then Z1, d = alpha / sqrt(1 + alpha^2),
+                       c = sqrt(1 - d^2)      (Azzalini's construction from two normals)
+
+Pinned against the laws themselves in tests/test_oracle_laws.py.
 """
 import numpy as np
 
 UNIF, NORMAL, LOGNORMAL, EXP, GUMBEL, PARETO, GPARETO, WEIBULL = range(1, 9)
-NPARAMS = {UNIF: 2, NORMAL: 2, LOGNORMAL: 2, EXP: 1, GUMBEL: 2, PARETO: 2, GPARETO: 3, WEIBULL: 2}
+GAMMA, BETA, CHI2, T, F, SKEWNORMAL = range(9, 15)
+NPARAMS = {UNIF: 2, NORMAL: 2, LOGNORMAL: 2, EXP: 1, GUMBEL: 2, PARETO: 2, GPARETO: 3, WEIBULL: 2,
+           GAMMA: 2, BETA: 2, CHI2: 1, T: 1, F: 2, SKEWNORMAL: 3}
 BASE = {UNIF: "u01", NORMAL: "norm", LOGNORMAL: "norm", EXP: "exp", GUMBEL: "u01", PARETO: "exp",
         GPARETO: "exp", WEIBULL: "exp"}
 
@@ -67,4 +82,36 @@ def transform(law, base, p):
 
 def draw(stream, law, p, n):
     """n draws of the law from one oracle stream (advancing it)."""
-    return transform(law, getattr(stream, BASE[law])(n), p)
+    p = [float(v) for v in p]
+    if law in BASE:
+        return transform(law, getattr(stream, BASE[law])(n), p)
+    if law == GAMMA:
+        alpha, theta = p
+        return theta * stream.gamma(alpha, n)
+    if law == BETA:
+        return stream.beta(p[0], p[1], n)
+    if law == CHI2:
+        return 2.0 * stream.gamma(p[0] / 2.0, n)
+    if law == T:
+        (nu,) = p
+        out = np.empty(n)
+        for k in range(n):
+            z = stream.norm(1)[0]
+            v = 2.0 * stream.gamma(nu / 2.0, 1)[0]
+            out[k] = z / np.sqrt(v / nu)
+        return out
+    if law == F:
+        nu1, nu2 = p
+        out = np.empty(n)
+        for k in range(n):
+            x = stream.gamma(nu1 / 2.0, 1)[0]
+            y = stream.gamma(nu2 / 2.0, 1)[0]
+            out[k] = (x / nu1) / (y / nu2)
+        return out
+    if law == SKEWNORMAL:
+        mu, s, alpha = p
+        d = alpha / np.sqrt(1.0 + alpha * alpha)
+        c = np.sqrt(1.0 - d * d)
+        z = stream.norm(2 * n).reshape(n, 2)
+        return mu + s * (d * np.abs(z[:, 0]) + c * z[:, 1])
+    raise ValueError(f"unknown law {law}")

@@ -25,7 +25,7 @@ RP_RAW, RP_U01, RP_BOUNDED, RP_NORM, RP_EXP = range(5)
 RP_U64, RP_U32, RP_F64, RP_F32 = range(4)
 RP_FLAG_52BIT = 1
 (RP_LAW_UNIF, RP_LAW_NORMAL, RP_LAW_LOGNORMAL, RP_LAW_EXP, RP_LAW_GUMBEL, RP_LAW_PARETO, RP_LAW_GPARETO,
- RP_LAW_WEIBULL) = range(1, 9)
+ RP_LAW_WEIBULL, RP_LAW_GAMMA, RP_LAW_BETA, RP_LAW_CHI2, RP_LAW_T, RP_LAW_F, RP_LAW_SKEWNORMAL) = range(1, 15)
 
 ENGINES = {"x256++": RP_X256PP, "pcg64": RP_PCG64, "philox4x32": RP_PHILOX4X32, "philox": RP_PHILOX,
            "sfc64": RP_SFC64, "ranlux++": RP_RANLUX}

@@ -975,8 +975,8 @@ extern "C" int rp_fill_law(rp_streams *s, int law, const double *p, int np, doub
                            void *hip_stream)
 {
     if (!s) return fail(RP_ENULL, "rp_fill_law: NULL streams");
-    static const int kParams[9] = {0, 2, 2, 2, 1, 2, 2, 3, 2};
-    if (law < RP_LAW_UNIF || law > RP_LAW_WEIBULL) return fail(RP_EINVAL, "rp_fill_law: unknown law %d", law);
+    static const int kParams[15] = {0, 2, 2, 2, 1, 2, 2, 3, 2, 2, 2, 1, 1, 2, 3};
+    if (law < RP_LAW_UNIF || law > RP_LAW_SKEWNORMAL) return fail(RP_EINVAL, "rp_fill_law: unknown law %d", law);
     if (np != kParams[law]) return fail(RP_EINVAL, "rp_fill_law: law %d takes %d parameters, not %d", law, kParams[law], np);
     if (!p) return fail(RP_ENULL, "rp_fill_law: NULL parameters");
     for (int k = 0; k < np; k++)
@@ -1025,6 +1025,33 @@ extern "C" int rp_fill_law(rp_streams *s, int law, const double *p, int np, doub
         a.xp[2] = 1.0 / p[0];
         ok = ok && std::isfinite(a.xp[2]);
         break;
+    case RP_LAW_GAMMA:
+    case RP_LAW_BETA:
+        ok = p[0] > 0.0 && p[1] > 0.0;
+        a.xp[0] = p[0];
+        a.xp[1] = p[1];
+        break;
+    case RP_LAW_CHI2:
+    case RP_LAW_T:
+        ok = p[0] > 0.0 && p[0] / 2.0 > 0.0;
+        a.xp[0] = p[0] / 2.0;
+        a.xp[1] = p[0];
+        break;
+    case RP_LAW_F:
+        ok = p[0] / 2.0 > 0.0 && p[1] / 2.0 > 0.0;
+        a.xp[0] = p[0] / 2.0;
+        a.xp[1] = p[1] / 2.0;
+        break;
+    case RP_LAW_SKEWNORMAL: {
+        ok = p[1] >= 0.0;
+        const double dl = p[2] / std::sqrt(1.0 + p[2] * p[2]);
+        a.xp[0] = p[0];
+        a.xp[1] = p[1];
+        a.xp[2] = dl;
+        a.xp[3] = std::sqrt(1.0 - dl * dl);
+        ok = ok && std::isfinite(dl);
+        break;
+    }
     }
     if (!ok) return fail(RP_EINVAL, "rp_fill_law: parameters outside the law's domain");
     if (per_stream == 0) return RP_OK;
@@ -1038,6 +1065,7 @@ extern "C" int rp_fill_law(rp_streams *s, int law, const double *p, int np, doub
     a.n = s->n;
     a.per_stream = per_stream;
     a.out = d_out;
+    if (law >= RP_LAW_GAMMA) return launch_fill_mix(s->engine, law, a, (hipStream_t)hip_stream);
     return launch_fill_law(s->engine, law, a, (hipStream_t)hip_stream);
 }
 

@@ -342,8 +342,12 @@ __device__ __forceinline__ GamParam gam_param(double a)
 // words used and the decisions are those of the serial sampler: a rejected
 // candidate or attempt is followed by a fresh one, as in its loops.  Beta
 // draws X ~ Gamma(a), then Y ~ Gamma(b), then returns X / (X + Y).
-template <bool BETA>
+// MODE 0: Gamma(a) draws; 1: Beta(a, b) = X / (X + Y); 2: the F ratio
+// (X / nu1) / (Y / nu2) of X ~ Gamma(a), Y ~ Gamma(b), nu1 = 2a, nu2 = 2b (both
+// doublings exact).  X is drawn before Y.
+template <int MODE>
 struct GamMachine {
+    static constexpr bool BETA = MODE != 0;
     GamParam pa, pb;
     bool second;
     double X;
@@ -384,6 +388,10 @@ struct GamMachine {
             return false;
         }
         second = false;
+        if constexpr (MODE == 2) {
+            val = (X / (2.0 * pa.a)) / (g / (2.0 * pb.a));
+            return true;
+        }
         const double t = X + g;
         val = (t == 0.0) ? pa.a / (pa.a + pb.a) : X / t;
         return true;
@@ -488,6 +496,108 @@ __global__ __launch_bounds__(256) void k_norm_rows(SampArgs s)
         }
     }
     if (s.advance) eng.store(s.f, i);
+}
+
+// Derived laws that need more than one base draw per value (Table 4):
+// chi-square, Student t, F, skew-normal, and gamma / beta with scalar
+// parameters, one lane per substream writing its own run of per_stream
+// values, each a state machine that takes at most four words per step:
+//   GAMMA   theta G,  G ~ Gamma(alpha)              xp = {alpha, theta}
+//   BETA    X / (X + Y), X ~ Gamma(a), Y ~ Gamma(b) xp = {a, b}
+//   CHI2    2 G, G ~ Gamma(nu / 2)                  xp = {nu / 2}
+//   T       Z / sqrt(V / nu), Z normal, then V = 2 G, G ~ Gamma(nu / 2)
+//                                                   xp = {nu / 2, nu}
+//   F       (X / nu1) / (Y / nu2), X ~ Gamma(nu1 / 2), Y ~ Gamma(nu2 / 2)
+//                                                   xp = {nu1 / 2, nu2 / 2}
+//   SKEW    mu + sigma (delta |U0| + c U1), U0 then U1 normal,
+//           delta = alpha / sqrt(1 + alpha^2), c = sqrt(1 - delta^2)
+//                                                   xp = {mu, sigma, delta, c}
+template <class E, int LAW>
+__global__ __launch_bounds__(256) void k_fill_mix(FillArgs f)
+{
+    __shared__ ZigLds zt;
+    __shared__ LogLds lt;
+    load_zig<RP_NORM>(&zt);
+    load_logt(&lt);
+    __syncthreads();
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= f.n) return;
+    E eng;
+    eng.load(f, i);
+    const uint64_t P = f.per_stream;
+    double *out = (double *)f.out + i * P;
+    constexpr int GM = LAW == RP_LAW_BETA ? 1 : (LAW == RP_LAW_F ? 2 : 0);
+    GamMachine<GM> gm;
+    NormMachine nm;
+    nm.reset();
+    if constexpr (LAW == RP_LAW_GAMMA) gm.set(f.xp[0], 1.0);
+    else if constexpr (LAW == RP_LAW_BETA) gm.set(f.xp[0], f.xp[1]);
+    else if constexpr (LAW == RP_LAW_F) gm.set(f.xp[0], f.xp[1]);
+    else gm.set(f.xp[0], 1.0);
+    int phase = 0;  // t and skew-normal: which draw of the value is being made
+    double z0 = 0.0;
+    for (uint64_t t = 0; t < P;) {
+        eng.reserve(4);
+        double v;
+        if constexpr (LAW == RP_LAW_GAMMA || LAW == RP_LAW_BETA || LAW == RP_LAW_F || LAW == RP_LAW_CHI2) {
+            if (gm.step(eng, &zt, &lt, v)) {
+                if constexpr (LAW == RP_LAW_GAMMA) v = f.xp[1] * v;
+                if constexpr (LAW == RP_LAW_CHI2) v = 2.0 * v;
+                out[t++] = v;
+            }
+        } else if constexpr (LAW == RP_LAW_T) {
+            if (phase == 0) {
+                if (nm.step(eng, &zt, z0)) phase = 1;
+            } else if (gm.step(eng, &zt, &lt, v)) {
+                out[t++] = z0 / sqrt((2.0 * v) / f.xp[1]);
+                phase = 0;
+            }
+        } else {  // skew-normal
+            if (nm.step(eng, &zt, v)) {
+                if (phase == 0) {
+                    z0 = v;
+                    phase = 1;
+                } else {
+                    out[t++] = f.xp[0] + f.xp[1] * (f.xp[2] * fabs(z0) + f.xp[3] * v);
+                    phase = 0;
+                }
+            }
+        }
+    }
+    eng.store(f, i);
+}
+
+template <class E>
+static int launch_mix_e(int law, const FillArgs &f, hipStream_t st)
+{
+    const dim3 grid((unsigned)((f.n + 255) / 256)), block(256);
+    switch (law) {
+    case RP_LAW_GAMMA: hipLaunchKernelGGL((k_fill_mix<E, RP_LAW_GAMMA>), grid, block, 0, st, f); break;
+    case RP_LAW_BETA: hipLaunchKernelGGL((k_fill_mix<E, RP_LAW_BETA>), grid, block, 0, st, f); break;
+    case RP_LAW_CHI2: hipLaunchKernelGGL((k_fill_mix<E, RP_LAW_CHI2>), grid, block, 0, st, f); break;
+    case RP_LAW_T: hipLaunchKernelGGL((k_fill_mix<E, RP_LAW_T>), grid, block, 0, st, f); break;
+    case RP_LAW_F: hipLaunchKernelGGL((k_fill_mix<E, RP_LAW_F>), grid, block, 0, st, f); break;
+    case RP_LAW_SKEWNORMAL: hipLaunchKernelGGL((k_fill_mix<E, RP_LAW_SKEWNORMAL>), grid, block, 0, st, f); break;
+    default: return fail(RP_EINVAL, "unknown law");
+    }
+    return RP_OK;
+}
+
+int launch_fill_mix(int engine, int law, const FillArgs &f, hipStream_t st)
+{
+    int rc;
+    switch (engine) {
+    case RP_X256PP: rc = launch_mix_e<LaneX256>(law, f, st); break;
+    case RP_PCG64: rc = launch_mix_e<LanePcg>(law, f, st); break;
+    case RP_PHILOX4X32: rc = launch_mix_e<LanePhilox32>(law, f, st); break;
+    case RP_PHILOX: rc = launch_mix_e<LanePhilox64>(law, f, st); break;
+    case RP_SFC64: rc = launch_mix_e<LaneSfc64>(law, f, st); break;
+    case RP_RANLUX: rc = launch_mix_e<LaneRanlux>(law, f, st); break;
+    default: return fail(RP_EINVAL, "unknown engine");
+    }
+    if (rc) return rc;
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RP_OK : fail(RP_EDEVICE, "law fill launch: %s", hipGetErrorString(e));
 }
 
 template <class E>

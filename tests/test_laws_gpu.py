@@ -152,3 +152,89 @@ def test_law_errors():
     assert (S.get()[0] == before).all()
     rp.rp_fill_law(S, rp.RP_LAW_EXP, (1.0,), out, 0)     # per_stream = 0 does nothing
     assert (S.get()[0] == before).all()
+
+
+MIX = [
+    (rp.RP_LAW_GAMMA, (2.5, 1.5)),
+    (rp.RP_LAW_GAMMA, (0.4, 3.0)),
+    (rp.RP_LAW_BETA, (2.0, 5.0)),
+    (rp.RP_LAW_BETA, (0.5, 0.7)),
+    (rp.RP_LAW_CHI2, (3.0,)),
+    (rp.RP_LAW_CHI2, (0.8,)),
+    (rp.RP_LAW_T, (4.5,)),
+    (rp.RP_LAW_F, (5.0, 7.0)),
+    (rp.RP_LAW_SKEWNORMAL, (1.0, 2.0, 3.0)),
+]
+MIX_IDS = [f"law{l}_{'_'.join(str(v) for v in p)}" for l, p in MIX]
+
+
+@pytest.mark.parametrize("law,p", MIX, ids=MIX_IDS)
+@pytest.mark.parametrize("engine", ["philox4x32", "pcg64", "x256++", "sfc64"])
+def test_mix_law_matches_oracle(engine, law, p):
+    """Laws of several draws per value: every decision (so every state) is
+    the oracle's; values differ by the boost's power (4 ulp per gamma draw,
+    shape < 1), the ziggurat tails and a division or square root: within 64
+    eps of the value (skew-normal: of its terms)."""
+    n = 64
+    per = 150 if law in (rp.RP_LAW_T, rp.RP_LAW_F) else 300
+    S = make_streams(engine, n)
+    out = torch.empty(n * per, dtype=torch.float64, device="cuda")
+    rp.rp_fill_law(S, law, p, out, per)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().reshape(n, per)
+    ost = [oracle_stream(engine, i) for i in range(n)]
+    for i, o in enumerate(ost):
+        ref = laws.draw(o, law, p, per)
+        scale = np.abs(ref)
+        if law == rp.RP_LAW_SKEWNORMAL:
+            scale = scale + abs(p[0]) + p[1] * (np.abs(ref - p[0]) / p[1] + 10.0)
+        bad = ~(np.abs(got[i] - ref) <= 64 * EPS * scale) & ~(got[i] == ref)
+        assert not bad.any(), (engine, i, int(np.argmax(bad)), float(got[i][bad][0]), float(ref[bad][0]))
+    _states_equal(S, engine, ost)
+
+
+def test_mix_law_errors():
+    S = make_streams("philox4x32", 4)
+    out = torch.empty(16, dtype=torch.float64, device="cuda")
+    for law, p in ((rp.RP_LAW_GAMMA, (0.0, 1.0)), (rp.RP_LAW_BETA, (1.0, -1.0)), (rp.RP_LAW_CHI2, (0.0,)),
+                   (rp.RP_LAW_T, (-2.0,)), (rp.RP_LAW_F, (1.0, 0.0)), (rp.RP_LAW_SKEWNORMAL, (0.0, -1.0, 1.0)),
+                   (rp.RP_LAW_T, (1.0, 2.0)), (rp.RP_LAW_SKEWNORMAL, (0.0, 1.0, float("inf")))):
+        with pytest.raises(rp.RpError) as ei:
+            rp.rp_fill_law(S, law, p, out, 4)
+        assert ei.value.code == rp.RP_EINVAL, (law, p)
+
+
+def test_mix_law_ranlux_lanes_and_continuation():
+    """ranlux++ (block engine with the table step): two mixture laws in a row
+    continue the substreams where the first left them."""
+    n, per = 64, 200
+    S = make_streams("ranlux++", n)
+    ost = [oracle_stream("ranlux++", i) for i in range(n)]
+    for law, p in ((rp.RP_LAW_GAMMA, (0.7, 1.0)), (rp.RP_LAW_SKEWNORMAL, (0.0, 1.0, -1.5))):
+        out = torch.empty(n * per, dtype=torch.float64, device="cuda")
+        rp.rp_fill_law(S, law, p, out, per)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().reshape(n, per)
+        for i, o in enumerate(ost):
+            ref = laws.draw(o, law, p, per)
+            tol = 64 * EPS * (np.abs(ref) + (10.0 if law == rp.RP_LAW_SKEWNORMAL else 0.0))
+            assert (np.abs(got[i] - ref) <= tol).all(), (law, i)
+    _states_equal(S, "ranlux++", ost)
+
+
+def test_mix_law_full_size_sampled():
+    """Gamma and t at the substream workload's size (2^16 x 2^14 values):
+    sampled substreams in full."""
+    n, per = workloads.SUB_N, workloads.SUB_PER
+    S = make_streams("philox4x32", n)
+    out = torch.empty(n * per, dtype=torch.float64, device="cuda")
+    idx = workloads.sampled_substreams(n, k=32)
+    ost = [oracle_stream("philox4x32", int(i)) for i in idx]
+    for law, p in ((rp.RP_LAW_GAMMA, (2.5, 1.5)), (rp.RP_LAW_T, (4.5,))):
+        rp.rp_fill_law(S, law, p, out, per)
+        torch.cuda.synchronize()
+        got = out.view(n, per)[torch.as_tensor(idx, device="cuda")].cpu().numpy()
+        for k, o in enumerate(ost):
+            ref = laws.draw(o, law, p, per)
+            assert (np.abs(got[k] - ref) <= 64 * EPS * np.abs(ref)).all(), (law, int(idx[k]))
+    del out

@@ -23,13 +23,22 @@ CASES = [
     (laws.GPARETO, (0.5, 2.0, -0.4), stats.genpareto(c=-0.4, loc=0.5, scale=2.0)),
     (laws.GPARETO, (0.5, 2.0, 0.0), stats.genpareto(c=0.0, loc=0.5, scale=2.0)),
     (laws.WEIBULL, (1.7, 4.0), stats.weibull_min(c=1.7, scale=4.0)),
+    (laws.GAMMA, (2.5, 1.5), stats.gamma(a=2.5, scale=1.5)),
+    (laws.GAMMA, (0.4, 3.0), stats.gamma(a=0.4, scale=3.0)),
+    (laws.BETA, (2.0, 5.0), stats.beta(2.0, 5.0)),
+    (laws.CHI2, (3.0,), stats.chi2(df=3.0)),
+    (laws.CHI2, (0.8,), stats.chi2(df=0.8)),
+    (laws.T, (4.5,), stats.t(df=4.5)),
+    (laws.F, (5.0, 7.0), stats.f(dfn=5.0, dfd=7.0)),
+    (laws.SKEWNORMAL, (1.0, 2.0, 3.0), stats.skewnorm(a=3.0, loc=1.0, scale=2.0)),
+    (laws.SKEWNORMAL, (0.0, 1.0, -1.5), stats.skewnorm(a=-1.5, loc=0.0, scale=1.0)),
 ]
 
 
 @pytest.mark.parametrize("law,p,dist", CASES, ids=lambda c: str(c) if not hasattr(c, "cdf") else "")
 def test_law_matches_its_distribution(law, p, dist):
     s = oracle.Stream.seeded("x256++", 1000 + law)
-    x = laws.draw(s, law, p, N)
+    x = laws.draw(s, law, p, N if law not in (laws.T, laws.F) else N // 4)
     assert np.isfinite(x).all()
     assert stats.kstest(x, dist.cdf).pvalue > 1e-3
 
