@@ -40,6 +40,7 @@ struct PcgAffineDev {
 };
 __constant__ PcgAffineDev c_pcg_lane[65];  // A^(8l), G_(8l) for l = 0..64 (8 words per lane)
 __constant__ PcgAffineDev c_pcg_pow2[64];  // A^(2^k), G_(2^k)
+__constant__ PcgAffineDev c_pcg_s127;      // A^127, G_127 (direct order: pair to pair)
 __constant__ uint32_t c_rl_B[kRlL * kRlL];  // ranlux++ folded step table (rl_mul_tab)
 
 static PcgAffineDev to_dev(const PcgAffine &p) { return {p.mult.lo, p.mult.hi, p.plus.lo, p.plus.hi}; }
@@ -74,8 +75,12 @@ int ensure_device_tables()
         pow2[k] = to_dev(p);
         p = compose(p, p);
     }
+    PcgAffine s127{{1, 0}, {0, 0}};
+    for (int k = 0; k < 127; k++) s127 = compose(step, s127);
+    const PcgAffineDev s127d = to_dev(s127);
     e = hipMemcpyToSymbol(HIP_SYMBOL(c_pcg_lane), lane, sizeof lane);
     if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_pcg_pow2), pow2, sizeof pow2);
+    if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_pcg_s127), &s127d, sizeof s127d);
     if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_rl_B), ranlux_B(), sizeof c_rl_B);
     if (e != hipSuccess) return fail(RP_EDEVICE, "uploading constant tables: %s", hipGetErrorString(e));
     done[dev] = true;
@@ -172,6 +177,14 @@ __device__ __forceinline__ bool wedge_accept(const ZigLds *t, int j, double x, u
 // positions are counted from the start of the block (or state) the substream
 // pointed at when the call began.  Per-substream values (keys, increments) are
 // wave-uniform and live in scalar registers.
+//
+// Direct order (fills of one item per word or half, which need no parse):
+// the same chunk, but lane l holds groups of G consecutive words at positions
+// 64 G k + G l .. 64 G k + G l + G - 1, k = 0 .. R/G - 1, so that one store
+// instruction per group covers 64 G consecutive words with no transpose
+// through LDS.  G is the engine's block size (2 for Philox4x32-10 and PCG64,
+// 4 for Philox-4x64).  load_direct / gen_direct replace load / gen /
+// next_chunk; gen_direct also moves to the next chunk.
 static constexpr int kWaveR = 8;
 
 __device__ __forceinline__ uint64_t uni64(uint64_t v)
@@ -195,6 +208,25 @@ struct WavePhilox32 {
         phase0 = __builtin_amdgcn_readfirstlane(a.phase[i]);
         clo = b0lo + (uint64_t)(lane * (R / 2));
         chi = b0hi + (clo < b0lo ? 1u : 0u);
+    }
+    static constexpr int G = 2;
+    __device__ void load_direct(const FillArgs &a, uint64_t i, int lane)
+    {
+        load(a, i, lane);
+        clo = b0lo + (uint64_t)lane;  // block 64 k + lane of the chunk
+        chi = b0hi + (clo < b0lo ? 1u : 0u);
+    }
+    __device__ void gen_direct(uint64_t w[R])
+    {
+        uint64_t kk = key;
+        asm volatile("" : "+s"(kk));
+#pragma unroll
+        for (int k = 0; k < R / 2; k++) {
+            uint64_t lo = clo + (uint64_t)(64 * k);
+            uint64_t hi = chi + (lo < clo ? 1u : 0u);
+            philox4x32(lo, hi, kk, w[2 * k], w[2 * k + 1]);
+        }
+        next_chunk();
     }
     __device__ void gen(uint64_t w[R]) const
     {
@@ -257,6 +289,22 @@ struct WavePhilox64 {
         phase0 = __builtin_amdgcn_readfirstlane(a.phase[i]);
         add256(b0, (uint64_t)(lane * (R / 4)), c);
     }
+    static constexpr int G = 4;
+    __device__ void load_direct(const FillArgs &a, uint64_t i, int lane)
+    {
+        load(a, i, lane);
+        add256(b0, (uint64_t)lane, c);  // block 64 k + lane of the chunk
+    }
+    __device__ void gen_direct(uint64_t w[R])
+    {
+#pragma unroll
+        for (int k = 0; k < R / 4; k++) {
+            uint64_t blk[4];
+            add256(c, (uint64_t)(64 * k), blk);
+            philox4x64(blk, k0, k1, &w[4 * k]);
+        }
+        next_chunk();
+    }
     __device__ void gen(uint64_t w[R]) const
     {
 #pragma unroll
@@ -303,6 +351,32 @@ struct WavePcg {
         inc = u128{uni64(a.words[2 * a.n + i]), uni64(a.words[3 * a.n + i])};
         phase0 = 0;
         s = pcg_apply(c_pcg_lane[lane], s0, inc);
+    }
+    // direct order: words 128 k + 2 l and 128 k + 2 l + 1; from the second
+    // of a pair to the first of the next pair is 127 steps (A^127 s + c127,
+    // c127 = G_127 inc formed once)
+    static constexpr int G = 2;
+    u128 c127;
+    __device__ void load_direct(const FillArgs &a, uint64_t i, int lane)
+    {
+        s0 = u128{uni64(a.words[i]), uni64(a.words[a.n + i])};
+        inc = u128{uni64(a.words[2 * a.n + i]), uni64(a.words[3 * a.n + i])};
+        phase0 = 0;
+        s = pcg_jump(s0, inc, 2 * (uint64_t)lane);
+        c127 = mul128(u128{c_pcg_s127.plo, c_pcg_s127.phi}, inc);
+    }
+    __device__ void gen_direct(uint64_t w[R])
+    {
+        const u128 m{c_pcg_s127.mlo, c_pcg_s127.mhi};
+        u128 t = s;
+#pragma unroll
+        for (int k = 0; k < R / 2; k++) {
+            w[2 * k] = pcg_dxsm(t);
+            t = pcg_step(t, inc);
+            w[2 * k + 1] = pcg_dxsm(t);
+            t = add128(mul128(m, t), c127);
+        }
+        s = t;
     }
     __device__ void gen(uint64_t w[R]) const
     {
@@ -585,7 +659,8 @@ __global__ __launch_bounds__(256) void k_fill_wave(FillArgs a)
     T *const out = (T *)a.out + sub * P;
 
     E eng;
-    eng.load(a, sub, lane);
+    if constexpr (FIXED) eng.load_direct(a, sub, lane);
+    else eng.load(a, sub, lane);
     int e = (int)eng.phase0 * IPW;  // items of this chunk already used
     uint64_t produced = 0;
     uint64_t final_pos = 0;         // words from the start, after the last value
@@ -597,58 +672,63 @@ __global__ __launch_bounds__(256) void k_fill_wave(FillArgs a)
     // reached; it only guarantees that the wavefront exits.
     const uint64_t max_chunks = 2 * (P / CHW) + 1024;
     for (uint64_t chunk = 0; chunk < max_chunks; chunk++) {
-        // ---- generate R consecutive words per lane, transpose through LDS:
-        //      afterwards w[r] is the word at chunk position 64 r + lane ----
-        {
-            uint64_t g[R];
-            eng.gen(g);
-#pragma unroll
-            for (int k = 0; k < R; k += 2) {
-                ulonglong2 q;
-                q.x = g[k];
-                q.y = g[k + 1];
-                *(ulonglong2 *)(wbuf + wpos(R * lane + k)) = q;
-            }
-            eng.next_chunk();
-        }
-        wave_sync();
-        uint64_t w[R];
-#pragma unroll
-        for (int r = 0; r < R; r++) w[r] = wbuf[wpos(64 * r + lane)];
         const uint64_t base_pos = chunk * CHW;
+        uint64_t w[R];
+        if constexpr (FIXED) {
+            // direct order: w[j] is the word at chunk position
+            // 64 G (j / G) + G lane + j % G
+            eng.gen_direct(w);
+        } else {
+            // ---- generate R consecutive words per lane, transpose through
+            //      LDS: afterwards w[r] is the word at chunk position
+            //      64 r + lane ----
+            {
+                uint64_t g[R];
+                eng.gen(g);
+#pragma unroll
+                for (int k = 0; k < R; k += 2) {
+                    ulonglong2 q;
+                    q.x = g[k];
+                    q.y = g[k + 1];
+                    *(ulonglong2 *)(wbuf + wpos(R * lane + k)) = q;
+                }
+                eng.next_chunk();
+            }
+            wave_sync();
+#pragma unroll
+            for (int r = 0; r < R; r++) w[r] = wbuf[wpos(64 * r + lane)];
+        }
 
         if constexpr (FIXED) {
+            constexpr int G = E::G;
             const uint64_t need = P - produced;
             const uint64_t got = (uint64_t)(IPW * CHW - e);
             T *dst = out + produced - e;  // item q of the chunk goes to dst[q]
-            if constexpr (IPW == 1) {
+            // a whole chunk in range: unpredicated stores, which the compiler
+            // merges into one 16-byte store per pair of u64 / f64 or per four
+            // u32 / f32 (dword alignment suffices on gfx950)
+            T v[IPW * R];
 #pragma unroll
-                for (int r = 0; r < R; r++) {
-                    T v;
-                    item_value<DIST, OT>(w[r], a, v);
-                    if constexpr (XF != 0) v = xform<XF>(v, a);
-                    const int q = 64 * r + lane;
-                    if (q >= e && (uint64_t)(q - e) < need) dst[q] = v;
+            for (int j = 0; j < R; j++) {
+                if constexpr (IPW == 1) {
+                    item_value<DIST, OT>(w[j], a, v[j]);
+                    if constexpr (XF != 0) v[j] = xform<XF>(v[j], a);
+                } else {
+                    item_value<DIST, OT>(w[j] & 0xffffffffull, a, v[2 * j]);
+                    item_value<DIST, OT>(w[j] >> 32, a, v[2 * j + 1]);
                 }
-            } else {
-                const bool al8 = (((uintptr_t)dst) & 7) == 0;
+            }
+            // item i of this lane sits at chunk item q(i)
+            auto qof = [&](int i) { return IPW * (64 * G * ((i / IPW) / G) + G * lane + (i / IPW) % G) + i % IPW; };
+            if (e == 0 && need >= (uint64_t)(IPW * CHW)) {
+                T *d = dst + qof(0);
 #pragma unroll
-                for (int r = 0; r < R; r++) {
-                    T v0, v1;
-                    item_value<DIST, OT>(w[r] & 0xffffffffull, a, v0);
-                    item_value<DIST, OT>(w[r] >> 32, a, v1);
-                    const int q = 2 * (64 * r + lane);
-                    const bool ok0 = q >= e && (uint64_t)(q - e) < need;
-                    const bool ok1 = q + 1 >= e && (uint64_t)(q + 1 - e) < need;
-                    if (al8 && ok0 && ok1) {
-                        uint2 pr;
-                        pr.x = __builtin_bit_cast(uint32_t, v0);
-                        pr.y = __builtin_bit_cast(uint32_t, v1);
-                        *(uint2 *)(dst + q) = pr;
-                    } else {
-                        if (ok0) dst[q] = v0;
-                        if (ok1) dst[q + 1] = v1;
-                    }
+                for (int i = 0; i < IPW * R; i++) d[qof(i) - qof(0)] = v[i];
+            } else {
+#pragma unroll
+                for (int i = 0; i < IPW * R; i++) {
+                    const int q = qof(i);
+                    if (q >= e && (uint64_t)(q - e) < need) dst[q] = v[i];
                 }
             }
             if (got >= need) {
