@@ -49,7 +49,7 @@ def parse():
     p.add_argument("--no-parts", action="store_true", help="time only the ten-fill step")
     p.add_argument("--parts", default=None,
                    help="comma-separated parts to time after the step: serial, batched, elem, mvn, "
-                        "moments, laws, setup (default all; none with --only)")
+                        "moments, laws, float, setup (default all; none with --only)")
     p.add_argument("--only", default="", help="comma-separated fill names to run (profiling)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="run only plain fill/copy kernels of known size (counter calibration)")
@@ -166,6 +166,8 @@ def parts(torch, rp, workloads, stream, only):
         out.update(part_moments(torch, rp, workloads, tm, sp))
     if "laws" in only:
         out.update(part_laws(torch, rp, workloads, tm, sp))
+    if "float" in only:
+        out.update(part_float(torch, rp, workloads, tm, sp))
     if "setup" in only:
         out.update(part_setup(torch, rp, workloads))
     return out
@@ -314,6 +316,23 @@ def part_laws(torch, rp, workloads, tm, sp):
     return {"laws_philox4x32_2p16x2p14": res}
 
 
+def part_float(torch, rp, workloads, tm, sp):
+    """Float ziggurat normal and exponential (binary32 draws from 32-bit
+    items) on the substream workload, both wavefront engines."""
+    n, per = workloads.SUB_N, workloads.SUB_PER
+    buf = torch.empty(n * per, dtype=torch.float32, device="cuda")
+    res = {}
+    for eng, kind in (("philox4x32", rp.RP_SUB_KEY), ("pcg64", rp.RP_SUB_INC)):
+        S = rp.rp_streams_create(rp.rp_create(eng).seed(workloads.BASE_SEED), kind, n)
+        for name, dist in (("normal_f32", rp.RP_NORM), ("exp_f32", rp.RP_EXP)):
+            ms = tm(lambda: rp.rp_fill(S, dist, rp.RP_F32, 0, 0, buf, per, sp), reps=3)
+            res[f"{eng}/{name}"] = {"ms": round(ms, 4), "gsamples_s": round(n * per / ms / 1e6, 2),
+                                    "hbm_frac": round(4.0 * n * per / ms / 1e6 / HBM_PEAK_GBS, 4)}
+        del S
+    del buf
+    return {"float_zig_2p16x2p14": res}
+
+
 def part_setup(torch, rp, workloads):
     """Substream construction (host seeding and per-substream keys, increments,
     spawn keys or jumps, then the copy to device), timed on its own: it is
@@ -437,7 +456,7 @@ def main():
                      "algorithmic_bytes_per_launch": total * dom[4], "avg_launch_ms": round(dom_ms, 4)},
         "rows": rows,
     }
-    want = args.parts if args.parts is not None else ("" if args.only else "serial,batched,elem,mvn,moments,laws,setup")
+    want = args.parts if args.parts is not None else ("" if args.only else "serial,batched,elem,mvn,moments,laws,float,setup")
     if not args.no_parts and want:
         result["parts"] = parts(torch, rp, workloads, stream, set(want.split(",")))
     if not args.no_cpu_baseline:

@@ -139,8 +139,8 @@ enum {
     RP_U01 = 1,     /* uniform [0,1): F64 from the top 53 bits (or 52, flag),*/
                     /*   F32 from the top 24 bits of a 32-bit half (or 23)   */
     RP_BOUNDED = 2, /* {0..b-1} by Lemire's method, U64 or U32; b = 0: full  */
-    RP_NORM = 3,    /* standard normal, ziggurat, F64                        */
-    RP_EXP = 4      /* standard exponential, ziggurat, F64                   */
+    RP_NORM = 3,    /* standard normal, ziggurat, F64 (or F32, see below)    */
+    RP_EXP = 4      /* standard exponential, ziggurat, F64 (or F32)          */
 };
 enum { RP_U64 = 0, RP_U32 = 1, RP_F64 = 2, RP_F32 = 3 };
 enum { RP_FLAG_52BIT = 1 }; /* uniform method 2 (mantissa fill, 52/23 bits) */
@@ -150,7 +150,15 @@ enum { RP_FLAG_52BIT = 1 }; /* uniform method 2 (mantissa fill, 52/23 bits) */
  * past the words it used, so a second call continues the streams.  32-bit
  * outputs use the two halves of each word, low first; a half left over at
  * the end of a call is dropped.  d_out must hold n * per_stream elements of
- * dtype and be aligned to the element size. */
+ * dtype and be aligned to the element size.
+ *
+ * RP_NORM / RP_EXP with RP_F32 are the float versions of the two samplers
+ * (Section 4.4, float versions): each draw reads 32-bit items; strip = low
+ * byte, normal sign = bit 8, magnitude = the remaining 23 (normal) or 24
+ * (exponential) bits; candidate and tests are the binary64 ziggurat's for
+ * the magnitude m 2^29 (same tables); wedge and tail uniforms are 24-bit
+ * uniforms of the following items; the value is rounded once to binary32.
+ * rp_fill_serial has no float form of these two samplers. */
 int rp_fill(rp_streams *s, int dist, int dtype, uint64_t bound, int flags, void *d_out,
             uint64_t per_stream, void *hip_stream);
 

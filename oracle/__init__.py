@@ -48,6 +48,7 @@ def lib():
             "or_bounded64": ([vp, u64, vp, sz], None),
             "or_bounded32": ([vp, ctypes.c_uint32, vp, sz], None),
             "or_norm": ([vp, vp, sz, vp], None), "or_exp": ([vp, vp, sz, vp], None),
+            "or_normf": ([vp, vp, sz], None), "or_expf": ([vp, vp, sz], None),
             "or_norm_moments": ([vp, sz, vp, vp], None),
             "or_gamma": ([vp, ctypes.c_double, vp, sz, vp], None),
             "or_beta": ([vp, ctypes.c_double, ctypes.c_double, vp, sz], None),
@@ -206,6 +207,18 @@ class Stream:
     def exp(self, n, counts=None):
         out = np.empty(n, dtype=np.float64)
         lib().or_exp(_p(self.buf), _p(out), n, _p(counts.buf) if counts else None)
+        return out
+
+    def normf(self, n):
+        """n binary32 standard normals from 32-bit items (float ziggurat)."""
+        out = np.empty(n, dtype=np.float32)
+        lib().or_normf(_p(self.buf), _p(out), n)
+        return out
+
+    def expf(self, n):
+        """n binary32 standard exponentials from 32-bit items (float ziggurat)."""
+        out = np.empty(n, dtype=np.float32)
+        lib().or_expf(_p(self.buf), _p(out), n)
         return out
 
     def norm_moments(self, n):

@@ -27,6 +27,7 @@
  *   u01 / u01f / bounded ints              pinned: NumPy Generator
  *   ziggurat normal                        pinned: NumPy layout/ratio test, geometry, rates, KS
  *   ziggurat exponential                   pinned: geometry, paper's rejection rate, KS
+ *   float ziggurat (normf, expf)           pinned: KS, fast-accept rates, strip boundaries, tails
  *   gamma (alpha >= 1)                     pinned: NumPy Marsaglia-Tsang, moments, KS
  *   gamma boost (alpha < 1), beta          pinned: mpmath power, moments, KS
  */
@@ -940,6 +941,70 @@ static double exp_one(or_stream *s, or_counts *c)
         if (y < exp(-x)) return x;
         if (c) c->rejections++;
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Float ziggurat (the paper's float versions: a binary32 function for each  */
+/* continuous law; it states only that the float case is analogous to the   */
+/* double one).  Reading taken here: a float draw consumes 32-bit items of    */
+/* the word stream (low half first, as every 32-bit consumer).  Strip j =     */
+/* low byte; normal: bit 8 = sign, bits 9..31 = 23-bit magnitude m;           */
+/* exponential: bits 8..31 = 24-bit magnitude m.  The candidate and every     */
+/* test are those of the double ziggurat for the magnitude m 2^29 (the same  */
+/* geometry and tables), in binary64; wedge and tail uniforms are 24-bit     */
+/* float uniforms of the following items.  The returned value is the        */
+/* binary64 result rounded once to binary32.                                  */
+/* ------------------------------------------------------------------------ */
+static double u01_24(uint32_t u) { return (double)(u >> 8) * 0x1.0p-24; }
+
+static float normf_one(half_reader *h)
+{
+    for (;;) {
+        uint32_t u = next32(h);
+        int j = (int)(u & 0xff);
+        int neg = (int)((u >> 8) & 1);
+        uint64_t m = (uint64_t)(u >> 9) << 29;
+        double x = (double)m * OR_NORM_W[j];
+        if (m < OR_NORM_K[j]) return (float)(neg ? -x : x);
+        if (j == 0) {
+            for (;;) {
+                double e1 = -log1p(-u01_24(next32(h))) / OR_NORM_R;
+                double e2 = -log1p(-u01_24(next32(h)));
+                if (e2 + e2 > e1 * e1) {
+                    double t = OR_NORM_R + e1;
+                    return (float)(neg ? -t : t);
+                }
+            }
+        }
+        double y = OR_NORM_F[j] + u01_24(next32(h)) * (OR_NORM_F[j - 1] - OR_NORM_F[j]);
+        if (y < exp(-0.5 * x * x)) return (float)(neg ? -x : x);
+    }
+}
+
+static float expf_one(half_reader *h)
+{
+    for (;;) {
+        uint32_t u = next32(h);
+        int j = (int)(u & 0xff);
+        uint64_t m = (uint64_t)(u >> 8) << 29;
+        double x = (double)m * OR_EXP_W[j];
+        if (m < OR_EXP_K[j]) return (float)x;
+        if (j == 0) return (float)(OR_EXP_R - log1p(-u01_24(next32(h))));
+        double y = OR_EXP_F[j] + u01_24(next32(h)) * (OR_EXP_F[j - 1] - OR_EXP_F[j]);
+        if (y < exp(-x)) return (float)x;
+    }
+}
+
+void or_normf(or_stream *s, float *out, size_t n)
+{
+    half_reader h = {s, 0, 0};
+    for (size_t i = 0; i < n; i++) out[i] = normf_one(&h);
+}
+
+void or_expf(or_stream *s, float *out, size_t n)
+{
+    half_reader h = {s, 0, 0};
+    for (size_t i = 0; i < n; i++) out[i] = expf_one(&h);
 }
 
 void or_norm(or_stream *s, double *out, size_t n, or_counts *c)

@@ -102,6 +102,26 @@ __device__ __forceinline__ double u01_52(uint64_t w)
     return __longlong_as_double((long long)((w >> 12) | 0x3ff0000000000000ull)) - 1.0;
 }
 __device__ __forceinline__ float u01f_24(uint32_t u) { return (float)(u >> 8) * 0x1.0p-24f; }
+// float ziggurat: the wedge / tail uniform of a 32-bit item, exact in binary64
+__device__ __forceinline__ double u01_24d(uint64_t it) { return (double)((uint32_t)it >> 8) * 0x1.0p-24; }
+// The float ziggurat reads 32-bit items: strip = low byte, normal sign = bit
+// 8, magnitude = the remaining 23 (normal) or 24 (exponential) bits.  It is
+// the binary64 ziggurat run on the magnitude m 2^29, i.e. on the word with
+// the same low byte (and sign) and m 2^29 in the magnitude field.
+template <int DIST>
+__device__ __forceinline__ uint64_t item_word(uint64_t it)
+{
+    const uint32_t u = (uint32_t)it;
+    if (DIST == RP_NORM) return (uint64_t)(u & 0x1ffu) | ((uint64_t)(u >> 9) << 38);
+    return (uint64_t)(u & 0xffu) | ((uint64_t)(u >> 8) << 37);
+}
+// the uniform of a follow-up word (binary64 draws) or item (float draws)
+template <bool HALF>
+__device__ __forceinline__ double zig_u(uint64_t w)
+{
+    if constexpr (HALF) return u01_24d(w);
+    else return (double)(w >> 11) * 0x1.0p-53;
+}
 __device__ __forceinline__ float u01f_23(uint32_t u) { return __uint_as_float((u >> 9) | 0x3f800000u) - 1.0f; }
 
 __device__ __forceinline__ u128 pcg_apply(const PcgAffineDev &m, u128 s, u128 inc)
@@ -158,10 +178,10 @@ __device__ __forceinline__ void load_zig(ZigLds *t)
 // decides most cases without exp(); its bounds carry a margin far above the
 // rounding of the secant and of exp, so a squeeze decision always equals the
 // plain test evaluated in binary64.
-template <int DIST>
+template <int DIST, bool HALF = false>
 __device__ __forceinline__ bool wedge_accept(const ZigLds *t, int j, double x, uint64_t uword)
 {
-    double U = u01_53(uword);
+    double U = zig_u<HALF>(uword);
     double fj = t->F[j], fj1 = t->F[j - 1];
     double y = fj + U * (fj1 - fj);
     double l = fj1 + t->S[j] * (x - t->X[j - 1]);
@@ -208,6 +228,27 @@ struct WavePhilox32 {
         phase0 = __builtin_amdgcn_readfirstlane(a.phase[i]);
         clo = b0lo + (uint64_t)(lane * (R / 2));
         chi = b0hi + (clo < b0lo ? 1u : 0u);
+    }
+    // float draws: R / 2 words per lane (R / 4 blocks), 32 R words per chunk
+    __device__ void load_half(const FillArgs &a, uint64_t i, int lane)
+    {
+        load(a, i, lane);
+        clo = b0lo + (uint64_t)(lane * (R / 4));
+        chi = b0hi + (clo < b0lo ? 1u : 0u);
+    }
+    __device__ void gen_half(uint64_t w[R / 2])
+    {
+        uint64_t kk = key;
+        asm volatile("" : "+s"(kk));
+#pragma unroll
+        for (int k = 0; k < R / 4; k++) {
+            uint64_t lo = clo + (uint64_t)k;
+            uint64_t hi = chi + (lo < clo ? 1u : 0u);
+            philox4x32(lo, hi, kk, w[2 * k], w[2 * k + 1]);
+        }
+        const uint64_t o = clo;
+        clo += 64 * (R / 4);
+        chi += (clo < o) ? 1u : 0u;
     }
     static constexpr int G = 2;
     __device__ void load_direct(const FillArgs &a, uint64_t i, int lane)
@@ -289,6 +330,18 @@ struct WavePhilox64 {
         phase0 = __builtin_amdgcn_readfirstlane(a.phase[i]);
         add256(b0, (uint64_t)(lane * (R / 4)), c);
     }
+    // float draws: R / 2 = 4 words (one block) per lane, 64 blocks per chunk
+    static_assert(R == 8, "one block per lane for float draws");
+    __device__ void load_half(const FillArgs &a, uint64_t i, int lane)
+    {
+        load(a, i, lane);
+        add256(b0, (uint64_t)lane, c);
+    }
+    __device__ void gen_half(uint64_t w[R / 2])
+    {
+        philox4x64(c, k0, k1, w);
+        add256(c, 64, c);
+    }
     static constexpr int G = 4;
     __device__ void load_direct(const FillArgs &a, uint64_t i, int lane)
     {
@@ -351,6 +404,26 @@ struct WavePcg {
         inc = u128{uni64(a.words[2 * a.n + i]), uni64(a.words[3 * a.n + i])};
         phase0 = 0;
         s = pcg_apply(c_pcg_lane[lane], s0, inc);
+    }
+    // float draws: words (R / 2) l .. (R / 2) l + R / 2 - 1 of a 32 R-word
+    // chunk; the next chunk is A^(32 R) = A^256 away
+    static_assert(R == 8, "A^256 advances a float-draw chunk");
+    __device__ void load_half(const FillArgs &a, uint64_t i, int lane)
+    {
+        s0 = u128{uni64(a.words[i]), uni64(a.words[a.n + i])};
+        inc = u128{uni64(a.words[2 * a.n + i]), uni64(a.words[3 * a.n + i])};
+        phase0 = 0;
+        s = pcg_jump(s0, inc, (uint64_t)(R / 2) * (uint64_t)lane);
+    }
+    __device__ void gen_half(uint64_t w[R / 2])
+    {
+        u128 t = s;
+#pragma unroll
+        for (int k = 0; k < R / 2; k++) {
+            w[k] = pcg_dxsm(t);
+            if (k + 1 < R / 2) t = pcg_step(t, inc);
+        }
+        s = pcg_apply(c_pcg_pow2[8], s, inc);
     }
     // direct order: words 128 k + 2 l and 128 k + 2 l + 1; from the second
     // of a pair to the first of the next pair is 127 steps (A^127 s + c127,
@@ -447,9 +520,10 @@ __device__ __forceinline__ uint32_t mbcnt64(uint64_t mask)
 // Fast ziggurat test of one word as the first word of a sample.  Returns true
 // when the sample is accepted from this word alone (value in val); otherwise
 // the word starts a wedge test or the tail and needs the next word(s).
-template <int DIST>
-__device__ __forceinline__ bool zig_fast(const WKe *wk, uint64_t w, double &val)
+template <int DIST, bool HALF = false>
+__device__ __forceinline__ bool zig_fast(const WKe *wk, uint64_t w_or_item, double &val)
 {
+    const uint64_t w = HALF ? item_word<DIST>(w_or_item) : w_or_item;
     const int j = (int)(w & 0xff);
     const WKe e = wk[j];
     if (DIST == RP_NORM) {
@@ -489,10 +563,11 @@ __device__ __forceinline__ void wave_sync()
 __device__ __noinline__ double exp_ool(double x) { return exp(x); }
 __device__ __noinline__ double log1p_ool(double x) { return log1p(x); }
 // one pair of the normal tail test: accepted iff e2 + e2 > e1 e1; t = r + e1
+template <bool HALF>
 __device__ __noinline__ bool normal_tail_pair(uint64_t a, uint64_t b, double &t)
 {
-    const double e1 = -log1p(-u01_53(a)) / RP_ZN_R;
-    const double e2 = -log1p(-u01_53(b));
+    const double e1 = -log1p(-zig_u<HALF>(a)) / RP_ZN_R;
+    const double e2 = -log1p(-zig_u<HALF>(b));
     t = RP_ZN_R + e1;
     return e2 + e2 > e1 * e1;
 }
@@ -515,7 +590,7 @@ struct ZigG {
     static __device__ __forceinline__ double DM(int j) { return opaque(DIST == RP_NORM ? RP_ZN_DM : RP_ZE_DM)[j]; }
 };
 
-template <int DIST, class Word>
+template <int DIST, bool HALF, class Word>
 __device__ __forceinline__ int zig_resolve(const WKe *t, uint64_t w0, Word word, int avail, bool &accepted,
                                            double &val, bool &has_u1, uint64_t &u1)
 {
@@ -527,11 +602,11 @@ __device__ __forceinline__ int zig_resolve(const WKe *t, uint64_t w0, Word word,
         const uint64_t u = word(1);
         if (j != 0) {
             double x;
-            zig_fast<DIST>(t, w0, x);
+            zig_fast<DIST, HALF>(t, w0, x);
             val = x;
             // the wedge test of wedge_accept, with the exp out of line
             const double ax = DIST == RP_NORM ? fabs(x) : x;
-            const double U = u01_53(u);
+            const double U = zig_u<HALF>(u);
             using G = ZigG<DIST>;
             const double fj = G::F(j), fj1 = G::F(j - 1);
             const double y = fj + U * (fj1 - fj);
@@ -540,7 +615,7 @@ __device__ __forceinline__ int zig_resolve(const WKe *t, uint64_t w0, Word word,
             else if (y > l + G::DP(j)) accepted = false;
             else accepted = y < exp_ool(DIST == RP_NORM ? -0.5 * ax * ax : -ax);
         } else {
-            val = RP_ZE_R - log1p_ool(-u01_53(u));
+            val = RP_ZE_R - log1p_ool(-zig_u<HALF>(u));
             accepted = true;
         }
         return 2;
@@ -555,7 +630,7 @@ __device__ __forceinline__ int zig_resolve(const WKe *t, uint64_t w0, Word word,
             return 0;
         }
         double tt;
-        if (normal_tail_pair(word(1 + 2 * it), word(2 + 2 * it), tt)) {
+        if (normal_tail_pair<HALF>(word(1 + 2 * it), word(2 + 2 * it), tt)) {
             val = ((w0 >> 8) & 1) ? -tt : tt;
             accepted = true;
             return 3 + 2 * it;
@@ -613,7 +688,7 @@ __device__ __forceinline__ double xform(double v, const FillArgs &a)
 }
 
 template <class E, int DIST, int OT, int XF = 0>
-__global__ __launch_bounds__(256) void k_fill_wave(FillArgs a)
+__global__ __launch_bounds__(256, (DIST == RP_NORM || (DIST == RP_EXP && OT == RP_F32)) ? 5 : 1) void k_fill_wave(FillArgs a)
 {
     using T = typename OutType<DIST, OT>::T;
     constexpr int R = E::R;              // words per lane per chunk
@@ -622,6 +697,9 @@ __global__ __launch_bounds__(256) void k_fill_wave(FillArgs a)
     constexpr bool ZIG = DIST == RP_NORM || DIST == RP_EXP;
     constexpr bool FIXED = DIST == RP_RAW || DIST == RP_U01;
     constexpr int IPW = (OT == RP_U32 || OT == RP_F32) ? 2 : 1;  // items per word
+    // float ziggurat: the chunk holds 64 R 32-bit items (32 R words), and
+    // every position below counts items; the state store converts back
+    constexpr bool ZH = ZIG && IPW == 2;
 
     const int wib = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
@@ -660,6 +738,7 @@ __global__ __launch_bounds__(256) void k_fill_wave(FillArgs a)
 
     E eng;
     if constexpr (FIXED) eng.load_direct(a, sub, lane);
+    else if constexpr (ZH) eng.load_half(a, sub, lane);
     else eng.load(a, sub, lane);
     int e = (int)eng.phase0 * IPW;  // items of this chunk already used
     uint64_t produced = 0;
@@ -682,7 +761,19 @@ __global__ __launch_bounds__(256) void k_fill_wave(FillArgs a)
             // ---- generate R consecutive words per lane, transpose through
             //      LDS: afterwards w[r] is the word at chunk position
             //      64 r + lane ----
-            {
+            if constexpr (ZH) {
+                // R / 2 words per lane: items R lane .. R lane + R - 1, the
+                // low half of each word first
+                uint64_t g[R / 2];
+                eng.gen_half(g);
+#pragma unroll
+                for (int k = 0; k < R / 2; k++) {
+                    ulonglong2 q;
+                    q.x = g[k] & 0xffffffffull;
+                    q.y = g[k] >> 32;
+                    *(ulonglong2 *)(wbuf + wpos(R * lane + 2 * k)) = q;
+                }
+            } else {
                 uint64_t g[R];
                 eng.gen(g);
 #pragma unroll
@@ -792,7 +883,7 @@ __global__ __launch_bounds__(256) void k_fill_wave(FillArgs a)
 #pragma unroll
                 for (int r = 0; r < R; r++) {
                     double v0;
-                    const bool f = zig_fast<DIST>(zt, w[r], v0);
+                    const bool f = zig_fast<DIST, ZH>(zt, w[r], v0);
                     fb |= (f ? 1u : 0u) << r;
                     lb |= (f ? 0u : 1u) << r;
                 }
@@ -851,7 +942,7 @@ __global__ __launch_bounds__(256) void k_fill_wave(FillArgs a)
                         q = cp ? -1 : (int)sp;
                         const int off = cp ? -1 - hu : q;
                         w0 = cp ? pend_w : wbuf[wpos(q)];
-                        L = zig_resolve<DIST>(
+                        L = zig_resolve<DIST, ZH>(
                             zt, w0, [&](int kk) { return (hu && kk == 1) ? pend_u1 : wbuf[wpos(off + kk)]; },
                             cp ? CHW + hu : CHW - 1 - q, acc, v, hu_out, u1o);
                     }
@@ -950,7 +1041,7 @@ __global__ __launch_bounds__(256) void k_fill_wave(FillArgs a)
                         if ((fo >> lane) & 1) {
                             // the value again from the word (cheaper than keeping R values live)
                             double v0;
-                            zig_fast<DIST>(zt, wbuf[wpos(64 * r + lane)], v0);
+                            zig_fast<DIST, ZH>(zt, wbuf[wpos(64 * r + lane)], v0);
                             dst[total + mbcnt64(om)] = xform<XF>(v0, a);
                         }
                         if (lane == 0) {
@@ -977,7 +1068,7 @@ __global__ __launch_bounds__(256) void k_fill_wave(FillArgs a)
                         if ((fo >> lane) & 1) {
                             const uint32_t idx = total + mbcnt64(om);
                             double v0;
-                            zig_fast<DIST>(zt, wbuf[wpos(64 * r + lane)], v0);
+                            zig_fast<DIST, ZH>(zt, wbuf[wpos(64 * r + lane)], v0);
                             if (idx < need) dst[idx] = xform<XF>(v0, a);
                         }
                         if (lane == 0) {
@@ -1017,7 +1108,8 @@ __global__ __launch_bounds__(256) void k_fill_wave(FillArgs a)
         }
         wave_sync();  // the next chunk overwrites wbuf
     }
-    if (lane == 0) eng.store(a, sub, final_pos);
+    // float draws: a high half left over at the end of the call is dropped
+    if (lane == 0) eng.store(a, sub, ZH ? (final_pos + 1) / 2 : final_pos);
 }
 
 // ---------------------------------------------------------------------------
@@ -1159,11 +1251,14 @@ struct LaneRanlux {
 };
 
 // serial ziggurat (identical decisions to the wavefront classifier)
-template <int DIST, class E>
-__device__ double zig_serial(const ZigLds *t, E &eng)
+// One serial ziggurat draw.  next() yields the next 64-bit word (binary64
+// draws) or 32-bit item (float draws, HALF).
+template <int DIST, bool HALF, class Next>
+__device__ __forceinline__ double zig_serial_g(const ZigLds *t, Next next)
 {
     for (;;) {
-        const uint64_t w = eng.next();
+        const uint64_t it = next();
+        const uint64_t w = HALF ? item_word<DIST>(it) : it;
         const int j = (int)(w & 0xff);
         if (DIST == RP_NORM) {
             const uint64_t m = (w >> 9) & ((1ull << 52) - 1);
@@ -1172,9 +1267,9 @@ __device__ double zig_serial(const ZigLds *t, E &eng)
             const double x = (double)m * e.w;
             if (m < e.k) return neg ? -x : x;
             if (j == 0) {
-                for (int it = 0; it < kMaxTailIters; it++) {
-                    const double e1 = -log1p(-u01_53(eng.next())) / RP_ZN_R;
-                    const double e2 = -log1p(-u01_53(eng.next()));
+                for (int k = 0; k < kMaxTailIters; k++) {
+                    const double e1 = -log1p(-zig_u<HALF>(next())) / RP_ZN_R;
+                    const double e2 = -log1p(-zig_u<HALF>(next()));
                     if (e2 + e2 > e1 * e1) {
                         const double tt = RP_ZN_R + e1;
                         return neg ? -tt : tt;
@@ -1182,16 +1277,22 @@ __device__ double zig_serial(const ZigLds *t, E &eng)
                 }
                 continue;  // unreachable in practice (see kMaxTailIters)
             }
-            if (wedge_accept<DIST>(t, j, x, eng.next())) return neg ? -x : x;
+            if (wedge_accept<DIST, HALF>(t, j, x, next())) return neg ? -x : x;
         } else {
             const uint64_t m = (w >> 8) & ((1ull << 53) - 1);
             const WKe e = t->WK[j];
             const double x = (double)m * e.w;
             if (m < e.k) return x;
-            if (j == 0) return RP_ZE_R - log1p(-u01_53(eng.next()));
-            if (wedge_accept<DIST>(t, j, x, eng.next())) return x;
+            if (j == 0) return RP_ZE_R - log1p(-zig_u<HALF>(next()));
+            if (wedge_accept<DIST, HALF>(t, j, x, next())) return x;
         }
     }
+}
+
+template <int DIST, class E>
+__device__ double zig_serial(const ZigLds *t, E &eng)
+{
+    return zig_serial_g<DIST, false>(t, [&]() { return eng.next(); });
 }
 
 template <class E, int DIST, int OT, int XF = 0>
@@ -1216,7 +1317,21 @@ __global__ __launch_bounds__(256) void k_fill_lane(FillArgs a)
     bool have = false;
     uint32_t hi = 0;
     for (uint64_t t = 0; t < P;) {
-        if constexpr (ZIG) {
+        if constexpr (ZIG && HALF) {
+            eng.reserve(2);
+            out[t++] = (T)xform<XF>(zig_serial_g<DIST, true>(zt,
+                                                           [&]() -> uint64_t {
+                                                               if (have) {
+                                                                   have = false;
+                                                                   return hi;
+                                                               }
+                                                               const uint64_t w = eng.next();
+                                                               hi = (uint32_t)(w >> 32);
+                                                               have = true;
+                                                               return w & 0xffffffffull;
+                                                           }),
+                                    a);
+        } else if constexpr (ZIG) {
             eng.reserve(3);
             out[t++] = (T)xform<XF>(zig_serial<DIST>(zt, eng), a);
         } else {
@@ -1275,9 +1390,11 @@ static int dispatch_dist(int dist, int dtype, const FillArgs &a, hipStream_t st)
         return dtype == RP_U64 ? launch_one<WAVE, E, RP_BOUNDED, RP_U64>(a, st)
                                : launch_one<WAVE, E, RP_BOUNDED, RP_U32>(a, st);
     case RP_NORM:
-        return launch_one<WAVE, E, RP_NORM, RP_F64>(a, st);
+        return dtype == RP_F64 ? launch_one<WAVE, E, RP_NORM, RP_F64>(a, st)
+                               : launch_one<WAVE, E, RP_NORM, RP_F32>(a, st);
     case RP_EXP:
-        return launch_one<WAVE, E, RP_EXP, RP_F64>(a, st);
+        return dtype == RP_F64 ? launch_one<WAVE, E, RP_EXP, RP_F64>(a, st)
+                               : launch_one<WAVE, E, RP_EXP, RP_F32>(a, st);
     }
     return fail(RP_EINVAL, "unknown distribution");
 }

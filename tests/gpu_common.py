@@ -28,7 +28,12 @@ def oracle_stream(engine, i, seed=42, jump_log2=64):
 
 
 def ulp_diff(a, b):
-    """Distance in units of the last place between float64 arrays of equal sign."""
+    """Distance in units of the last place between float arrays of equal sign
+    (binary32 arrays in binary32 ulps, anything else in binary64 ulps)."""
+    if np.asarray(a).dtype == np.float32 and np.asarray(b).dtype == np.float32:
+        ia = np.asarray(a).view(np.int32).astype(np.int64)
+        ib = np.asarray(b).view(np.int32).astype(np.int64)
+        return np.abs(ia - ib)
     ia = np.asarray(a, dtype=np.float64).view(np.int64)
     ib = np.asarray(b, dtype=np.float64).view(np.int64)
     return np.abs(ia - ib)
@@ -44,9 +49,9 @@ def oracle_fill(s, dist, dtype, n, bound=0, flags=0):
     if dist == rp.RP_BOUNDED:
         return s.bounded64(bound, n) if dtype == rp.RP_U64 else s.bounded32(bound, n)
     if dist == rp.RP_NORM:
-        return s.norm(n)
+        return s.norm(n) if dtype == rp.RP_F64 else s.normf(n)
     if dist == rp.RP_EXP:
-        return s.exp(n)
+        return s.exp(n) if dtype == rp.RP_F64 else s.expf(n)
     raise ValueError(dist)
 
 

@@ -3,8 +3,11 @@
 Bit-exact for raw words, uniforms and bounded integers.  For the ziggurat the
 accept/reject decisions must all agree, which shows as the two sequences
 staying aligned; values are then equal except in the tail, where log1p may
-differ by an ulp (tolerance: 4 ulp).  The substream states left behind must
-equal the oracle's after the same draws, so a second call continues exactly.
+differ by an ulp (tolerance: 4 ulp; for the float draws 4 binary32 ulp, and
+a tail value rounds to binary32 identically unless log1p's last-bit
+difference straddles a binary32 rounding boundary).  The substream states
+left behind must equal the oracle's after the same draws, so a second call
+continues exactly.
 """
 import numpy as np
 import pytest
@@ -31,6 +34,8 @@ CASES = [
     (rp.RP_BOUNDED, rp.RP_U32, 2**31, 0),
     (rp.RP_NORM, rp.RP_F64, 0, 0),
     (rp.RP_EXP, rp.RP_F64, 0, 0),
+    (rp.RP_NORM, rp.RP_F32, 0, 0),
+    (rp.RP_EXP, rp.RP_F32, 0, 0),
 ]
 
 
@@ -78,18 +83,37 @@ def test_fill_matches_oracle(engine, case):
 
 
 @pytest.mark.parametrize("engine", ["philox4x32", "pcg64", "philox"])
-def test_ziggurat_long_run_with_tails(engine):
+@pytest.mark.parametrize("dtype", [rp.RP_F64, rp.RP_F32])
+def test_ziggurat_long_run_with_tails(engine, dtype):
     """Enough normals to cross many chunks and hit the tail path in the
     wavefront kernel (tail probability 2.6e-4 per sample)."""
     n, per = 20, 20000
     S = make_streams(engine, n)
-    got = _gpu_fill(S, rp.RP_NORM, rp.RP_F64, per, 0, 0)
+    got = _gpu_fill(S, rp.RP_NORM, dtype, per, 0, 0)
     tails = 0
     for i in range(n):
-        ref = oracle_stream(engine, i).norm(per)
+        o = oracle_stream(engine, i)
+        ref = o.norm(per) if dtype == rp.RP_F64 else o.normf(per)
         _compare(got[i], ref, rp.RP_NORM)
         tails += int((np.abs(ref) > 3.6541528853610088).sum())
     assert tails > 30
+
+
+@pytest.mark.parametrize("engine", ["philox4x32", "pcg64", "philox", "x256++", "sfc64"])
+def test_float_exponential_long_run_with_tails(engine):
+    """Float exponentials over many chunks; the tail (P = 4.5e-4) included."""
+    n, per = 16, 20000
+    S = make_streams(engine, n)
+    got = _gpu_fill(S, rp.RP_EXP, rp.RP_F32, per, 0, 0)
+    tails = 0
+    ost = {}
+    for i in range(n):
+        ost[i] = oracle_stream(engine, i)
+        ref = ost[i].expf(per)
+        _compare(got[i], ref, rp.RP_EXP)
+        tails += int((ref > 7.69711747013105).sum())
+    assert tails > 50
+    _states_equal(S, engine, ost)
 
 
 def test_zero_and_invalid():
@@ -99,7 +123,7 @@ def test_zero_and_invalid():
     rp.rp_fill(S, rp.RP_NORM, rp.RP_F64, 0, 0, t, 0)    # per_stream = 0 is a no-op
     assert (S.get()[0] == before).all()
     with pytest.raises(rp.RpError) as ei:
-        rp.rp_fill(S, rp.RP_NORM, rp.RP_F32, 0, 0, torch.empty(8, device="cuda"), 1)
+        rp.rp_fill(S, rp.RP_NORM, rp.RP_U64, 0, 0, torch.empty(8, dtype=torch.int64, device="cuda"), 1)
     assert ei.value.code == rp.RP_EUNSUPPORTED
     with pytest.raises(rp.RpError) as ei:
         rp.rp_fill(S, rp.RP_NORM, rp.RP_F64, 0, 0, 0, 4)
@@ -111,7 +135,8 @@ def test_zero_and_invalid():
 
 @pytest.mark.parametrize("engine,kind", [("philox4x32", "key"), ("pcg64", "inc")])
 @pytest.mark.parametrize("dist,dtype", [(rp.RP_RAW, rp.RP_U64), (rp.RP_U01, rp.RP_F32), (rp.RP_U01, rp.RP_F64),
-                                        (rp.RP_NORM, rp.RP_F64), (rp.RP_EXP, rp.RP_F64)])
+                                        (rp.RP_NORM, rp.RP_F64), (rp.RP_EXP, rp.RP_F64),
+                                        (rp.RP_NORM, rp.RP_F32), (rp.RP_EXP, rp.RP_F32)])
 def test_full_size_substreams_sampled(engine, kind, dist, dtype):
     """2^16 substreams x 2^14 values (the benchmark's launch); 258 substreams
     checked in full against the oracle."""
