@@ -54,7 +54,9 @@ enum {
     RP_PHILOX = 3,     /* "philox"     Philox-4x64-10, counter 4 + key 2    */
     RP_SFC64 = 4,      /* "sfc64"      sfc64, (a, b, c) + counter           */
     RP_RANLUX = 5,     /* "ranlux++"   ranlux++, 9 words (576-bit LCG)      */
-    RP_NENGINES = 6
+    RP_X256SS = 6,     /* "x256**"     xoshiro256**, 4 state words; seeding, */
+                       /*              jumps and substreams as x256++       */
+    RP_NENGINES = 7
 };
 
 typedef struct rp_rng rp_rng;         /* one serial stream, host resident  */

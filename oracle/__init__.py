@@ -17,8 +17,8 @@ import numpy as np
 from . import build as _build
 from . import jumppoly
 
-X256PP, PCG64, PHILOX4X32, PHILOX4X64, SFC64, RANLUX = range(6)
-ENGINE_IDS = {"x256++": X256PP, "pcg64": PCG64, "philox4x32": PHILOX4X32,
+X256PP, PCG64, PHILOX4X32, PHILOX4X64, SFC64, RANLUX, X256SS = range(7)
+ENGINE_IDS = {"x256++": X256PP, "x256**": X256SS, "pcg64": PCG64, "philox4x32": PHILOX4X32,
               "philox": PHILOX4X64, "sfc64": SFC64, "ranlux++": RANLUX}
 
 _lib = None
@@ -154,7 +154,7 @@ class Stream:
     def advance(self, n):
         """Move forward by n engine steps (blocks for block engines)."""
         n = int(n)
-        if self.engine == X256PP:
+        if self.engine in (X256PP, X256SS):
             p = jumppoly.x256_char_poly(lib())
             return self.x256_apply_poly(jumppoly.xpow_mod(n, p))
         if self.engine == PCG64:

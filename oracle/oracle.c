@@ -22,6 +22,7 @@
  *   philox4x32-10                          pinned: rocRAND host engine + derived Weyl constants
  *   xoshiro256++ linear core               pinned: primitive characteristic polynomial
  *   xoshiro256++ output scrambler          parity unpinned (no external implementation here)
+ *   xoshiro256** output scrambler          parity unpinned (no external implementation here)
  *   ranlux++                               pinned: modulus/multiplier/period, big-integer arithmetic
  *   seeding mixer (seed_seq_fe128)         pinned: NumPy SeedSequence
  *   u01 / u01f / bounded ints              pinned: NumPy Generator
@@ -52,7 +53,8 @@ enum {
     OR_PHILOX4X64 = 3,
     OR_SFC64 = 4,
     OR_RANLUX = 5,
-    OR_NENGINE = 6
+    OR_X256SS = 6,
+    OR_NENGINE = 7
 };
 
 /*
@@ -115,6 +117,16 @@ static void x256_linear(uint64_t s[4])
 static uint64_t x256pp_word(uint64_t s[4])
 {
     uint64_t out = rotl64(s[0] + s[3], 23) + s[0];
+    x256_linear(s);
+    return out;
+}
+
+/* xoshiro256** (Blackman and Vigna 2018; Table 2 "x256**"): the same linear
+ * map T, with the "**" output rotl(5 s1, 7) 9 of the state before the
+ * update.  Seeding, jumps and substreams are those of xoshiro256++. */
+static uint64_t x256ss_word(uint64_t s[4])
+{
+    uint64_t out = rotl64(s[1] * 5u, 7) * 9u;
     x256_linear(s);
     return out;
 }
@@ -480,6 +492,7 @@ static uint64_t next_word(or_stream *s)
 {
     switch (s->engine) {
     case OR_X256PP: return x256pp_word(s->st);
+    case OR_X256SS: return x256ss_word(s->st);
     case OR_PCG64: return pcg64_word(s->st);
     case OR_SFC64: return sfc64_word(s->st);
     default: {
@@ -563,6 +576,7 @@ static int seeded_words(uint64_t engine)
 {
     switch (engine) {
     case OR_X256PP: return 4;
+    case OR_X256SS: return 4;
     case OR_PCG64: return 4;
     case OR_PHILOX4X32: return 3;
     case OR_PHILOX4X64: return 6;
@@ -606,6 +620,7 @@ int or_seed(or_stream *s, uint64_t engine, uint64_t seed, const uint32_t *key, s
     s->engine = engine;
     switch (engine) {
     case OR_X256PP:
+    case OR_X256SS:
         memcpy(s->st, w, 4 * 8);
         if (!(w[0] | w[1] | w[2] | w[3])) s->st[0] = 1;
         break;
@@ -681,7 +696,7 @@ void or_sfc64_set_abc(or_stream *s, uint64_t a, uint64_t b, uint64_t c)
  *   s' = sum_k p_k T^k s. */
 int or_x256_apply_poly(or_stream *s, const uint64_t poly[4])
 {
-    if (s->engine != OR_X256PP) return -1;
+    if (s->engine != OR_X256PP && s->engine != OR_X256SS) return -1;
     uint64_t acc[4] = {0, 0, 0, 0}, cur[4];
     memcpy(cur, s->st, sizeof cur);
     for (int k = 0; k < 256; k++) {

@@ -68,6 +68,14 @@ struct X256 {
         linear();
         return r;
     }
+    // xoshiro256** (Table 2 "x256**"): the same linear map, output
+    // rotl(5 s1, 7) 9 of the state before the update
+    RP_HD uint64_t next_ss()
+    {
+        uint64_t r = rotl(s1 * 5u, 7) * 9u;
+        linear();
+        return r;
+    }
 };
 
 // ---------------------------------------------------------------------------

@@ -1114,13 +1114,15 @@ __global__ __launch_bounds__(256, (DIST == RP_NORM || (DIST == RP_EXP && OT == R
 
 // ---------------------------------------------------------------------------
 // lane-per-substream engines (serial word streams)
-struct LaneX256 {
+// xoshiro256++ (SS = false) and xoshiro256** (SS = true): one state, two outputs
+template <bool SS>
+struct LaneX256T {
     X256 s;
     __device__ void load(const FillArgs &a, uint64_t i)
     {
         s = X256{a.words[i], a.words[a.n + i], a.words[2 * a.n + i], a.words[3 * a.n + i]};
     }
-    __device__ uint64_t next() { return s.next(); }
+    __device__ uint64_t next() { return SS ? s.next_ss() : s.next(); }
     __device__ void reserve(int) {}
     __device__ void store(const FillArgs &a, uint64_t i) const
     {
@@ -1130,6 +1132,8 @@ struct LaneX256 {
         a.words[3 * a.n + i] = s.s3;
     }
 };
+using LaneX256 = LaneX256T<false>;
+using LaneX256SS = LaneX256T<true>;
 
 struct LaneSfc64 {
     Sfc64 s;
@@ -1407,6 +1411,7 @@ int launch_fill(int engine, int dist, int dtype, const FillArgs &a, hipStream_t 
     case RP_PHILOX: return dispatch_dist<true, WavePhilox64>(dist, dtype, a, st);
     case RP_PCG64: return dispatch_dist<true, WavePcg>(dist, dtype, a, st);
     case RP_X256PP: return dispatch_dist<false, LaneX256>(dist, dtype, a, st);
+    case RP_X256SS: return dispatch_dist<false, LaneX256SS>(dist, dtype, a, st);
     case RP_SFC64: return dispatch_dist<false, LaneSfc64>(dist, dtype, a, st);
     case RP_RANLUX: return dispatch_dist<false, LaneRanlux>(dist, dtype, a, st);
     }
@@ -1437,6 +1442,7 @@ int launch_fill_law(int engine, int law, const FillArgs &a, hipStream_t st)
     case RP_PHILOX: return dispatch_law<true, WavePhilox64>(law, a, st);
     case RP_PCG64: return dispatch_law<true, WavePcg>(law, a, st);
     case RP_X256PP: return dispatch_law<false, LaneX256>(law, a, st);
+    case RP_X256SS: return dispatch_law<false, LaneX256SS>(law, a, st);
     case RP_SFC64: return dispatch_law<false, LaneSfc64>(law, a, st);
     case RP_RANLUX: return dispatch_law<false, LaneRanlux>(law, a, st);
     }

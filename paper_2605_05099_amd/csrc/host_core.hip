@@ -85,6 +85,7 @@ static const EngineInfo kEngines[RP_NENGINES] = {
     {"philox", "Philox-4x64-10 (Salmon and Moraes, 2011), 6 state words, period 2^258 per key", 6, 4},
     {"sfc64", "sfc64 (Chris Doty-Humphrey, 2010), 4 state words, average period >= 2^64", 4, 1},
     {"ranlux++", "ranlux++ (Sibidanov, 2017), 9 state words, period about 2^570", 9, 9},
+    {"x256**", "xoshiro256** (Blackman and Vigna, 2018), 4 state words, period 2^256-1", 4, 1},
 };
 
 namespace rp {
@@ -409,9 +410,10 @@ static uint64_t host_next(rp_rng *r)
 {
     uint64_t *st = r->st;
     switch (r->engine) {
-    case RP_X256PP: {
+    case RP_X256PP:
+    case RP_X256SS: {
         X256 s{st[0], st[1], st[2], st[3]};
-        uint64_t w = s.next();
+        uint64_t w = r->engine == RP_X256SS ? s.next_ss() : s.next();
         st[0] = s.s0; st[1] = s.s1; st[2] = s.s2; st[3] = s.s3;
         return w;
     }
@@ -491,6 +493,7 @@ static void seed_state(rp_rng *r, uint64_t seed, const uint32_t *key, size_t n_k
     r->phase = 0;
     switch (r->engine) {
     case RP_X256PP:
+    case RP_X256SS:
         memcpy(r->st, w, 32);
         if (!(w[0] | w[1] | w[2] | w[3])) r->st[0] = 1;
         break;
@@ -589,6 +592,7 @@ static int advance_impl(rp_rng *rng, uint64_t lo, uint64_t hi)
     uint64_t *st = rng->st;
     switch (rng->engine) {
     case RP_X256PP:
+    case RP_X256SS:
         x256_apply(st, poly_xpow(lo, hi, x256_charpoly()));
         return RP_OK;
     case RP_PCG64: {
@@ -642,7 +646,8 @@ extern "C" int rp_jump(rp_rng *rng, int k)
         return fail_rng(rng, RP_EINVAL, "rp_jump: k must be 32, 64, 96, 128 or 192 (got %d)", k);
     if (k < 128) return advance_impl(rng, k < 64 ? (1ull << k) : 0, k >= 64 ? (1ull << (k - 64)) : 0);
     switch (rng->engine) {
-    case RP_X256PP: {
+    case RP_X256PP:
+    case RP_X256SS: {
         Poly x;
         x.flip(1);
         const Poly &P = x256_charpoly();
@@ -794,7 +799,7 @@ extern "C" int rp_streams_create(const rp_rng *base, int kind, uint64_t n, int j
     uint64_t jmul[9];
     PcgAffine jpcg{};
     if (kind == RP_SUB_JUMP && n > 1) {
-        if (e == RP_X256PP) {
+        if (e == RP_X256PP || e == RP_X256SS) {
             Poly base_x;
             base_x.flip(1);
             const Poly &P = x256_charpoly();
@@ -832,7 +837,7 @@ extern "C" int rp_streams_create(const rp_rng *base, int kind, uint64_t n, int j
         }
         case RP_SUB_JUMP:
             if (i > 0) {
-                if (e == RP_X256PP) x256_apply(jumped.st, jpoly);
+                if (e == RP_X256PP || e == RP_X256SS) x256_apply(jumped.st, jpoly);
                 else if (e == RP_RANLUX) rl_mulmod(jumped.st, jmul, jumped.st);
                 else if (e == RP_PCG64) {
                     u128 s{jumped.st[0], jumped.st[1]}, inc{jumped.st[2], jumped.st[3]};
@@ -1158,6 +1163,7 @@ void serial_tables(int engine, uint64_t C, uint64_t *jt)
     std::lock_guard<std::mutex> lock(g_ser.mu);
     switch (engine) {
     case RP_X256PP:
+    case RP_X256SS:
         if (g_ser.c_x256 != C) {
             // lanes l < 64: x^(l C) mod P; waves: x^(64 C 2^k), k < 12
             const Poly &P = x256_charpoly();

@@ -34,12 +34,12 @@ int serial_chunks_per_block() { return ser::kBlk; }
 template <int ENG>
 struct SerLane;
 
-// xoshiro256++: the wave's base by the jump polynomials x^(64 C 2^k) for the
-// set bits k of the wave index (uniform in the wave), then lane l applies
-// x^(l C) mod P.  All lanes of a wave share one orbit T^i b, i < 256, and
+// xoshiro256++ and xoshiro256** (one linear core): the wave's base by the
+// jump polynomials x^(64 C 2^k) for the set bits k of the wave index
+// (uniform in the wave), then lane l applies x^(l C) mod P.  All lanes of a wave share one orbit T^i b, i < 256, and
 // each accumulates the terms its own polynomial selects.
-template <>
-struct SerLane<RP_X256PP> : LaneX256 {
+template <bool SS>
+struct SerLaneX256 : LaneX256T<SS> {
     __device__ static X256 jump(X256 cur, uint64_t q0, uint64_t q1, uint64_t q2, uint64_t q3)
     {
         uint64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
@@ -64,9 +64,14 @@ struct SerLane<RP_X256PP> : LaneX256 {
                 b = jump(b, q[0], q[1], q[2], q[3]);
             }
         const uint64_t *q = &a.jt[4 * (id & 63)];
-        s = jump(b, q[0], q[1], q[2], q[3]);
+        this->s = jump(b, q[0], q[1], q[2], q[3]);
     }
 };
+
+template <>
+struct SerLane<RP_X256PP> : SerLaneX256<false> {};
+template <>
+struct SerLane<RP_X256SS> : SerLaneX256<true> {};
 
 // PCG64: affine maps (A^(C 2^k), G_(C 2^k)) for the set bits of the lane id.
 template <>
@@ -519,6 +524,7 @@ int launch_serial_fixed(int engine, int dist, int dtype, const SerialArgs &a, hi
     int rc;
     switch (engine) {
     case RP_X256PP: rc = ser_fixed_eng<RP_X256PP>(dist, dtype, a, st); break;
+    case RP_X256SS: rc = ser_fixed_eng<RP_X256SS>(dist, dtype, a, st); break;
     case RP_PCG64: rc = ser_fixed_eng<RP_PCG64>(dist, dtype, a, st); break;
     case RP_PHILOX4X32: rc = ser_fixed_eng<RP_PHILOX4X32>(dist, dtype, a, st); break;
     case RP_PHILOX: rc = ser_fixed_eng<RP_PHILOX>(dist, dtype, a, st); break;
@@ -544,6 +550,7 @@ int launch_serial_stitch(int engine, int dist, int dtype, const SerialArgs &a, h
     const dim3 grid((a.lanes + 255) / 256), block(256);
     switch (engine) {
     case RP_X256PP: hipLaunchKernelGGL((k_ser_gen<RP_X256PP, RP_RAW, RP_U64, false>), grid, block, 0, st, a); break;
+    case RP_X256SS: hipLaunchKernelGGL((k_ser_gen<RP_X256SS, RP_RAW, RP_U64, false>), grid, block, 0, st, a); break;
     case RP_PCG64: hipLaunchKernelGGL((k_ser_gen<RP_PCG64, RP_RAW, RP_U64, false>), grid, block, 0, st, a); break;
     case RP_PHILOX4X32:
         hipLaunchKernelGGL((k_ser_gen<RP_PHILOX4X32, RP_RAW, RP_U64, false>), grid, block, 0, st, a);

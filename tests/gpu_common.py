@@ -10,6 +10,7 @@ FAMILY = {
     "philox": (rp.RP_SUB_KEY, "key"),
     "pcg64": (rp.RP_SUB_INC, "inc"),
     "x256++": (rp.RP_SUB_JUMP, "jump"),
+    "x256**": (rp.RP_SUB_JUMP, "jump"),
     "ranlux++": (rp.RP_SUB_JUMP, "jump"),
     "sfc64": (rp.RP_SUB_SPAWN, "spawn"),
 }
