@@ -49,7 +49,7 @@ def parse():
     p.add_argument("--no-parts", action="store_true", help="time only the ten-fill step")
     p.add_argument("--parts", default=None,
                    help="comma-separated parts to time after the step: serial, batched, elem, mvn, "
-                        "moments, laws, float, setup (default all; none with --only)")
+                        "moments, laws, float, engines, setup (default all; none with --only)")
     p.add_argument("--only", default="", help="comma-separated fill names to run (profiling)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="run only plain fill/copy kernels of known size (counter calibration)")
@@ -168,6 +168,8 @@ def parts(torch, rp, workloads, stream, only):
         out.update(part_laws(torch, rp, workloads, tm, sp))
     if "float" in only:
         out.update(part_float(torch, rp, workloads, tm, sp))
+    if "engines" in only:
+        out.update(part_engines(torch, rp, workloads, tm, sp))
     if "setup" in only:
         out.update(part_setup(torch, rp, workloads))
     return out
@@ -333,6 +335,28 @@ def part_float(torch, rp, workloads, tm, sp):
     return {"float_zig_2p16x2p14": res}
 
 
+def part_engines(torch, rp, workloads, tm, sp):
+    """Raw u64 and normal f64 fills of every engine on the substream
+    workload's shape (2^16 substreams x 2^14 values): wavefront engines
+    (philox4x32, philox, pcg64, squares) and lane engines (x256++, x256**,
+    sfc64, ranlux++)."""
+    n, per = workloads.SUB_N, workloads.SUB_PER
+    buf = torch.empty(n * per, dtype=torch.float64, device="cuda")
+    kinds = {"philox4x32": rp.RP_SUB_KEY, "philox": rp.RP_SUB_KEY, "pcg64": rp.RP_SUB_INC,
+             "squares": rp.RP_SUB_SPAWN, "x256++": rp.RP_SUB_JUMP, "x256**": rp.RP_SUB_JUMP,
+             "sfc64": rp.RP_SUB_SPAWN, "ranlux++": rp.RP_SUB_JUMP}
+    res = {}
+    for eng, kind in kinds.items():
+        S = rp.rp_streams_create(rp.rp_create(eng).seed(workloads.BASE_SEED), kind, n, 64)
+        for name, dist, dtype in (("u64", rp.RP_RAW, rp.RP_U64), ("normal_f64", rp.RP_NORM, rp.RP_F64)):
+            ms = tm(lambda: rp.rp_fill(S, dist, dtype, 0, 0, buf, per, sp), reps=2)
+            res[f"{eng}/{name}"] = {"ms": round(ms, 4), "gsamples_s": round(n * per / ms / 1e6, 2),
+                                    "hbm_frac": round(8.0 * n * per / ms / 1e6 / HBM_PEAK_GBS, 4)}
+        del S
+    del buf
+    return {"engines_2p16x2p14": res}
+
+
 def part_setup(torch, rp, workloads):
     """Substream construction (host seeding and per-substream keys, increments,
     spawn keys or jumps, then the copy to device), timed on its own: it is
@@ -456,7 +480,7 @@ def main():
                      "algorithmic_bytes_per_launch": total * dom[4], "avg_launch_ms": round(dom_ms, 4)},
         "rows": rows,
     }
-    want = args.parts if args.parts is not None else ("" if args.only else "serial,batched,elem,mvn,moments,laws,float,setup")
+    want = args.parts if args.parts is not None else ("" if args.only else "serial,batched,elem,mvn,moments,laws,float,engines,setup")
     if not args.no_parts and want:
         result["parts"] = parts(torch, rp, workloads, stream, set(want.split(",")))
     if not args.no_cpu_baseline:

@@ -56,7 +56,8 @@ enum {
     RP_RANLUX = 5,     /* "ranlux++"   ranlux++, 9 words (576-bit LCG)      */
     RP_X256SS = 6,     /* "x256**"     xoshiro256**, 4 state words; seeding, */
                        /*              jumps and substreams as x256++       */
-    RP_NENGINES = 7
+    RP_SQUARES = 7,    /* "squares"    squares64, counter 1 + key 1         */
+    RP_NENGINES = 8
 };
 
 typedef struct rp_rng rp_rng;         /* one serial stream, host resident  */
@@ -97,14 +98,16 @@ int rp_set_state(rp_rng *rng, const uint64_t *words, size_t n, uint32_t phase);
 /* Jump by 2^k engine steps, k in {32, 64, 96, 128, 192} (Section 2.3). */
 int rp_jump(rp_rng *rng, int k);
 /* Advance by n = lo + hi 2^64 engine steps (a block for block engines):
- * PCG64 affine powering, Philox counter addition, xoshiro256++ jump
- * polynomial x^n mod P(x) (Section 4.4 "Jumping"), ranlux++ A^n mod m.
- * sfc64 has no jump: RP_EUNSUPPORTED. */
+ * PCG64 affine powering, Philox and squares64 counter addition (squares64:
+ * modulo its period 2^64), xoshiro jump polynomial x^n mod P(x) (Section
+ * 4.4 "Jumping"), ranlux++ A^n mod m.  sfc64 has no jump: RP_EUNSUPPORTED.
+ * rp_jump rejects 2^k at or beyond the engine's period (RP_EINVAL). */
 int rp_advance(rp_rng *rng, uint64_t lo, uint64_t hi);
 /* Stream setters (Table 3). */
 int rp_pcg64_set_inc(rp_rng *rng, uint64_t lo, uint64_t hi);       /* inc |= 1 */
 int rp_philox_set_key(rp_rng *rng, uint64_t k0, uint64_t k1);      /* 4x32: key = k0 */
 int rp_sfc64_set_abc(rp_rng *rng, uint64_t a, uint64_t b, uint64_t c); /* +18 steps */
+int rp_squares_set_key(rp_rng *rng, uint64_t key);                  /* key |= 1 */
 /* Checkpointing (Section 4.4): opaque byte image of the stream.  With
  * buf == NULL only *needed is set. */
 int rp_serialize(const rp_rng *rng, void *buf, size_t len, size_t *needed);

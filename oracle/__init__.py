@@ -17,8 +17,8 @@ import numpy as np
 from . import build as _build
 from . import jumppoly
 
-X256PP, PCG64, PHILOX4X32, PHILOX4X64, SFC64, RANLUX, X256SS = range(7)
-ENGINE_IDS = {"x256++": X256PP, "x256**": X256SS, "pcg64": PCG64, "philox4x32": PHILOX4X32,
+X256PP, PCG64, PHILOX4X32, PHILOX4X64, SFC64, RANLUX, X256SS, SQUARES = range(8)
+ENGINE_IDS = {"x256++": X256PP, "x256**": X256SS, "squares": SQUARES, "pcg64": PCG64, "philox4x32": PHILOX4X32,
               "philox": PHILOX4X64, "sfc64": SFC64, "ranlux++": RANLUX}
 
 _lib = None
@@ -37,6 +37,7 @@ def lib():
             "or_pcg64_set_inc": ([vp, u64, u64], ctypes.c_int),
             "or_philox_set_key": ([vp, u64, u64], ctypes.c_int),
             "or_sfc64_set_abc": ([vp, u64, u64, u64], None),
+            "or_squares_set_key": ([vp, u64], ctypes.c_int),
             "or_x256_apply_poly": ([vp, vp], ctypes.c_int),
             "or_x256_linear_steps": ([vp, vp, sz], None),
             "or_pcg64_advance": ([vp, u64, u64], ctypes.c_int),
@@ -142,6 +143,10 @@ class Stream:
         assert lib().or_philox_set_key(_p(self.buf), ctypes.c_uint64(k0), ctypes.c_uint64(k1)) == 0
         return self
 
+    def squares_set_key(self, key):
+        assert lib().or_squares_set_key(_p(self.buf), ctypes.c_uint64(key)) == 0
+        return self
+
     def sfc64_set_abc(self, a, b, c):
         lib().or_sfc64_set_abc(_p(self.buf), a, b, c)
         return self
@@ -157,6 +162,10 @@ class Stream:
         if self.engine in (X256PP, X256SS):
             p = jumppoly.x256_char_poly(lib())
             return self.x256_apply_poly(jumppoly.xpow_mod(n, p))
+        if self.engine == SQUARES:
+            # counter engine with period 2^64: the counter word moves by n
+            self.buf[2] = np.uint64((int(self.buf[2]) + n) % 2**64)
+            return self
         if self.engine == PCG64:
             lo, hi = _split(n % 2**128)
             assert lib().or_pcg64_advance(_p(self.buf), lo, hi) == 0

@@ -23,6 +23,7 @@
  *   xoshiro256++ linear core               pinned: primitive characteristic polynomial
  *   xoshiro256++ output scrambler          parity unpinned (no external implementation here)
  *   xoshiro256** output scrambler          parity unpinned (no external implementation here)
+ *   squares64 output function              parity unpinned (no external implementation here)
  *   ranlux++                               pinned: modulus/multiplier/period, big-integer arithmetic
  *   seeding mixer (seed_seq_fe128)         pinned: NumPy SeedSequence
  *   u01 / u01f / bounded ints              pinned: NumPy Generator
@@ -54,7 +55,8 @@ enum {
     OR_SFC64 = 4,
     OR_RANLUX = 5,
     OR_X256SS = 6,
-    OR_NENGINE = 7
+    OR_SQUARES = 7,
+    OR_NENGINE = 8
 };
 
 /*
@@ -129,6 +131,28 @@ static uint64_t x256ss_word(uint64_t s[4])
     uint64_t out = rotl64(s[1] * 5u, 7) * 9u;
     x256_linear(s);
     return out;
+}
+
+/* ------------------------------------------------------------------------ */
+/* squares64 (Widynski; Table 2 "squares", Table 3: counter (1) + key (1)).  */
+/* Word = five rounds on x = counter * key: square, add y = x0 or            */
+/* z = x0 + key alternately, swap the 32-bit halves; the fourth round's      */
+/* value t is kept and the fifth returns t ^ ((x^2 + y) >> 32).  The counter */
+/* then increases by one (period 2^64 per key).                              */
+/* ------------------------------------------------------------------------ */
+static uint64_t swap32(uint64_t x) { return (x >> 32) | (x << 32); }
+
+static uint64_t squares_word(uint64_t st[2])
+{
+    uint64_t x = st[0] * st[1];
+    uint64_t y = x, z = y + st[1];
+    x = swap32(x * x + y);
+    x = swap32(x * x + z);
+    x = swap32(x * x + y);
+    uint64_t t = x * x + z;
+    x = swap32(t);
+    st[0] += 1u;
+    return t ^ ((x * x + y) >> 32);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -493,6 +517,7 @@ static uint64_t next_word(or_stream *s)
     switch (s->engine) {
     case OR_X256PP: return x256pp_word(s->st);
     case OR_X256SS: return x256ss_word(s->st);
+    case OR_SQUARES: return squares_word(s->st);
     case OR_PCG64: return pcg64_word(s->st);
     case OR_SFC64: return sfc64_word(s->st);
     default: {
@@ -577,6 +602,7 @@ static int seeded_words(uint64_t engine)
     switch (engine) {
     case OR_X256PP: return 4;
     case OR_X256SS: return 4;
+    case OR_SQUARES: return 2;
     case OR_PCG64: return 4;
     case OR_PHILOX4X32: return 3;
     case OR_PHILOX4X64: return 6;
@@ -635,6 +661,12 @@ int or_seed(or_stream *s, uint64_t engine, uint64_t seed, const uint32_t *key, s
     case OR_SFC64:
         or_sfc64_set_abc(s, w[0], w[1], w[2]);
         break;
+    case OR_SQUARES:
+        /* reading: the key is made odd (the key 0 would give a constant
+         * stream); the counter is the first mixer word */
+        s->st[0] = w[0];
+        s->st[1] = w[1] | 1u;
+        break;
     case OR_RANLUX:
         memcpy(s->st, w, 9 * 8);
         rl_seed_fixup(s->st);
@@ -674,6 +706,14 @@ int or_philox_set_key(or_stream *s, uint64_t k0, uint64_t k1)
         return -1;
     }
     s->blk_ok = 0;
+    return 0;
+}
+
+/* squares stream setter (Table 3): the key, made odd as in seeding. */
+int or_squares_set_key(or_stream *s, uint64_t key)
+{
+    if (s->engine != OR_SQUARES) return -1;
+    s->st[1] = key | 1u;
     return 0;
 }
 

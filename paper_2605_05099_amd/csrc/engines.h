@@ -111,6 +111,25 @@ static constexpr uint64_t kPh64W0 = 0x9E3779B97F4A7C15ull, kPh64W1 = 0xBB67AE858
 
 // Block for 128-bit counter (c_lo, c_hi) and key (k0 | k1 << 32); returns the
 // two 64-bit words (earlier 32-bit output in the low half).
+// squares64 (Widynski; Table 2 "squares"): the word of counter c under key k.
+// Five rounds on x = c k: square, add y = c k or z = y + k alternately and
+// swap the 32-bit halves; the fourth round's square-plus-z t is kept, and
+// the word is t xor the high half of the fifth round's x^2 + y.
+RP_HD uint64_t squares64(uint64_t c, uint64_t k)
+{
+    uint64_t x = c * k;
+    const uint64_t y = x, z = y + k;
+    x = x * x + y;
+    x = (x >> 32) | (x << 32);
+    x = x * x + z;
+    x = (x >> 32) | (x << 32);
+    x = x * x + y;
+    x = (x >> 32) | (x << 32);
+    const uint64_t t = x * x + z;
+    x = (t >> 32) | (t << 32);
+    return t ^ ((x * x + y) >> 32);
+}
+
 RP_HD void philox4x32(uint64_t c_lo, uint64_t c_hi, uint64_t key, uint64_t &w0, uint64_t &w1)
 {
     uint32_t x0 = (uint32_t)c_lo, x1 = (uint32_t)(c_lo >> 32);

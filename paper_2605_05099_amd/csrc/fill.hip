@@ -389,6 +389,53 @@ struct WavePhilox64 {
     }
 };
 
+// squares64: word p of the substream is squares64(c0 + p, key); any
+// position is one evaluation away.  No block phase (one word per counter).
+struct WaveSquares {
+    static constexpr int R = kWaveR;
+    static constexpr int G = 1;
+    uint64_t c0, key;  // uniform
+    uint64_t c;        // this lane's first counter in the chunk
+    uint32_t phase0;
+
+    __device__ void load(const FillArgs &a, uint64_t i, int lane)
+    {
+        c0 = uni64(a.words[i]);
+        key = uni64(a.words[a.n + i]);
+        phase0 = 0;
+        c = c0 + (uint64_t)(lane * R);
+    }
+    __device__ void gen(uint64_t w[R]) const
+    {
+#pragma unroll
+        for (int k = 0; k < R; k++) w[k] = squares64(c + (uint64_t)k, key);
+    }
+    __device__ void next_chunk() { c += 64 * R; }
+    __device__ void load_direct(const FillArgs &a, uint64_t i, int lane)
+    {
+        load(a, i, lane);
+        c = c0 + (uint64_t)lane;  // positions 64 k + lane
+    }
+    __device__ void gen_direct(uint64_t w[R])
+    {
+#pragma unroll
+        for (int k = 0; k < R; k++) w[k] = squares64(c + (uint64_t)(64 * k), key);
+        c += 64 * R;
+    }
+    __device__ void load_half(const FillArgs &a, uint64_t i, int lane)
+    {
+        load(a, i, lane);
+        c = c0 + (uint64_t)(lane * (R / 2));
+    }
+    __device__ void gen_half(uint64_t w[R / 2])
+    {
+#pragma unroll
+        for (int k = 0; k < R / 2; k++) w[k] = squares64(c + (uint64_t)k, key);
+        c += 32 * R;
+    }
+    __device__ void store(const FillArgs &a, uint64_t i, uint64_t pos) const { a.words[i] = c0 + pos; }
+};
+
 // PCG64: lane l starts each chunk at word R l (state A^(R l) s + G_(R l) inc),
 // takes R - 1 ordinary steps inside the chunk, and moves to the next chunk
 // with the stride-64R map from the constant table.
@@ -1135,6 +1182,18 @@ struct LaneX256T {
 using LaneX256 = LaneX256T<false>;
 using LaneX256SS = LaneX256T<true>;
 
+struct LaneSquares {
+    uint64_t c, key;
+    __device__ void load(const FillArgs &a, uint64_t i)
+    {
+        c = a.words[i];
+        key = a.words[a.n + i];
+    }
+    __device__ uint64_t next() { return squares64(c++, key); }
+    __device__ void reserve(int) {}
+    __device__ void store(const FillArgs &a, uint64_t i) const { a.words[i] = c; }
+};
+
 struct LaneSfc64 {
     Sfc64 s;
     __device__ void load(const FillArgs &a, uint64_t i)
@@ -1412,6 +1471,7 @@ int launch_fill(int engine, int dist, int dtype, const FillArgs &a, hipStream_t 
     case RP_PCG64: return dispatch_dist<true, WavePcg>(dist, dtype, a, st);
     case RP_X256PP: return dispatch_dist<false, LaneX256>(dist, dtype, a, st);
     case RP_X256SS: return dispatch_dist<false, LaneX256SS>(dist, dtype, a, st);
+    case RP_SQUARES: return dispatch_dist<true, WaveSquares>(dist, dtype, a, st);
     case RP_SFC64: return dispatch_dist<false, LaneSfc64>(dist, dtype, a, st);
     case RP_RANLUX: return dispatch_dist<false, LaneRanlux>(dist, dtype, a, st);
     }
@@ -1443,6 +1503,7 @@ int launch_fill_law(int engine, int law, const FillArgs &a, hipStream_t st)
     case RP_PCG64: return dispatch_law<true, WavePcg>(law, a, st);
     case RP_X256PP: return dispatch_law<false, LaneX256>(law, a, st);
     case RP_X256SS: return dispatch_law<false, LaneX256SS>(law, a, st);
+    case RP_SQUARES: return dispatch_law<true, WaveSquares>(law, a, st);
     case RP_SFC64: return dispatch_law<false, LaneSfc64>(law, a, st);
     case RP_RANLUX: return dispatch_law<false, LaneRanlux>(law, a, st);
     }

@@ -86,6 +86,7 @@ static const EngineInfo kEngines[RP_NENGINES] = {
     {"sfc64", "sfc64 (Chris Doty-Humphrey, 2010), 4 state words, average period >= 2^64", 4, 1},
     {"ranlux++", "ranlux++ (Sibidanov, 2017), 9 state words, period about 2^570", 9, 9},
     {"x256**", "xoshiro256** (Blackman and Vigna, 2018), 4 state words, period 2^256-1", 4, 1},
+    {"squares", "squares64 (Widynski, 2021), 2 state words, period 2^64 per key", 2, 1},
 };
 
 namespace rp {
@@ -425,6 +426,8 @@ static uint64_t host_next(rp_rng *r)
         st[1] = s.hi;
         return w;
     }
+    case RP_SQUARES:
+        return squares64(st[0]++, st[1]);
     case RP_SFC64: {
         Sfc64 s{st[0], st[1], st[2], st[3]};
         uint64_t w = s.next();
@@ -500,6 +503,11 @@ static void seed_state(rp_rng *r, uint64_t seed, const uint32_t *key, size_t n_k
     case RP_PCG64:
         memcpy(r->st, w, 32);
         r->st[2] |= 1u;
+        break;
+    case RP_SQUARES:
+        // reading: the key is made odd (key 0 gives a constant stream)
+        r->st[0] = w[0];
+        r->st[1] = w[1] | 1u;
         break;
     case RP_PHILOX4X32:
     case RP_PHILOX:
@@ -595,6 +603,9 @@ static int advance_impl(rp_rng *rng, uint64_t lo, uint64_t hi)
     case RP_X256SS:
         x256_apply(st, poly_xpow(lo, hi, x256_charpoly()));
         return RP_OK;
+    case RP_SQUARES:  // period 2^64: hi 2^64 steps are a full period
+        st[0] += lo;
+        return RP_OK;
     case RP_PCG64: {
         PcgAffine m = pcg_power(lo, hi);
         u128 s{st[0], st[1]}, inc{st[2], st[3]};
@@ -644,6 +655,8 @@ extern "C" int rp_jump(rp_rng *rng, int k)
     if (!rng) return fail(RP_ENULL, "rp_jump: NULL rng");
     if (k != 32 && k != 64 && k != 96 && k != 128 && k != 192)
         return fail_rng(rng, RP_EINVAL, "rp_jump: k must be 32, 64, 96, 128 or 192 (got %d)", k);
+    if (rng->engine == RP_SQUARES && k >= 64)
+        return fail_rng(rng, RP_EINVAL, "rp_jump: 2^%d is not below the period of 'squares'", k);
     if (k < 128) return advance_impl(rng, k < 64 ? (1ull << k) : 0, k >= 64 ? (1ull << (k - 64)) : 0);
     switch (rng->engine) {
     case RP_X256PP:
@@ -709,6 +722,14 @@ extern "C" int rp_sfc64_set_abc(rp_rng *rng, uint64_t a, uint64_t b, uint64_t c)
     if (!rng) return fail(RP_ENULL, "rp_sfc64_set_abc: NULL rng");
     if (rng->engine != RP_SFC64) return fail_rng(rng, RP_EUNSUPPORTED, "sfc64_set_abc: engine is not sfc64");
     sfc64_setabc(rng, a, b, c);
+    return RP_OK;
+}
+
+extern "C" int rp_squares_set_key(rp_rng *rng, uint64_t key)
+{
+    if (!rng) return fail(RP_ENULL, "rp_squares_set_key: NULL rng");
+    if (rng->engine != RP_SQUARES) return fail_rng(rng, RP_EUNSUPPORTED, "squares_set_key: engine is not squares");
+    rng->st[1] = key | 1u;
     return RP_OK;
 }
 

@@ -119,6 +119,16 @@ struct SerLane<RP_PHILOX> : LanePhilox64 {
     }
 };
 
+// squares64: counter plus id C.
+template <>
+struct SerLane<RP_SQUARES> : LaneSquares {
+    __device__ void init(const SerialArgs &a, uint64_t id)
+    {
+        c = a.base[0] + id * a.C;
+        key = a.base[1];
+    }
+};
+
 // ranlux++: x times A^((C/9) 2^k) mod m for the set bits of the lane id.
 template <>
 struct SerLane<RP_RANLUX> : LaneRanlux {
@@ -525,6 +535,7 @@ int launch_serial_fixed(int engine, int dist, int dtype, const SerialArgs &a, hi
     switch (engine) {
     case RP_X256PP: rc = ser_fixed_eng<RP_X256PP>(dist, dtype, a, st); break;
     case RP_X256SS: rc = ser_fixed_eng<RP_X256SS>(dist, dtype, a, st); break;
+    case RP_SQUARES: rc = ser_fixed_eng<RP_SQUARES>(dist, dtype, a, st); break;
     case RP_PCG64: rc = ser_fixed_eng<RP_PCG64>(dist, dtype, a, st); break;
     case RP_PHILOX4X32: rc = ser_fixed_eng<RP_PHILOX4X32>(dist, dtype, a, st); break;
     case RP_PHILOX: rc = ser_fixed_eng<RP_PHILOX>(dist, dtype, a, st); break;
@@ -551,6 +562,7 @@ int launch_serial_stitch(int engine, int dist, int dtype, const SerialArgs &a, h
     switch (engine) {
     case RP_X256PP: hipLaunchKernelGGL((k_ser_gen<RP_X256PP, RP_RAW, RP_U64, false>), grid, block, 0, st, a); break;
     case RP_X256SS: hipLaunchKernelGGL((k_ser_gen<RP_X256SS, RP_RAW, RP_U64, false>), grid, block, 0, st, a); break;
+    case RP_SQUARES: hipLaunchKernelGGL((k_ser_gen<RP_SQUARES, RP_RAW, RP_U64, false>), grid, block, 0, st, a); break;
     case RP_PCG64: hipLaunchKernelGGL((k_ser_gen<RP_PCG64, RP_RAW, RP_U64, false>), grid, block, 0, st, a); break;
     case RP_PHILOX4X32:
         hipLaunchKernelGGL((k_ser_gen<RP_PHILOX4X32, RP_RAW, RP_U64, false>), grid, block, 0, st, a);

@@ -13,6 +13,7 @@ FAMILY = {
     "x256**": (rp.RP_SUB_JUMP, "jump"),
     "ranlux++": (rp.RP_SUB_JUMP, "jump"),
     "sfc64": (rp.RP_SUB_SPAWN, "spawn"),
+    "squares": (rp.RP_SUB_SPAWN, "spawn"),
 }
 ENGINES = list(FAMILY)
 
