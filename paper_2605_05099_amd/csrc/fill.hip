@@ -1352,18 +1352,71 @@ __device__ __forceinline__ double zig_serial_g(const ZigLds *t, Next next)
     }
 }
 
+// the binary64 draw, written out with the engine's next() (no callable
+// wrapper, so an engine's out-of-line step sees only its own live values)
 template <int DIST, class E>
 __device__ double zig_serial(const ZigLds *t, E &eng)
 {
-    return zig_serial_g<DIST, false>(t, [&]() { return eng.next(); });
+    for (;;) {
+        const uint64_t w = eng.next();
+        const int j = (int)(w & 0xff);
+        if (DIST == RP_NORM) {
+            const uint64_t m = (w >> 9) & ((1ull << 52) - 1);
+            const bool neg = (w >> 8) & 1;
+            const WKe e = t->WK[j];
+            const double x = (double)m * e.w;
+            if (m < e.k) return neg ? -x : x;
+            if (j == 0) {
+                for (int k = 0; k < kMaxTailIters; k++) {
+                    const double e1 = -log1p(-u01_53(eng.next())) / RP_ZN_R;
+                    const double e2 = -log1p(-u01_53(eng.next()));
+                    if (e2 + e2 > e1 * e1) {
+                        const double tt = RP_ZN_R + e1;
+                        return neg ? -tt : tt;
+                    }
+                }
+                continue;  // unreachable in practice (see kMaxTailIters)
+            }
+            if (wedge_accept<DIST>(t, j, x, eng.next())) return neg ? -x : x;
+        } else {
+            const uint64_t m = (w >> 8) & ((1ull << 53) - 1);
+            const WKe e = t->WK[j];
+            const double x = (double)m * e.w;
+            if (m < e.k) return x;
+            if (j == 0) return RP_ZE_R - log1p(-u01_53(eng.next()));
+            if (wedge_accept<DIST>(t, j, x, eng.next())) return x;
+        }
+    }
 }
 
+// Lane engines whose rows go through the LDS stage.  ranlux++ keeps the
+// per-lane body: compiled into the staged body, its 27-word state and
+// out-of-line block step took 392-552 bytes of scratch per lane (168 in the
+// per-lane body) and its fills ran about 2.5 times slower.
+template <class E>
+struct LaneStaged {
+    static constexpr bool value = true;
+};
+template <>
+struct LaneStaged<LaneRanlux> {
+    static constexpr bool value = false;
+};
+
+// One lane per substream: lane i produces the values of row i in order.
+// Rows are P values apart, so per-lane stores would touch 64 lines per
+// instruction; a wavefront whose 64 substreams all exist instead produces V
+// values per lane per round (V = 128 bytes of output), stages them in LDS
+// and writes 64 / V whole rows runs of 128 bytes per store instruction.  The
+// last P mod V values of each row, and wavefronts past the last full one,
+// use per-lane stores.
 template <class E, int DIST, int OT, int XF = 0>
 __global__ __launch_bounds__(256) void k_fill_lane(FillArgs a)
 {
     using T = typename OutType<DIST, OT>::T;
     constexpr bool ZIG = DIST == RP_NORM || DIST == RP_EXP;
     constexpr bool HALF = OT == RP_U32 || OT == RP_F32;
+    constexpr int V = 128 / (int)sizeof(T);  // values per lane per round
+    constexpr int VP = V + 16 / (int)sizeof(T);  // padded row: 16-byte aligned, banks spread
     ZigLds *zt = nullptr;
     if constexpr (ZIG) {
         __shared__ ZigLds zbuf;
@@ -1371,56 +1424,122 @@ __global__ __launch_bounds__(256) void k_fill_lane(FillArgs a)
         __syncthreads();
         zt = &zbuf;
     }
+    __shared__ __align__(16) T stage_all[4][64 * VP];
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = (int)(threadIdx.x & 63);
+    const uint64_t id0 = i - (uint64_t)lane;
     if (i >= a.n) return;
     const uint64_t P = a.per_stream;
     T *out = (T *)a.out + i * P;
-    E eng;
-    eng.load(a, i);
-    bool have = false;
-    uint32_t hi = 0;
-    for (uint64_t t = 0; t < P;) {
-        if constexpr (ZIG && HALF) {
-            eng.reserve(2);
-            out[t++] = (T)xform<XF>(zig_serial_g<DIST, true>(zt,
-                                                           [&]() -> uint64_t {
-                                                               if (have) {
-                                                                   have = false;
-                                                                   return hi;
-                                                               }
-                                                               const uint64_t w = eng.next();
-                                                               hi = (uint32_t)(w >> 32);
-                                                               have = true;
-                                                               return w & 0xffffffffull;
-                                                           }),
-                                    a);
-        } else if constexpr (ZIG) {
-            eng.reserve(3);
-            out[t++] = (T)xform<XF>(zig_serial<DIST>(zt, eng), a);
-        } else {
-            eng.reserve(1);
-            uint64_t it;
-            if constexpr (HALF) {
-                if (have) {
-                    it = hi;
-                    have = false;
-                } else {
-                    const uint64_t w = eng.next();
-                    it = w & 0xffffffffull;
-                    hi = (uint32_t)(w >> 32);
-                    have = true;
-                }
+    if constexpr (!LaneStaged<E>::value) {
+        // per-lane stores (see LaneStaged)
+        E eng;
+        eng.load(a, i);
+        bool have = false;
+        uint32_t hi = 0;
+        for (uint64_t t = 0; t < P;) {
+            if constexpr (ZIG && HALF) {
+                eng.reserve(2);
+                out[t++] = (T)xform<XF>(zig_serial_g<DIST, true>(zt,
+                                                               [&]() -> uint64_t {
+                                                                   if (have) {
+                                                                       have = false;
+                                                                       return hi;
+                                                                   }
+                                                                   const uint64_t w = eng.next();
+                                                                   hi = (uint32_t)(w >> 32);
+                                                                   have = true;
+                                                                   return w & 0xffffffffull;
+                                                               }),
+                                        a);
+            } else if constexpr (ZIG) {
+                eng.reserve(3);
+                out[t++] = (T)xform<XF>(zig_serial<DIST>(zt, eng), a);
             } else {
-                it = eng.next();
-            }
-            T v;
-            if (item_value<DIST, OT>(it, a, v)) {
-                if constexpr (XF != 0) v = xform<XF>(v, a);
-                out[t++] = v;
+                eng.reserve(1);
+                uint64_t it;
+                if constexpr (HALF) {
+                    if (have) {
+                        it = hi;
+                        have = false;
+                    } else {
+                        const uint64_t w = eng.next();
+                        it = w & 0xffffffffull;
+                        hi = (uint32_t)(w >> 32);
+                        have = true;
+                    }
+                } else {
+                    it = eng.next();
+                }
+                T v;
+                if (item_value<DIST, OT>(it, a, v)) {
+                    if constexpr (XF != 0) v = xform<XF>(v, a);
+                    out[t++] = v;
+                }
             }
         }
+        eng.store(a, i);
+        return;
+    } else {
+        E eng;
+        eng.load(a, i);
+        bool have = false;
+        uint32_t hi = 0;
+        auto next32 = [&]() __attribute__((always_inline)) -> uint64_t {
+            if (have) {
+                have = false;
+                return hi;
+            }
+            const uint64_t w = eng.next();
+            hi = (uint32_t)(w >> 32);
+            have = true;
+            return w & 0xffffffffull;
+        };
+        // the next value of this lane's row
+        auto produce = [&]() __attribute__((always_inline)) -> T {
+            if constexpr (ZIG && HALF) {
+                eng.reserve(2);
+                return (T)xform<XF>(zig_serial_g<DIST, true>(zt, next32), a);
+            } else if constexpr (ZIG) {
+                eng.reserve(3);
+                return (T)xform<XF>(zig_serial<DIST>(zt, eng), a);
+            } else {
+                T v;
+                for (;;) {
+                    eng.reserve(1);
+                    uint64_t it;
+                    if constexpr (HALF) it = next32();
+                    else it = eng.next();
+                    if (item_value<DIST, OT>(it, a, v)) break;
+                }
+                if constexpr (XF != 0) v = xform<XF>(v, a);
+                return v;
+            }
+        };
+        uint64_t t = 0;
+        if (blockDim.x <= 256 && id0 + 64 <= a.n) {  // wave-uniform: all 64 rows exist
+            T *const stage = stage_all[(threadIdx.x >> 6) & 3];
+            constexpr int RPI = 64 / V;  // rows per store instruction
+            for (; t + V <= P; t += V) {
+#pragma unroll 1
+                for (int k = 0; k < V; k++) stage[lane * VP + k] = produce();
+                wave_sync();
+                // instruction j: rows RPI j .. RPI j + RPI - 1, this lane's
+                // row lane / V of them at element t + lane mod V
+                T *p = (T *)a.out + (id0 + (uint64_t)(lane / V)) * P + t + (uint64_t)(lane % V);
+                const T *q = stage + (lane / V) * VP + lane % V;
+                const uint64_t step = (uint64_t)RPI * P;
+#pragma unroll
+                for (int j = 0; j < V; j++) {
+                    *p = q[j * RPI * VP];
+                    p += step;
+                }
+                wave_sync();
+            }
+        }
+        for (; t < P; t++) out[t] = produce();
+        eng.store(a, i);
     }
-    eng.store(a, i);
 }
 
 // ---------------------------------------------------------------------------
