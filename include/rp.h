@@ -322,6 +322,17 @@ int rp_beta_grad(const float *d_z, const float *d_a, const float *d_b, const flo
  * zeros above the diagonal) with Sigma = L L^T.  RP_ENOTSPD when a leading
  * minor is not positive definite (or not finite); L is then incomplete. */
 int rp_cholesky(const double *Sigma, int d, double *L);
+/* The factor A with Sigma = A A^T that rp_mvn takes (host, binary64; Section
+ * 3.1): the Cholesky factor when Sigma (lower triangle read) is positive
+ * definite, otherwise A = P L from a pivoted Cholesky factorization (LAPACK
+ * dpstrf's rule: the largest remaining diagonal entry as pivot, stop at
+ * tol = d eps max_i Sigma_ii), so A is not triangular and its columns from
+ * *rank on are zero.  *rank = d in the definite case.  RP_ENOTSPD when a
+ * trailing diagonal entry is below -tol (Sigma not semidefinite);
+ * RP_EINVAL for non-finite entries.  A is d x d row-major host memory.
+ * rp_mvn accepts this A unchanged (it reads the whole matrix); rp_mvn_backward
+ * returns the gradient's lower triangle, the parameters of a Cholesky factor. */
+int rp_mvn_factor(const double *Sigma, int d, double *A, int *rank);
 /* Row i < n of X (n x d, row-major, binary32) is mu + L z_i, where z_i is the
  * next d standard normals of substream i (ziggurat in binary64, rounded to
  * binary32); that is X = mu + Z L^T.  The contraction runs on the matrix

@@ -74,6 +74,7 @@ _SIGS = {
     "rp_gamma_batched": ([_vp, _vp, _vp, _u64, _vp, _vp, _vp], _int),
     "rp_beta_batched": ([_vp, _vp, _vp, _vp, _u64, _vp, _vp, _vp], _int),
     "rp_cholesky": ([_vp, _int, _vp], _int),
+    "rp_mvn_factor": ([_vp, _int, _vp, _vp], _int),
     "rp_mvn": ([_vp, _vp, _vp, _int, _u64, _vp, _vp], _int),
     "rp_mvn_backward": ([_vp, _vp, _int, _u64, _vp, _vp, _vp], _int),
     "rp_gamma_grad": ([_vp, _vp, _vp, _vp, _u64, _vp], _int),
@@ -237,6 +238,19 @@ def rp_cholesky(sigma):
     out = np.zeros((d, d), dtype=np.float64)
     _check(lib().rp_cholesky(_ptr(a), d, _ptr(out)))
     return out
+
+
+def rp_mvn_factor(sigma):
+    """(A, rank) with sigma = A A^T on the host: Cholesky, else pivoted
+    Cholesky for a semidefinite sigma (numpy in, numpy out)."""
+    a = np.ascontiguousarray(sigma, dtype=np.float64)
+    d = a.shape[0]
+    if a.shape != (d, d):
+        raise ValueError("sigma must be square")
+    out = np.zeros((d, d), dtype=np.float64)
+    rank = ctypes.c_int(0)
+    _check(lib().rp_mvn_factor(_ptr(a), d, _ptr(out), ctypes.byref(rank)))
+    return out, rank.value
 
 
 def rp_mvn(streams, mu, L, d, n, X, stream=None):

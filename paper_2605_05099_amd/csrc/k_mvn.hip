@@ -11,7 +11,10 @@
 // so nothing of size n x d is kept between the two.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <limits>
+#include <vector>
 
 #include "rp_internal.h"
 
@@ -424,6 +427,92 @@ extern "C" int rp_mvn_backward(rp_streams *s, const float *d_G, int d, uint64_t 
     }
     (void)hipFreeAsync(ws, st);
     return rc;
+}
+
+// Pivoted Cholesky (the paper's fallback for semidefinite covariances,
+// with LAPACK dpstrf's rule): step j pivots on the largest diagonal entry of
+// the remaining Schur complement and stops when it is at most
+// tol = d eps max_i Sigma_ii; column j of L is formed left-looking from the
+// permuted Sigma and the earlier columns.  A = P L (row perm[k] of A is row
+// k of L), so Sigma = A A^T.  A trailing diagonal entry below -tol means
+// Sigma is not semidefinite.
+extern "C" int rp_mvn_factor(const double *Sigma, int d, double *A, int *rank)
+{
+    if (!Sigma || !A || !rank) return fail(RP_ENULL, "rp_mvn_factor: NULL pointer");
+    if (d < 1) return fail(RP_EINVAL, "rp_mvn_factor: d = %d", d);
+    const size_t D = (size_t)d;
+    for (size_t i = 0; i < D; i++)
+        for (size_t j = 0; j <= i; j++)
+            if (!std::isfinite(Sigma[i * D + j])) return fail(RP_EINVAL, "rp_mvn_factor: Sigma is not finite");
+    // the plain factorization first (its failure is not an error here)
+    std::vector<double> L(D * D, 0.0), S(D * D);
+    bool pd = true;
+    for (size_t i = 0; i < D && pd; i++) {
+        for (size_t j = 0; j <= i; j++) {
+            double s = Sigma[i * D + j];
+            for (size_t k = 0; k < j; k++) s -= L[i * D + k] * L[j * D + k];
+            if (i == j) {
+                if (!(s > 0.0)) {
+                    pd = false;
+                    break;
+                }
+                L[i * D + i] = std::sqrt(s);
+            } else {
+                L[i * D + j] = s / L[j * D + j];
+            }
+        }
+    }
+    if (pd) {
+        std::copy(L.begin(), L.end(), A);
+        *rank = d;
+        return RP_OK;
+    }
+    for (size_t i = 0; i < D; i++)
+        for (size_t j = 0; j <= i; j++) S[i * D + j] = S[j * D + i] = Sigma[i * D + j];
+    std::fill(L.begin(), L.end(), 0.0);
+    std::vector<size_t> perm(D);
+    std::vector<double> diag(D);
+    double dmax = S[0];
+    for (size_t i = 1; i < D; i++) dmax = std::max(dmax, S[i * D + i]);
+    const double tol = (double)d * std::numeric_limits<double>::epsilon() * dmax;
+    for (size_t i = 0; i < D; i++) perm[i] = i;
+    size_t r = D;
+    double rest = 0.0;
+    for (size_t j = 0; j < D; j++) {
+        size_t p = j;
+        for (size_t i = j; i < D; i++) {
+            double v = S[i * D + i];
+            for (size_t k = 0; k < j; k++) v -= L[i * D + k] * L[i * D + k];
+            diag[i] = v;
+            if (v > diag[p]) p = i;
+        }
+        if (!(diag[p] > tol)) {
+            r = j;
+            rest = diag[j];
+            for (size_t i = j + 1; i < D; i++) rest = std::min(rest, diag[i]);
+            break;
+        }
+        if (p != j) {
+            for (size_t c = 0; c < D; c++) std::swap(S[j * D + c], S[p * D + c]);
+            for (size_t c = 0; c < D; c++) std::swap(S[c * D + j], S[c * D + p]);
+            for (size_t c = 0; c < j; c++) std::swap(L[j * D + c], L[p * D + c]);
+            std::swap(perm[j], perm[p]);
+        }
+        const double ljj = std::sqrt(diag[p]);
+        L[j * D + j] = ljj;
+        for (size_t i = j + 1; i < D; i++) {
+            double s = S[i * D + j];
+            for (size_t k = 0; k < j; k++) s -= L[i * D + k] * L[j * D + k];
+            L[i * D + j] = s / ljj;
+        }
+    }
+    if (r < D && rest < -tol)
+        return fail(RP_ENOTSPD, "rp_mvn_factor: covariance is not positive semidefinite (trailing diagonal %g)",
+                    rest);
+    for (size_t k = 0; k < D; k++)
+        for (size_t c = 0; c < D; c++) A[perm[k] * D + c] = L[k * D + c];
+    *rank = (int)r;
+    return RP_OK;
 }
 
 // Cholesky-Banachiewicz in binary64 on the host, reading the lower triangle

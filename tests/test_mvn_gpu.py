@@ -156,3 +156,30 @@ def test_mvn_autograd():
     rp.rp_mvn_backward(make_streams("philox4x32", n), G, d, n, gmu, gL)
     torch.cuda.synchronize()
     assert torch.equal(mu_t.grad, gmu) and torch.equal(L_t.grad, gL)
+
+
+@pytest.mark.parametrize("d,r", [(64, 40), (100, 1), (256, 200)])
+def test_mvn_forward_semidefinite_pivoted_factor(d, r):
+    """A rank-r covariance: rp_mvn_factor falls back to the pivoted
+    factorization (A = P L, not triangular); rp_mvn reads the whole A."""
+    rng = np.random.default_rng(d + r)
+    B = rng.standard_normal((d, r))
+    A, rank = rp.rp_mvn_factor(B @ B.T)
+    assert rank == r
+    A = A.astype(np.float32)
+    mu = rng.standard_normal(d).astype(np.float32)
+    n = 777
+    S = make_streams("philox4x32", n)
+    X = torch.empty((n, d), dtype=torch.float32, device="cuda")
+    rp.rp_mvn(S, _dev(mu), _dev(A), d, n, X)
+    torch.cuda.synchronize()
+    z = _z_oracle(range(n), d)
+    ref = omvn.forward(z, A, mu)
+    err = np.abs(X.cpu().numpy().astype(np.float64) - ref)
+    assert (err <= omvn.forward_bound(z, A, mu)).all(), err.max()
+    # the sample covariance lives in the column space of B: X - mu is
+    # orthogonal to the complement of range(B)
+    if r < d:
+        q, _ = np.linalg.qr(B, mode="complete")
+        off = (X.cpu().numpy().astype(np.float64) - mu) @ q[:, r:]
+        assert np.abs(off).max() < 1e-3 * max(1.0, np.abs(X.cpu().numpy()).max())
