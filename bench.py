@@ -49,7 +49,7 @@ def parse():
     p.add_argument("--no-parts", action="store_true", help="time only the ten-fill step")
     p.add_argument("--parts", default=None,
                    help="comma-separated parts to time after the step: serial, batched, elem, mvn, "
-                        "moments, laws, float, engines, setup (default all; none with --only)")
+                        "moments, laws, float, engines, discrete, setup (default all; none with --only)")
     p.add_argument("--only", default="", help="comma-separated fill names to run (profiling)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="run only plain fill/copy kernels of known size (counter calibration)")
@@ -170,6 +170,8 @@ def parts(torch, rp, workloads, stream, only):
         out.update(part_float(torch, rp, workloads, tm, sp))
     if "engines" in only:
         out.update(part_engines(torch, rp, workloads, tm, sp))
+    if "discrete" in only:
+        out.update(part_discrete(torch, rp, workloads, tm, sp))
     if "setup" in only:
         out.update(part_setup(torch, rp, workloads))
     return out
@@ -357,6 +359,24 @@ def part_engines(torch, rp, workloads, tm, sp):
     return {"engines_2p16x2p14": res}
 
 
+def part_discrete(torch, rp, workloads, tm, sp):
+    """Batched permutations and samples, one instance per substream
+    (Philox4x32-10, 2^16 substreams): permutations of 1024, Floyd samples of
+    64 from 10^6, reservoir samples of 900 from 1000."""
+    m = workloads.SUB_N
+    S = rp.rp_streams_create(rp.rp_create("philox4x32").seed(workloads.BASE_SEED), rp.RP_SUB_KEY, m)
+    res = {}
+    buf = torch.empty(m * 1024, dtype=torch.int32, device="cuda")
+    ms = tm(lambda: rp.rp_permutations(S, 1024, buf, sp), reps=3)
+    res["permutation_1024"] = {"ms": round(ms, 4), "instances_per_s_m": round(m / ms / 1e3, 3),
+                               "gelem_s": round(m * 1024 / ms / 1e6, 3)}
+    for name, n, k in (("floyd_64_of_1e6", 10**6, 64), ("reservoir_900_of_1000", 1000, 900)):
+        ms = tm(lambda: rp.rp_sample(S, n, k, buf, sp), reps=3)
+        res[name] = {"ms": round(ms, 4), "instances_per_s_m": round(m / ms / 1e3, 3)}
+    del buf, S
+    return {"discrete_2p16": res}
+
+
 def part_setup(torch, rp, workloads):
     """Substream construction (host seeding and per-substream keys, increments,
     spawn keys or jumps, then the copy to device), timed on its own: it is
@@ -480,7 +500,7 @@ def main():
                      "algorithmic_bytes_per_launch": total * dom[4], "avg_launch_ms": round(dom_ms, 4)},
         "rows": rows,
     }
-    want = args.parts if args.parts is not None else ("" if args.only else "serial,batched,elem,mvn,moments,laws,float,engines,setup")
+    want = args.parts if args.parts is not None else ("" if args.only else "serial,batched,elem,mvn,moments,laws,float,engines,discrete,setup")
     if not args.no_parts and want:
         result["parts"] = parts(torch, rp, workloads, stream, set(want.split(",")))
     if not args.no_cpu_baseline:

@@ -316,6 +316,26 @@ int rp_gamma_grad(const float *d_z, const float *d_alpha, const float *d_gz, flo
 int rp_beta_grad(const float *d_z, const float *d_a, const float *d_b, const float *d_gz, float *d_ga, float *d_gb,
                  uint64_t n, void *hip_stream);
 
+/* ---- permutations and samples (Section 3.2) ------------------------------ */
+/* One instance per substream; every draw is a 32-bit bounded integer by
+ * Lemire's method on the substream's 32-bit items (low half first; a half
+ * left over at the end of the call is dropped), and each substream advances
+ * past the items it used.
+ * rp_permutations: d_out[i * n + q] (uint32, device) is the Fisher-Yates
+ * permutation of 0..n-1 of substream i: start from the identity, for j from
+ * n-1 down to 1 swap entries j and r, r uniform on {0..j}.  n = 0 does
+ * nothing.
+ * rp_sample: d_out[i * k + c] is a sample of k distinct elements of 0..n-1
+ * (k <= n, k < 2^30): for k <= n/2 Floyd's algorithm (for j from n-k to n-1
+ * draw t on {0..j}, append t, or j when t is already in the sample; entries
+ * in the order appended), otherwise reservoir sampling (Vitter's algorithm
+ * R: start from 0..k-1, for v from k to n-1 draw j on {0..v} and replace
+ * entry j by v when j < k).  Floyd's membership test takes a workspace of
+ * 2^ceil(log2(2k)) uint32 per substream from the stream-ordered pool.
+ * k = 0 does nothing; k > n gives RP_EINVAL.  Asynchronous on hip_stream. */
+int rp_permutations(rp_streams *s, uint32_t n, uint32_t *d_out, void *hip_stream);
+int rp_sample(rp_streams *s, uint32_t n, uint32_t k, uint32_t *d_out, void *hip_stream);
+
 /* ---- multivariate normal (Section 3.1, "Multivariate normal distribution") */
 /* Cholesky factor of a covariance matrix, on the host in binary64: reads the
  * lower triangle of Sigma (row-major d x d, host memory), writes L (row-major,

@@ -50,6 +50,8 @@ def lib():
             "or_bounded32": ([vp, ctypes.c_uint32, vp, sz], None),
             "or_norm": ([vp, vp, sz, vp], None), "or_exp": ([vp, vp, sz, vp], None),
             "or_normf": ([vp, vp, sz], None), "or_expf": ([vp, vp, sz], None),
+            "or_permutation": ([vp, ctypes.c_uint32, vp], None),
+            "or_sample": ([vp, ctypes.c_uint32, ctypes.c_uint32, vp], None),
             "or_norm_moments": ([vp, sz, vp, vp], None),
             "or_gamma": ([vp, ctypes.c_double, vp, sz, vp], None),
             "or_beta": ([vp, ctypes.c_double, ctypes.c_double, vp, sz], None),
@@ -228,6 +230,18 @@ class Stream:
         """n binary32 standard exponentials from 32-bit items (float ziggurat)."""
         out = np.empty(n, dtype=np.float32)
         lib().or_expf(_p(self.buf), _p(out), n)
+        return out
+
+    def permutation(self, n):
+        """Fisher-Yates permutation of 0..n-1 (32-bit Lemire draws)."""
+        out = np.empty(n, dtype=np.uint32)
+        lib().or_permutation(_p(self.buf), n, _p(out))
+        return out
+
+    def sample(self, n, k):
+        """k distinct elements of 0..n-1: Floyd (k <= n/2) or reservoir."""
+        out = np.empty(k, dtype=np.uint32)
+        lib().or_sample(_p(self.buf), n, k, _p(out))
         return out
 
     def norm_moments(self, n):

@@ -30,6 +30,7 @@
  *   ziggurat normal                        pinned: NumPy layout/ratio test, geometry, rates, KS
  *   ziggurat exponential                   pinned: geometry, paper's rejection rate, KS
  *   float ziggurat (normf, expf)           pinned: KS, fast-accept rates, strip boundaries, tails
+ *   permutations, Floyd / reservoir samples pinned: exact laws on small cases (enumeration), validity
  *   gamma (alpha >= 1)                     pinned: NumPy Marsaglia-Tsang, moments, KS
  *   gamma boost (alpha < 1), beta          pinned: mpmath power, moments, KS
  */
@@ -928,6 +929,67 @@ void or_bounded32(or_stream *s, uint32_t b, uint32_t *out, size_t n)
             }
         }
         out[i] = (uint32_t)(p >> 32);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Permutations and sampling (Section 3.2).  Every draw is a 32-bit bounded */
+/* integer by Lemire's method on the 32-bit item stream (low half first),   */
+/* one item reader per call.                                                 */
+/* ------------------------------------------------------------------------ */
+static uint32_t bounded_item(half_reader *h, uint32_t b)
+{
+    uint32_t u = next32(h);
+    uint64_t p = (uint64_t)u * b;
+    uint32_t low = (uint32_t)p;
+    if (low < b) {
+        uint32_t threshold = (0u - b) % b;
+        while (low < threshold) {
+            u = next32(h);
+            p = (uint64_t)u * b;
+            low = (uint32_t)p;
+        }
+    }
+    return (uint32_t)(p >> 32);
+}
+
+/* Fisher-Yates (Durstenfeld's form): start from the identity; for j from  */
+/* n-1 down to 1 swap entry j with entry r, r uniform on {0..j}.            */
+void or_permutation(or_stream *s, uint32_t n, uint32_t *out)
+{
+    half_reader h = {s, 0, 0};
+    for (uint32_t i = 0; i < n; i++) out[i] = i;
+    for (uint32_t j = n; j-- > 1;) {
+        uint32_t r = bounded_item(&h, j + 1);
+        uint32_t t = out[j];
+        out[j] = out[r];
+        out[r] = t;
+    }
+}
+
+/* k distinct elements of {0..n-1}.  k <= n/2: Floyd's algorithm -- for j   */
+/* from n-k to n-1 draw t uniform on {0..j}; append t if it is not yet in   */
+/* the sample, else append j (the sample in the order of insertion).        */
+/* k > n/2: reservoir sampling (Vitter's algorithm R) -- start from         */
+/* 0..k-1; for i from k to n-1 draw j uniform on {0..i} and replace entry j */
+/* by i when j < k.  The membership test is a plain scan.                   */
+void or_sample(or_stream *s, uint32_t n, uint32_t k, uint32_t *out)
+{
+    half_reader h = {s, 0, 0};
+    if (2 * (uint64_t)k <= n) {
+        for (uint32_t c = 0; c < k; c++) {
+            uint32_t j = n - k + c;
+            uint32_t t = bounded_item(&h, j + 1);
+            int seen = 0;
+            for (uint32_t q = 0; q < c; q++) seen |= out[q] == t;
+            out[c] = seen ? j : t;
+        }
+    } else {
+        for (uint32_t i = 0; i < k; i++) out[i] = i;
+        for (uint32_t i = k; i < n; i++) {
+            uint32_t j = bounded_item(&h, i + 1);
+            if (j < k) out[j] = i;
+        }
     }
 }
 

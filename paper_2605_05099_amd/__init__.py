@@ -75,6 +75,8 @@ _SIGS = {
     "rp_beta_batched": ([_vp, _vp, _vp, _vp, _u64, _vp, _vp, _vp], _int),
     "rp_cholesky": ([_vp, _int, _vp], _int),
     "rp_mvn_factor": ([_vp, _int, _vp, _vp], _int),
+    "rp_permutations": ([_vp, _u32, _vp, _vp], _int),
+    "rp_sample": ([_vp, _u32, _u32, _vp, _vp], _int),
     "rp_mvn": ([_vp, _vp, _vp, _int, _u64, _vp, _vp], _int),
     "rp_mvn_backward": ([_vp, _vp, _int, _u64, _vp, _vp, _vp], _int),
     "rp_gamma_grad": ([_vp, _vp, _vp, _vp, _u64, _vp], _int),
@@ -163,6 +165,14 @@ def rp_streams_create(base, kind, n, jump_log2=0):
 
 def rp_fill(streams, dist, dtype, bound, flags, out, per_stream, stream=None):
     _check(lib().rp_fill(streams.h, dist, dtype, bound, flags, _dev_ptr(out), per_stream, _stream_ptr(stream)))
+
+
+def rp_permutations(streams, n, out, stream=None):
+    _check(lib().rp_permutations(streams.h, n, _dev_ptr(out), _stream_ptr(stream)))
+
+
+def rp_sample(streams, n, k, out, stream=None):
+    _check(lib().rp_sample(streams.h, n, k, _dev_ptr(out), _stream_ptr(stream)))
 
 
 def rp_fill_law(streams, law, params, out, per_stream, stream=None):

@@ -1630,6 +1630,7 @@ int launch_fill_law(int engine, int law, const FillArgs &a, hipStream_t st)
 }
 
 #include "k_samplers.h"
+#include "k_discrete.h"
 #include "k_batched.h"
 #include "k_serial.h"
 

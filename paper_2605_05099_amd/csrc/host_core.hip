@@ -997,6 +997,54 @@ extern "C" int rp_fill(rp_streams *s, int dist, int dtype, uint64_t bound, int f
     return launch_fill(s->engine, dist, dtype, a, (hipStream_t)hip_stream);
 }
 
+extern "C" int rp_permutations(rp_streams *s, uint32_t n, uint32_t *d_out, void *hip_stream)
+{
+    if (!s) return fail(RP_ENULL, "rp_permutations: NULL streams");
+    if (n == 0) return RP_OK;
+    if (!d_out) return fail(RP_ENULL, "rp_permutations: NULL output");
+    if ((uintptr_t)d_out % 4) return fail(RP_EINVAL, "rp_permutations: output not aligned to 4 bytes");
+    int rc = ensure_device_tables();
+    if (rc) return rc;
+    FillArgs a{};
+    a.words = s->d_words;
+    a.phase = s->d_phase;
+    a.n = s->n;
+    a.per_stream = n;
+    a.out = d_out;
+    return launch_discrete(s->engine, true, a, nullptr, 0, (hipStream_t)hip_stream);
+}
+
+extern "C" int rp_sample(rp_streams *s, uint32_t n, uint32_t k, uint32_t *d_out, void *hip_stream)
+{
+    if (!s) return fail(RP_ENULL, "rp_sample: NULL streams");
+    if (k > n) return fail(RP_EINVAL, "rp_sample: k = %u exceeds n = %u", k, n);
+    if (k >= (1u << 30)) return fail(RP_EINVAL, "rp_sample: k = %u too large", k);
+    if (k == 0) return RP_OK;
+    if (!d_out) return fail(RP_ENULL, "rp_sample: NULL output");
+    if ((uintptr_t)d_out % 4) return fail(RP_EINVAL, "rp_sample: output not aligned to 4 bytes");
+    int rc = ensure_device_tables();
+    if (rc) return rc;
+    FillArgs a{};
+    a.words = s->d_words;
+    a.phase = s->d_phase;
+    a.n = s->n;
+    a.per_stream = k;
+    a.bound = n;
+    a.out = d_out;
+    const hipStream_t st = (hipStream_t)hip_stream;
+    if (2 * (uint64_t)k > n) return launch_discrete(s->engine, false, a, nullptr, 0, st);
+    int tbits = 1;
+    while ((1ull << tbits) < 2 * (uint64_t)k) tbits++;
+    const uint64_t cap = 1ull << tbits;
+    if (s->n > UINT64_MAX / (cap * 4)) return fail(RP_EINVAL, "rp_sample: workspace size overflow");
+    uint32_t *tab = nullptr;
+    hipError_t e = hipMallocAsync((void **)&tab, s->n * cap * 4, st);
+    if (e != hipSuccess) return fail(RP_ENOMEM, "rp_sample: workspace: %s", hipGetErrorString(e));
+    rc = launch_discrete(s->engine, false, a, tab, tbits, st);
+    (void)hipFreeAsync(tab, st);
+    return rc;
+}
+
 extern "C" int rp_fill_law(rp_streams *s, int law, const double *p, int np, double *d_out, uint64_t per_stream,
                            void *hip_stream)
 {

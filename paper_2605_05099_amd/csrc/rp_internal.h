@@ -126,6 +126,9 @@ int serial_entries();
 int serial_chunks_per_block();
 
 int launch_moments(int engine, const SampArgs &s, hipStream_t stream);
+// batched permutations (perm) or samples (k_discrete.h); f.per_stream = n or
+// k, f.bound = n for samples; tab: 2^tbits entries per substream (Floyd)
+int launch_discrete(int engine, bool perm, const FillArgs &f, uint32_t *tab, int tbits, hipStream_t stream);
 int launch_gamma_elem(int engine, const SampArgs &s, bool beta, hipStream_t stream);
 // rows of normals: z[i * d + t] = t-th normal of substream i, binary32
 int launch_norm_rows(int engine, const SampArgs &s, hipStream_t stream);
