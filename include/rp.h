@@ -57,7 +57,10 @@ enum {
     RP_X256SS = 6,     /* "x256**"     xoshiro256**, 4 state words; seeding, */
                        /*              jumps and substreams as x256++       */
     RP_SQUARES = 7,    /* "squares"    squares64, counter 1 + key 1         */
-    RP_NENGINES = 8
+    RP_XORO128 = 8,    /* "xoro++"     xoroshiro128++, 2 state words        */
+    RP_XS128 = 9,      /* "x128+"      xorshift128+, 2 state words; jumps   */
+                       /*              2^k only for k < 128 (both engines)  */
+    RP_NENGINES = 10
 };
 
 typedef struct rp_rng rp_rng;         /* one serial stream, host resident  */

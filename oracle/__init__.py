@@ -17,8 +17,9 @@ import numpy as np
 from . import build as _build
 from . import jumppoly
 
-X256PP, PCG64, PHILOX4X32, PHILOX4X64, SFC64, RANLUX, X256SS, SQUARES = range(8)
-ENGINE_IDS = {"x256++": X256PP, "x256**": X256SS, "squares": SQUARES, "pcg64": PCG64, "philox4x32": PHILOX4X32,
+X256PP, PCG64, PHILOX4X32, PHILOX4X64, SFC64, RANLUX, X256SS, SQUARES, XORO128PP, XS128P = range(10)
+ENGINE_IDS = {"x256++": X256PP, "x256**": X256SS, "squares": SQUARES, "xoro++": XORO128PP, "x128+": XS128P,
+              "pcg64": PCG64, "philox4x32": PHILOX4X32,
               "philox": PHILOX4X64, "sfc64": SFC64, "ranlux++": RANLUX}
 
 _lib = None
@@ -40,6 +41,8 @@ def lib():
             "or_squares_set_key": ([vp, u64], ctypes.c_int),
             "or_x256_apply_poly": ([vp, vp], ctypes.c_int),
             "or_x256_linear_steps": ([vp, vp, sz], None),
+            "or_x128_linear_steps": ([u64, vp, vp, sz], ctypes.c_int),
+            "or_x128_apply_poly": ([vp, vp], ctypes.c_int),
             "or_pcg64_advance": ([vp, u64, u64], ctypes.c_int),
             "or_philox_advance": ([vp, vp], ctypes.c_int),
             "or_ranlux_advance": ([vp, vp], ctypes.c_int),
@@ -164,6 +167,11 @@ class Stream:
         if self.engine in (X256PP, X256SS):
             p = jumppoly.x256_char_poly(lib())
             return self.x256_apply_poly(jumppoly.xpow_mod(n, p))
+        if self.engine in (XORO128PP, XS128P):
+            p = jumppoly.x128_char_poly(lib(), self.engine)
+            w = jumppoly.poly_words(jumppoly.xpow_mod(n, p), 2)
+            assert lib().or_x128_apply_poly(_p(self.buf), _p(w)) == 0
+            return self
         if self.engine == SQUARES:
             # counter engine with period 2^64: the counter word moves by n
             self.buf[2] = np.uint64((int(self.buf[2]) + n) % 2**64)

@@ -98,3 +98,21 @@ def x256_char_poly(lib):
         assert length == 256, length
         _X256_P = p
     return _X256_P
+
+
+_X128_P = {}
+
+
+def x128_char_poly(lib, engine):
+    """Characteristic polynomial of a 128-bit xor engine's linear core
+    (xoroshiro128 or xorshift128; degree 128)."""
+    if engine not in _X128_P:
+        st = np.array([0x0123456789ABCDEF, 0x0F1E2D3C4B5A6978], dtype=np.uint64)
+        bits = np.zeros(256, dtype=np.uint64)
+        rc = lib.or_x128_linear_steps(ctypes.c_uint64(engine), st.ctypes.data_as(ctypes.c_void_p),
+                                      bits.ctypes.data_as(ctypes.c_void_p), ctypes.c_size_t(256))
+        assert rc == 0
+        p, length = char_poly_from_bits([int(b) for b in bits])
+        assert length == 128, length
+        _X128_P[engine] = p
+    return _X128_P[engine]

@@ -24,6 +24,8 @@
  *   xoshiro256++ output scrambler          parity unpinned (no external implementation here)
  *   xoshiro256** output scrambler          parity unpinned (no external implementation here)
  *   squares64 output function              parity unpinned (no external implementation here)
+ *   xoroshiro128++, xorshift128+ cores     pinned: primitive characteristic polynomials (period 2^128-1)
+ *   their output scramblers                parity unpinned (no external implementation here)
  *   ranlux++                               pinned: modulus/multiplier/period, big-integer arithmetic
  *   seeding mixer (seed_seq_fe128)         pinned: NumPy SeedSequence
  *   u01 / u01f / bounded ints              pinned: NumPy Generator
@@ -57,7 +59,9 @@ enum {
     OR_RANLUX = 5,
     OR_X256SS = 6,
     OR_SQUARES = 7,
-    OR_NENGINE = 8
+    OR_XORO128PP = 8,
+    OR_XS128P = 9,
+    OR_NENGINE = 10
 };
 
 /*
@@ -132,6 +136,57 @@ static uint64_t x256ss_word(uint64_t s[4])
     uint64_t out = rotl64(s[1] * 5u, 7) * 9u;
     x256_linear(s);
     return out;
+}
+
+/* ------------------------------------------------------------------------ */
+/* xoroshiro128++ (Blackman and Vigna 2019; Table 2 "xoro++") and           */
+/* xorshift128+ (Vigna; Table 2 "x128+"), two state words each.  The ++     */
+/* output is rotl(s0 + s1, 17) + s0 and the + output s0 + s1, both of the   */
+/* state before the update.  xorshift128+ uses the shift triple (23, 18, 5) */
+/* of the current reference code (the 2014 paper's constants were           */
+/* (23, 17, 26)).                                                            */
+/* ------------------------------------------------------------------------ */
+static void xoro128_linear(uint64_t s[2])
+{
+    uint64_t s0 = s[0], s1 = s[1];
+    s1 ^= s0;
+    s[0] = rotl64(s0, 49) ^ s1 ^ (s1 << 21);
+    s[1] = rotl64(s1, 28);
+}
+
+static uint64_t xoro128pp_word(uint64_t s[2])
+{
+    uint64_t out = rotl64(s[0] + s[1], 17) + s[0];
+    xoro128_linear(s);
+    return out;
+}
+
+static void xs128_linear(uint64_t s[2])
+{
+    uint64_t a = s[0];
+    const uint64_t b = s[1];
+    s[0] = b;
+    a ^= a << 23;
+    s[1] = a ^ b ^ (a >> 18) ^ (b >> 5);
+}
+
+static uint64_t xs128p_word(uint64_t s[2])
+{
+    uint64_t out = s[0] + s[1];
+    xs128_linear(s);
+    return out;
+}
+
+/* one step of a 128-bit linear core (characteristic polynomials) */
+int or_x128_linear_steps(uint64_t engine, uint64_t st[2], uint64_t *bit0_out, size_t n)
+{
+    if (engine != OR_XORO128PP && engine != OR_XS128P) return -1;
+    for (size_t i = 0; i < n; i++) {
+        bit0_out[i] = st[0] & 1u;
+        if (engine == OR_XORO128PP) xoro128_linear(st);
+        else xs128_linear(st);
+    }
+    return 0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -519,6 +574,8 @@ static uint64_t next_word(or_stream *s)
     case OR_X256PP: return x256pp_word(s->st);
     case OR_X256SS: return x256ss_word(s->st);
     case OR_SQUARES: return squares_word(s->st);
+    case OR_XORO128PP: return xoro128pp_word(s->st);
+    case OR_XS128P: return xs128p_word(s->st);
     case OR_PCG64: return pcg64_word(s->st);
     case OR_SFC64: return sfc64_word(s->st);
     default: {
@@ -604,6 +661,8 @@ static int seeded_words(uint64_t engine)
     case OR_X256PP: return 4;
     case OR_X256SS: return 4;
     case OR_SQUARES: return 2;
+    case OR_XORO128PP: return 2;
+    case OR_XS128P: return 2;
     case OR_PCG64: return 4;
     case OR_PHILOX4X32: return 3;
     case OR_PHILOX4X64: return 6;
@@ -661,6 +720,11 @@ int or_seed(or_stream *s, uint64_t engine, uint64_t seed, const uint32_t *key, s
         break;
     case OR_SFC64:
         or_sfc64_set_abc(s, w[0], w[1], w[2]);
+        break;
+    case OR_XORO128PP:
+    case OR_XS128P:
+        memcpy(s->st, w, 2 * 8);
+        if (!(w[0] | w[1])) s->st[0] = 1; /* the excluded all-zero state */
         break;
     case OR_SQUARES:
         /* reading: the key is made odd (the key 0 would give a constant
@@ -747,6 +811,24 @@ int or_x256_apply_poly(or_stream *s, const uint64_t poly[4])
         x256_linear(cur);
     }
     memcpy(s->st, acc, sizeof acc);
+    return 0;
+}
+
+/* 128-bit xor engines: s' = sum_k p_k T^k s for a polynomial of degree < 128 */
+int or_x128_apply_poly(or_stream *s, const uint64_t poly[2])
+{
+    if (s->engine != OR_XORO128PP && s->engine != OR_XS128P) return -1;
+    uint64_t acc[2] = {0, 0}, cur[2] = {s->st[0], s->st[1]};
+    for (int k = 0; k < 128; k++) {
+        if ((poly[k / 64] >> (k % 64)) & 1) {
+            acc[0] ^= cur[0];
+            acc[1] ^= cur[1];
+        }
+        if (s->engine == OR_XORO128PP) xoro128_linear(cur);
+        else xs128_linear(cur);
+    }
+    s->st[0] = acc[0];
+    s->st[1] = acc[1];
     return 0;
 }
 

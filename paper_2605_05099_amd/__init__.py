@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "librp.so")
 
 # status codes, engines, distributions, dtypes (include/rp.h)
 RP_OK, RP_EINVAL, RP_ENOMEM, RP_EUNSUPPORTED, RP_EDEVICE, RP_ENOTSPD, RP_ENULL = 0, -1, -2, -3, -4, -5, -6
-RP_X256PP, RP_PCG64, RP_PHILOX4X32, RP_PHILOX, RP_SFC64, RP_RANLUX, RP_X256SS, RP_SQUARES = range(8)
+RP_X256PP, RP_PCG64, RP_PHILOX4X32, RP_PHILOX, RP_SFC64, RP_RANLUX, RP_X256SS, RP_SQUARES, RP_XORO128, RP_XS128 = range(10)
 RP_SUB_KEY, RP_SUB_INC, RP_SUB_SPAWN, RP_SUB_JUMP = range(4)
 RP_RAW, RP_U01, RP_BOUNDED, RP_NORM, RP_EXP = range(5)
 RP_U64, RP_U32, RP_F64, RP_F32 = range(4)
@@ -28,8 +28,8 @@ RP_FLAG_52BIT = 1
  RP_LAW_WEIBULL, RP_LAW_GAMMA, RP_LAW_BETA, RP_LAW_CHI2, RP_LAW_T, RP_LAW_F, RP_LAW_SKEWNORMAL) = range(1, 15)
 
 ENGINES = {"x256++": RP_X256PP, "x256**": RP_X256SS, "pcg64": RP_PCG64, "philox4x32": RP_PHILOX4X32, "philox": RP_PHILOX,
-           "sfc64": RP_SFC64, "ranlux++": RP_RANLUX, "squares": RP_SQUARES}
-STATE_WORDS = {RP_X256PP: 4, RP_PCG64: 4, RP_PHILOX4X32: 3, RP_PHILOX: 6, RP_SFC64: 4, RP_RANLUX: 9, RP_X256SS: 4, RP_SQUARES: 2}
+           "sfc64": RP_SFC64, "ranlux++": RP_RANLUX, "squares": RP_SQUARES, "xoro++": RP_XORO128, "x128+": RP_XS128}
+STATE_WORDS = {RP_X256PP: 4, RP_PCG64: 4, RP_PHILOX4X32: 3, RP_PHILOX: 6, RP_SFC64: 4, RP_RANLUX: 9, RP_X256SS: 4, RP_SQUARES: 2, RP_XORO128: 2, RP_XS128: 2}
 
 _vp, _sz, _u64, _u32, _int = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
 _SIGS = {

@@ -78,6 +78,44 @@ struct X256 {
     }
 };
 
+// xoroshiro128++ (Table 2 "xoro++"): linear map s1 ^= s0;
+// s0 = rotl(s0, 49) ^ s1 ^ (s1 << 21); s1 = rotl(s1, 28); output
+// rotl(s0 + s1, 17) + s0 of the state before the update.
+struct Xoro128 {
+    uint64_t s0, s1;
+    RP_HD void linear()
+    {
+        const uint64_t t = s1 ^ s0;
+        s0 = rotl(s0, 49) ^ t ^ (t << 21);
+        s1 = rotl(t, 28);
+    }
+    RP_HD uint64_t next()
+    {
+        const uint64_t r = rotl(s0 + s1, 17) + s0;
+        linear();
+        return r;
+    }
+};
+
+// xorshift128+ (Table 2 "x128+"), with the shift triple (23, 18, 5) of the
+// current reference code: t = s0 ^ (s0 << 23); (s0, s1) <- (s1, t ^ s1 ^
+// (t >> 18) ^ (s1 >> 5)); output s0 + s1 of the state before the update.
+struct Xs128 {
+    uint64_t s0, s1;
+    RP_HD void linear()
+    {
+        uint64_t t = s0 ^ (s0 << 23);
+        s0 = s1;
+        s1 = t ^ s1 ^ (t >> 18) ^ (s1 >> 5);
+    }
+    RP_HD uint64_t next()
+    {
+        const uint64_t r = s0 + s1;
+        linear();
+        return r;
+    }
+};
+
 // ---------------------------------------------------------------------------
 // PCG64 DXSM: s <- s * M + inc (mod 2^128) with the 64-bit multiplier M;
 // the output permutes the state before the step.

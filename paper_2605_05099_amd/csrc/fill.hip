@@ -1182,6 +1182,22 @@ struct LaneX256T {
 using LaneX256 = LaneX256T<false>;
 using LaneX256SS = LaneX256T<true>;
 
+// xoroshiro128++ and xorshift128+ (two state words each)
+template <class S>
+struct Lane2 {
+    S s;
+    __device__ void load(const FillArgs &a, uint64_t i) { s = S{a.words[i], a.words[a.n + i]}; }
+    __device__ uint64_t next() { return s.next(); }
+    __device__ void reserve(int) {}
+    __device__ void store(const FillArgs &a, uint64_t i) const
+    {
+        a.words[i] = s.s0;
+        a.words[a.n + i] = s.s1;
+    }
+};
+using LaneXoro128 = Lane2<Xoro128>;
+using LaneXs128 = Lane2<Xs128>;
+
 struct LaneSquares {
     uint64_t c, key;
     __device__ void load(const FillArgs &a, uint64_t i)
@@ -1591,6 +1607,8 @@ int launch_fill(int engine, int dist, int dtype, const FillArgs &a, hipStream_t 
     case RP_X256PP: return dispatch_dist<false, LaneX256>(dist, dtype, a, st);
     case RP_X256SS: return dispatch_dist<false, LaneX256SS>(dist, dtype, a, st);
     case RP_SQUARES: return dispatch_dist<true, WaveSquares>(dist, dtype, a, st);
+    case RP_XORO128: return dispatch_dist<false, LaneXoro128>(dist, dtype, a, st);
+    case RP_XS128: return dispatch_dist<false, LaneXs128>(dist, dtype, a, st);
     case RP_SFC64: return dispatch_dist<false, LaneSfc64>(dist, dtype, a, st);
     case RP_RANLUX: return dispatch_dist<false, LaneRanlux>(dist, dtype, a, st);
     }
@@ -1623,6 +1641,8 @@ int launch_fill_law(int engine, int law, const FillArgs &a, hipStream_t st)
     case RP_X256PP: return dispatch_law<false, LaneX256>(law, a, st);
     case RP_X256SS: return dispatch_law<false, LaneX256SS>(law, a, st);
     case RP_SQUARES: return dispatch_law<true, WaveSquares>(law, a, st);
+    case RP_XORO128: return dispatch_law<false, LaneXoro128>(law, a, st);
+    case RP_XS128: return dispatch_law<false, LaneXs128>(law, a, st);
     case RP_SFC64: return dispatch_law<false, LaneSfc64>(law, a, st);
     case RP_RANLUX: return dispatch_law<false, LaneRanlux>(law, a, st);
     }

@@ -87,6 +87,8 @@ static const EngineInfo kEngines[RP_NENGINES] = {
     {"ranlux++", "ranlux++ (Sibidanov, 2017), 9 state words, period about 2^570", 9, 9},
     {"x256**", "xoshiro256** (Blackman and Vigna, 2018), 4 state words, period 2^256-1", 4, 1},
     {"squares", "squares64 (Widynski, 2021), 2 state words, period 2^64 per key", 2, 1},
+    {"xoro++", "xoroshiro128++ (Blackman and Vigna, 2019), 2 state words, period 2^128-1", 2, 1},
+    {"x128+", "xorshift128+ (Vigna, 2014), 2 state words, period 2^128-1", 2, 1},
 };
 
 namespace rp {
@@ -365,6 +367,114 @@ Poly poly_xpow(uint64_t lo, uint64_t hi, const Poly &P)
     return r;
 }
 
+// degree-D versions for the 128-bit xor engines (D = 128)
+template <int D>
+void poly_mulx_d(Poly &a, const Poly &P)
+{
+    uint64_t carry = 0;
+    for (int k = 0; k < 5; k++) {
+        uint64_t nc = a.w[k] >> 63;
+        a.w[k] = (a.w[k] << 1) | carry;
+        carry = nc;
+    }
+    if (a.bit(D))
+        for (int k = 0; k < 5; k++) a.w[k] ^= P.w[k];
+}
+
+template <int D>
+Poly poly_mulmod_d(const Poly &a, const Poly &b, const Poly &P)
+{
+    Poly r;
+    for (int i = D - 1; i >= 0; i--) {
+        poly_mulx_d<D>(r, P);
+        if (b.bit(i))
+            for (int k = 0; k < 5; k++) r.w[k] ^= a.w[k];
+    }
+    return r;
+}
+
+template <int D>
+Poly poly_xpow_d(uint64_t lo, uint64_t hi, const Poly &P)
+{
+    Poly r, base;
+    r.flip(0);
+    base.flip(1);
+    for (int half = 0; half < 2; half++) {
+        uint64_t e = half ? hi : lo;
+        for (int bit = 0; bit < 64; bit++) {
+            if ((e >> bit) & 1) r = poly_mulmod_d<D>(r, base, P);
+            base = poly_mulmod_d<D>(base, base, P);
+        }
+    }
+    return r;
+}
+
+// characteristic polynomial of a 2-word linear core from 256 output bits
+// (Berlekamp-Massey over GF(2); the reciprocal of the connection polynomial)
+template <class S>
+Poly x128_charpoly_of()
+{
+    S s{0x0123456789ABCDEFull, 0x0F1E2D3C4B5A6978ull};
+    std::vector<int> bits(256);
+    for (int i = 0; i < 256; i++) {
+        bits[i] = (int)(s.s0 & 1);
+        s.linear();
+    }
+    std::vector<int> C(257, 0), B(257, 0), T;
+    C[0] = B[0] = 1;
+    int L = 0, m = 1;
+    for (int n = 0; n < 256; n++) {
+        int d = bits[n];
+        for (int i = 1; i <= L; i++) d ^= C[i] & bits[n - i];
+        if (!d) {
+            m++;
+            continue;
+        }
+        T = C;
+        for (int i = 0; i + m <= 256; i++) C[i + m] ^= B[i];
+        if (2 * L <= n) {
+            L = n + 1 - L;
+            B = T;
+            m = 1;
+        } else {
+            m++;
+        }
+    }
+    Poly p;
+    for (int i = 0; i <= L; i++)
+        if (C[i]) p.flip(L - i);
+    return p;  // L is 128 (primitive of degree 128)
+}
+
+const Poly &x128_charpoly(int engine)
+{
+    static const Poly xoro = x128_charpoly_of<Xoro128>();
+    static const Poly xs = x128_charpoly_of<Xs128>();
+    return engine == RP_XORO128 ? xoro : xs;
+}
+
+template <class S>
+void x128_apply_s(uint64_t st[2], const Poly &p)
+{
+    S cur{st[0], st[1]};
+    uint64_t a0 = 0, a1 = 0;
+    for (int k = 0; k < 128; k++) {
+        if (p.bit(k)) {
+            a0 ^= cur.s0;
+            a1 ^= cur.s1;
+        }
+        cur.linear();
+    }
+    st[0] = a0;
+    st[1] = a1;
+}
+
+void x128_apply(int engine, uint64_t st[2], const Poly &p)
+{
+    if (engine == RP_XORO128) x128_apply_s<Xoro128>(st, p);
+    else x128_apply_s<Xs128>(st, p);
+}
+
 void x256_apply(uint64_t st[4], const Poly &p)
 {
     X256 cur{st[0], st[1], st[2], st[3]};
@@ -428,6 +538,20 @@ static uint64_t host_next(rp_rng *r)
     }
     case RP_SQUARES:
         return squares64(st[0]++, st[1]);
+    case RP_XORO128: {
+        Xoro128 s{st[0], st[1]};
+        const uint64_t w = s.next();
+        st[0] = s.s0;
+        st[1] = s.s1;
+        return w;
+    }
+    case RP_XS128: {
+        Xs128 s{st[0], st[1]};
+        const uint64_t w = s.next();
+        st[0] = s.s0;
+        st[1] = s.s1;
+        return w;
+    }
     case RP_SFC64: {
         Sfc64 s{st[0], st[1], st[2], st[3]};
         uint64_t w = s.next();
@@ -503,6 +627,11 @@ static void seed_state(rp_rng *r, uint64_t seed, const uint32_t *key, size_t n_k
     case RP_PCG64:
         memcpy(r->st, w, 32);
         r->st[2] |= 1u;
+        break;
+    case RP_XORO128:
+    case RP_XS128:
+        memcpy(r->st, w, 16);
+        if (!(w[0] | w[1])) r->st[0] = 1;  // the excluded all-zero state
         break;
     case RP_SQUARES:
         // reading: the key is made odd (key 0 gives a constant stream)
@@ -606,6 +735,10 @@ static int advance_impl(rp_rng *rng, uint64_t lo, uint64_t hi)
     case RP_SQUARES:  // period 2^64: hi 2^64 steps are a full period
         st[0] += lo;
         return RP_OK;
+    case RP_XORO128:
+    case RP_XS128:
+        x128_apply(rng->engine, st, poly_xpow_d<128>(lo, hi, x128_charpoly(rng->engine)));
+        return RP_OK;
     case RP_PCG64: {
         PcgAffine m = pcg_power(lo, hi);
         u128 s{st[0], st[1]}, inc{st[2], st[3]};
@@ -657,6 +790,9 @@ extern "C" int rp_jump(rp_rng *rng, int k)
         return fail_rng(rng, RP_EINVAL, "rp_jump: k must be 32, 64, 96, 128 or 192 (got %d)", k);
     if (rng->engine == RP_SQUARES && k >= 64)
         return fail_rng(rng, RP_EINVAL, "rp_jump: 2^%d is not below the period of 'squares'", k);
+    if ((rng->engine == RP_XORO128 || rng->engine == RP_XS128) && k >= 128)
+        return fail_rng(rng, RP_EINVAL, "rp_jump: 2^%d is not below the period of '%s'", k,
+                        kEngines[rng->engine].id);
     if (k < 128) return advance_impl(rng, k < 64 ? (1ull << k) : 0, k >= 64 ? (1ull << (k - 64)) : 0);
     switch (rng->engine) {
     case RP_X256PP:
@@ -826,6 +962,13 @@ extern "C" int rp_streams_create(const rp_rng *base, int kind, uint64_t n, int j
             const Poly &P = x256_charpoly();
             for (int i = 0; i < jump_log2; i++) base_x = poly_mulmod(base_x, base_x, P);
             jpoly = base_x;
+        } else if (e == RP_XORO128 || e == RP_XS128) {
+            if (jump_log2 >= 128) return fail(RP_EINVAL, "%s jump_log2 must be < 128", kEngines[e].id);
+            Poly base_x;
+            base_x.flip(1);
+            const Poly &P = x128_charpoly(e);
+            for (int i = 0; i < jump_log2; i++) base_x = poly_mulmod_d<128>(base_x, base_x, P);
+            jpoly = base_x;
         } else if (e == RP_RANLUX) {
             uint64_t ex[4] = {0, 0, 0, 0};
             ex[jump_log2 / 64] = 1ull << (jump_log2 % 64);
@@ -859,6 +1002,7 @@ extern "C" int rp_streams_create(const rp_rng *base, int kind, uint64_t n, int j
         case RP_SUB_JUMP:
             if (i > 0) {
                 if (e == RP_X256PP || e == RP_X256SS) x256_apply(jumped.st, jpoly);
+                else if (e == RP_XORO128 || e == RP_XS128) x128_apply(e, jumped.st, jpoly);
                 else if (e == RP_RANLUX) rl_mulmod(jumped.st, jmul, jumped.st);
                 else if (e == RP_PCG64) {
                     u128 s{jumped.st[0], jumped.st[1]}, inc{jumped.st[2], jumped.st[3]};
@@ -1359,7 +1503,8 @@ extern "C" int rp_fill_serial(rp_rng *rng, int dist, int dtype, uint64_t bound, 
     int rc = ensure_device_tables();
     if (rc) return rc;
     hipStream_t st = (hipStream_t)hip_stream;
-    if (rng->engine == RP_SFC64)  // no jump: one lane
+    // sfc64 has no jump; the 128-bit xor engines have no lane jump tables
+    if (rng->engine == RP_SFC64 || rng->engine == RP_XORO128 || rng->engine == RP_XS128)
         return serial_fallback(rng, dist, dtype, bound, flags, d_out, n, st);
     SerialArgs a{};
     memcpy(a.base, rng->st, sizeof a.base);

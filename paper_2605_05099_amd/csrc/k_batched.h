@@ -233,6 +233,8 @@ int launch_batched_gen(int engine, const BatchArgs &a, bool beta, unsigned grid,
     case RP_X256PP: launch_batched_e<LaneX256>(a, beta, grid, block, st); break;
     case RP_X256SS: launch_batched_e<LaneX256SS>(a, beta, grid, block, st); break;
     case RP_SQUARES: launch_batched_e<LaneSquares>(a, beta, grid, block, st); break;
+    case RP_XORO128: launch_batched_e<LaneXoro128>(a, beta, grid, block, st); break;
+    case RP_XS128: launch_batched_e<LaneXs128>(a, beta, grid, block, st); break;
     case RP_PCG64: launch_batched_e<LanePcg>(a, beta, grid, block, st); break;
     case RP_PHILOX4X32: launch_batched_e<LanePhilox32>(a, beta, grid, block, st); break;
     case RP_PHILOX: launch_batched_e<LanePhilox64>(a, beta, grid, block, st); break;

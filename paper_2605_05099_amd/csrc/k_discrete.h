@@ -138,6 +138,8 @@ int launch_discrete(int engine, bool perm, const FillArgs &f, uint32_t *tab, int
     case RP_SFC64: launch_discrete_e<LaneSfc64>(perm, f, tab, tbits, st); break;
     case RP_RANLUX: launch_discrete_e<LaneRanlux>(perm, f, tab, tbits, st); break;
     case RP_SQUARES: launch_discrete_e<LaneSquares>(perm, f, tab, tbits, st); break;
+    case RP_XORO128: launch_discrete_e<LaneXoro128>(perm, f, tab, tbits, st); break;
+    case RP_XS128: launch_discrete_e<LaneXs128>(perm, f, tab, tbits, st); break;
     default: return fail(RP_EINVAL, "unknown engine");
     }
     const hipError_t e = hipGetLastError();

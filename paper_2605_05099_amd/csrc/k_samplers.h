@@ -590,6 +590,8 @@ int launch_fill_mix(int engine, int law, const FillArgs &f, hipStream_t st)
     case RP_X256PP: rc = launch_mix_e<LaneX256>(law, f, st); break;
     case RP_X256SS: rc = launch_mix_e<LaneX256SS>(law, f, st); break;
     case RP_SQUARES: rc = launch_mix_e<LaneSquares>(law, f, st); break;
+    case RP_XORO128: rc = launch_mix_e<LaneXoro128>(law, f, st); break;
+    case RP_XS128: rc = launch_mix_e<LaneXs128>(law, f, st); break;
     case RP_PCG64: rc = launch_mix_e<LanePcg>(law, f, st); break;
     case RP_PHILOX4X32: rc = launch_mix_e<LanePhilox32>(law, f, st); break;
     case RP_PHILOX: rc = launch_mix_e<LanePhilox64>(law, f, st); break;
@@ -628,6 +630,8 @@ int launch_moments(int engine, const SampArgs &s, hipStream_t st)
     case RP_X256PP: launch_moments_e<LaneX256>(s, st); break;
     case RP_X256SS: launch_moments_e<LaneX256SS>(s, st); break;
     case RP_SQUARES: launch_moments_e<LaneSquares>(s, st); break;
+    case RP_XORO128: launch_moments_e<LaneXoro128>(s, st); break;
+    case RP_XS128: launch_moments_e<LaneXs128>(s, st); break;
     case RP_PCG64: launch_moments_e<LanePcg>(s, st); break;
     case RP_PHILOX4X32: launch_moments_e<LanePhilox32>(s, st); break;
     case RP_PHILOX: launch_moments_e<LanePhilox64>(s, st); break;
@@ -646,6 +650,8 @@ int launch_norm_rows(int engine, const SampArgs &s, hipStream_t st)
     case RP_X256PP: hipLaunchKernelGGL(k_norm_rows<LaneX256>, grid, block, 0, st, s); break;
     case RP_X256SS: hipLaunchKernelGGL(k_norm_rows<LaneX256SS>, grid, block, 0, st, s); break;
     case RP_SQUARES: hipLaunchKernelGGL(k_norm_rows<LaneSquares>, grid, block, 0, st, s); break;
+    case RP_XORO128: hipLaunchKernelGGL(k_norm_rows<LaneXoro128>, grid, block, 0, st, s); break;
+    case RP_XS128: hipLaunchKernelGGL(k_norm_rows<LaneXs128>, grid, block, 0, st, s); break;
     case RP_PCG64: hipLaunchKernelGGL(k_norm_rows<LanePcg>, grid, block, 0, st, s); break;
     case RP_PHILOX4X32: hipLaunchKernelGGL(k_norm_rows<LanePhilox32>, grid, block, 0, st, s); break;
     case RP_PHILOX: hipLaunchKernelGGL(k_norm_rows<LanePhilox64>, grid, block, 0, st, s); break;
@@ -663,6 +669,8 @@ int launch_gamma_elem(int engine, const SampArgs &s, bool beta, hipStream_t st)
     case RP_X256PP: launch_elem_e<LaneX256>(s, beta, st); break;
     case RP_X256SS: launch_elem_e<LaneX256SS>(s, beta, st); break;
     case RP_SQUARES: launch_elem_e<LaneSquares>(s, beta, st); break;
+    case RP_XORO128: launch_elem_e<LaneXoro128>(s, beta, st); break;
+    case RP_XS128: launch_elem_e<LaneXs128>(s, beta, st); break;
     case RP_PCG64: launch_elem_e<LanePcg>(s, beta, st); break;
     case RP_PHILOX4X32: launch_elem_e<LanePhilox32>(s, beta, st); break;
     case RP_PHILOX: launch_elem_e<LanePhilox64>(s, beta, st); break;

@@ -14,6 +14,8 @@ FAMILY = {
     "ranlux++": (rp.RP_SUB_JUMP, "jump"),
     "sfc64": (rp.RP_SUB_SPAWN, "spawn"),
     "squares": (rp.RP_SUB_SPAWN, "spawn"),
+    "xoro++": (rp.RP_SUB_JUMP, "jump"),
+    "x128+": (rp.RP_SUB_JUMP, "jump"),
 }
 ENGINES = list(FAMILY)
 

@@ -394,3 +394,39 @@ def test_squares_streams_differ_and_are_uniform():
     assert stats.kstest(u, "uniform").pvalue > 1e-4
     bits = np.unpackbits(a.view(np.uint8)).reshape(-1, 64).mean(axis=0)
     assert np.abs(bits - 0.5).max() < 5 * 0.5 / np.sqrt(len(a))
+
+
+# ---- xoroshiro128++ and xorshift128+ (Table 2 "xoro++", "x128+") --------------
+# The linear cores are pinned by the period Table 2 states (2^128 - 1 <=> a
+# primitive characteristic polynomial); the output scramblers have no
+# implementation in this container (parity unpinned; checked statistically).
+
+def _factor_2_128_minus_1():
+    f = sympy.factorint(2**128 - 1)
+    assert sympy.prod([p**e for p, e in f.items()]) == 2**128 - 1
+    assert all(e == 1 and sympy.isprime(p) for p, e in f.items())
+    return list(f)
+
+
+@pytest.mark.parametrize("eng", [oracle.XORO128PP, oracle.XS128P])
+def test_x128_linear_cores_are_primitive(eng):
+    p = jumppoly.x128_char_poly(oracle.lib(), eng)
+    assert p.bit_length() - 1 == 128
+    order = 2**128 - 1
+    assert jumppoly.xpow_mod(order, p) == 1
+    for q in _factor_2_128_minus_1():
+        assert jumppoly.xpow_mod(order // q, p) != 1, q
+
+
+@pytest.mark.parametrize("eng", ["xoro++", "x128+"])
+def test_x128_jump_equals_stepping_and_outputs_uniform(eng):
+    for n in (1, 127, 128, 1000):
+        a = Stream.seeded(eng, 8).advance(n)
+        b = Stream.seeded(eng, 8)
+        b.raw(n)
+        assert a.state[:2] == b.state[:2]
+    x = Stream.seeded(eng, 9).raw(200000)
+    u = (x >> np.uint64(11)).astype(np.float64) * 2.0**-53
+    assert stats.kstest(u, "uniform").pvalue > 1e-4
+    bits = np.unpackbits(x.view(np.uint8)).reshape(-1, 64).mean(axis=0)
+    assert np.abs(bits - 0.5).max() < 5 * 0.5 / np.sqrt(len(x))
