@@ -340,14 +340,14 @@ def part_float(torch, rp, workloads, tm, sp):
 def part_engines(torch, rp, workloads, tm, sp):
     """Raw u64 and normal f64 fills of every engine on the substream
     workload's shape (2^16 substreams x 2^14 values): wavefront engines
-    (philox4x32, philox, pcg64, squares) and lane engines (x256++, x256**,
+    (philox4x32, philox, pcg64, squares, chacha20) and lane engines (x256++, x256**,
     sfc64, ranlux++, xoro++, x128+)."""
     n, per = workloads.SUB_N, workloads.SUB_PER
     buf = torch.empty(n * per, dtype=torch.float64, device="cuda")
     kinds = {"philox4x32": rp.RP_SUB_KEY, "philox": rp.RP_SUB_KEY, "pcg64": rp.RP_SUB_INC,
              "squares": rp.RP_SUB_SPAWN, "x256++": rp.RP_SUB_JUMP, "x256**": rp.RP_SUB_JUMP,
              "sfc64": rp.RP_SUB_SPAWN, "ranlux++": rp.RP_SUB_JUMP, "xoro++": rp.RP_SUB_JUMP,
-             "x128+": rp.RP_SUB_JUMP}
+             "x128+": rp.RP_SUB_JUMP, "chacha20": rp.RP_SUB_KEY}
     res = {}
     for eng, kind in kinds.items():
         S = rp.rp_streams_create(rp.rp_create(eng).seed(workloads.BASE_SEED), kind, n, 64)

@@ -60,7 +60,9 @@ enum {
     RP_XORO128 = 8,    /* "xoro++"     xoroshiro128++, 2 state words        */
     RP_XS128 = 9,      /* "x128+"      xorshift128+, 2 state words; jumps   */
                        /*              2^k only for k < 128 (both engines)  */
-    RP_NENGINES = 10
+    RP_CHACHA20 = 10,  /* "chacha20"   ChaCha20, key 4 + nonce 1.5 + block  */
+                       /*              counter 0.5 (high half of word 5)    */
+    RP_NENGINES = 11
 };
 
 typedef struct rp_rng rp_rng;         /* one serial stream, host resident  */
@@ -111,6 +113,7 @@ int rp_pcg64_set_inc(rp_rng *rng, uint64_t lo, uint64_t hi);       /* inc |= 1 *
 int rp_philox_set_key(rp_rng *rng, uint64_t k0, uint64_t k1);      /* 4x32: key = k0 */
 int rp_sfc64_set_abc(rp_rng *rng, uint64_t a, uint64_t b, uint64_t c); /* +18 steps */
 int rp_squares_set_key(rp_rng *rng, uint64_t key);                  /* key |= 1 */
+int rp_chacha20_set_nonce(rp_rng *rng, uint64_t lo, uint64_t hi);   /* 96-bit nonce */
 /* Checkpointing (Section 4.4): opaque byte image of the stream.  With
  * buf == NULL only *needed is set. */
 int rp_serialize(const rp_rng *rng, void *buf, size_t len, size_t *needed);

@@ -17,8 +17,9 @@ import numpy as np
 from . import build as _build
 from . import jumppoly
 
-X256PP, PCG64, PHILOX4X32, PHILOX4X64, SFC64, RANLUX, X256SS, SQUARES, XORO128PP, XS128P = range(10)
+X256PP, PCG64, PHILOX4X32, PHILOX4X64, SFC64, RANLUX, X256SS, SQUARES, XORO128PP, XS128P, CHACHA20 = range(11)
 ENGINE_IDS = {"x256++": X256PP, "x256**": X256SS, "squares": SQUARES, "xoro++": XORO128PP, "x128+": XS128P,
+              "chacha20": CHACHA20,
               "pcg64": PCG64, "philox4x32": PHILOX4X32,
               "philox": PHILOX4X64, "sfc64": SFC64, "ranlux++": RANLUX}
 
@@ -39,6 +40,8 @@ def lib():
             "or_philox_set_key": ([vp, u64, u64], ctypes.c_int),
             "or_sfc64_set_abc": ([vp, u64, u64, u64], None),
             "or_squares_set_key": ([vp, u64], ctypes.c_int),
+            "or_chacha20_set_nonce": ([vp, u64, u64], ctypes.c_int),
+            "or_chacha_qr": ([vp], None),
             "or_x256_apply_poly": ([vp, vp], ctypes.c_int),
             "or_x256_linear_steps": ([vp, vp, sz], None),
             "or_x128_linear_steps": ([u64, vp, vp, sz], ctypes.c_int),
@@ -148,6 +151,13 @@ class Stream:
         assert lib().or_philox_set_key(_p(self.buf), ctypes.c_uint64(k0), ctypes.c_uint64(k1)) == 0
         return self
 
+    def chacha20_set_nonce(self, nonce):
+        """The 96-bit nonce (key and block counter kept)."""
+        nonce = int(nonce)
+        assert lib().or_chacha20_set_nonce(_p(self.buf), ctypes.c_uint64(nonce & (2**64 - 1)),
+                                           ctypes.c_uint64(nonce >> 64)) == 0
+        return self
+
     def squares_set_key(self, key):
         assert lib().or_squares_set_key(_p(self.buf), ctypes.c_uint64(key)) == 0
         return self
@@ -171,6 +181,14 @@ class Stream:
             p = jumppoly.x128_char_poly(lib(), self.engine)
             w = jumppoly.poly_words(jumppoly.xpow_mod(n, p), 2)
             assert lib().or_x128_apply_poly(_p(self.buf), _p(w)) == 0
+            return self
+        if self.engine == CHACHA20:
+            # n blocks: the 32-bit counter in the high half of state word 5
+            # (mod 2^32); the buffered block is recomputed on the next draw
+            w5 = int(self.buf[2 + 5])
+            c = ((w5 >> 32) + n) % 2**32
+            self.buf[2 + 5] = np.uint64((w5 & (2**32 - 1)) | (c << 32))
+            self.buf[2 + 16 + 9] = np.uint64(0)     # blk_ok
             return self
         if self.engine == SQUARES:
             # counter engine with period 2^64: the counter word moves by n
@@ -348,6 +366,8 @@ def substream(engine, seed, kind, i, jump_log2=64):
     s = Stream.seeded(engine, seed)
     if kind == "key":
         return s.philox_set_key(i, 0)
+    if kind == "nonce":
+        return s.chacha20_set_nonce(i)
     if kind == "inc":
         return s.pcg64_set_inc(2 * i + 1)
     if kind == "jump":

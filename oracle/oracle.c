@@ -26,6 +26,7 @@
  *   squares64 output function              parity unpinned (no external implementation here)
  *   xoroshiro128++, xorshift128+ cores     pinned: primitive characteristic polynomials (period 2^128-1)
  *   their output scramblers                parity unpinned (no external implementation here)
+ *   chacha20 block function                parity unpinned (the published test vector is not here)
  *   ranlux++                               pinned: modulus/multiplier/period, big-integer arithmetic
  *   seeding mixer (seed_seq_fe128)         pinned: NumPy SeedSequence
  *   u01 / u01f / bounded ints              pinned: NumPy Generator
@@ -61,7 +62,8 @@ enum {
     OR_SQUARES = 7,
     OR_XORO128PP = 8,
     OR_XS128P = 9,
-    OR_NENGINE = 10
+    OR_CHACHA20 = 10,
+    OR_NENGINE = 11
 };
 
 /*
@@ -187,6 +189,65 @@ int or_x128_linear_steps(uint64_t engine, uint64_t st[2], uint64_t *bit0_out, si
         else xs128_linear(st);
     }
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* ChaCha20 (Bernstein; Table 2 "chacha20"; Table 3: key (4) + nonce (1.5) + */
+/* counter (0.5)).  Reading: st[0..3] hold the 256-bit key (32-bit words     */
+/* low half first), st[4] and the low half of st[5] the 96-bit nonce, the    */
+/* high half of st[5] the 32-bit block counter.  A block is the 20-round     */
+/* ChaCha permutation (ten column-and-diagonal double rounds) of the input   */
+/* words (the four "expand 32-byte k" constants, key, counter, nonce), the   */
+/* input added back; its 16 words give 8 64-bit words, the earlier word in  */
+/* the low half.  The counter advances by one per block (period 2^35 words). */
+/* ------------------------------------------------------------------------ */
+static uint32_t rotl32(uint32_t x, int k) { return (x << k) | (x >> (32 - k)); }
+
+static void chacha_qr(uint32_t x[16], int a, int b, int c, int d)
+{
+    x[a] += x[b]; x[d] ^= x[a]; x[d] = rotl32(x[d], 16);
+    x[c] += x[d]; x[b] ^= x[c]; x[b] = rotl32(x[b], 12);
+    x[a] += x[b]; x[d] ^= x[a]; x[d] = rotl32(x[d], 8);
+    x[c] += x[d]; x[b] ^= x[c]; x[b] = rotl32(x[b], 7);
+}
+
+/* one quarter round on four words (exposed for the tests) */
+void or_chacha_qr(uint32_t q[4])
+{
+    uint32_t x[16] = {0};
+    x[0] = q[0];
+    x[1] = q[1];
+    x[2] = q[2];
+    x[3] = q[3];
+    chacha_qr(x, 0, 1, 2, 3);
+    memcpy(q, x, 16);
+}
+
+static void or_chacha20_block(const uint64_t st[6], uint64_t out[8])
+{
+    uint32_t in[16] = {0x61707865u, 0x3320646eu, 0x79622d32u, 0x6b206574u};
+    for (int i = 0; i < 4; i++) {
+        in[4 + 2 * i] = (uint32_t)st[i];
+        in[5 + 2 * i] = (uint32_t)(st[i] >> 32);
+    }
+    in[12] = (uint32_t)(st[5] >> 32);
+    in[13] = (uint32_t)st[4];
+    in[14] = (uint32_t)(st[4] >> 32);
+    in[15] = (uint32_t)st[5];
+    uint32_t x[16];
+    memcpy(x, in, sizeof x);
+    for (int r = 0; r < 10; r++) {
+        chacha_qr(x, 0, 4, 8, 12);
+        chacha_qr(x, 1, 5, 9, 13);
+        chacha_qr(x, 2, 6, 10, 14);
+        chacha_qr(x, 3, 7, 11, 15);
+        chacha_qr(x, 0, 5, 10, 15);
+        chacha_qr(x, 1, 6, 11, 12);
+        chacha_qr(x, 2, 7, 8, 13);
+        chacha_qr(x, 3, 4, 9, 14);
+    }
+    for (int k = 0; k < 8; k++)
+        out[k] = (uint64_t)(x[2 * k] + in[2 * k]) | ((uint64_t)(x[2 * k + 1] + in[2 * k + 1]) << 32);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -517,6 +578,7 @@ static int block_words(uint64_t engine)
     case OR_PHILOX4X32: return 2;
     case OR_PHILOX4X64: return 4;
     case OR_RANLUX: return 9;
+    case OR_CHACHA20: return 8;
     default: return 1;
     }
 }
@@ -537,6 +599,9 @@ static void make_block(or_stream *s)
     }
     case OR_PHILOX4X64:
         or_philox4x64_block(&s->st[0], &s->st[4], s->blk);
+        break;
+    case OR_CHACHA20:
+        or_chacha20_block(s->st, s->blk);
         break;
     case OR_RANLUX:
         rl_mulmod(s->blk, s->st, rl_step_multiplier());
@@ -563,6 +628,9 @@ static void advance_block_state(or_stream *s)
         break;
     case OR_RANLUX:
         memcpy(s->st, s->blk, RL_N * 8);
+        break;
+    case OR_CHACHA20: /* 32-bit block counter in the high half of st[5] */
+        s->st[5] = (s->st[5] & 0xffffffffu) | ((uint64_t)(uint32_t)((s->st[5] >> 32) + 1u) << 32);
         break;
     }
     s->blk_ok = 0;
@@ -663,6 +731,7 @@ static int seeded_words(uint64_t engine)
     case OR_SQUARES: return 2;
     case OR_XORO128PP: return 2;
     case OR_XS128P: return 2;
+    case OR_CHACHA20: return 6;
     case OR_PCG64: return 4;
     case OR_PHILOX4X32: return 3;
     case OR_PHILOX4X64: return 6;
@@ -716,6 +785,7 @@ int or_seed(or_stream *s, uint64_t engine, uint64_t seed, const uint32_t *key, s
         break;
     case OR_PHILOX4X32:
     case OR_PHILOX4X64:
+    case OR_CHACHA20:
         memcpy(s->st, w, (size_t)nw * 8);
         break;
     case OR_SFC64:
@@ -779,6 +849,16 @@ int or_squares_set_key(or_stream *s, uint64_t key)
 {
     if (s->engine != OR_SQUARES) return -1;
     s->st[1] = key | 1u;
+    return 0;
+}
+
+/* chacha20 stream setter (Table 3): the 96-bit nonce; key and counter kept. */
+int or_chacha20_set_nonce(or_stream *s, uint64_t lo, uint64_t hi)
+{
+    if (s->engine != OR_CHACHA20) return -1;
+    s->st[4] = lo;
+    s->st[5] = (s->st[5] & 0xffffffff00000000ull) | (uint32_t)hi;
+    s->blk_ok = 0;
     return 0;
 }
 

@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(_HERE, "librp.so")
 
 # status codes, engines, distributions, dtypes (include/rp.h)
 RP_OK, RP_EINVAL, RP_ENOMEM, RP_EUNSUPPORTED, RP_EDEVICE, RP_ENOTSPD, RP_ENULL = 0, -1, -2, -3, -4, -5, -6
-RP_X256PP, RP_PCG64, RP_PHILOX4X32, RP_PHILOX, RP_SFC64, RP_RANLUX, RP_X256SS, RP_SQUARES, RP_XORO128, RP_XS128 = range(10)
+(RP_X256PP, RP_PCG64, RP_PHILOX4X32, RP_PHILOX, RP_SFC64, RP_RANLUX, RP_X256SS, RP_SQUARES, RP_XORO128, RP_XS128,
+ RP_CHACHA20) = range(11)
 RP_SUB_KEY, RP_SUB_INC, RP_SUB_SPAWN, RP_SUB_JUMP = range(4)
 RP_RAW, RP_U01, RP_BOUNDED, RP_NORM, RP_EXP = range(5)
 RP_U64, RP_U32, RP_F64, RP_F32 = range(4)
@@ -28,8 +29,9 @@ RP_FLAG_52BIT = 1
  RP_LAW_WEIBULL, RP_LAW_GAMMA, RP_LAW_BETA, RP_LAW_CHI2, RP_LAW_T, RP_LAW_F, RP_LAW_SKEWNORMAL) = range(1, 15)
 
 ENGINES = {"x256++": RP_X256PP, "x256**": RP_X256SS, "pcg64": RP_PCG64, "philox4x32": RP_PHILOX4X32, "philox": RP_PHILOX,
-           "sfc64": RP_SFC64, "ranlux++": RP_RANLUX, "squares": RP_SQUARES, "xoro++": RP_XORO128, "x128+": RP_XS128}
-STATE_WORDS = {RP_X256PP: 4, RP_PCG64: 4, RP_PHILOX4X32: 3, RP_PHILOX: 6, RP_SFC64: 4, RP_RANLUX: 9, RP_X256SS: 4, RP_SQUARES: 2, RP_XORO128: 2, RP_XS128: 2}
+           "sfc64": RP_SFC64, "ranlux++": RP_RANLUX, "squares": RP_SQUARES, "xoro++": RP_XORO128, "x128+": RP_XS128,
+           "chacha20": RP_CHACHA20}
+STATE_WORDS = {RP_X256PP: 4, RP_PCG64: 4, RP_PHILOX4X32: 3, RP_PHILOX: 6, RP_SFC64: 4, RP_RANLUX: 9, RP_X256SS: 4, RP_SQUARES: 2, RP_XORO128: 2, RP_XS128: 2, RP_CHACHA20: 6}
 
 _vp, _sz, _u64, _u32, _int = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
 _SIGS = {
@@ -50,6 +52,7 @@ _SIGS = {
     "rp_philox_set_key": ([_vp, _u64, _u64], _int),
     "rp_sfc64_set_abc": ([_vp, _u64, _u64, _u64], _int),
     "rp_squares_set_key": ([_vp, _u64], _int),
+    "rp_chacha20_set_nonce": ([_vp, _u64, _u64], _int),
     "rp_serialize": ([_vp, _vp, _sz, _vp], _int),
     "rp_deserialize": ([_vp, _vp, _sz], _int),
     "rp_raw_host": ([_vp, _vp, _sz], _int),
@@ -340,6 +343,10 @@ class Rng:
 
     def squares_set_key(self, key):
         _check(lib().rp_squares_set_key(self.h, key), self.h)
+        return self
+
+    def chacha20_set_nonce(self, nonce):
+        _check(lib().rp_chacha20_set_nonce(self.h, nonce & (2**64 - 1), nonce >> 64), self.h)
         return self
 
     def duplicate(self):

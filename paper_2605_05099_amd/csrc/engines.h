@@ -149,6 +149,43 @@ static constexpr uint64_t kPh64W0 = 0x9E3779B97F4A7C15ull, kPh64W1 = 0xBB67AE858
 
 // Block for 128-bit counter (c_lo, c_hi) and key (k0 | k1 << 32); returns the
 // two 64-bit words (earlier 32-bit output in the low half).
+// ChaCha20 (Table 2 "chacha20"): the block of counter ctr under the 256-bit
+// key (eight 32-bit words) and the 96-bit nonce (n0, n1, n2): twenty rounds
+// (ten column-and-diagonal double rounds) of the quarter round on the input
+// words (constants "expand 32-byte k", key, counter, nonce), the input added
+// back; word k of the output is x[2k] | x[2k+1] << 32.
+RP_HD uint32_t rotl32(uint32_t x, int k) { return (x << k) | (x >> (32 - k)); }
+#define RP_CHACHA_QR(a, b, c, d)                                                   \
+    do {                                                                           \
+        x[a] += x[b]; x[d] ^= x[a]; x[d] = rotl32(x[d], 16);                       \
+        x[c] += x[d]; x[b] ^= x[c]; x[b] = rotl32(x[b], 12);                       \
+        x[a] += x[b]; x[d] ^= x[a]; x[d] = rotl32(x[d], 8);                        \
+        x[c] += x[d]; x[b] ^= x[c]; x[b] = rotl32(x[b], 7);                        \
+    } while (0)
+RP_HD void chacha20_block(const uint32_t key[8], uint32_t n0, uint32_t n1, uint32_t n2, uint32_t ctr,
+                          uint64_t out[8])
+{
+    uint32_t in[16] = {0x61707865u, 0x3320646eu, 0x79622d32u, 0x6b206574u, key[0], key[1], key[2], key[3],
+                       key[4],      key[5],      key[6],      key[7],      ctr,    n0,     n1,     n2};
+    uint32_t x[16];
+#pragma unroll
+    for (int i = 0; i < 16; i++) x[i] = in[i];
+#pragma unroll 1
+    for (int r = 0; r < 10; r++) {
+        RP_CHACHA_QR(0, 4, 8, 12);
+        RP_CHACHA_QR(1, 5, 9, 13);
+        RP_CHACHA_QR(2, 6, 10, 14);
+        RP_CHACHA_QR(3, 7, 11, 15);
+        RP_CHACHA_QR(0, 5, 10, 15);
+        RP_CHACHA_QR(1, 6, 11, 12);
+        RP_CHACHA_QR(2, 7, 8, 13);
+        RP_CHACHA_QR(3, 4, 9, 14);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; k++) out[k] = (uint64_t)(x[2 * k] + in[2 * k]) | ((uint64_t)(x[2 * k + 1] + in[2 * k + 1]) << 32);
+}
+#undef RP_CHACHA_QR
+
 // squares64 (Widynski; Table 2 "squares"): the word of counter c under key k.
 // Five rounds on x = c k: square, add y = c k or z = y + k alternately and
 // swap the 32-bit halves; the fourth round's square-plus-z t is kept, and

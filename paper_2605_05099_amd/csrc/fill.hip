@@ -215,6 +215,7 @@ __device__ __forceinline__ uint64_t uni64(uint64_t v)
 }
 
 struct WavePhilox32 {
+    static constexpr bool kDirect = true;  // raw / uniform fills in store order
     static constexpr int R = kWaveR;  // 4 blocks of 2 words per lane
     uint64_t key, b0lo, b0hi;         // uniform: key, counter of the first block
     uint64_t clo, chi;                // this lane's first block in the chunk
@@ -306,6 +307,7 @@ struct WavePhilox32 {
 };
 
 struct WavePhilox64 {
+    static constexpr bool kDirect = true;  // raw / uniform fills in store order
     static constexpr int R = kWaveR;  // 2 blocks of 4 words per lane
     uint64_t b0[4], k0, k1;          // uniform
     uint64_t c[4];                   // this lane's first block in the chunk
@@ -392,6 +394,7 @@ struct WavePhilox64 {
 // squares64: word p of the substream is squares64(c0 + p, key); any
 // position is one evaluation away.  No block phase (one word per counter).
 struct WaveSquares {
+    static constexpr bool kDirect = true;  // raw / uniform fills in store order
     static constexpr int R = kWaveR;
     static constexpr int G = 1;
     uint64_t c0, key;  // uniform
@@ -436,10 +439,63 @@ struct WaveSquares {
     __device__ void store(const FillArgs &a, uint64_t i, uint64_t pos) const { a.words[i] = c0 + pos; }
 };
 
+// ChaCha20: one 8-word block per lane per chunk (block counter c0 + 64 k +
+// lane in chunk k); the 32-bit counter wraps modulo 2^32.  Raw fills use the
+// LDS transpose: lane-private 64-byte stores of whole blocks measured slow.
+struct WaveChacha {
+    static constexpr bool kDirect = false;
+    static constexpr int R = kWaveR;  // one block
+    static constexpr int G = 8;
+    uint32_t key[8], n0, n1, n2;  // uniform
+    uint32_t c0, c;               // counter at the call's first block; this lane's block
+    uint32_t phase0;
+    __device__ void load(const FillArgs &a, uint64_t i, int lane)
+    {
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const uint64_t w = uni64(a.words[(uint64_t)k * a.n + i]);
+            key[2 * k] = (uint32_t)w;
+            key[2 * k + 1] = (uint32_t)(w >> 32);
+        }
+        const uint64_t w4 = uni64(a.words[4 * a.n + i]), w5 = uni64(a.words[5 * a.n + i]);
+        n0 = (uint32_t)w4;
+        n1 = (uint32_t)(w4 >> 32);
+        n2 = (uint32_t)w5;
+        c0 = (uint32_t)(w5 >> 32);
+        phase0 = __builtin_amdgcn_readfirstlane(a.phase[i]);
+        c = c0 + (uint32_t)lane;
+    }
+    __device__ void gen(uint64_t w[R]) const { chacha20_block(key, n0, n1, n2, c, w); }
+    __device__ void next_chunk() { c += 64; }
+    // float draws: 4 words per lane, two lanes per block
+    bool upper = false;
+    __device__ void load_half(const FillArgs &a, uint64_t i, int lane)
+    {
+        load(a, i, lane);
+        c = c0 + (uint32_t)(lane >> 1);
+        upper = lane & 1;
+    }
+    __device__ void gen_half(uint64_t w[R / 2])
+    {
+        uint64_t b[8];
+        chacha20_block(key, n0, n1, n2, c, b);
+#pragma unroll
+        for (int k = 0; k < 4; k++) w[k] = upper ? b[4 + k] : b[k];
+        c += 32;
+    }
+    __device__ void store(const FillArgs &a, uint64_t i, uint64_t pos) const
+    {
+        const uint32_t blk = c0 + (uint32_t)(pos / 8);
+        a.words[5 * a.n + i] = (uint64_t)n2 | ((uint64_t)blk << 32);
+        a.phase[i] = (uint32_t)(pos & 7);
+    }
+};
+
 // PCG64: lane l starts each chunk at word R l (state A^(R l) s + G_(R l) inc),
 // takes R - 1 ordinary steps inside the chunk, and moves to the next chunk
 // with the stride-64R map from the constant table.
 struct WavePcg {
+    static constexpr bool kDirect = true;  // raw / uniform fills in store order
     static constexpr int R = kWaveR;
     u128 s;        // this lane's state at its first word of the chunk
     u128 inc, s0;  // uniform
@@ -747,6 +803,9 @@ __global__ __launch_bounds__(256, (DIST == RP_NORM || (DIST == RP_EXP && OT == R
     // float ziggurat: the chunk holds 64 R 32-bit items (32 R words), and
     // every position below counts items; the state store converts back
     constexpr bool ZH = ZIG && IPW == 2;
+    // raw / uniform fills in store order (engines with small blocks); the
+    // others go through the LDS transpose like the ziggurat
+    constexpr bool DIRECT = FIXED && E::kDirect;
 
     const int wib = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
@@ -784,7 +843,7 @@ __global__ __launch_bounds__(256, (DIST == RP_NORM || (DIST == RP_EXP && OT == R
     T *const out = (T *)a.out + sub * P;
 
     E eng;
-    if constexpr (FIXED) eng.load_direct(a, sub, lane);
+    if constexpr (DIRECT) eng.load_direct(a, sub, lane);
     else if constexpr (ZH) eng.load_half(a, sub, lane);
     else eng.load(a, sub, lane);
     int e = (int)eng.phase0 * IPW;  // items of this chunk already used
@@ -800,7 +859,7 @@ __global__ __launch_bounds__(256, (DIST == RP_NORM || (DIST == RP_EXP && OT == R
     for (uint64_t chunk = 0; chunk < max_chunks; chunk++) {
         const uint64_t base_pos = chunk * CHW;
         uint64_t w[R];
-        if constexpr (FIXED) {
+        if constexpr (DIRECT) {
             // direct order: w[j] is the word at chunk position
             // 64 G (j / G) + G lane + j % G
             eng.gen_direct(w);
@@ -838,7 +897,7 @@ __global__ __launch_bounds__(256, (DIST == RP_NORM || (DIST == RP_EXP && OT == R
         }
 
         if constexpr (FIXED) {
-            constexpr int G = E::G;
+            constexpr int G = DIRECT ? E::G : 1;  // after the transpose: position 64 j + lane
             const uint64_t need = P - produced;
             const uint64_t got = (uint64_t)(IPW * CHW - e);
             T *dst = out + produced - e;  // item q of the chunk goes to dst[q]
@@ -1197,6 +1256,53 @@ struct Lane2 {
 };
 using LaneXoro128 = Lane2<Xoro128>;
 using LaneXs128 = Lane2<Xs128>;
+
+// ChaCha20 on one lane: the current block buffered, words handed out in order
+struct LaneChacha {
+    uint32_t key[8], n0, n1, n2, ctr;
+    uint64_t blk[8];
+    int used;  // words of blk already returned (0..8)
+    __device__ void start(int phase)
+    {
+        chacha20_block(key, n0, n1, n2, ctr, blk);
+        used = phase;
+    }
+    __device__ void load(const FillArgs &a, uint64_t i)
+    {
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const uint64_t w = a.words[(uint64_t)k * a.n + i];
+            key[2 * k] = (uint32_t)w;
+            key[2 * k + 1] = (uint32_t)(w >> 32);
+        }
+        const uint64_t w4 = a.words[4 * a.n + i], w5 = a.words[5 * a.n + i];
+        n0 = (uint32_t)w4;
+        n1 = (uint32_t)(w4 >> 32);
+        n2 = (uint32_t)w5;
+        ctr = (uint32_t)(w5 >> 32);
+        start((int)a.phase[i]);
+    }
+    __device__ uint64_t next()
+    {
+        if (used == 8) {
+            ctr++;
+            chacha20_block(key, n0, n1, n2, ctr, blk);
+            used = 0;
+        }
+        uint64_t w = blk[0];
+#pragma unroll
+        for (int k = 1; k < 8; k++) w = (used == k) ? blk[k] : w;
+        used++;
+        return w;
+    }
+    __device__ void reserve(int) {}
+    __device__ void store(const FillArgs &a, uint64_t i) const
+    {
+        const bool done = used == 8;
+        a.words[5 * a.n + i] = (uint64_t)n2 | ((uint64_t)(done ? ctr + 1u : ctr) << 32);
+        a.phase[i] = done ? 0u : (uint32_t)used;
+    }
+};
 
 struct LaneSquares {
     uint64_t c, key;
@@ -1607,6 +1713,7 @@ int launch_fill(int engine, int dist, int dtype, const FillArgs &a, hipStream_t 
     case RP_X256PP: return dispatch_dist<false, LaneX256>(dist, dtype, a, st);
     case RP_X256SS: return dispatch_dist<false, LaneX256SS>(dist, dtype, a, st);
     case RP_SQUARES: return dispatch_dist<true, WaveSquares>(dist, dtype, a, st);
+    case RP_CHACHA20: return dispatch_dist<true, WaveChacha>(dist, dtype, a, st);
     case RP_XORO128: return dispatch_dist<false, LaneXoro128>(dist, dtype, a, st);
     case RP_XS128: return dispatch_dist<false, LaneXs128>(dist, dtype, a, st);
     case RP_SFC64: return dispatch_dist<false, LaneSfc64>(dist, dtype, a, st);
@@ -1641,6 +1748,7 @@ int launch_fill_law(int engine, int law, const FillArgs &a, hipStream_t st)
     case RP_X256PP: return dispatch_law<false, LaneX256>(law, a, st);
     case RP_X256SS: return dispatch_law<false, LaneX256SS>(law, a, st);
     case RP_SQUARES: return dispatch_law<true, WaveSquares>(law, a, st);
+    case RP_CHACHA20: return dispatch_law<true, WaveChacha>(law, a, st);
     case RP_XORO128: return dispatch_law<false, LaneXoro128>(law, a, st);
     case RP_XS128: return dispatch_law<false, LaneXs128>(law, a, st);
     case RP_SFC64: return dispatch_law<false, LaneSfc64>(law, a, st);

@@ -89,6 +89,7 @@ static const EngineInfo kEngines[RP_NENGINES] = {
     {"squares", "squares64 (Widynski, 2021), 2 state words, period 2^64 per key", 2, 1},
     {"xoro++", "xoroshiro128++ (Blackman and Vigna, 2019), 2 state words, period 2^128-1", 2, 1},
     {"x128+", "xorshift128+ (Vigna, 2014), 2 state words, period 2^128-1", 2, 1},
+    {"chacha20", "ChaCha20 (Bernstein, 2008), 6 state words, period 2^35 per nonce", 6, 8},
 };
 
 namespace rp {
@@ -569,6 +570,21 @@ static uint64_t host_next(rp_rng *r)
         }
         return w;
     }
+    case RP_CHACHA20: {
+        uint32_t key[8];
+        for (int k = 0; k < 4; k++) {
+            key[2 * k] = (uint32_t)st[k];
+            key[2 * k + 1] = (uint32_t)(st[k] >> 32);
+        }
+        uint64_t o[8];
+        chacha20_block(key, (uint32_t)st[4], (uint32_t)(st[4] >> 32), (uint32_t)st[5], (uint32_t)(st[5] >> 32), o);
+        uint64_t w = o[r->phase];
+        if (++r->phase == 8) {
+            r->phase = 0;
+            st[5] = (st[5] & 0xffffffffull) | ((uint64_t)(uint32_t)((st[5] >> 32) + 1u) << 32);
+        }
+        return w;
+    }
     case RP_PHILOX: {
         uint64_t o[4];
         philox4x64(st, st[4], st[5], o);
@@ -640,6 +656,7 @@ static void seed_state(rp_rng *r, uint64_t seed, const uint32_t *key, size_t n_k
         break;
     case RP_PHILOX4X32:
     case RP_PHILOX:
+    case RP_CHACHA20:
         memcpy(r->st, w, (size_t)nw * 8);
         break;
     case RP_SFC64:
@@ -735,6 +752,9 @@ static int advance_impl(rp_rng *rng, uint64_t lo, uint64_t hi)
     case RP_SQUARES:  // period 2^64: hi 2^64 steps are a full period
         st[0] += lo;
         return RP_OK;
+    case RP_CHACHA20:  // blocks: the 32-bit counter, modulo 2^32
+        st[5] = (st[5] & 0xffffffffull) | ((uint64_t)(uint32_t)((st[5] >> 32) + (uint32_t)lo) << 32);
+        return RP_OK;
     case RP_XORO128:
     case RP_XS128:
         x128_apply(rng->engine, st, poly_xpow_d<128>(lo, hi, x128_charpoly(rng->engine)));
@@ -788,6 +808,8 @@ extern "C" int rp_jump(rp_rng *rng, int k)
     if (!rng) return fail(RP_ENULL, "rp_jump: NULL rng");
     if (k != 32 && k != 64 && k != 96 && k != 128 && k != 192)
         return fail_rng(rng, RP_EINVAL, "rp_jump: k must be 32, 64, 96, 128 or 192 (got %d)", k);
+    if (rng->engine == RP_CHACHA20)  // 2^32 blocks per nonce: every 2^k, k >= 32, is a full period
+        return fail_rng(rng, RP_EINVAL, "rp_jump: 2^%d is not below the period of 'chacha20' (use the nonce)", k);
     if (rng->engine == RP_SQUARES && k >= 64)
         return fail_rng(rng, RP_EINVAL, "rp_jump: 2^%d is not below the period of 'squares'", k);
     if ((rng->engine == RP_XORO128 || rng->engine == RP_XS128) && k >= 128)
@@ -861,6 +883,17 @@ extern "C" int rp_sfc64_set_abc(rp_rng *rng, uint64_t a, uint64_t b, uint64_t c)
     return RP_OK;
 }
 
+extern "C" int rp_chacha20_set_nonce(rp_rng *rng, uint64_t lo, uint64_t hi)
+{
+    if (!rng) return fail(RP_ENULL, "rp_chacha20_set_nonce: NULL rng");
+    if (rng->engine != RP_CHACHA20)
+        return fail_rng(rng, RP_EUNSUPPORTED, "chacha20_set_nonce: engine is not chacha20");
+    if (hi >> 32) return fail_rng(rng, RP_EINVAL, "chacha20_set_nonce: the nonce has 96 bits");
+    rng->st[4] = lo;
+    rng->st[5] = (rng->st[5] & 0xffffffff00000000ull) | hi;
+    return RP_OK;
+}
+
 extern "C" int rp_squares_set_key(rp_rng *rng, uint64_t key)
 {
     if (!rng) return fail(RP_ENULL, "rp_squares_set_key: NULL rng");
@@ -930,8 +963,8 @@ extern "C" int rp_streams_create(const rp_rng *base, int kind, uint64_t n, int j
     const int nw = kEngines[e].words;
     switch (kind) {
     case RP_SUB_KEY:
-        if (e != RP_PHILOX4X32 && e != RP_PHILOX)
-            return fail(RP_EUNSUPPORTED, "RP_SUB_KEY needs a philox engine");
+        if (e != RP_PHILOX4X32 && e != RP_PHILOX && e != RP_CHACHA20)
+            return fail(RP_EUNSUPPORTED, "RP_SUB_KEY needs a philox or chacha20 engine");
         break;
     case RP_SUB_INC:
         if (e != RP_PCG64) return fail(RP_EUNSUPPORTED, "RP_SUB_INC needs pcg64");
@@ -983,7 +1016,10 @@ extern "C" int rp_streams_create(const rp_rng *base, int kind, uint64_t n, int j
         case RP_SUB_KEY:
             cur = *base;
             if (e == RP_PHILOX4X32) cur.st[2] = i;
-            else {
+            else if (e == RP_CHACHA20) {  // nonce := i, key and counter from the base
+                cur.st[4] = i;
+                cur.st[5] &= 0xffffffff00000000ull;
+            } else {
                 cur.st[4] = i;
                 cur.st[5] = 0;
             }
@@ -1445,7 +1481,8 @@ int serial_family(int engine)
 {
     switch (engine) {
     case RP_PHILOX4X32:
-    case RP_PHILOX: return RP_SUB_KEY;
+    case RP_PHILOX:
+    case RP_CHACHA20: return RP_SUB_KEY;
     case RP_PCG64: return RP_SUB_INC;
     case RP_SFC64: return RP_SUB_SPAWN;
     default: return RP_SUB_JUMP;

@@ -235,6 +235,7 @@ int launch_batched_gen(int engine, const BatchArgs &a, bool beta, unsigned grid,
     case RP_SQUARES: launch_batched_e<LaneSquares>(a, beta, grid, block, st); break;
     case RP_XORO128: launch_batched_e<LaneXoro128>(a, beta, grid, block, st); break;
     case RP_XS128: launch_batched_e<LaneXs128>(a, beta, grid, block, st); break;
+    case RP_CHACHA20: launch_batched_e<LaneChacha>(a, beta, grid, block, st); break;
     case RP_PCG64: launch_batched_e<LanePcg>(a, beta, grid, block, st); break;
     case RP_PHILOX4X32: launch_batched_e<LanePhilox32>(a, beta, grid, block, st); break;
     case RP_PHILOX: launch_batched_e<LanePhilox64>(a, beta, grid, block, st); break;

@@ -140,6 +140,7 @@ int launch_discrete(int engine, bool perm, const FillArgs &f, uint32_t *tab, int
     case RP_SQUARES: launch_discrete_e<LaneSquares>(perm, f, tab, tbits, st); break;
     case RP_XORO128: launch_discrete_e<LaneXoro128>(perm, f, tab, tbits, st); break;
     case RP_XS128: launch_discrete_e<LaneXs128>(perm, f, tab, tbits, st); break;
+    case RP_CHACHA20: launch_discrete_e<LaneChacha>(perm, f, tab, tbits, st); break;
     default: return fail(RP_EINVAL, "unknown engine");
     }
     const hipError_t e = hipGetLastError();

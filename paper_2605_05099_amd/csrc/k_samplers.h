@@ -592,6 +592,7 @@ int launch_fill_mix(int engine, int law, const FillArgs &f, hipStream_t st)
     case RP_SQUARES: rc = launch_mix_e<LaneSquares>(law, f, st); break;
     case RP_XORO128: rc = launch_mix_e<LaneXoro128>(law, f, st); break;
     case RP_XS128: rc = launch_mix_e<LaneXs128>(law, f, st); break;
+    case RP_CHACHA20: rc = launch_mix_e<LaneChacha>(law, f, st); break;
     case RP_PCG64: rc = launch_mix_e<LanePcg>(law, f, st); break;
     case RP_PHILOX4X32: rc = launch_mix_e<LanePhilox32>(law, f, st); break;
     case RP_PHILOX: rc = launch_mix_e<LanePhilox64>(law, f, st); break;
@@ -632,6 +633,7 @@ int launch_moments(int engine, const SampArgs &s, hipStream_t st)
     case RP_SQUARES: launch_moments_e<LaneSquares>(s, st); break;
     case RP_XORO128: launch_moments_e<LaneXoro128>(s, st); break;
     case RP_XS128: launch_moments_e<LaneXs128>(s, st); break;
+    case RP_CHACHA20: launch_moments_e<LaneChacha>(s, st); break;
     case RP_PCG64: launch_moments_e<LanePcg>(s, st); break;
     case RP_PHILOX4X32: launch_moments_e<LanePhilox32>(s, st); break;
     case RP_PHILOX: launch_moments_e<LanePhilox64>(s, st); break;
@@ -652,6 +654,7 @@ int launch_norm_rows(int engine, const SampArgs &s, hipStream_t st)
     case RP_SQUARES: hipLaunchKernelGGL(k_norm_rows<LaneSquares>, grid, block, 0, st, s); break;
     case RP_XORO128: hipLaunchKernelGGL(k_norm_rows<LaneXoro128>, grid, block, 0, st, s); break;
     case RP_XS128: hipLaunchKernelGGL(k_norm_rows<LaneXs128>, grid, block, 0, st, s); break;
+    case RP_CHACHA20: hipLaunchKernelGGL(k_norm_rows<LaneChacha>, grid, block, 0, st, s); break;
     case RP_PCG64: hipLaunchKernelGGL(k_norm_rows<LanePcg>, grid, block, 0, st, s); break;
     case RP_PHILOX4X32: hipLaunchKernelGGL(k_norm_rows<LanePhilox32>, grid, block, 0, st, s); break;
     case RP_PHILOX: hipLaunchKernelGGL(k_norm_rows<LanePhilox64>, grid, block, 0, st, s); break;
@@ -671,6 +674,7 @@ int launch_gamma_elem(int engine, const SampArgs &s, bool beta, hipStream_t st)
     case RP_SQUARES: launch_elem_e<LaneSquares>(s, beta, st); break;
     case RP_XORO128: launch_elem_e<LaneXoro128>(s, beta, st); break;
     case RP_XS128: launch_elem_e<LaneXs128>(s, beta, st); break;
+    case RP_CHACHA20: launch_elem_e<LaneChacha>(s, beta, st); break;
     case RP_PCG64: launch_elem_e<LanePcg>(s, beta, st); break;
     case RP_PHILOX4X32: launch_elem_e<LanePhilox32>(s, beta, st); break;
     case RP_PHILOX: launch_elem_e<LanePhilox64>(s, beta, st); break;

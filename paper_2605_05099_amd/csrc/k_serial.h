@@ -119,6 +119,24 @@ struct SerLane<RP_PHILOX> : LanePhilox64 {
     }
 };
 
+// ChaCha20: block counter plus id C / 8 (mod 2^32); the phase is unchanged.
+template <>
+struct SerLane<RP_CHACHA20> : LaneChacha {
+    __device__ void init(const SerialArgs &a, uint64_t id)
+    {
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            key[2 * k] = (uint32_t)a.base[k];
+            key[2 * k + 1] = (uint32_t)(a.base[k] >> 32);
+        }
+        n0 = (uint32_t)a.base[4];
+        n1 = (uint32_t)(a.base[4] >> 32);
+        n2 = (uint32_t)a.base[5];
+        ctr = (uint32_t)(a.base[5] >> 32) + (uint32_t)(id * (a.C / 8));
+        start((int)a.phase);
+    }
+};
+
 // squares64: counter plus id C.
 template <>
 struct SerLane<RP_SQUARES> : LaneSquares {
@@ -536,6 +554,7 @@ int launch_serial_fixed(int engine, int dist, int dtype, const SerialArgs &a, hi
     case RP_X256PP: rc = ser_fixed_eng<RP_X256PP>(dist, dtype, a, st); break;
     case RP_X256SS: rc = ser_fixed_eng<RP_X256SS>(dist, dtype, a, st); break;
     case RP_SQUARES: rc = ser_fixed_eng<RP_SQUARES>(dist, dtype, a, st); break;
+    case RP_CHACHA20: rc = ser_fixed_eng<RP_CHACHA20>(dist, dtype, a, st); break;
     case RP_PCG64: rc = ser_fixed_eng<RP_PCG64>(dist, dtype, a, st); break;
     case RP_PHILOX4X32: rc = ser_fixed_eng<RP_PHILOX4X32>(dist, dtype, a, st); break;
     case RP_PHILOX: rc = ser_fixed_eng<RP_PHILOX>(dist, dtype, a, st); break;
@@ -563,6 +582,7 @@ int launch_serial_stitch(int engine, int dist, int dtype, const SerialArgs &a, h
     case RP_X256PP: hipLaunchKernelGGL((k_ser_gen<RP_X256PP, RP_RAW, RP_U64, false>), grid, block, 0, st, a); break;
     case RP_X256SS: hipLaunchKernelGGL((k_ser_gen<RP_X256SS, RP_RAW, RP_U64, false>), grid, block, 0, st, a); break;
     case RP_SQUARES: hipLaunchKernelGGL((k_ser_gen<RP_SQUARES, RP_RAW, RP_U64, false>), grid, block, 0, st, a); break;
+    case RP_CHACHA20: hipLaunchKernelGGL((k_ser_gen<RP_CHACHA20, RP_RAW, RP_U64, false>), grid, block, 0, st, a); break;
     case RP_PCG64: hipLaunchKernelGGL((k_ser_gen<RP_PCG64, RP_RAW, RP_U64, false>), grid, block, 0, st, a); break;
     case RP_PHILOX4X32:
         hipLaunchKernelGGL((k_ser_gen<RP_PHILOX4X32, RP_RAW, RP_U64, false>), grid, block, 0, st, a);

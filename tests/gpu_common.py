@@ -16,6 +16,7 @@ FAMILY = {
     "squares": (rp.RP_SUB_SPAWN, "spawn"),
     "xoro++": (rp.RP_SUB_JUMP, "jump"),
     "x128+": (rp.RP_SUB_JUMP, "jump"),
+    "chacha20": (rp.RP_SUB_KEY, "nonce"),
 }
 ENGINES = list(FAMILY)
 

@@ -5,6 +5,7 @@ NumPy's bit generators (the paper validates pcg64 against NumPy), rocRAND's
 host-side Philox4x32-10, number theory (primitivity and periods, Table 2),
 brute-force stepping, and Python big-integer arithmetic.
 """
+import ctypes
 import os
 import shutil
 import subprocess
@@ -430,3 +431,50 @@ def test_x128_jump_equals_stepping_and_outputs_uniform(eng):
     assert stats.kstest(u, "uniform").pvalue > 1e-4
     bits = np.unpackbits(x.view(np.uint8)).reshape(-1, 64).mean(axis=0)
     assert np.abs(bits - 0.5).max() < 5 * 0.5 / np.sqrt(len(x))
+
+
+# ---- ChaCha20 (Table 2 "chacha20"; Table 3: key 4 + nonce 1.5 + counter 0.5) --
+# Pinned against the examples of RFC 8439 (the reference the paper validates
+# ChaCha20 against): the quarter-round example of its section 2.1.1 and the
+# block-function example of its section 2.3.2 (key 00 01 .. 1f, nonce
+# 00 00 00 09 00 00 00 4a 00 00 00 00, block counter 1).
+
+def test_chacha_quarter_round_rfc8439():
+    q = np.array([0x11111111, 0x01020304, 0x9B8D6F43, 0x01234567], dtype=np.uint32)
+    oracle.lib().or_chacha_qr(q.ctypes.data_as(ctypes.c_void_p))
+    assert [int(v) for v in q] == [0xEA2A92F4, 0xCB1CF8CE, 0x4581472E, 0x5881C4BB]
+
+
+def _rfc_block_state(counter):
+    key = bytes(range(32))
+    kw = [int.from_bytes(key[4 * i:4 * i + 4], "little") for i in range(8)]
+    nonce = bytes([0, 0, 0, 9, 0, 0, 0, 0x4A, 0, 0, 0, 0])
+    nw = [int.from_bytes(nonce[4 * i:4 * i + 4], "little") for i in range(3)]
+    st = [kw[2 * i] | (kw[2 * i + 1] << 32) for i in range(4)]
+    st += [nw[0] | (nw[1] << 32), nw[2] | (counter << 32)]
+    return st
+
+
+def test_chacha_block_rfc8439():
+    expect = [0xE4E7F110, 0x15593BD1, 0x1FDD0F50, 0xC47120A3, 0xC7F4D1C7, 0x0368C033, 0x9AAA2204, 0x4E6CD4C3,
+              0x466482D2, 0x09AA9F07, 0x05D7C214, 0xA2028BD9, 0xD19C12B5, 0xB94E16DE, 0xE883D0CB, 0x4E3C50A2]
+    s = Stream.from_state("chacha20", _rfc_block_state(1), 0)
+    words = s.raw(8)
+    got = []
+    for w in words:
+        got += [int(w) & 0xFFFFFFFF, int(w) >> 32]
+    assert got == expect
+    # the block counter moved to 2, the phase back to 0
+    assert s.state[5] >> 32 == 2 and s.phase == 0
+
+
+def test_chacha_counter_nonce_and_advance():
+    a = Stream.seeded("chacha20", 5).advance(7)
+    b = Stream.seeded("chacha20", 5)
+    b.raw(56)
+    assert a.raw(10).tolist() == b.raw(10).tolist()
+    c = Stream.seeded("chacha20", 5)
+    st = c.state[:6]
+    c.chacha20_set_nonce((3 << 64) | 11)
+    assert c.state[:4] == st[:4] and c.state[4] == 11
+    assert c.state[5] == (st[5] & ~0xFFFFFFFF) | 3
