@@ -205,7 +205,13 @@ int rp_fill(rp_streams *s, int dist, int dtype, uint64_t bound, int flags, void 
  * These run one lane per substream.  Parameters must be finite; others give
  * RP_EINVAL.  d_out must be 8-byte aligned device memory of n * per_stream
  * doubles owned by the caller.  Asynchronous on hip_stream; per_stream = 0
- * does nothing. */
+ * does nothing.
+ * rp_fill_lawf is the binary32 form of laws 1-8 (the paper's float
+ * versions): the base draw is the binary32 one rp_fill(..., RP_F32) returns
+ * (24-bit uniform of a 32-bit item, or the float ziggurat's value), the
+ * transform is evaluated in binary64 on that value and rounded once to
+ * binary32; d_out holds n * per_stream floats (4-byte aligned).  Laws 9-14
+ * give RP_EUNSUPPORTED. */
 enum {
     RP_LAW_UNIF = 1,
     RP_LAW_NORMAL = 2,
@@ -224,6 +230,8 @@ enum {
 };
 int rp_fill_law(rp_streams *s, int law, const double *p, int np, double *d_out, uint64_t per_stream,
                 void *hip_stream);
+int rp_fill_lawf(rp_streams *s, int law, const double *p, int np, float *d_out, uint64_t per_stream,
+                 void *hip_stream);
 
 /* ---- one stream split over many lanes (Section 4.4 jumps) -------------- */
 /* Fills d_out[0 .. n-1] with the next n values of the single stream `rng`,

@@ -115,3 +115,18 @@ def draw(stream, law, p, n):
         z = stream.norm(2 * n).reshape(n, 2)
         return mu + s * (d * np.abs(z[:, 0]) + c * z[:, 1])
     raise ValueError(f"unknown law {law}")
+
+
+# binary32 base draws of the float versions (32-bit items)
+BASE_F32 = {"u01": "u01f", "norm": "normf", "exp": "expf"}
+
+
+def draw_f32(stream, law, p, n):
+    """n binary32 draws of a transform law (the paper's float versions): the
+    binary32 base draw, the transform in binary64 on that value, one
+    rounding to binary32."""
+    if law not in BASE:
+        raise ValueError(f"law {law} has no binary32 form")
+    base = getattr(stream, BASE_F32[BASE[law]])(n).astype(np.float64)
+    with np.errstate(divide="ignore", over="ignore", invalid="ignore"):
+        return transform(law, base, [float(v) for v in p]).astype(np.float32)

@@ -65,6 +65,7 @@ _SIGS = {
     "rp_streams_duplicate": ([_vp, _vp], _int),
     "rp_fill": ([_vp, _int, _int, _u64, _int, _vp, _u64, _vp], _int),
     "rp_fill_law": ([_vp, _int, _vp, _int, _vp, _u64, _vp], _int),
+    "rp_fill_lawf": ([_vp, _int, _vp, _int, _vp, _u64, _vp], _int),
     "rp_fill_serial": ([_vp, _int, _int, _u64, _int, _vp, _u64, _vp], _int),
     "rp_norm_moments": ([_vp, _u64, _vp, _vp, _vp], _int),
     "rp_gamma_elem": ([_vp, _vp, _vp, _u64, _vp], _int),
@@ -168,6 +169,12 @@ def rp_streams_create(base, kind, n, jump_log2=0):
 
 def rp_fill(streams, dist, dtype, bound, flags, out, per_stream, stream=None):
     _check(lib().rp_fill(streams.h, dist, dtype, bound, flags, _dev_ptr(out), per_stream, _stream_ptr(stream)))
+
+
+def rp_fill_lawf(streams, law, params, out, per_stream, stream=None):
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(-1))
+    _check(lib().rp_fill_lawf(streams.h, law, _ptr(p) if len(p) else None, len(p), _dev_ptr(out), per_stream,
+                              _stream_ptr(stream)))
 
 
 def rp_permutations(streams, n, out, stream=None):

@@ -759,6 +759,15 @@ __device__ __forceinline__ uint64_t range_mask(int r, int lo, int hi)
     return top & ~((1ull << a) - 1);
 }
 
+// The base value a derived law transforms: the binary64 draw, or for the
+// binary32 laws (float draws) the binary32 value the float sampler returns
+template <bool HALF>
+__device__ __forceinline__ double zbase(double v)
+{
+    if constexpr (HALF) return (double)(float)v;
+    else return v;
+}
+
 // The derived laws of rp_fill_law: one transform of one base draw (U, Z or
 // E), in binary64, in the order the boundary documents, fused into the store
 // of the base fill.  XF = 0 is the base value itself.
@@ -913,6 +922,10 @@ __global__ __launch_bounds__(256, (DIST == RP_NORM || (DIST == RP_EXP && OT == R
                 } else {
                     item_value<DIST, OT>(w[j] & 0xffffffffull, a, v[2 * j]);
                     item_value<DIST, OT>(w[j] >> 32, a, v[2 * j + 1]);
+                    if constexpr (XF != 0) {
+                        v[2 * j] = (T)xform<XF>(v[2 * j], a);
+                        v[2 * j + 1] = (T)xform<XF>(v[2 * j + 1], a);
+                    }
                 }
             }
             // item i of this lane sits at chunk item q(i)
@@ -1132,7 +1145,7 @@ __global__ __launch_bounds__(256, (DIST == RP_NORM || (DIST == RP_EXP && OT == R
                 const uint64_t need = P - produced;
                 T *const dst = out + produced;
                 uint32_t total = first;
-                if (yq == -2) dst[0] = xform<XF>(yv, a);  // need >= 1 here
+                if (yq == -2) dst[0] = xform<XF>(zbase<ZH>(yv), a);  // need >= 1 here
                 if (first && need == 1) {
                     final_pos = base_pos + (uint64_t)e;
                     break;
@@ -1148,7 +1161,7 @@ __global__ __launch_bounds__(256, (DIST == RP_NORM || (DIST == RP_EXP && OT == R
                             // the value again from the word (cheaper than keeping R values live)
                             double v0;
                             zig_fast<DIST, ZH>(zt, wbuf[wpos(64 * r + lane)], v0);
-                            dst[total + mbcnt64(om)] = xform<XF>(v0, a);
+                            dst[total + mbcnt64(om)] = xform<XF>(zbase<ZH>(v0), a);
                         }
                         if (lane == 0) {
                             omem[r] = om;
@@ -1159,7 +1172,7 @@ __global__ __launch_bounds__(256, (DIST == RP_NORM || (DIST == RP_EXP && OT == R
                     wave_sync();
                     if (yq >= 0) {
                         const int r = yq >> 6, b = yq & 63;
-                        dst[pmem[r] + (uint32_t)__popcll(omem[r] & ((1ull << b) - 1))] = xform<XF>(yv, a);
+                        dst[pmem[r] + (uint32_t)__popcll(omem[r] & ((1ull << b) - 1))] = xform<XF>(zbase<ZH>(yv), a);
                     }
                 } else {
                     // the last chunk of this call: only need values, and the
@@ -1175,7 +1188,7 @@ __global__ __launch_bounds__(256, (DIST == RP_NORM || (DIST == RP_EXP && OT == R
                             const uint32_t idx = total + mbcnt64(om);
                             double v0;
                             zig_fast<DIST, ZH>(zt, wbuf[wpos(64 * r + lane)], v0);
-                            if (idx < need) dst[idx] = xform<XF>(v0, a);
+                            if (idx < need) dst[idx] = xform<XF>(zbase<ZH>(v0), a);
                         }
                         if (lane == 0) {
                             omem[r] = om;
@@ -1197,7 +1210,7 @@ __global__ __launch_bounds__(256, (DIST == RP_NORM || (DIST == RP_EXP && OT == R
                     if (yq >= 0) {
                         const int r = yq >> 6, b = yq & 63;
                         const uint32_t idx = pmem[r] + (uint32_t)__popcll(omem[r] & ((1ull << b) - 1));
-                        if (idx < need) dst[idx] = xform<XF>(yv, a);
+                        if (idx < need) dst[idx] = xform<XF>(zbase<ZH>(yv), a);
                     }
                     if (done) break;
                 }
@@ -1562,7 +1575,7 @@ __global__ __launch_bounds__(256) void k_fill_lane(FillArgs a)
         for (uint64_t t = 0; t < P;) {
             if constexpr (ZIG && HALF) {
                 eng.reserve(2);
-                out[t++] = (T)xform<XF>(zig_serial_g<DIST, true>(zt,
+                out[t++] = (T)xform<XF>(zbase<true>(zig_serial_g<DIST, true>(zt,
                                                                [&]() -> uint64_t {
                                                                    if (have) {
                                                                        have = false;
@@ -1572,7 +1585,7 @@ __global__ __launch_bounds__(256) void k_fill_lane(FillArgs a)
                                                                    hi = (uint32_t)(w >> 32);
                                                                    have = true;
                                                                    return w & 0xffffffffull;
-                                                               }),
+                                                               })),
                                         a);
             } else if constexpr (ZIG) {
                 eng.reserve(3);
@@ -1621,7 +1634,7 @@ __global__ __launch_bounds__(256) void k_fill_lane(FillArgs a)
         auto produce = [&]() __attribute__((always_inline)) -> T {
             if constexpr (ZIG && HALF) {
                 eng.reserve(2);
-                return (T)xform<XF>(zig_serial_g<DIST, true>(zt, next32), a);
+                return (T)xform<XF>(zbase<true>(zig_serial_g<DIST, true>(zt, next32)), a);
             } else if constexpr (ZIG) {
                 eng.reserve(3);
                 return (T)xform<XF>(zig_serial<DIST>(zt, eng), a);
@@ -1722,37 +1735,43 @@ int launch_fill(int engine, int dist, int dtype, const FillArgs &a, hipStream_t 
     return fail(RP_EINVAL, "unknown engine");
 }
 
-template <bool WAVE, class E>
-static int dispatch_law(int law, const FillArgs &a, hipStream_t st)
+template <bool WAVE, class E, int OT>
+static int dispatch_law_t(int law, const FillArgs &a, hipStream_t st)
 {
     switch (law) {
-    case RP_LAW_UNIF: return launch_one<WAVE, E, RP_U01, RP_F64, RP_LAW_UNIF>(a, st);
-    case RP_LAW_NORMAL: return launch_one<WAVE, E, RP_NORM, RP_F64, RP_LAW_NORMAL>(a, st);
-    case RP_LAW_LOGNORMAL: return launch_one<WAVE, E, RP_NORM, RP_F64, RP_LAW_LOGNORMAL>(a, st);
-    case RP_LAW_EXP: return launch_one<WAVE, E, RP_EXP, RP_F64, RP_LAW_EXP>(a, st);
-    case RP_LAW_GUMBEL: return launch_one<WAVE, E, RP_U01, RP_F64, RP_LAW_GUMBEL>(a, st);
-    case RP_LAW_PARETO: return launch_one<WAVE, E, RP_EXP, RP_F64, RP_LAW_PARETO>(a, st);
-    case RP_LAW_GPARETO: return launch_one<WAVE, E, RP_EXP, RP_F64, RP_LAW_GPARETO>(a, st);
-    case RP_LAW_WEIBULL: return launch_one<WAVE, E, RP_EXP, RP_F64, RP_LAW_WEIBULL>(a, st);
+    case RP_LAW_UNIF: return launch_one<WAVE, E, RP_U01, OT, RP_LAW_UNIF>(a, st);
+    case RP_LAW_NORMAL: return launch_one<WAVE, E, RP_NORM, OT, RP_LAW_NORMAL>(a, st);
+    case RP_LAW_LOGNORMAL: return launch_one<WAVE, E, RP_NORM, OT, RP_LAW_LOGNORMAL>(a, st);
+    case RP_LAW_EXP: return launch_one<WAVE, E, RP_EXP, OT, RP_LAW_EXP>(a, st);
+    case RP_LAW_GUMBEL: return launch_one<WAVE, E, RP_U01, OT, RP_LAW_GUMBEL>(a, st);
+    case RP_LAW_PARETO: return launch_one<WAVE, E, RP_EXP, OT, RP_LAW_PARETO>(a, st);
+    case RP_LAW_GPARETO: return launch_one<WAVE, E, RP_EXP, OT, RP_LAW_GPARETO>(a, st);
+    case RP_LAW_WEIBULL: return launch_one<WAVE, E, RP_EXP, OT, RP_LAW_WEIBULL>(a, st);
     }
     return fail(RP_EINVAL, "unknown law");
 }
 
-int launch_fill_law(int engine, int law, const FillArgs &a, hipStream_t st)
+template <bool WAVE, class E>
+static int dispatch_law(int law, bool f32, const FillArgs &a, hipStream_t st)
+{
+    return f32 ? dispatch_law_t<WAVE, E, RP_F32>(law, a, st) : dispatch_law_t<WAVE, E, RP_F64>(law, a, st);
+}
+
+int launch_fill_law(int engine, int law, bool f32, const FillArgs &a, hipStream_t st)
 {
     if (a.n > (uint64_t)UINT32_MAX * 4) return fail(RP_EINVAL, "too many substreams for one launch");
     switch (engine) {
-    case RP_PHILOX4X32: return dispatch_law<true, WavePhilox32>(law, a, st);
-    case RP_PHILOX: return dispatch_law<true, WavePhilox64>(law, a, st);
-    case RP_PCG64: return dispatch_law<true, WavePcg>(law, a, st);
-    case RP_X256PP: return dispatch_law<false, LaneX256>(law, a, st);
-    case RP_X256SS: return dispatch_law<false, LaneX256SS>(law, a, st);
-    case RP_SQUARES: return dispatch_law<true, WaveSquares>(law, a, st);
-    case RP_CHACHA20: return dispatch_law<true, WaveChacha>(law, a, st);
-    case RP_XORO128: return dispatch_law<false, LaneXoro128>(law, a, st);
-    case RP_XS128: return dispatch_law<false, LaneXs128>(law, a, st);
-    case RP_SFC64: return dispatch_law<false, LaneSfc64>(law, a, st);
-    case RP_RANLUX: return dispatch_law<false, LaneRanlux>(law, a, st);
+    case RP_PHILOX4X32: return dispatch_law<true, WavePhilox32>(law, f32, a, st);
+    case RP_PHILOX: return dispatch_law<true, WavePhilox64>(law, f32, a, st);
+    case RP_PCG64: return dispatch_law<true, WavePcg>(law, f32, a, st);
+    case RP_X256PP: return dispatch_law<false, LaneX256>(law, f32, a, st);
+    case RP_X256SS: return dispatch_law<false, LaneX256SS>(law, f32, a, st);
+    case RP_SQUARES: return dispatch_law<true, WaveSquares>(law, f32, a, st);
+    case RP_CHACHA20: return dispatch_law<true, WaveChacha>(law, f32, a, st);
+    case RP_XORO128: return dispatch_law<false, LaneXoro128>(law, f32, a, st);
+    case RP_XS128: return dispatch_law<false, LaneXs128>(law, f32, a, st);
+    case RP_SFC64: return dispatch_law<false, LaneSfc64>(law, f32, a, st);
+    case RP_RANLUX: return dispatch_law<false, LaneRanlux>(law, f32, a, st);
     }
     return fail(RP_EINVAL, "unknown engine");
 }

@@ -1225,8 +1225,10 @@ extern "C" int rp_sample(rp_streams *s, uint32_t n, uint32_t k, uint32_t *d_out,
     return rc;
 }
 
-extern "C" int rp_fill_law(rp_streams *s, int law, const double *p, int np, double *d_out, uint64_t per_stream,
-                           void *hip_stream)
+// rp_fill_law (binary64 output) and rp_fill_lawf (binary32: the float base
+// draws, the transform in binary64, one rounding)
+static int fill_law_impl(rp_streams *s, int law, const double *p, int np, void *d_out, uint64_t per_stream,
+                         void *hip_stream, bool f32)
 {
     if (!s) return fail(RP_ENULL, "rp_fill_law: NULL streams");
     static const int kParams[15] = {0, 2, 2, 2, 1, 2, 2, 3, 2, 2, 2, 1, 1, 2, 3};
@@ -1308,9 +1310,11 @@ extern "C" int rp_fill_law(rp_streams *s, int law, const double *p, int np, doub
     }
     }
     if (!ok) return fail(RP_EINVAL, "rp_fill_law: parameters outside the law's domain");
+    if (f32 && law >= RP_LAW_GAMMA)
+        return fail(RP_EUNSUPPORTED, "rp_fill_lawf: law %d has no binary32 form (laws 1-8 only)", law);
     if (per_stream == 0) return RP_OK;
     if (!d_out) return fail(RP_ENULL, "rp_fill_law: NULL output");
-    if ((uintptr_t)d_out % 8) return fail(RP_EINVAL, "rp_fill_law: output not aligned to 8 bytes");
+    if ((uintptr_t)d_out % (f32 ? 4 : 8)) return fail(RP_EINVAL, "rp_fill_law: output not aligned to its element size");
     if (s->n > UINT64_MAX / per_stream) return fail(RP_EINVAL, "rp_fill_law: size overflow");
     int rc = ensure_device_tables();
     if (rc) return rc;
@@ -1320,7 +1324,19 @@ extern "C" int rp_fill_law(rp_streams *s, int law, const double *p, int np, doub
     a.per_stream = per_stream;
     a.out = d_out;
     if (law >= RP_LAW_GAMMA) return launch_fill_mix(s->engine, law, a, (hipStream_t)hip_stream);
-    return launch_fill_law(s->engine, law, a, (hipStream_t)hip_stream);
+    return launch_fill_law(s->engine, law, f32, a, (hipStream_t)hip_stream);
+}
+
+extern "C" int rp_fill_law(rp_streams *s, int law, const double *p, int np, double *d_out, uint64_t per_stream,
+                           void *hip_stream)
+{
+    return fill_law_impl(s, law, p, np, d_out, per_stream, hip_stream, false);
+}
+
+extern "C" int rp_fill_lawf(rp_streams *s, int law, const double *p, int np, float *d_out, uint64_t per_stream,
+                            void *hip_stream)
+{
+    return fill_law_impl(s, law, p, np, d_out, per_stream, hip_stream, true);
 }
 
 // ---------------------------------------------------------------------------

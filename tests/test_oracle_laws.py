@@ -65,3 +65,16 @@ def test_draw_advances_like_the_base_fill():
     laws.draw(a, laws.PARETO, (1.0, 2.0), 777)
     b.exp(777)
     assert a.state == b.state and a.phase == b.phase
+
+
+@pytest.mark.parametrize("law,p,dist", [
+    (laws.LOGNORMAL, (0.5, 0.75), lambda: stats.lognorm(s=0.75, scale=np.exp(0.5))),
+    (laws.WEIBULL, (1.7, 4.0), lambda: stats.weibull_min(c=1.7, scale=4.0)),
+    (laws.GUMBEL, (1.0, 2.0), lambda: stats.gumbel_r(loc=1.0, scale=2.0)),
+])
+def test_float_laws_ks(law, p, dist):
+    """Binary32 laws (float base draws, binary64 transform, one rounding)
+    follow the named law."""
+    x = laws.draw_f32(oracle.Stream.seeded("pcg64", 41), law, p, 200000)
+    assert x.dtype == np.float32
+    assert stats.kstest(x.astype(np.float64), dist().cdf).pvalue > 1e-4
