@@ -278,3 +278,25 @@ def test_float_law_errors():
     with pytest.raises(rp.RpError) as ei:
         rp.rp_fill_lawf(S, rp.RP_LAW_UNIF, (1.0, 1.0), out, 4)
     assert ei.value.code == rp.RP_EINVAL
+
+
+@pytest.mark.parametrize("engine", ["ranlux++", "sfc64", "xoro++"])
+def test_float_law_lane_bodies(engine):
+    """The binary32 laws through the per-lane kernel body (ranlux++) and the
+    staged one (sfc64, xoroshiro128++), ziggurat and uniform bases."""
+    from tests.gpu_common import ulp_diff
+    n, per = 64, 300
+    S = make_streams(engine, n)
+    ost = [oracle_stream(engine, i) for i in range(n)]
+    for law, p in ((rp.RP_LAW_LOGNORMAL, (0.5, 0.75)), (rp.RP_LAW_GUMBEL, (1.0, 2.0)),
+                   (rp.RP_LAW_WEIBULL, (1.7, 4.0))):
+        out = torch.empty(n * per, dtype=torch.float32, device="cuda")
+        rp.rp_fill_lawf(S, law, p, out, per)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().reshape(n, per)
+        for i, o in enumerate(ost):
+            ref = laws.draw_f32(o, law, p, per)
+            same = got[i] == ref
+            if not same.all():
+                assert ulp_diff(got[i][~same], ref[~same]).max() <= 2, (engine, law, i)
+    _states_equal(S, engine, ost)
