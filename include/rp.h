@@ -210,8 +210,11 @@ int rp_fill(rp_streams *s, int dist, int dtype, uint64_t bound, int flags, void 
  * versions): the base draw is the binary32 one rp_fill(..., RP_F32) returns
  * (24-bit uniform of a 32-bit item, or the float ziggurat's value), the
  * transform is evaluated in binary64 on that value and rounded once to
- * binary32; d_out holds n * per_stream floats (4-byte aligned).  Laws 9-14
- * give RP_EUNSUPPORTED. */
+ * binary32; d_out holds n * per_stream floats (4-byte aligned).  Law 9 is
+ * the float gamma: Marsaglia-Tsang on 32-bit items (the float ziggurat's
+ * binary32 normal, 24-bit uniforms for the test and the shape < 1 boost),
+ * binary64 arithmetic, theta G rounded once.  Laws 10-14 give
+ * RP_EUNSUPPORTED. */
 enum {
     RP_LAW_UNIF = 1,
     RP_LAW_NORMAL = 2,

@@ -57,6 +57,7 @@ def lib():
             "or_norm": ([vp, vp, sz, vp], None), "or_exp": ([vp, vp, sz, vp], None),
             "or_normf": ([vp, vp, sz], None), "or_expf": ([vp, vp, sz], None),
             "or_permutation": ([vp, ctypes.c_uint32, vp], None),
+            "or_gammaf": ([vp, ctypes.c_double, ctypes.c_double, vp, sz], None),
             "or_sample": ([vp, ctypes.c_uint32, ctypes.c_uint32, vp], None),
             "or_norm_moments": ([vp, sz, vp, vp], None),
             "or_gamma": ([vp, ctypes.c_double, vp, sz, vp], None),
@@ -256,6 +257,12 @@ class Stream:
         """n binary32 standard exponentials from 32-bit items (float ziggurat)."""
         out = np.empty(n, dtype=np.float32)
         lib().or_expf(_p(self.buf), _p(out), n)
+        return out
+
+    def gammaf(self, alpha, n, theta=1.0):
+        """n binary32 Gamma(alpha, theta) draws (float gamma)."""
+        out = np.empty(n, dtype=np.float32)
+        lib().or_gammaf(_p(self.buf), float(alpha), float(theta), _p(out), n)
         return out
 
     def permutation(self, n):

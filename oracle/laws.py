@@ -124,7 +124,9 @@ BASE_F32 = {"u01": "u01f", "norm": "normf", "exp": "expf"}
 def draw_f32(stream, law, p, n):
     """n binary32 draws of a transform law (the paper's float versions): the
     binary32 base draw, the transform in binary64 on that value, one
-    rounding to binary32."""
+    rounding to binary32; Gamma(alpha, theta) is the float gamma."""
+    if law == GAMMA:
+        return stream.gammaf(p[0], n, p[1])
     if law not in BASE:
         raise ValueError(f"law {law} has no binary32 form")
     base = getattr(stream, BASE_F32[BASE[law]])(n).astype(np.float64)

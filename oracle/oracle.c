@@ -34,6 +34,7 @@
  *   ziggurat exponential                   pinned: geometry, paper's rejection rate, KS
  *   float ziggurat (normf, expf)           pinned: KS, fast-accept rates, strip boundaries, tails
  *   permutations, Floyd / reservoir samples pinned: exact laws on small cases (enumeration), validity
+ *   float gamma (gammaf)                   pinned: KS against the gamma law, moments
  *   gamma (alpha >= 1)                     pinned: NumPy Marsaglia-Tsang, moments, KS
  *   gamma boost (alpha < 1), beta          pinned: mpmath power, moments, KS
  */
@@ -1355,6 +1356,43 @@ static double gamma_one(or_stream *s, double a, or_counts *cn)
         return g * or_boost_pow(u, a);
     }
     return mt_gamma(s, a, cn);
+}
+
+/* Float gamma (the paper's gammaf; reading as for the float ziggurat):
+ * Marsaglia-Tsang with the binary32 normal of the float ziggurat, the
+ * 24-bit uniform of the next 32-bit item for the test and for the shape < 1
+ * boost, binary64 arithmetic throughout, theta g rounded once to binary32. */
+static double mt_gammaf(half_reader *h, double a)
+{
+    double d = a - 1.0 / 3.0;
+    double c = 1.0 / sqrt(9.0 * d);
+    for (;;) {
+        double x, v;
+        do {
+            x = (double)normf_one(h);
+            v = 1.0 + c * x;
+        } while (v <= 0.0);
+        v = v * v * v;
+        double u = u01_24(next32(h));
+        double x2 = x * x;
+        if (u < 1.0 - 0.0331 * (x2 * x2)) return d * v;
+        if (log(u) < 0.5 * x2 + d * ((1.0 - v) + log(v))) return d * v;
+    }
+}
+
+void or_gammaf(or_stream *s, double a, double theta, float *out, size_t n)
+{
+    half_reader h = {s, 0, 0};
+    for (size_t i = 0; i < n; i++) {
+        double g;
+        if (a < 1.0) {
+            g = mt_gammaf(&h, a + 1.0);
+            g = g * or_boost_pow(u01_24(next32(&h)), a);
+        } else {
+            g = mt_gammaf(&h, a);
+        }
+        out[i] = (float)(theta * g);
+    }
 }
 
 void or_gamma(or_stream *s, double a, double *out, size_t n, or_counts *cn)

@@ -1310,8 +1310,8 @@ static int fill_law_impl(rp_streams *s, int law, const double *p, int np, void *
     }
     }
     if (!ok) return fail(RP_EINVAL, "rp_fill_law: parameters outside the law's domain");
-    if (f32 && law >= RP_LAW_GAMMA)
-        return fail(RP_EUNSUPPORTED, "rp_fill_lawf: law %d has no binary32 form (laws 1-8 only)", law);
+    if (f32 && law > RP_LAW_GAMMA)
+        return fail(RP_EUNSUPPORTED, "rp_fill_lawf: law %d has no binary32 form (laws 1-9 only)", law);
     if (per_stream == 0) return RP_OK;
     if (!d_out) return fail(RP_ENULL, "rp_fill_law: NULL output");
     if ((uintptr_t)d_out % (f32 ? 4 : 8)) return fail(RP_EINVAL, "rp_fill_law: output not aligned to its element size");
@@ -1323,7 +1323,7 @@ static int fill_law_impl(rp_streams *s, int law, const double *p, int np, void *
     a.n = s->n;
     a.per_stream = per_stream;
     a.out = d_out;
-    if (law >= RP_LAW_GAMMA) return launch_fill_mix(s->engine, law, a, (hipStream_t)hip_stream);
+    if (law >= RP_LAW_GAMMA) return launch_fill_mix(s->engine, law, f32, a, (hipStream_t)hip_stream);
     return launch_fill_law(s->engine, law, f32, a, (hipStream_t)hip_stream);
 }
 

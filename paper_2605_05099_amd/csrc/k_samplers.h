@@ -217,37 +217,60 @@ __device__ double boost_pow(double u, double a, double ia, const LogLds *lt)
 // One ziggurat normal candidate (the serial ziggurat's decisions): true with
 // the value when it is accepted, false when rejected (the caller starts a
 // new candidate, exactly where the serial sampler would).
-template <class E>
+// HALF: the float ziggurat on 32-bit items (the binary32 value it returns).
+template <class E, bool HALF = false>
 __device__ __forceinline__ bool zig_candidate(E &eng, const ZigLds *zt, double &x)
 {
-    const uint64_t w = eng.next();
+    const uint64_t w = HALF ? item_word<RP_NORM>(eng.next()) : eng.next();
     const int j = (int)(w & 0xff);
     const uint64_t m = (w >> 9) & ((1ull << 52) - 1);
     const bool neg = (w >> 8) & 1;
     const WKe e = zt->WK[j];
     const double xx = (double)m * e.w;
     if (m < e.k) {
-        x = neg ? -xx : xx;
+        x = zbase<HALF>(neg ? -xx : xx);
         return true;
     }
     if (j == 0) {
         for (int it = 0; it < kMaxTailIters; it++) {
-            const double e1 = -log1p(-u01_53(eng.next())) / RP_ZN_R;
-            const double e2 = -log1p(-u01_53(eng.next()));
+            const double e1 = -log1p(-zig_u<HALF>(eng.next())) / RP_ZN_R;
+            const double e2 = -log1p(-zig_u<HALF>(eng.next()));
             if (e2 + e2 > e1 * e1) {
                 const double t = RP_ZN_R + e1;
-                x = neg ? -t : t;
+                x = zbase<HALF>(neg ? -t : t);
                 return true;
             }
         }
         return false;
     }
-    if (wedge_accept<RP_NORM>(zt, j, xx, eng.next())) {
-        x = neg ? -xx : xx;
+    if (wedge_accept<RP_NORM, HALF>(zt, j, xx, eng.next())) {
+        x = zbase<HALF>(neg ? -xx : xx);
         return true;
     }
     return false;
 }
+
+// 32-bit items of a lane engine, low half first (a half left over when the
+// caller stops is dropped: the engine's state is after the last word)
+template <class E>
+struct ItemEng {
+    E &e;
+    bool have = false;
+    uint32_t hi = 0;
+    __device__ explicit ItemEng(E &x) : e(x) {}
+    __device__ uint64_t next()
+    {
+        if (have) {
+            have = false;
+            return hi;
+        }
+        const uint64_t w = e.next();
+        hi = (uint32_t)(w >> 32);
+        have = true;
+        return (uint32_t)w;
+    }
+    __device__ void reserve(int k) { e.reserve((k + 1) / 2); }
+};
 
 // The normal ziggurat as a step machine: a step takes at most two words (a
 // candidate and its wedge word, or one tail pair) and either yields a value
@@ -345,7 +368,9 @@ __device__ __forceinline__ GamParam gam_param(double a)
 // MODE 0: Gamma(a) draws; 1: Beta(a, b) = X / (X + Y); 2: the F ratio
 // (X / nu1) / (Y / nu2) of X ~ Gamma(a), Y ~ Gamma(b), nu1 = 2a, nu2 = 2b (both
 // doublings exact).  X is drawn before Y.
-template <int MODE>
+// HALF: the float gamma (32-bit items: the float ziggurat's binary32 normal,
+// 24-bit uniforms for the test and the boost; binary64 arithmetic)
+template <int MODE, bool HALF = false>
 struct GamMachine {
     static constexpr bool BETA = MODE != 0;
     GamParam pa, pb;
@@ -364,11 +389,11 @@ struct GamMachine {
         const bool sb = BETA && second;
         const double d = sb ? pb.d : pa.d, c = sb ? pb.c : pa.c;
         double x;
-        if (!zig_candidate(eng, zt, x)) return false;
+        if (!zig_candidate<E, HALF>(eng, zt, x)) return false;
         double v = 1.0 + c * x;
         if (v <= 0.0) return false;
         v = v * v * v;
-        const double u = u01_53(eng.next());
+        const double u = zig_u<HALF>(eng.next());
         const double x2 = x * x;
         bool acc = u < 1.0 - 0.0331 * (x2 * x2);
         if (!acc) acc = mt_log_test(u, x2, v, d);
@@ -376,7 +401,7 @@ struct GamMachine {
         double g = d * v;
         if (sb ? pb.boost : pa.boost) {
             const double a = sb ? pb.a : pa.a, ia = sb ? pb.ia : pa.ia;
-            g = g * boost_pow(u01_53(eng.next()), a, ia, lt);
+            g = g * boost_pow(zig_u<HALF>(eng.next()), a, ia, lt);
         }
         if (!BETA) {
             val = g;
@@ -583,21 +608,56 @@ static int launch_mix_e(int law, const FillArgs &f, hipStream_t st)
     return RP_OK;
 }
 
-int launch_fill_mix(int engine, int law, const FillArgs &f, hipStream_t st)
+// Float gamma (rp_fill_lawf with RP_LAW_GAMMA): theta G rounded to
+// binary32, G the float Marsaglia-Tsang draw on the substream's items.
+template <class E>
+__global__ __launch_bounds__(256) void k_fill_gammaf(FillArgs f)
+{
+    __shared__ ZigLds zt;
+    __shared__ LogLds lt;
+    load_zig<RP_NORM>(&zt);
+    load_logt(&lt);
+    __syncthreads();
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= f.n) return;
+    E eng;
+    eng.load(f, i);
+    ItemEng<E> it(eng);
+    const uint64_t P = f.per_stream;
+    float *out = (float *)f.out + i * P;
+    GamMachine<0, true> gm;
+    gm.set(f.xp[0], 1.0);
+    for (uint64_t t = 0; t < P;) {
+        double v;
+        if (gm.step(it, &zt, &lt, v)) out[t++] = (float)(f.xp[1] * v);
+    }
+    eng.store(f, i);
+}
+
+template <class E>
+static int launch_mix_any(int law, bool f32, const FillArgs &f, hipStream_t st)
+{
+    if (!f32) return launch_mix_e<E>(law, f, st);
+    if (law != RP_LAW_GAMMA) return fail(RP_EUNSUPPORTED, "law %d has no binary32 form", law);
+    hipLaunchKernelGGL(k_fill_gammaf<E>, dim3((unsigned)((f.n + 255) / 256)), dim3(256), 0, st, f);
+    return RP_OK;
+}
+
+int launch_fill_mix(int engine, int law, bool f32, const FillArgs &f, hipStream_t st)
 {
     int rc;
     switch (engine) {
-    case RP_X256PP: rc = launch_mix_e<LaneX256>(law, f, st); break;
-    case RP_X256SS: rc = launch_mix_e<LaneX256SS>(law, f, st); break;
-    case RP_SQUARES: rc = launch_mix_e<LaneSquares>(law, f, st); break;
-    case RP_XORO128: rc = launch_mix_e<LaneXoro128>(law, f, st); break;
-    case RP_XS128: rc = launch_mix_e<LaneXs128>(law, f, st); break;
-    case RP_CHACHA20: rc = launch_mix_e<LaneChacha>(law, f, st); break;
-    case RP_PCG64: rc = launch_mix_e<LanePcg>(law, f, st); break;
-    case RP_PHILOX4X32: rc = launch_mix_e<LanePhilox32>(law, f, st); break;
-    case RP_PHILOX: rc = launch_mix_e<LanePhilox64>(law, f, st); break;
-    case RP_SFC64: rc = launch_mix_e<LaneSfc64>(law, f, st); break;
-    case RP_RANLUX: rc = launch_mix_e<LaneRanlux>(law, f, st); break;
+    case RP_X256PP: rc = launch_mix_any<LaneX256>(law, f32, f, st); break;
+    case RP_X256SS: rc = launch_mix_any<LaneX256SS>(law, f32, f, st); break;
+    case RP_SQUARES: rc = launch_mix_any<LaneSquares>(law, f32, f, st); break;
+    case RP_XORO128: rc = launch_mix_any<LaneXoro128>(law, f32, f, st); break;
+    case RP_XS128: rc = launch_mix_any<LaneXs128>(law, f32, f, st); break;
+    case RP_CHACHA20: rc = launch_mix_any<LaneChacha>(law, f32, f, st); break;
+    case RP_PCG64: rc = launch_mix_any<LanePcg>(law, f32, f, st); break;
+    case RP_PHILOX4X32: rc = launch_mix_any<LanePhilox32>(law, f32, f, st); break;
+    case RP_PHILOX: rc = launch_mix_any<LanePhilox64>(law, f32, f, st); break;
+    case RP_SFC64: rc = launch_mix_any<LaneSfc64>(law, f32, f, st); break;
+    case RP_RANLUX: rc = launch_mix_any<LaneRanlux>(law, f32, f, st); break;
     default: return fail(RP_EINVAL, "unknown engine");
     }
     if (rc) return rc;

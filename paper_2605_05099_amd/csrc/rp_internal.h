@@ -65,7 +65,7 @@ int launch_fill(int engine, int dist, int dtype, const FillArgs &a, hipStream_t 
 // rp_fill_law: the base fill of the law with its transform fused at the store
 int launch_fill_law(int engine, int law, bool f32, const FillArgs &a, hipStream_t stream);
 // rp_fill_law for the laws of several base draws per value (k_samplers.h)
-int launch_fill_mix(int engine, int law, const FillArgs &a, hipStream_t stream);
+int launch_fill_mix(int engine, int law, bool f32, const FillArgs &a, hipStream_t stream);
 
 // lane-per-substream samplers (k_samplers.h)
 struct SampArgs {

@@ -273,7 +273,7 @@ def test_float_law_errors():
     S = make_streams("philox4x32", 4)
     out = torch.empty(16, dtype=torch.float32, device="cuda")
     with pytest.raises(rp.RpError) as ei:
-        rp.rp_fill_lawf(S, rp.RP_LAW_GAMMA, (2.0, 1.0), out, 4)
+        rp.rp_fill_lawf(S, rp.RP_LAW_BETA, (2.0, 1.0), out, 4)
     assert ei.value.code == rp.RP_EUNSUPPORTED
     with pytest.raises(rp.RpError) as ei:
         rp.rp_fill_lawf(S, rp.RP_LAW_UNIF, (1.0, 1.0), out, 4)
@@ -299,4 +299,31 @@ def test_float_law_lane_bodies(engine):
             same = got[i] == ref
             if not same.all():
                 assert ulp_diff(got[i][~same], ref[~same]).max() <= 2, (engine, law, i)
+    _states_equal(S, engine, ost)
+
+
+
+@pytest.mark.parametrize("alpha", [2.5, 0.4])
+@pytest.mark.parametrize("engine", ["philox4x32", "pcg64", "x256++", "ranlux++", "chacha20"])
+def test_float_gamma_matches_oracle(engine, alpha):
+    """The float gamma (rp_fill_lawf, RP_LAW_GAMMA): identical decisions on
+    the 32-bit items, binary64 arithmetic on both sides; values equal unless
+    the boost's power (about an ulp of binary64 apart) straddles a binary32
+    rounding boundary: at most 2 binary32 ulp, and rare."""
+    from tests.gpu_common import ulp_diff
+    n, per = 64, 400
+    S = make_streams(engine, n)
+    out = torch.empty(n * per, dtype=torch.float32, device="cuda")
+    rp.rp_fill_lawf(S, rp.RP_LAW_GAMMA, (alpha, 1.5), out, per)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().reshape(n, per)
+    ost = [oracle_stream(engine, i) for i in range(n)]
+    nz = 0
+    for i, o in enumerate(ost):
+        ref = laws.draw_f32(o, rp.RP_LAW_GAMMA, (alpha, 1.5), per)
+        same = got[i] == ref
+        if not same.all():
+            assert ulp_diff(got[i][~same], ref[~same]).max() <= 2, (engine, i)
+            nz += int((~same).sum())
+    assert nz <= max(8, n * per // 1000), nz
     _states_equal(S, engine, ost)

@@ -78,3 +78,12 @@ def test_float_laws_ks(law, p, dist):
     x = laws.draw_f32(oracle.Stream.seeded("pcg64", 41), law, p, 200000)
     assert x.dtype == np.float32
     assert stats.kstest(x.astype(np.float64), dist().cdf).pvalue > 1e-4
+
+
+
+@pytest.mark.parametrize("alpha", [2.5, 0.4])
+def test_float_gamma_ks_and_mean(alpha):
+    """The float gamma follows Gamma(alpha, theta)."""
+    x = oracle.Stream.seeded("x256++", 43).gammaf(alpha, 200000, 1.5).astype(np.float64)
+    assert stats.kstest(x, stats.gamma(alpha, scale=1.5).cdf).pvalue > 1e-4
+    assert abs(x.mean() - 1.5 * alpha) < 6 * 1.5 * np.sqrt(alpha / len(x))
