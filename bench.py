@@ -322,7 +322,8 @@ def part_laws(torch, rp, workloads, tm, sp):
 
 def part_float(torch, rp, workloads, tm, sp):
     """Float ziggurat normal and exponential (binary32 draws from 32-bit
-    items) on the substream workload, both wavefront engines."""
+    items) on the substream workload, both wavefront engines; binary32 laws
+    (transforms and the float gamma) on Philox4x32-10."""
     n, per = workloads.SUB_N, workloads.SUB_PER
     buf = torch.empty(n * per, dtype=torch.float32, device="cuda")
     res = {}
@@ -332,6 +333,13 @@ def part_float(torch, rp, workloads, tm, sp):
             ms = tm(lambda: rp.rp_fill(S, dist, rp.RP_F32, 0, 0, buf, per, sp), reps=3)
             res[f"{eng}/{name}"] = {"ms": round(ms, 4), "gsamples_s": round(n * per / ms / 1e6, 2),
                                     "hbm_frac": round(4.0 * n * per / ms / 1e6 / HBM_PEAK_GBS, 4)}
+        if eng == "philox4x32":
+            for name, law, p in (("lawf_unif", rp.RP_LAW_UNIF, (-2.0, 5.0)),
+                                 ("lawf_lognormal", rp.RP_LAW_LOGNORMAL, (0.5, 0.75)),
+                                 ("lawf_weibull", rp.RP_LAW_WEIBULL, (1.7, 4.0)),
+                                 ("lawf_gamma", rp.RP_LAW_GAMMA, (2.5, 1.5))):
+                ms = tm(lambda: rp.rp_fill_lawf(S, law, p, buf, per, sp), reps=3)
+                res[f"{eng}/{name}"] = {"ms": round(ms, 4), "gsamples_s": round(n * per / ms / 1e6, 2)}
         del S
     del buf
     return {"float_zig_2p16x2p14": res}
