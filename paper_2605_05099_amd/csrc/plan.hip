@@ -259,7 +259,7 @@ extern "C" int rp_plan_autotune(rp_plan *p, rp_streams *s, int beta, const doubl
         return hip_fail(e, "rp_plan_autotune: events");
     }
     static const int kBlocks[] = {64, 128, 256};
-    static const int kPerCu[] = {2, 4, 8, 16};
+    static const int kPerCu[] = {2, 4, 6, 8, 12, 16};
     static const int kSpl[] = {1, 2};
     float best = 1e30f;
     int bb = p->block, bp = p->blocks_per_cu, bs = p->spl;
