@@ -80,10 +80,15 @@ int rp_engines(char *buf, size_t len);
 int rp_engine_id(const char *name);
 
 /* ---- serial streams (Section 2.1, Section 2.3) -------------------------- */
-/* Creates a stream; NULL or "" selects x256++.  The state is seeded from
- * seed 0 with no spawn key (randomisation from OS entropy is not part of this
- * library; call rp_seed).  Returns NULL on failure (see rp_errmsg). */
+/* Creates a stream; NULL or "" selects x256++.  The new stream is
+ * randomized (rp_randomize); call rp_seed for a reproducible one.  Returns
+ * NULL on failure (see rp_errmsg). */
 rp_rng *rp_create(const char *engine);
+/* Seeds the stream from system entropy (Section 2.3): a 64-bit seed from
+ * getrandom (then /dev/urandom; if neither answers, the clock mixed with a
+ * counter), used as rp_seed(rng, seed, NULL, 0) would, so spawn-key
+ * substreams derive from it as from any seed.  Not reproducible. */
+int rp_randomize(rp_rng *rng);
 void rp_free(rp_rng *rng);
 /* Exact copy (Section 2.3 "duplicate"). */
 rp_rng *rp_duplicate(const rp_rng *rng);

@@ -52,6 +52,7 @@ _SIGS = {
     "rp_philox_set_key": ([_vp, _u64, _u64], _int),
     "rp_sfc64_set_abc": ([_vp, _u64, _u64, _u64], _int),
     "rp_squares_set_key": ([_vp, _u64], _int),
+    "rp_randomize": ([_vp], _int),
     "rp_chacha20_set_nonce": ([_vp, _u64, _u64], _int),
     "rp_serialize": ([_vp, _vp, _sz, _vp], _int),
     "rp_deserialize": ([_vp, _vp, _sz], _int),
@@ -346,6 +347,10 @@ class Rng:
 
     def sfc64_set_abc(self, a, b, c):
         _check(lib().rp_sfc64_set_abc(self.h, a, b, c), self.h)
+        return self
+
+    def randomize(self):
+        _check(lib().rp_randomize(self.h), self.h)
         return self
 
     def squares_set_key(self, key):

@@ -5,7 +5,10 @@
 // Section 4.4 (thread safety, serialization, engine query, jumping).
 #include <hip/hip_runtime.h>
 
+#include <sys/random.h>
+
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cctype>
 #include <cstdarg>
@@ -671,6 +674,38 @@ static void seed_state(rp_rng *r, uint64_t seed, const uint32_t *key, size_t n_k
 
 // ---------------------------------------------------------------------------
 // serial streams
+// 64 bits from the operating system's entropy source (Section 2.3): getrandom,
+// then /dev/urandom; if neither answers, the clock mixed with addresses and a
+// counter through a splitmix64 step (an emergency fallback, not secure).
+static uint64_t system_entropy64()
+{
+    uint64_t v = 0;
+    size_t got = 0;
+    while (got < sizeof v) {
+        const ssize_t r = getrandom((char *)&v + got, sizeof v - got, 0);
+        if (r <= 0) break;
+        got += (size_t)r;
+    }
+    if (got == sizeof v) return v;
+    if (FILE *f = std::fopen("/dev/urandom", "rb")) {
+        const size_t n = std::fread(&v, 1, sizeof v, f);
+        std::fclose(f);
+        if (n == sizeof v) return v;
+    }
+    static uint64_t counter = 0;
+    uint64_t z = (uint64_t)std::chrono::high_resolution_clock::now().time_since_epoch().count() ^
+                 (uint64_t)(uintptr_t)&v ^ (++counter * 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+extern "C" int rp_randomize(rp_rng *rng)
+{
+    if (!rng) return fail(RP_ENULL, "rp_randomize: NULL rng");
+    return rp_seed(rng, system_entropy64(), nullptr, 0);
+}
+
 extern "C" rp_rng *rp_create(const char *engine)
 {
     int e = RP_X256PP;
@@ -684,7 +719,8 @@ extern "C" rp_rng *rp_create(const char *engine)
         return nullptr;
     }
     r->engine = e;
-    seed_state(r, 0, nullptr, 0);
+    // a new engine is randomized from system entropy (Section 2.1)
+    rp_randomize(r);
     return r;
 }
 

@@ -44,7 +44,21 @@ def test_engine_query_and_ids():
     assert ei.value.code == rp.RP_EINVAL
     with pytest.raises(rp.RpError):
         rp.rp_create("mt19937")
-    assert rp.rp_create("").get_state()[0] == rp.rp_create("x256++").get_state()[0]
+    # a new stream is randomized: two of them differ; seeding makes them equal
+    a, b = rp.rp_create(""), rp.rp_create("x256++")
+    assert a.state_words() == b.state_words() == 4
+    assert a.get_state()[0] != b.get_state()[0]
+    assert a.seed(7).get_state()[0] == b.seed(7).get_state()[0]
+
+
+def test_randomize_gives_valid_distinct_states():
+    for eng in ENGINES:
+        r1 = rp.rp_create(eng).randomize()
+        r2 = rp.rp_create(eng).randomize()
+        assert r1.get_state()[0] != r2.get_state()[0], eng
+    # a randomized stream is an ordinary seeded one: re-seeding makes it reproducible
+    r = rp.rp_create("pcg64").randomize().seed(99)
+    assert r.get_state()[0] == rp.rp_create("pcg64").seed(99).get_state()[0]
 
 
 @pytest.mark.parametrize("engine", ENGINES)
