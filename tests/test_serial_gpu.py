@@ -16,7 +16,8 @@ from tests.gpu_common import NP_VIEW, TORCH_DTYPE, oracle_fill, ulp_diff
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-ENGINES = ["x256++", "pcg64", "philox4x32", "philox", "ranlux++", "sfc64"]
+ENGINES = ["x256++", "pcg64", "philox4x32", "philox", "ranlux++", "sfc64", "x256**", "squares", "chacha20",
+           "xoro++", "x128+"]
 CASES = [
     (rp.RP_RAW, rp.RP_U64, 0, 0),
     (rp.RP_RAW, rp.RP_U32, 0, 0),
@@ -66,7 +67,7 @@ def test_serial_matches_oracle(engine, case):
     else:
         rng.advance(3)
         o.advance(3)
-    if engine in ("philox4x32", "philox", "ranlux++"):
+    if engine in ("philox4x32", "philox", "ranlux++", "chacha20"):
         rng.raw_host(1)                 # and with a partly used block
         o.raw(1)
     for n in (1, 777, 40001):           # successive calls continue the stream
