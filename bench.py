@@ -370,15 +370,17 @@ def part_engines(torch, rp, workloads, tm, sp):
 
 def part_discrete(torch, rp, workloads, tm, sp):
     """Batched permutations and samples, one instance per substream
-    (Philox4x32-10, 2^16 substreams): permutations of 1024, Floyd samples of
-    64 from 10^6, reservoir samples of 900 from 1000."""
+    (Philox4x32-10, 2^16 substreams): permutations of 1024 (rows in HBM) and
+    512 (rows in LDS), Floyd samples of 64 from 10^6, reservoir samples of
+    900 from 1000."""
     m = workloads.SUB_N
     S = rp.rp_streams_create(rp.rp_create("philox4x32").seed(workloads.BASE_SEED), rp.RP_SUB_KEY, m)
     res = {}
     buf = torch.empty(m * 1024, dtype=torch.int32, device="cuda")
-    ms = tm(lambda: rp.rp_permutations(S, 1024, buf, sp), reps=3)
-    res["permutation_1024"] = {"ms": round(ms, 4), "instances_per_s_m": round(m / ms / 1e3, 3),
-                               "gelem_s": round(m * 1024 / ms / 1e6, 3)}
+    for pn in (1024, 512):
+        ms = tm(lambda: rp.rp_permutations(S, pn, buf, sp), reps=3)
+        res[f"permutation_{pn}"] = {"ms": round(ms, 4), "instances_per_s_m": round(m / ms / 1e3, 3),
+                                    "gelem_s": round(m * pn / ms / 1e6, 3)}
     for name, n, k in (("floyd_64_of_1e6", 10**6, 64), ("reservoir_900_of_1000", 1000, 900)):
         ms = tm(lambda: rp.rp_sample(S, n, k, buf, sp), reps=3)
         res[name] = {"ms": round(ms, 4), "instances_per_s_m": round(m / ms / 1e3, 3)}

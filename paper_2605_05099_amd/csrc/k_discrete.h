@@ -64,6 +64,42 @@ __global__ __launch_bounds__(256) void k_permutations(FillArgs f)
     eng.store(f, i);
 }
 
+// Rows of at most CAP entries (512: 64 KiB, two blocks per CU; 1024:
+// 128 KiB of gfx950's 160 KiB, one block): the 64 rows of a one-wavefront
+// block live in LDS as 16-bit entries, so the swaps are LDS accesses
+// instead of dependent reads of HBM; the identity is written and the
+// finished rows are stored cooperatively (consecutive lanes on consecutive
+// entries).
+template <class E, uint32_t CAP>
+__global__ __launch_bounds__(64) void k_permutations_lds(FillArgs f)
+{
+    __shared__ uint16_t rows[64 * CAP];
+    const uint32_t n = (uint32_t)f.per_stream;
+    const int lane = (int)threadIdx.x;
+    const uint64_t id0 = (uint64_t)blockIdx.x * 64;
+    const uint64_t i = id0 + (uint64_t)lane;
+    for (uint32_t q = (uint32_t)lane; q < 64 * n; q += 64) rows[q] = (uint16_t)(q % n);
+    wave_sync();
+    if (i < f.n) {
+        uint16_t *row = rows + (uint32_t)lane * n;
+        E eng;
+        eng.load(f, i);
+        Items32<E> it(eng);
+        for (uint32_t j = n - 1; j >= 1; j--) {
+            const uint32_t r = it.bounded(j + 1);
+            const uint16_t t = row[j];
+            row[j] = row[r];
+            row[r] = t;
+        }
+        eng.store(f, i);
+    }
+    wave_sync();
+    uint32_t *out = (uint32_t *)f.out;
+    const uint32_t rows_here = f.n - id0 < 64 ? (uint32_t)(f.n - id0) : 64u;
+    for (uint32_t rr = 0; rr < rows_here; rr++)
+        for (uint32_t q = (uint32_t)lane; q < n; q += 64) out[(id0 + rr) * n + q] = rows[rr * n + q];
+}
+
 // k distinct elements of {0 .. n-1} per substream (f.per_stream = k,
 // f.bound = n).  k <= n/2: Floyd's algorithm, for j from n-k to n-1 draw t
 // on {0 .. j} and append t, or j when t is already in the sample; the
@@ -123,7 +159,11 @@ template <class E>
 static void launch_discrete_e(bool perm, const FillArgs &f, uint32_t *tab, int tbits, hipStream_t st)
 {
     const dim3 grid((unsigned)((f.n + 255) / 256)), block(256);
-    if (perm) hipLaunchKernelGGL(k_permutations<E>, grid, block, 0, st, f);
+    const dim3 grid64((unsigned)((f.n + 63) / 64));
+    if (perm && f.per_stream <= 512) hipLaunchKernelGGL((k_permutations_lds<E, 512>), grid64, dim3(64), 0, st, f);
+    else if (perm && f.per_stream <= 1024)
+        hipLaunchKernelGGL((k_permutations_lds<E, 1024>), grid64, dim3(64), 0, st, f);
+    else if (perm) hipLaunchKernelGGL(k_permutations<E>, grid, block, 0, st, f);
     else hipLaunchKernelGGL(k_sample<E>, grid, block, 0, st, f, tab, tbits);
 }
 

@@ -30,7 +30,7 @@ def test_permutations_and_samples_match_oracle(engine):
     ost = [oracle_stream(engine, i) for i in range(m)]
     # permutations of several sizes, then samples by both methods; every
     # call continues the substreams
-    for n in (1, 2, 37, 1000):
+    for n in (1, 2, 37, 512, 1000, 1024, 1025):   # rows in LDS up to 1024 entries, in HBM above
         out = torch.empty(m * n, dtype=torch.int32, device="cuda")
         rp.rp_permutations(S, n, out)
         got = out.cpu().numpy().view(np.uint32).reshape(m, n)
