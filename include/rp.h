@@ -174,7 +174,7 @@ enum { RP_FLAG_52BIT = 1 }; /* uniform method 2 (mantissa fill, 52/23 bits) */
  * (exponential) bits; candidate and tests are the binary64 ziggurat's for
  * the magnitude m 2^29 (same tables); wedge and tail uniforms are 24-bit
  * uniforms of the following items; the value is rounded once to binary32.
- * rp_fill_serial has no float form of these two samplers. */
+ * rp_fill_serial gives the same float draws for one stream. */
 int rp_fill(rp_streams *s, int dist, int dtype, uint64_t bound, int flags, void *d_out,
             uint64_t per_stream, void *hip_stream);
 

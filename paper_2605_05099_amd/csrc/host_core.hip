@@ -1581,7 +1581,7 @@ extern "C" int rp_fill_serial(rp_rng *rng, int dist, int dtype, uint64_t bound, 
     case RP_U01: ok = dtype == RP_F64 || dtype == RP_F32; break;
     case RP_BOUNDED: ok = dtype == RP_U64 || (dtype == RP_U32 && bound <= 0xFFFFFFFFull); break;
     case RP_NORM:
-    case RP_EXP: ok = dtype == RP_F64; break;
+    case RP_EXP: ok = dtype == RP_F64 || dtype == RP_F32; break;
     default: return fail(RP_EINVAL, "rp_fill_serial: unknown distribution %d", dist);
     }
     if (!ok) return fail(RP_EUNSUPPORTED, "rp_fill_serial: distribution %d has no dtype %d form", dist, dtype);

@@ -272,7 +272,8 @@ __global__ __launch_bounds__(256) void k_ser_gen(SerialArgs a)
 // ---------------------------------------------------------------------------
 // One attempt starting at unit P: its length in units, whether it yields a
 // sample, and the sample.  The decisions are those of the serial ziggurat
-// (zig_serial) and of Lemire's method.
+// (zig_serial; the float ziggurat on 32-bit items for binary32 output) and
+// of Lemire's method.
 template <int DIST, int OT>
 __device__ __forceinline__ uint32_t ser_attempt(const SerialArgs &a, const ZigLds *zt, uint64_t P, bool &acc,
                                                 typename OutType<DIST, OT>::T &val)
@@ -283,8 +284,12 @@ __device__ __forceinline__ uint32_t ser_attempt(const SerialArgs &a, const ZigLd
         acc = item_value<DIST, OT>(it, a.fa, val);
         return 1;
     } else {
-        const uint64_t *wb = a.wbuf + P;
-        const uint64_t w = wb[0];
+        // unit q: a word, or (float draws) the 32-bit item q of the word stream
+        auto unit = [&](uint64_t q) -> uint64_t {
+            if constexpr (HALF) return (a.wbuf[q >> 1] >> (32 * (q & 1))) & 0xffffffffull;
+            else return a.wbuf[q];
+        };
+        const uint64_t w = HALF ? item_word<DIST>(unit(P)) : unit(P);
         const int j = (int)(w & 0xff);
         if constexpr (DIST == RP_NORM) {
             const uint64_t m = (w >> 9) & ((1ull << 52) - 1);
@@ -293,25 +298,25 @@ __device__ __forceinline__ uint32_t ser_attempt(const SerialArgs &a, const ZigLd
             const double x = (double)m * e.w;
             if (m < e.k) {
                 acc = true;
-                val = neg ? -x : x;
+                val = (typename OutType<DIST, OT>::T)(neg ? -x : x);
                 return 1;
             }
             if (j == 0) {
                 for (int it = 0; it < kMaxTailIters; it++) {
-                    const double e1 = -log1p(-u01_53(wb[1 + 2 * it])) / RP_ZN_R;
-                    const double e2 = -log1p(-u01_53(wb[2 + 2 * it]));
+                    const double e1 = -log1p(-zig_u<HALF>(unit(P + 1 + 2 * it))) / RP_ZN_R;
+                    const double e2 = -log1p(-zig_u<HALF>(unit(P + 2 + 2 * it)));
                     if (e2 + e2 > e1 * e1) {
                         const double t = RP_ZN_R + e1;
                         acc = true;
-                        val = neg ? -t : t;
+                        val = (typename OutType<DIST, OT>::T)(neg ? -t : t);
                         return 1 + 2 * (it + 1);
                     }
                 }
                 acc = false;
                 return 1 + 2 * kMaxTailIters;
             }
-            acc = wedge_accept<DIST>(zt, j, x, wb[1]);
-            val = neg ? -x : x;
+            acc = wedge_accept<DIST, HALF>(zt, j, x, unit(P + 1));
+            val = (typename OutType<DIST, OT>::T)(neg ? -x : x);
             return 2;
         } else {
             const uint64_t m = (w >> 8) & ((1ull << 53) - 1);
@@ -319,16 +324,16 @@ __device__ __forceinline__ uint32_t ser_attempt(const SerialArgs &a, const ZigLd
             const double x = (double)m * e.w;
             if (m < e.k) {
                 acc = true;
-                val = x;
+                val = (typename OutType<DIST, OT>::T)x;
                 return 1;
             }
             if (j == 0) {
                 acc = true;
-                val = RP_ZE_R - log1p(-u01_53(wb[1]));
+                val = (typename OutType<DIST, OT>::T)(RP_ZE_R - log1p(-zig_u<HALF>(unit(P + 1))));
                 return 2;
             }
-            acc = wedge_accept<DIST>(zt, j, x, wb[1]);
-            val = x;
+            acc = wedge_accept<DIST, HALF>(zt, j, x, unit(P + 1));
+            val = (typename OutType<DIST, OT>::T)x;
             return 2;
         }
     }
@@ -592,8 +597,14 @@ int launch_serial_stitch(int engine, int dist, int dtype, const SerialArgs &a, h
     default: return fail(RP_EUNSUPPORTED, "serial fill: engine has no jump");
     }
     switch (dist) {
-    case RP_NORM: ser_stitch_kernels<RP_NORM, RP_F64>(a, st); break;
-    case RP_EXP: ser_stitch_kernels<RP_EXP, RP_F64>(a, st); break;
+    case RP_NORM:
+        if (dtype == RP_F64) ser_stitch_kernels<RP_NORM, RP_F64>(a, st);
+        else ser_stitch_kernels<RP_NORM, RP_F32>(a, st);
+        break;
+    case RP_EXP:
+        if (dtype == RP_F64) ser_stitch_kernels<RP_EXP, RP_F64>(a, st);
+        else ser_stitch_kernels<RP_EXP, RP_F32>(a, st);
+        break;
     case RP_BOUNDED:
         if (dtype == RP_U64) ser_stitch_kernels<RP_BOUNDED, RP_U64>(a, st);
         else ser_stitch_kernels<RP_BOUNDED, RP_U32>(a, st);

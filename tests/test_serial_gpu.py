@@ -29,6 +29,8 @@ CASES = [
     (rp.RP_BOUNDED, rp.RP_U64, 0, 0),
     (rp.RP_NORM, rp.RP_F64, 0, 0),
     (rp.RP_EXP, rp.RP_F64, 0, 0),
+    (rp.RP_NORM, rp.RP_F32, 0, 0),
+    (rp.RP_EXP, rp.RP_F32, 0, 0),
 ]
 
 
@@ -76,12 +78,13 @@ def test_serial_matches_oracle(engine, case):
         _same_state(rng, o)
 
 
-@pytest.mark.parametrize("what", ["raw", "u01", "norm", "exp"])
+@pytest.mark.parametrize("what", ["raw", "u01", "norm", "exp", "normf", "expf"])
 def test_one_stream_workload(what):
     """x256++ from seed 12345, 10^6 values; each output from a fresh stream."""
     n = 10**6
     dist, dtype = {"raw": (rp.RP_RAW, rp.RP_U64), "u01": (rp.RP_U01, rp.RP_F64),
-                   "norm": (rp.RP_NORM, rp.RP_F64), "exp": (rp.RP_EXP, rp.RP_F64)}[what]
+                   "norm": (rp.RP_NORM, rp.RP_F64), "exp": (rp.RP_EXP, rp.RP_F64),
+                   "normf": (rp.RP_NORM, rp.RP_F32), "expf": (rp.RP_EXP, rp.RP_F32)}[what]
     rng = rp.rp_create("x256++").seed(12345)
     got = _gpu(rng, dist, dtype, 0, 0, n)
     o = oracle.Stream.seeded("x256++", 12345)
@@ -93,7 +96,7 @@ def test_serial_errors():
     rng = rp.rp_create("x256++").seed(1)
     t = torch.empty(4, dtype=torch.float64, device="cuda")
     with pytest.raises(rp.RpError) as ei:
-        rp.rp_fill_serial(rng, rp.RP_NORM, rp.RP_F32, 0, 0, t, 4)
+        rp.rp_fill_serial(rng, rp.RP_NORM, rp.RP_U64, 0, 0, t, 4)
     assert ei.value.code == rp.RP_EUNSUPPORTED
     with pytest.raises(rp.RpError) as ei:
         rp.rp_fill_serial(rng, rp.RP_RAW, rp.RP_U64, 0, 0, 0, 4)
