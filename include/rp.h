@@ -161,6 +161,21 @@ enum {
 enum { RP_U64 = 0, RP_U32 = 1, RP_F64 = 2, RP_F32 = 3 };
 enum { RP_FLAG_52BIT = 1 }; /* uniform method 2 (mantissa fill, 52/23 bits) */
 
+/* Full-mantissa setting of a stream (Section 3.1, uniform distribution: the
+ * switch between the two conversions).  on = 1 (the default of a new
+ * stream) keeps method 1, x = (u >> 11) 2^-53 (binary32: 24 bits of a
+ * 32-bit half); on = 0 selects method 2 for every U(0,1) fill from this
+ * stream (rp_fill_serial) and from substream sets created from it
+ * afterwards (rp_streams_create copies the setting; a set keeps it for
+ * life), exactly as if RP_FLAG_52BIT were passed.  RP_FLAG_52BIT in a call
+ * still selects method 2 when the setting is on.  Only RP_U01 fills read
+ * it: the laws, samplers and ziggurat keep their own uniforms.  The setting
+ * is copied by rp_duplicate, is not part of rp_serialize's state, and
+ * survives rp_seed / rp_randomize.  Errors: RP_ENULL, RP_EINVAL for on not
+ * 0 or 1.  rp_get_full_mantissa returns 1 or 0 (or RP_ENULL). */
+int rp_set_full_mantissa(rp_rng *rng, int on);
+int rp_get_full_mantissa(const rp_rng *rng);
+
 /* Fills d_out[i * per_stream + t] (substream-major) with the next per_stream
  * values of substream i, for every substream, and advances each substream
  * past the words it used, so a second call continues the streams.  32-bit

@@ -53,6 +53,8 @@ _SIGS = {
     "rp_sfc64_set_abc": ([_vp, _u64, _u64, _u64], _int),
     "rp_squares_set_key": ([_vp, _u64], _int),
     "rp_randomize": ([_vp], _int),
+    "rp_set_full_mantissa": ([_vp, _int], _int),
+    "rp_get_full_mantissa": ([_vp], _int),
     "rp_chacha20_set_nonce": ([_vp, _u64, _u64], _int),
     "rp_serialize": ([_vp, _vp, _sz, _vp], _int),
     "rp_deserialize": ([_vp, _vp, _sz], _int),
@@ -352,6 +354,14 @@ class Rng:
     def randomize(self):
         _check(lib().rp_randomize(self.h), self.h)
         return self
+
+    @property
+    def full_mantissa(self):
+        return bool(_check(lib().rp_get_full_mantissa(self.h), self.h))
+
+    @full_mantissa.setter
+    def full_mantissa(self, on):
+        _check(lib().rp_set_full_mantissa(self.h, int(bool(on))), self.h)
 
     def squares_set_key(self, key):
         _check(lib().rp_squares_set_key(self.h, key), self.h)

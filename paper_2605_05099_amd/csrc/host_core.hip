@@ -737,6 +737,20 @@ extern "C" rp_rng *rp_duplicate(const rp_rng *rng)
     return r;
 }
 
+extern "C" int rp_set_full_mantissa(rp_rng *rng, int on)
+{
+    if (!rng) return fail(RP_ENULL, "rp_set_full_mantissa: NULL rng");
+    if (on != 0 && on != 1) return fail(RP_EINVAL, "rp_set_full_mantissa: on must be 0 or 1, not %d", on);
+    rng->full_mantissa = on == 1;
+    return RP_OK;
+}
+
+extern "C" int rp_get_full_mantissa(const rp_rng *rng)
+{
+    if (!rng) return fail(RP_ENULL, "rp_get_full_mantissa: NULL rng");
+    return rng->full_mantissa ? 1 : 0;
+}
+
 extern "C" int rp_seed(rp_rng *rng, uint64_t seed, const uint32_t *spawn_key, size_t n_key)
 {
     if (!rng) return fail(RP_ENULL, "rp_seed: NULL rng");
@@ -1097,6 +1111,7 @@ extern "C" int rp_streams_create(const rp_rng *base, int kind, uint64_t n, int j
     s->engine = e;
     s->n = n;
     s->nwords = nw;
+    s->full_mantissa = base->full_mantissa;
     hipError_t err = hipGetDevice(&s->device);
     if (err != hipSuccess) {
         delete s;
@@ -1192,6 +1207,7 @@ extern "C" int rp_fill(rp_streams *s, int dist, int dtype, uint64_t bound, int f
     }
     if (!ok) return fail(RP_EUNSUPPORTED, "rp_fill: distribution %d has no dtype %d form (or bound too large)", dist, dtype);
     if (flags & ~RP_FLAG_52BIT) return fail(RP_EINVAL, "rp_fill: unknown flags 0x%x", flags);
+    if (!s->full_mantissa) flags |= RP_FLAG_52BIT;
     size_t esz = (dtype == RP_U64 || dtype == RP_F64) ? 8 : 4;
     if ((uintptr_t)d_out % esz) return fail(RP_EINVAL, "rp_fill: output not aligned to %zu bytes", esz);
     if (s->n > UINT64_MAX / per_stream) return fail(RP_EINVAL, "rp_fill: size overflow");
@@ -1586,6 +1602,7 @@ extern "C" int rp_fill_serial(rp_rng *rng, int dist, int dtype, uint64_t bound, 
     }
     if (!ok) return fail(RP_EUNSUPPORTED, "rp_fill_serial: distribution %d has no dtype %d form", dist, dtype);
     if (flags & ~RP_FLAG_52BIT) return fail(RP_EINVAL, "rp_fill_serial: unknown flags 0x%x", flags);
+    if (!rng->full_mantissa) flags |= RP_FLAG_52BIT;
     const bool half = dtype == RP_U32 || dtype == RP_F32;
     if ((uintptr_t)d_out % (half ? 4 : 8)) return fail(RP_EINVAL, "rp_fill_serial: output not aligned");
     if (n > (1ull << 40)) return fail(RP_EINVAL, "rp_fill_serial: n above 2^40");

@@ -16,6 +16,7 @@ struct rp_rng {
     uint64_t seed = 0;      // last seed given to rp_seed (base for substreams)
     std::vector<uint32_t> key;
     std::string err;
+    bool full_mantissa = true;  // U(0,1) by method 1 (53/24 bits); false: method 2 (52/23)
 };
 
 struct rp_streams {
@@ -25,6 +26,7 @@ struct rp_streams {
     uint64_t *d_words = nullptr;  // SoA: word k of substream i at [k * n + i]
     uint32_t *d_phase = nullptr;  // n entries
     int device = 0;
+    bool full_mantissa = true;    // taken from the base stream at creation
 };
 
 namespace rp {

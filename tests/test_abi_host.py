@@ -61,6 +61,24 @@ def test_randomize_gives_valid_distinct_states():
     assert r.get_state()[0] == rp.rp_create("pcg64").seed(99).get_state()[0]
 
 
+def test_full_mantissa_setting():
+    """The stream's U(0,1) resolution switch: on by default, kept across
+    seeding and randomizing, copied by duplicate, 0 or 1 only."""
+    r = rp.rp_create("pcg64")
+    assert r.full_mantissa is True
+    r.full_mantissa = False
+    assert r.full_mantissa is False
+    r.seed(3).randomize()
+    assert r.full_mantissa is False
+    assert r.duplicate().full_mantissa is False
+    r.full_mantissa = True
+    assert r.full_mantissa is True
+    assert rp.lib().rp_set_full_mantissa(r.h, 2) == rp.RP_EINVAL
+    assert r.full_mantissa is True
+    assert rp.lib().rp_set_full_mantissa(None, 0) == rp.RP_ENULL
+    assert rp.lib().rp_get_full_mantissa(None) == rp.RP_ENULL
+
+
 @pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("seed,key", [(42, ()), (12345, ()), (42, (0,)), (42, (7, 8, 9)), (2**64 - 1, (1,))])
 def test_seeding_matches_oracle(engine, seed, key):

@@ -15,7 +15,7 @@ import pytest
 import oracle
 import paper_2605_05099_amd as rp
 from paper_2605_05099_amd import workloads
-from tests.gpu_common import ENGINES, NP_VIEW, TORCH_DTYPE, make_streams, oracle_fill, oracle_stream, ulp_diff
+from tests.gpu_common import ENGINES, FAMILY, NP_VIEW, TORCH_DTYPE, make_streams, oracle_fill, oracle_stream, ulp_diff
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -150,3 +150,28 @@ def test_full_size_substreams_sampled(engine, kind, dist, dtype):
     for r, i in zip(rows, idx):
         ref = oracle_fill(oracle_stream(engine, i), dist, dtype, per)
         _compare(r, ref, dist)
+
+
+@pytest.mark.parametrize("engine", ["philox4x32", "pcg64", "x256++", "sfc64"])
+@pytest.mark.parametrize("dtype", [rp.RP_F64, rp.RP_F32])
+def test_full_mantissa_off_selects_method_2(engine, dtype):
+    """A stream with the full-mantissa setting off gives method-2 uniforms
+    (as RP_FLAG_52BIT does) from its substream sets, which keep the setting
+    they were created with, and from the one-stream split."""
+    kind, _ = FAMILY[engine]
+    base = rp.rp_create(engine).seed(42)
+    base.full_mantissa = False
+    S = rp.rp_streams_create(base, kind, 300, 64)
+    base.full_mantissa = True
+    got = _gpu_fill(S, rp.RP_U01, dtype, 777, 0, 0)
+    for i in (0, 1, 150, 299):
+        ref = oracle_fill(oracle_stream(engine, i), rp.RP_U01, dtype, 777, 0, rp.RP_FLAG_52BIT)
+        assert np.array_equal(got[i], ref)
+    rng = rp.rp_create(engine).seed(7)
+    rng.full_mantissa = False
+    o = oracle.Stream.seeded(engine, 7)
+    t = torch.empty(40001, dtype=getattr(torch, TORCH_DTYPE[dtype]), device="cuda")
+    rp.rp_fill_serial(rng, rp.RP_U01, dtype, 0, 0, t, 40001)
+    torch.cuda.synchronize()
+    ref = oracle_fill(o, rp.RP_U01, dtype, 40001, 0, rp.RP_FLAG_52BIT)
+    assert np.array_equal(t.cpu().numpy().view(NP_VIEW[dtype]), ref)
