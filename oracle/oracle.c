@@ -26,7 +26,7 @@
  *   squares64 output function              parity unpinned (no external implementation here)
  *   xoroshiro128++, xorshift128+ cores     pinned: primitive characteristic polynomials (period 2^128-1)
  *   their output scramblers                parity unpinned (no external implementation here)
- *   chacha20 block function                parity unpinned (the published test vector is not here)
+ *   chacha20 block function                pinned: RFC 8439 quarter-round and block examples
  *   ranlux++                               pinned: modulus/multiplier/period, big-integer arithmetic
  *   seeding mixer (seed_seq_fe128)         pinned: NumPy SeedSequence
  *   u01 / u01f / bounded ints              pinned: NumPy Generator
