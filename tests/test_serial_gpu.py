@@ -136,3 +136,18 @@ def test_serial_wavefront_runs_ragged(dist, dtype):
     assert np.array_equal(got, ref)
     del got, ref
     _same_state(rng, o)
+
+
+@pytest.mark.parametrize("engine", ["x256++", "philox4x32"])
+def test_serial_float_ziggurat_many_lanes(engine):
+    """2^24 binary32 normals, then 2^24 binary32 exponentials, from one
+    stream split over lanes: about 2^15 stitched chunks of 32-bit items."""
+    rng = rp.rp_create(engine).seed(11)
+    o = oracle.Stream.seeded(engine, 11)
+    m = 2**24
+    got = _gpu(rng, rp.RP_NORM, rp.RP_F32, 0, 0, m)
+    _compare(got, o.normf(m), rp.RP_NORM)
+    _same_state(rng, o)
+    got = _gpu(rng, rp.RP_EXP, rp.RP_F32, 0, 0, m)
+    _compare(got, o.expf(m), rp.RP_EXP)
+    _same_state(rng, o)
