@@ -185,7 +185,8 @@ def part_serial(torch, rp, workloads, tm, sp):
     buf = torch.empty(n, dtype=torch.float64, device="cuda")
     ser = {}
     for name, dist, dtype in (("raw_u64", rp.RP_RAW, rp.RP_U64), ("u01_f64", rp.RP_U01, rp.RP_F64),
-                              ("normal_f64", rp.RP_NORM, rp.RP_F64), ("exp_f64", rp.RP_EXP, rp.RP_F64)):
+                              ("normal_f64", rp.RP_NORM, rp.RP_F64), ("exp_f64", rp.RP_EXP, rp.RP_F64),
+                              ("normal_f32", rp.RP_NORM, rp.RP_F32), ("exp_f32", rp.RP_EXP, rp.RP_F32)):
         rng = rp.rp_create("x256++").seed(workloads.SERIAL_SEED)
         ms = tm(lambda: rp.rp_fill_serial(rng, dist, dtype, 0, 0, buf, n, sp), reps=5)
         ser[name] = {"ms": round(ms, 4), "gsamples_s": round(n / ms / 1e6, 3)}
