@@ -148,6 +148,17 @@ int rp_streams_get(const rp_streams *s, uint64_t *words, uint32_t *phase);
 int rp_streams_set(rp_streams *s, const uint64_t *words, const uint32_t *phase);
 /* New handle holding a device copy of the current states. */
 int rp_streams_duplicate(const rp_streams *s, rp_streams **out);
+/* Checkpointing of a substream set (Section 4.4, serialization, for the
+ * device-resident states): an opaque byte image of the engine, the
+ * full-mantissa setting and every substream's state and phase, host memory
+ * of *needed bytes (24 + 8 state_words n + 4 n).  With buf == NULL only
+ * *needed is set; len below it is RP_EINVAL.  Waits for the device.
+ * rp_streams_deserialize builds a new set on the current device from such
+ * an image; fills from it continue exactly where the serialized set stood.
+ * Errors: RP_ENULL, RP_EINVAL for an image that is not one (magic, engine,
+ * word count, setting, n, phases, length), RP_EDEVICE. */
+int rp_streams_serialize(const rp_streams *s, void *buf, size_t len, size_t *needed);
+int rp_streams_deserialize(const void *buf, size_t len, rp_streams **out);
 
 /* ---- bulk fills (Tables 4 and 5, Section 3) ------------------------------ */
 enum {

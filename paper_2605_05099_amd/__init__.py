@@ -66,6 +66,8 @@ _SIGS = {
     "rp_streams_get": ([_vp, _vp, _vp], _int),
     "rp_streams_set": ([_vp, _vp, _vp], _int),
     "rp_streams_duplicate": ([_vp, _vp], _int),
+    "rp_streams_serialize": ([_vp, _vp, _sz, _vp], _int),
+    "rp_streams_deserialize": ([_vp, _sz, _vp], _int),
     "rp_fill": ([_vp, _int, _int, _u64, _int, _vp, _u64, _vp], _int),
     "rp_fill_law": ([_vp, _int, _vp, _int, _vp, _u64, _vp], _int),
     "rp_fill_lawf": ([_vp, _int, _vp, _int, _vp, _u64, _vp], _int),
@@ -162,6 +164,12 @@ def rp_create(engine="x256++"):
     if not h:
         raise RpError(RP_EINVAL, rp_errmsg())
     return Rng(h)
+
+
+def rp_streams_deserialize(image):
+    out = ctypes.c_void_p()
+    _check(lib().rp_streams_deserialize(image, len(image), ctypes.byref(out)))
+    return Streams(out.value)
 
 
 def rp_streams_create(base, kind, n, jump_log2=0):
@@ -432,6 +440,13 @@ class Streams:
         out = ctypes.c_void_p()
         _check(lib().rp_streams_duplicate(self.h, ctypes.byref(out)))
         return Streams(out.value)
+
+    def serialize(self):
+        need = ctypes.c_size_t()
+        _check(lib().rp_streams_serialize(self.h, None, 0, ctypes.byref(need)))
+        buf = ctypes.create_string_buffer(need.value)
+        _check(lib().rp_streams_serialize(self.h, buf, need.value, None))
+        return buf.raw
 
     def fill(self, dist, out, per_stream, bound=0, flags=0, stream=None):
         """Fill a device tensor of n * per_stream elements (dtype decides the form)."""

@@ -1188,6 +1188,75 @@ extern "C" int rp_streams_duplicate(const rp_streams *s, rp_streams **out)
     return RP_OK;
 }
 
+// serialized image of a substream set: magic, engine, state words per
+// substream, full-mantissa setting (4 x u32), n (u64), then the state words
+// (SoA, word k of substream i at k n + i) and the n phases
+static constexpr uint32_t kStreamsMagic = 0x31535052u;  // "RPS1"
+
+extern "C" int rp_streams_serialize(const rp_streams *s, void *buf, size_t len, size_t *needed)
+{
+    if (!s) return fail(RP_ENULL, "rp_streams_serialize: NULL streams");
+    const size_t nw = (size_t)s->nwords * s->n;
+    const size_t need = 24 + nw * 8 + s->n * 4;
+    if (needed) *needed = need;
+    if (!buf) return RP_OK;
+    if (len < need) return fail(RP_EINVAL, "rp_streams_serialize: buffer too small (%zu < %zu)", len, need);
+    std::vector<uint64_t> words(nw);
+    std::vector<uint32_t> phase(s->n);
+    const int rc = rp_streams_get(s, words.data(), phase.data());
+    if (rc) return rc;
+    uint8_t *p = (uint8_t *)buf;
+    const uint32_t hdr[4] = {kStreamsMagic, (uint32_t)s->engine, (uint32_t)s->nwords, s->full_mantissa ? 1u : 0u};
+    memcpy(p, hdr, 16);
+    memcpy(p + 16, &s->n, 8);
+    memcpy(p + 24, words.data(), nw * 8);
+    memcpy(p + 24 + nw * 8, phase.data(), s->n * 4);
+    return RP_OK;
+}
+
+extern "C" int rp_streams_deserialize(const void *buf, size_t len, rp_streams **out)
+{
+    if (!buf || !out) return fail(RP_ENULL, "rp_streams_deserialize: NULL argument");
+    *out = nullptr;
+    if (len < 24) return fail(RP_EINVAL, "rp_streams_deserialize: buffer too small");
+    const uint8_t *p = (const uint8_t *)buf;
+    uint32_t hdr[4];
+    uint64_t n;
+    memcpy(hdr, p, 16);
+    memcpy(&n, p + 16, 8);
+    if (hdr[0] != kStreamsMagic || hdr[1] >= RP_NENGINES || hdr[2] != (uint32_t)kEngines[hdr[1]].words ||
+        hdr[3] > 1 || n == 0 || n > (1ull << 32))
+        return fail(RP_EINVAL, "rp_streams_deserialize: not a serialized substream set");
+    const size_t nw = (size_t)hdr[2] * n;
+    if (len < 24 + nw * 8 + n * 4) return fail(RP_EINVAL, "rp_streams_deserialize: image truncated");
+    std::vector<uint64_t> words(nw);
+    std::vector<uint32_t> phase(n);
+    memcpy(words.data(), p + 24, nw * 8);
+    memcpy(phase.data(), p + 24 + nw * 8, n * 4);
+    for (uint64_t i = 0; i < n; i++)
+        if (phase[i] >= (uint32_t)kEngines[hdr[1]].block)
+            return fail(RP_EINVAL, "rp_streams_deserialize: bad phase of substream %llu", (unsigned long long)i);
+    rp_streams *s = new (std::nothrow) rp_streams;
+    if (!s) return fail(RP_ENOMEM, "rp_streams_deserialize: out of memory");
+    s->engine = (int)hdr[1];
+    s->n = n;
+    s->nwords = (int)hdr[2];
+    s->full_mantissa = hdr[3] == 1;
+    hipError_t e = hipGetDevice(&s->device);
+    if (e == hipSuccess) e = hipMalloc(&s->d_words, nw * 8);
+    if (e == hipSuccess) e = hipMalloc(&s->d_phase, n * 4);
+    if (e == hipSuccess) e = hipMemcpy(s->d_words, words.data(), nw * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->d_phase, phase.data(), n * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(s->d_words);
+        (void)hipFree(s->d_phase);
+        delete s;
+        return hip_fail(e, "rp_streams_deserialize");
+    }
+    *out = s;
+    return RP_OK;
+}
+
 // ---------------------------------------------------------------------------
 // bulk fill dispatch
 extern "C" int rp_fill(rp_streams *s, int dist, int dtype, uint64_t bound, int flags, void *d_out,

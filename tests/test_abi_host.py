@@ -79,6 +79,26 @@ def test_full_mantissa_setting():
     assert rp.lib().rp_get_full_mantissa(None) == rp.RP_ENULL
 
 
+def test_streams_deserialize_rejects_bad_images():
+    """Images that are not a serialized substream set fail before any device
+    work: wrong magic, engine, word count, setting, n, phase or length."""
+    import struct
+    out = ctypes.c_void_p()
+
+    def image(magic=0x31535052, engine=rp.ENGINES["pcg64"], nw=4, fm=1, n=2, words=None, phase=(0, 0)):
+        words = [1] * (nw * n) if words is None else words
+        return (struct.pack("<4IQ", magic, engine, nw, fm, n) + struct.pack(f"<{len(words)}Q", *words)
+                + struct.pack(f"<{len(phase)}I", *phase))
+
+    L = rp.lib()
+    for bad in (image(magic=0), image(engine=len(rp.ENGINES)), image(nw=3), image(fm=2),
+                image(n=0, words=[], phase=()), image(phase=(0, 1)), image()[:-1], image()[:23]):
+        assert L.rp_streams_deserialize(bad, len(bad), ctypes.byref(out)) == rp.RP_EINVAL
+        assert not out.value
+    assert L.rp_streams_deserialize(None, 64, ctypes.byref(out)) == rp.RP_ENULL
+    assert L.rp_streams_serialize(None, None, 0, None) == rp.RP_ENULL
+
+
 @pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("seed,key", [(42, ()), (12345, ()), (42, (0,)), (42, (7, 8, 9)), (2**64 - 1, (1,))])
 def test_seeding_matches_oracle(engine, seed, key):

@@ -175,3 +175,31 @@ def test_full_mantissa_off_selects_method_2(engine, dtype):
     torch.cuda.synchronize()
     ref = oracle_fill(o, rp.RP_U01, dtype, 40001, 0, rp.RP_FLAG_52BIT)
     assert np.array_equal(t.cpu().numpy().view(NP_VIEW[dtype]), ref)
+
+
+@pytest.mark.parametrize("engine", ["philox4x32", "pcg64", "ranlux++", "chacha20", "x256++"])
+def test_streams_serialize_resumes_exactly(engine):
+    """A substream set restored from its byte image continues exactly as the
+    original does, partly used blocks and the full-mantissa setting included."""
+    kind, _ = FAMILY[engine]
+    base = rp.rp_create(engine).seed(42)
+    base.full_mantissa = False
+    S = rp.rp_streams_create(base, kind, 1000, 64)
+    _gpu_fill(S, rp.RP_NORM, rp.RP_F64, 333, 0, 0)
+    img = S.serialize()
+    assert len(img) == 24 + 8 * rp.STATE_WORDS[S.engine] * 1000 + 4 * 1000
+    a = _gpu_fill(S, rp.RP_U01, rp.RP_F64, 777, 0, 0)
+    T = rp.rp_streams_deserialize(img)
+    assert T.engine == S.engine and len(T) == len(S)
+    b = _gpu_fill(T, rp.RP_U01, rp.RP_F64, 777, 0, 0)
+    assert np.array_equal(a, b)
+    ws, ps = S.get()
+    wt, pt = T.get()
+    assert (ws == wt).all() and (ps == pt).all()
+    for i in (0, 999):
+        o = oracle_stream(engine, i)
+        o.norm(333)
+        assert np.array_equal(b[i], oracle_fill(o, rp.RP_U01, rp.RP_F64, 777, 0, rp.RP_FLAG_52BIT))
+    with pytest.raises(rp.RpError) as ei:
+        rp.rp_streams_deserialize(img[:-4])
+    assert ei.value.code == rp.RP_EINVAL
