@@ -34,6 +34,22 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
+# vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one 32-bit (or binary64)
+# lane operation per lane per cycle
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Algorithmic vector-ALU lane operations per value of each fill: engine
+# operations per 64-bit word times words per value, plus the conversion or
+# sampler's own operations (derivation in the design doc, section 6).
+ENGINE_OPS_PER_WORD = {"philox4x32": 30.0, "pcg64": 26.0}
+WORDS_PER_VALUE = {"u64": 1.0, "u01_f32": 0.5, "u01_f64": 1.0, "normal_f64": 1.0220, "exp_f64": 1.0336}
+SAMPLER_OPS_PER_VALUE = {"u64": 0.0, "u01_f32": 3.0, "u01_f64": 4.0, "normal_f64": 11.0, "exp_f64": 11.0}
+
+
+def alu_ops_per_value(fill):
+    eng, out = fill.split("/")
+    return ENGINE_OPS_PER_WORD[eng] * WORDS_PER_VALUE[out] + SAMPLER_OPS_PER_VALUE[out]
+
+
 METRIC = "Gsamples/s per engine x distribution, % HBM-write roofline; gamma grad/s"
 # counter summaries: profiles/pmc_fill_<engine>_<output>.md
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_fill_{}.md")
@@ -93,39 +109,55 @@ def calibrate_copy(steps):
     print(json.dumps({"calibration": "fill 8 GiB write + copy 2 GiB read / 2 GiB write", "steps": steps}))
 
 
-def cpu_baseline(target_cpu_s=12.0):
-    """The oracle on the host cores, on a bounded sample of the step's
-    workload: whole substreams of 2^14 values, both engines, all five fills."""
-    import concurrent.futures as cf
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
+
+def cpu_baseline(t1_s=1.6, tn_s=2.0):
+    """The oracle on the host cores, on a bounded sample of the step's
+    workload: whole substreams of 2^14 values, both engines, all five fills,
+    the substreams continuing from fill to fill as on the GPU.  Threads run
+    inside the C oracle (POSIX threads over contiguous substream ranges);
+    timed once on one thread and once on every core this process may use."""
     import oracle
     from paper_2605_05099_amd import workloads
 
     per = workloads.SUB_PER
+    threads = len(os.sched_getaffinity(0))
     kinds = [("philox4x32", "key"), ("pcg64", "inc")]
-    outs = ["raw", "u01f", "u01", "norm", "exp"]
-
-    def one(task):
-        eng, kind, i, what = task
-        s = oracle.substream(eng, workloads.BASE_SEED, kind, i)
-        t0 = time.perf_counter()
-        getattr(s, what)(per)
-        return time.perf_counter() - t0
-
-    cal = [one((e, k, 0, w)) for e, k in kinds for w in outs]
-    per_round = sum(cal)
-    rounds = max(1, int(target_cpu_s / per_round))
-    threads = min(os.cpu_count() or 1, 16)
-    tasks = [(e, k, i, w) for i in range(1, rounds + 1) for e, k in kinds for w in outs]
-    t0 = time.perf_counter()
-    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
-        list(ex.map(one, tasks))
-    wall = time.perf_counter() - t0
-    n_values = len(tasks) * per
-    return {"value": round(n_values / wall / 1e9, 4), "unit": "Gsamples/s", "cores": threads, "kind": "oracle",
-            "sample": f"{rounds} substreams x 2^14 values for each of the 10 fills ({n_values} values, "
-                      f"{wall:.1f} s wall on {threads} threads; single-substream estimate "
-                      f"{per_round:.3f} s per 10 x 2^14 values)"}
+    # one substream per fill on one thread: seconds per 2^14 values
+    cal = {}
+    for eng, kind in kinds:
+        s = [oracle.substream(eng, workloads.BASE_SEED, kind, 0)]
+        for what in range(5):
+            cal[eng, what] = max(oracle.time_fills(s, what, per, 1), 1e-6)
+    res = {}
+    for label, nthr, budget in (("t1", 1, t1_s), ("tn", threads, tn_s)):
+        values = wall = 0.0
+        subs = 0
+        for eng, kind in kinds:
+            k = max(nthr, int(budget * nthr / max(cal[eng, w] for w in range(5))))
+            k -= k % nthr
+            streams = [oracle.substream(eng, workloads.BASE_SEED, kind, i) for i in range(1, k + 1)]
+            for what in range(5):
+                wall += oracle.time_fills(streams, what, per, nthr)
+                values += k * per
+            subs += k
+        res[label] = {"value": round(values / wall / 1e9, 4), "unit": "Gsamples/s", "threads": nthr,
+                      "values": int(values), "wall_s": round(wall, 2), "substreams": subs}
+    return {"value": res["tn"]["value"], "unit": "Gsamples/s", "cores": threads, "kind": "oracle",
+            "threads": threads, "cpu": cpu_model(), "t1": res["t1"], "tn": res["tn"],
+            "sample": f"the step's ten fills (philox4x32 key = i, pcg64 inc = 2i+1, seed 42; u64, u01 f32, "
+                      f"u01 f64, normal f64, exponential f64) on whole substreams of 2^14 values continuing "
+                      f"from fill to fill: {res['t1']['substreams']} substreams on 1 thread "
+                      f"({res['t1']['wall_s']} s), {res['tn']['substreams']} substreams on {threads} threads "
+                      f"({res['tn']['wall_s']} s wall); threads inside the C oracle"}
 
 
 class Timer:
@@ -482,10 +514,15 @@ def main():
         ms = per_kernel[name]
         rows[name] = {"ms": round(ms, 4), "gsamples_s": round(total / ms / 1e6, 2),
                       "write_gb_s": round(total * nbytes / ms / 1e6, 1),
-                      "hbm_frac": round(total * nbytes / ms / 1e6 / HBM_PEAK_GBS, 4)}
+                      "hbm_frac": round(total * nbytes / ms / 1e6 / HBM_PEAK_GBS, 4),
+                      "alu_frac": round(total * alu_ops_per_value(name) / ms / 1e9 / ALU_PEAK_TOPS, 4)}
     dom = max(fills, key=lambda f: per_kernel[f[0]])
     dom_ms = per_kernel[dom[0]]
     achieved = total * dom[4] / dom_ms / 1e6
+    ops = alu_ops_per_value(dom[0])
+    alu_achieved = total * ops / dom_ms / 1e9  # Top/s
+    # the binding roofline is the lower of the two ceilings on values per second
+    alu_binds = ALU_PEAK_TOPS * 1e12 / ops < HBM_PEAK_GBS * 1e9 / dom[4]
     traffic = measured_traffic(dom[0])
     samples_step = total * len(fills)
     del buf
@@ -506,9 +543,15 @@ def main():
                                "seed 42, 2^16 substreams x 2^14 values; u64, u01 f32, u01 f64, normal f64, "
                                "exponential f64 (10 fills of 2^30 values per step)",
                    "substreams": n, "per_substream": per, "fills": [f[0] for f in fills]},
-        "roofline": {"bound": "hbm", "kernel": dom[0], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "roofline": {"bound": "alu" if alu_binds else "hbm", "kernel": dom[0],
+                     "achieved": round(alu_achieved, 3) if alu_binds else round(achieved, 1),
+                     "peak": round(ALU_PEAK_TOPS, 2) if alu_binds else HBM_PEAK_GBS,
+                     "unit": "Top/s" if alu_binds else "GB/s",
+                     "frac": round(alu_achieved / ALU_PEAK_TOPS if alu_binds else achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
+                     "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "alu_frac": round(alu_achieved / ALU_PEAK_TOPS, 4),
+                     "alu_ops_per_value": round(ops, 2),
                      "algorithmic_bytes_per_launch": total * dom[4], "avg_launch_ms": round(dom_ms, 4)},
         "rows": rows,
     }

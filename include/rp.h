@@ -102,10 +102,19 @@ int rp_state_words(const rp_rng *rng);
 /* Exact state get/set (Section 2.3 "set_state").  words has
  * rp_state_words() entries in Table 3 order; phase is the number of 64-bit
  * words already used from the current output block (always 0 except for
- * philox4x32 (< 2), philox (< 4) and ranlux++ (< 9)). */
+ * philox4x32 (< 2), philox (< 4) and ranlux++ (< 9)).  rp_set_state (and
+ * rp_deserialize, rp_streams_set, rp_streams_deserialize) reject with
+ * RP_EINVAL the states that seeding never produces because they are not
+ * proper states of the engine: the all-zero state of xoshiro256,
+ * xoroshiro128++ and xorshift128+ (a fixed point), an even PCG64 increment,
+ * an even squares64 key, and a ranlux++ value outside [1, m). */
 int rp_get_state(const rp_rng *rng, uint64_t *words, size_t n, uint32_t *phase);
 int rp_set_state(rp_rng *rng, const uint64_t *words, size_t n, uint32_t phase);
-/* Jump by 2^k engine steps, k in {32, 64, 96, 128, 192} (Section 2.3). */
+/* Jump by 2^k engine steps, k in {32, 64, 96, 128, 192} (Section 2.3).
+ * RP_EINVAL when 2^k is not below the period of one stream (squares64:
+ * k >= 64; ChaCha20: every k, its block counter has 32 bits; pcg64,
+ * philox4x32, xoroshiro128++, xorshift128+: k >= 128); RP_EUNSUPPORTED for
+ * sfc64, which has no jump. */
 int rp_jump(rp_rng *rng, int k);
 /* Advance by n = lo + hi 2^64 engine steps (a block for block engines):
  * PCG64 affine powering, Philox and squares64 counter addition (squares64:
@@ -131,13 +140,17 @@ enum {
     RP_SUB_KEY = 0,   /* philox*: substream i has key i (k1 = 0)             */
     RP_SUB_INC = 1,   /* pcg64: substream i has increment 2 i + 1            */
     RP_SUB_SPAWN = 2, /* any engine: seeded with (seed, spawn key [i])       */
-    RP_SUB_JUMP = 3   /* x256++, pcg64, ranlux++, philox*: base advanced by  */
+    RP_SUB_JUMP = 3   /* every engine but sfc64: base advanced by           */
                       /*   i * 2^jump_log2 engine steps                      */
 };
 /* Builds n substreams from `base` (its seed is remembered by rp_seed) and
  * copies them to device memory owned by the returned handle.  The state
  * layout in device memory is structure-of-arrays: state word k of substream
- * i at words[k * n + i], phase[i] separately. */
+ * i at words[k * n + i], phase[i] separately.  RP_SUB_JUMP takes jump_log2
+ * from 0 up to (not including) the bound rp_jump applies: 256 for x256++,
+ * x256**, philox and ranlux++, 128 for pcg64, philox4x32, xoro++ and x128+,
+ * 64 for squares and 32 for chacha20 (RP_EINVAL otherwise; RP_EUNSUPPORTED
+ * for sfc64), so distinct substreams always start at distinct states. */
 int rp_streams_create(const rp_rng *base, int kind, uint64_t n, int jump_log2, rp_streams **out);
 void rp_streams_free(rp_streams *s);
 uint64_t rp_streams_count(const rp_streams *s);
@@ -186,6 +199,29 @@ enum { RP_FLAG_52BIT = 1 }; /* uniform method 2 (mantissa fill, 52/23 bits) */
  * 0 or 1.  rp_get_full_mantissa returns 1 or 0 (or RP_ENULL). */
 int rp_set_full_mantissa(rp_rng *rng, int on);
 int rp_get_full_mantissa(const rp_rng *rng);
+
+/* Settings of a stream (rp_set_flag) or of a substream set
+ * (rp_streams_set_flag), value 0 or 1.  A set takes its stream's settings
+ * when it is created (rp_streams_create) and keeps them in its image
+ * (rp_streams_serialize); rp_duplicate and rp_streams_duplicate copy them.
+ *   RP_FULL_MANTISSA  the full-mantissa setting above (default 1).
+ *   RP_SQUEEZE        the ziggurat's squeeze (Section 3.1: the secant and
+ *                     tangent bands of each strip decide most wedge tests
+ *                     without evaluating f(x)); default 1.  The bands carry
+ *                     margins far above the rounding of the secant and of
+ *                     exp, so the decisions, and therefore every value and
+ *                     every state, are bit-identical with the squeeze on or
+ *                     off; off evaluates f(x) for every wedge test.  Read by
+ *                     every sampler built on the ziggurat (normal,
+ *                     exponential, the laws, gamma, beta, moments, rows of
+ *                     the multivariate normal, the one-stream split).
+ * rp_get_flag / rp_streams_get_flag return 1 or 0.  Errors: RP_ENULL;
+ * RP_EINVAL for an unknown setting or a value other than 0 and 1. */
+enum { RP_FULL_MANTISSA = 1, RP_SQUEEZE = 2 };
+int rp_set_flag(rp_rng *rng, int flag, int value);
+int rp_get_flag(const rp_rng *rng, int flag);
+int rp_streams_set_flag(rp_streams *s, int flag, int value);
+int rp_streams_get_flag(const rp_streams *s, int flag);
 
 /* Fills d_out[i * per_stream + t] (substream-major) with the next per_stream
  * values of substream i, for every substream, and advances each substream

@@ -74,6 +74,7 @@ def lib():
             "or_philox_constants": ([vp], None),
             "or_ranlux_constants": ([vp, vp, vp], None),
             "or_ranlux_mulmod": ([vp, vp, vp], None),
+            "or_time_fills": ([vp, sz, ctypes.c_int, sz, ctypes.c_int], ctypes.c_double),
         }
         for name, (args, res) in sig.items():
             fn = getattr(_lib, name)
@@ -384,3 +385,17 @@ def substream(engine, seed, kind, i, jump_log2=64):
 
 def boost_pow(u, a):
     return lib().or_boost_pow(float(u), float(a))
+
+
+def time_fills(streams, what, per, threads):
+    """Wall seconds for `per` values of fill `what` (0 raw, 1 U(0,1)
+    binary32, 2 U(0,1) binary64, 3 normal, 4 exponential) from each stream,
+    on `threads` POSIX threads inside the C oracle (the streams advance)."""
+    w = lib().or_stream_words()
+    buf = np.concatenate([s.buf for s in streams]).astype(np.uint64)
+    t = lib().or_time_fills(_p(buf), len(streams), int(what), int(per), int(threads))
+    if t < 0:
+        raise RuntimeError("or_time_fills: could not start threads")
+    for k, s in enumerate(streams):
+        s.buf[:] = buf[k * w:(k + 1) * w]
+    return t

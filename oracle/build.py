@@ -21,7 +21,7 @@ def build(force=False):
         if os.path.getmtime(LIB) >= newest:
             return LIB
     tmp = LIB + ".tmp"
-    cmd = ["gcc", *FLAGS, SRC, "-o", tmp, "-lquadmath", "-lm"]
+    cmd = ["gcc", *FLAGS, SRC, "-o", tmp, "-pthread", "-lquadmath", "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB

@@ -1459,3 +1459,78 @@ void or_mvn_z(or_stream *streams, int d, size_t n, float *z)
     for (size_t j = 0; j < n; j++)
         for (int i = 0; i < d; i++) z[j * (size_t)d + (size_t)i] = (float)norm_one(&streams[j], NULL);
 }
+
+/* ---- timing harness for the CPU baseline of the benchmark ---------------
+ * Not part of the method: it runs the plain routines above, unchanged, over
+ * many streams at once so that the benchmark can time the oracle on all host
+ * cores.  Each of `threads` POSIX threads takes a contiguous range of the n
+ * streams (stored back to back) and draws `per` values from each, in place,
+ * into a private buffer.  what: 0 raw 64-bit words, 1 U(0,1) binary32, 2
+ * U(0,1) binary64, 3 standard normal, 4 standard exponential.  Returns the
+ * wall time in seconds (CLOCK_MONOTONIC around thread start and join), or a
+ * negative value if a thread could not be started or a buffer allocated. */
+#include <pthread.h>
+#include <stdlib.h>
+#include <time.h>
+
+typedef struct {
+    or_stream *streams;
+    size_t first, count, per;
+    int what, failed;
+} or_timing_job;
+
+static void *or_timing_worker(void *arg)
+{
+    or_timing_job *j = (or_timing_job *)arg;
+    void *buf = malloc(j->per * 8 + 8);
+    if (!buf) {
+        j->failed = 1;
+        return NULL;
+    }
+    for (size_t i = j->first; i < j->first + j->count; i++) {
+        or_stream *s = &j->streams[i];
+        switch (j->what) {
+        case 0: or_raw64(s, (uint64_t *)buf, j->per); break;
+        case 1: or_u01f(s, (float *)buf, j->per, 1); break;
+        case 2: or_u01(s, (double *)buf, j->per, 1); break;
+        case 3: or_norm(s, (double *)buf, j->per, NULL); break;
+        default: or_exp(s, (double *)buf, j->per, NULL); break;
+        }
+    }
+    free(buf);
+    return NULL;
+}
+
+double or_time_fills(or_stream *streams, size_t n, int what, size_t per, int threads)
+{
+    if (threads < 1) threads = 1;
+    if ((size_t)threads > n) threads = (int)n;
+    or_timing_job *jobs = (or_timing_job *)calloc((size_t)threads, sizeof *jobs);
+    pthread_t *tid = (pthread_t *)calloc((size_t)threads, sizeof *tid);
+    if (!jobs || !tid) {
+        free(jobs);
+        free(tid);
+        return -1.0;
+    }
+    struct timespec t0, t1;
+    clock_gettime(CLOCK_MONOTONIC, &t0);
+    int started = 0, failed = 0;
+    for (int t = 0; t < threads; t++) {
+        const size_t lo = n * (size_t)t / (size_t)threads, hi = n * (size_t)(t + 1) / (size_t)threads;
+        jobs[t] = (or_timing_job){streams, lo, hi - lo, per, what, 0};
+        if (pthread_create(&tid[t], NULL, or_timing_worker, &jobs[t]) != 0) {
+            failed = 1;
+            break;
+        }
+        started++;
+    }
+    for (int t = 0; t < started; t++) {
+        pthread_join(tid[t], NULL);
+        failed |= jobs[t].failed;
+    }
+    clock_gettime(CLOCK_MONOTONIC, &t1);
+    free(jobs);
+    free(tid);
+    if (failed) return -1.0;
+    return (double)(t1.tv_sec - t0.tv_sec) + 1e-9 * (double)(t1.tv_nsec - t0.tv_nsec);
+}

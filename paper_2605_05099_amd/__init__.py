@@ -25,6 +25,7 @@ RP_SUB_KEY, RP_SUB_INC, RP_SUB_SPAWN, RP_SUB_JUMP = range(4)
 RP_RAW, RP_U01, RP_BOUNDED, RP_NORM, RP_EXP = range(5)
 RP_U64, RP_U32, RP_F64, RP_F32 = range(4)
 RP_FLAG_52BIT = 1
+RP_FULL_MANTISSA, RP_SQUEEZE = 1, 2  # settings (rp_set_flag)
 (RP_LAW_UNIF, RP_LAW_NORMAL, RP_LAW_LOGNORMAL, RP_LAW_EXP, RP_LAW_GUMBEL, RP_LAW_PARETO, RP_LAW_GPARETO,
  RP_LAW_WEIBULL, RP_LAW_GAMMA, RP_LAW_BETA, RP_LAW_CHI2, RP_LAW_T, RP_LAW_F, RP_LAW_SKEWNORMAL) = range(1, 15)
 
@@ -55,6 +56,10 @@ _SIGS = {
     "rp_randomize": ([_vp], _int),
     "rp_set_full_mantissa": ([_vp, _int], _int),
     "rp_get_full_mantissa": ([_vp], _int),
+    "rp_set_flag": ([_vp, _int, _int], _int),
+    "rp_get_flag": ([_vp, _int], _int),
+    "rp_streams_set_flag": ([_vp, _int, _int], _int),
+    "rp_streams_get_flag": ([_vp, _int], _int),
     "rp_chacha20_set_nonce": ([_vp, _u64, _u64], _int),
     "rp_serialize": ([_vp, _vp, _sz, _vp], _int),
     "rp_deserialize": ([_vp, _vp, _sz], _int),
@@ -371,6 +376,13 @@ class Rng:
     def full_mantissa(self, on):
         _check(lib().rp_set_full_mantissa(self.h, int(bool(on))), self.h)
 
+    def set_flag(self, flag, value):
+        _check(lib().rp_set_flag(self.h, flag, int(value)), self.h)
+        return self
+
+    def get_flag(self, flag):
+        return bool(_check(lib().rp_get_flag(self.h, flag), self.h))
+
     def squares_set_key(self, key):
         _check(lib().rp_squares_set_key(self.h, key), self.h)
         return self
@@ -440,6 +452,13 @@ class Streams:
         out = ctypes.c_void_p()
         _check(lib().rp_streams_duplicate(self.h, ctypes.byref(out)))
         return Streams(out.value)
+
+    def set_flag(self, flag, value):
+        _check(lib().rp_streams_set_flag(self.h, flag, int(value)))
+        return self
+
+    def get_flag(self, flag):
+        return bool(_check(lib().rp_streams_get_flag(self.h, flag)))
 
     def serialize(self):
         need = ctypes.c_size_t()

@@ -158,18 +158,22 @@ struct ZigLds {
     double DM[256];
 };
 
+// flags: the FillArgs flags of the call.  With the squeeze switched off the
+// bands are infinite, so neither squeeze test decides and every wedge test
+// evaluates f(x) (the decisions, and so the values, are the same).
 template <int DIST>
-__device__ __forceinline__ void load_zig(ZigLds *t)
+__device__ __forceinline__ void load_zig(ZigLds *t, int flags)
 {
     const bool nrm = DIST == RP_NORM;
+    const bool sq = !(flags & kFlagNoSqueeze);
     for (int k = threadIdx.x; k < 256; k += blockDim.x) {
         t->WK[k].w = nrm ? RP_ZN_W[k] : RP_ZE_W[k];
         t->WK[k].k = nrm ? RP_ZN_K[k] : RP_ZE_K[k];
         t->F[k] = nrm ? RP_ZN_F[k] : RP_ZE_F[k];
         t->X[k] = nrm ? RP_ZN_X[k] : RP_ZE_X[k];
         t->S[k] = nrm ? RP_ZN_S[k] : RP_ZE_S[k];
-        t->DP[k] = nrm ? RP_ZN_DP[k] : RP_ZE_DP[k];
-        t->DM[k] = nrm ? RP_ZN_DM[k] : RP_ZE_DM[k];
+        t->DP[k] = sq ? (nrm ? RP_ZN_DP[k] : RP_ZE_DP[k]) : __builtin_huge_val();
+        t->DM[k] = sq ? (nrm ? RP_ZN_DM[k] : RP_ZE_DM[k]) : __builtin_huge_val();
     }
 }
 
@@ -694,8 +698,8 @@ struct ZigG {
 };
 
 template <int DIST, bool HALF, class Word>
-__device__ __forceinline__ int zig_resolve(const WKe *t, uint64_t w0, Word word, int avail, bool &accepted,
-                                           double &val, bool &has_u1, uint64_t &u1)
+__device__ __forceinline__ int zig_resolve(const WKe *t, uint64_t w0, Word word, int avail, bool squeeze,
+                                           bool &accepted, double &val, bool &has_u1, uint64_t &u1)
 {
     const int j = (int)(w0 & 0xff);
     accepted = false;
@@ -714,8 +718,8 @@ __device__ __forceinline__ int zig_resolve(const WKe *t, uint64_t w0, Word word,
             const double fj = G::F(j), fj1 = G::F(j - 1);
             const double y = fj + U * (fj1 - fj);
             const double l = fj1 + G::S(j) * (ax - G::X(j - 1));
-            if (y < l - G::DM(j)) accepted = true;
-            else if (y > l + G::DP(j)) accepted = false;
+            if (squeeze && y < l - G::DM(j)) accepted = true;
+            else if (squeeze && y > l + G::DP(j)) accepted = false;
             else accepted = y < exp_ool(DIST == RP_NORM ? -0.5 * ax * ax : -ax);
         } else {
             val = RP_ZE_R - log1p_ool(-zig_u<HALF>(u));
@@ -1063,7 +1067,7 @@ __global__ __launch_bounds__(256, (DIST == RP_NORM || (DIST == RP_EXP && OT == R
                         w0 = cp ? pend_w : wbuf[wpos(q)];
                         L = zig_resolve<DIST, ZH>(
                             zt, w0, [&](int kk) { return (hu && kk == 1) ? pend_u1 : wbuf[wpos(off + kk)]; },
-                            cp ? CHW + hu : CHW - 1 - q, acc, v, hu_out, u1o);
+                            cp ? CHW + hu : CHW - 1 - q, !(a.flags & kFlagNoSqueeze), acc, v, hu_out, u1o);
                     }
                     int i0 = 0;
                     if (npre && base == 0) {
@@ -1555,7 +1559,7 @@ __global__ __launch_bounds__(256) void k_fill_lane(FillArgs a)
     ZigLds *zt = nullptr;
     if constexpr (ZIG) {
         __shared__ ZigLds zbuf;
-        load_zig<DIST>(&zbuf);
+        load_zig<DIST>(&zbuf, a.flags);
         __syncthreads();
         zt = &zbuf;
     }

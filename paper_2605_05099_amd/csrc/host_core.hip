@@ -751,6 +751,38 @@ extern "C" int rp_get_full_mantissa(const rp_rng *rng)
     return rng->full_mantissa ? 1 : 0;
 }
 
+// Settings of a stream or substream set (RP_FULL_MANTISSA, RP_SQUEEZE).
+static bool *setting_slot(bool *full_mantissa, bool *squeeze, int flag)
+{
+    switch (flag) {
+    case RP_FULL_MANTISSA:
+        return full_mantissa;
+    case RP_SQUEEZE:
+        return squeeze;
+    default:
+        return nullptr;
+    }
+}
+
+extern "C" int rp_set_flag(rp_rng *rng, int flag, int value)
+{
+    if (!rng) return fail(RP_ENULL, "rp_set_flag: NULL rng");
+    bool *slot = setting_slot(&rng->full_mantissa, &rng->squeeze, flag);
+    if (!slot) return fail_rng(rng, RP_EINVAL, "rp_set_flag: unknown setting %d", flag);
+    if (value != 0 && value != 1) return fail_rng(rng, RP_EINVAL, "rp_set_flag: value must be 0 or 1, not %d", value);
+    *slot = value == 1;
+    return RP_OK;
+}
+
+extern "C" int rp_get_flag(const rp_rng *rng, int flag)
+{
+    if (!rng) return fail(RP_ENULL, "rp_get_flag: NULL rng");
+    rp_rng *r = const_cast<rp_rng *>(rng);
+    bool *slot = setting_slot(&r->full_mantissa, &r->squeeze, flag);
+    if (!slot) return fail_rng(rng, RP_EINVAL, "rp_get_flag: unknown setting %d", flag);
+    return *slot ? 1 : 0;
+}
+
 extern "C" int rp_seed(rp_rng *rng, uint64_t seed, const uint32_t *spawn_key, size_t n_key)
 {
     if (!rng) return fail(RP_ENULL, "rp_seed: NULL rng");
@@ -766,6 +798,72 @@ extern "C" int rp_state_words(const rp_rng *rng)
 {
     if (!rng) return fail(RP_ENULL, "rp_state_words: NULL rng");
     return kEngines[rng->engine].words;
+}
+
+// Why the words w (Table 3 order, `stride` apart) are not a state the engine
+// can reach, or nullptr.  The excluded states are those the seeding fix-ups
+// replace: the all-zero state of the xor family (a fixed point that outputs
+// zeros for ever), an even PCG64 increment, an even squares64 key, and a
+// ranlux++ value outside [1, m).
+static const char *state_defect(int e, const uint64_t *w, size_t stride)
+{
+    auto W = [&](int k) { return w[(size_t)k * stride]; };
+    switch (e) {
+    case RP_X256PP:
+    case RP_X256SS:
+        if (!(W(0) | W(1) | W(2) | W(3))) return "the all-zero xoshiro256 state (a fixed point)";
+        break;
+    case RP_XORO128:
+    case RP_XS128:
+        if (!(W(0) | W(1))) return "the all-zero state (a fixed point)";
+        break;
+    case RP_PCG64:
+        if (!(W(2) & 1)) return "an even PCG64 increment";
+        break;
+    case RP_SQUARES:
+        if (!(W(1) & 1)) return "an even squares64 key";
+        break;
+    case RP_RANLUX: {
+        // m = 2^576 - 2^240 + 1: limbs 4..8 all ones, limb 3 bits 48..63, limb 0 = 1
+        static const uint64_t m[9] = {1, 0, 0, 0xFFFF000000000000ull, ~0ull, ~0ull, ~0ull, ~0ull, ~0ull};
+        bool zero = true;
+        for (int k = 0; k < 9; k++) zero = zero && W(k) == 0;
+        if (zero) return "the ranlux++ value 0";
+        for (int k = 8; k >= 0; k--) {
+            if (W(k) < m[k]) return nullptr;
+            if (W(k) > m[k]) return "a ranlux++ value not below m = 2^576 - 2^240 + 1";
+        }
+        return "the ranlux++ value m";
+    }
+    default:
+        break;
+    }
+    return nullptr;
+}
+
+// Exclusive bound on k for jumps by 2^k engine steps: 2^k must stay below the
+// period of one stream (one key, increment or nonce).  0: the engine has no
+// jump (sfc64 is not linear).
+static int jump_limit(int e)
+{
+    switch (e) {
+    case RP_X256PP:
+    case RP_X256SS:
+    case RP_PHILOX:  // 256-bit block counter
+    case RP_RANLUX:  // period about 2^570; exponents up to 2^256 are formed
+        return 256;
+    case RP_PCG64:
+    case RP_PHILOX4X32:  // 128-bit block counter
+    case RP_XORO128:
+    case RP_XS128:
+        return 128;
+    case RP_SQUARES:
+        return 64;
+    case RP_CHACHA20:  // 32-bit block counter per nonce
+        return 32;
+    default:
+        return 0;
+    }
 }
 
 extern "C" int rp_get_state(const rp_rng *rng, uint64_t *words, size_t n, uint32_t *phase)
@@ -785,6 +883,8 @@ extern "C" int rp_set_state(rp_rng *rng, const uint64_t *words, size_t n, uint32
     if (n != (size_t)nw) return fail_rng(rng, RP_EINVAL, "rp_set_state: expected %d words", nw);
     if (phase >= (uint32_t)kEngines[rng->engine].block)
         return fail_rng(rng, RP_EINVAL, "rp_set_state: phase %u out of range", phase);
+    if (const char *why = state_defect(rng->engine, words, 1))
+        return fail_rng(rng, RP_EINVAL, "rp_set_state: %s is not a state of '%s'", why, kEngines[rng->engine].id);
     memset(rng->st, 0, sizeof rng->st);
     memcpy(rng->st, words, n * 8);
     rng->phase = phase;
@@ -853,18 +953,9 @@ extern "C" int rp_advance(rp_rng *rng, uint64_t lo, uint64_t hi)
     return advance_impl(rng, lo, hi);
 }
 
-extern "C" int rp_jump(rp_rng *rng, int k)
+// Advances the stream by 2^k engine steps, 0 <= k < jump_limit(engine).
+static int jump_pow2(rp_rng *rng, int k)
 {
-    if (!rng) return fail(RP_ENULL, "rp_jump: NULL rng");
-    if (k != 32 && k != 64 && k != 96 && k != 128 && k != 192)
-        return fail_rng(rng, RP_EINVAL, "rp_jump: k must be 32, 64, 96, 128 or 192 (got %d)", k);
-    if (rng->engine == RP_CHACHA20)  // 2^32 blocks per nonce: every 2^k, k >= 32, is a full period
-        return fail_rng(rng, RP_EINVAL, "rp_jump: 2^%d is not below the period of 'chacha20' (use the nonce)", k);
-    if (rng->engine == RP_SQUARES && k >= 64)
-        return fail_rng(rng, RP_EINVAL, "rp_jump: 2^%d is not below the period of 'squares'", k);
-    if ((rng->engine == RP_XORO128 || rng->engine == RP_XS128) && k >= 128)
-        return fail_rng(rng, RP_EINVAL, "rp_jump: 2^%d is not below the period of '%s'", k,
-                        kEngines[rng->engine].id);
     if (k < 128) return advance_impl(rng, k < 64 ? (1ull << k) : 0, k >= 64 ? (1ull << (k - 64)) : 0);
     switch (rng->engine) {
     case RP_X256PP:
@@ -894,12 +985,22 @@ extern "C" int rp_jump(rp_rng *rng, int k)
         rl_mulmod(rng->st, An, rng->st);
         return RP_OK;
     }
-    case RP_SFC64:
-        return fail_rng(rng, RP_EUNSUPPORTED, "rp_jump: sfc64 has no jump");
-    default:  // pcg64 period and philox4x32 counter are 2^128
-        return fail_rng(rng, RP_EINVAL, "rp_jump: 2^%d is not below the period of '%s'", k,
-                        kEngines[rng->engine].id);
+    default:
+        return fail_rng(rng, RP_EINVAL, "jump: 2^%d is not below the period of '%s'", k, kEngines[rng->engine].id);
     }
+}
+
+extern "C" int rp_jump(rp_rng *rng, int k)
+{
+    if (!rng) return fail(RP_ENULL, "rp_jump: NULL rng");
+    if (k != 32 && k != 64 && k != 96 && k != 128 && k != 192)
+        return fail_rng(rng, RP_EINVAL, "rp_jump: k must be 32, 64, 96, 128 or 192 (got %d)", k);
+    const int lim = jump_limit(rng->engine);
+    if (lim == 0) return fail_rng(rng, RP_EUNSUPPORTED, "rp_jump: '%s' has no jump", kEngines[rng->engine].id);
+    if (k >= lim)
+        return fail_rng(rng, RP_EINVAL, "rp_jump: 2^%d is not below the period of '%s'%s", k,
+                        kEngines[rng->engine].id, rng->engine == RP_CHACHA20 ? " (use the nonce)" : "");
+    return jump_pow2(rng, k);
 }
 
 extern "C" int rp_pcg64_set_inc(rp_rng *rng, uint64_t lo, uint64_t hi)
@@ -978,9 +1079,15 @@ extern "C" int rp_deserialize(rp_rng *rng, const void *buf, size_t len)
     const uint8_t *p = (const uint8_t *)buf;
     uint32_t hdr[4];
     memcpy(hdr, p, 16);
-    if (hdr[0] != kMagic || hdr[1] >= RP_NENGINES || hdr[2] >= (uint32_t)kEngines[hdr[1]].block ||
+    if (hdr[0] != kMagic || hdr[1] >= RP_NENGINES || hdr[2] >= (uint32_t)kEngines[hdr[1]].block || hdr[3] > 1024 ||
         len < 152 + (size_t)hdr[3] * 4)
         return fail_rng(rng, RP_EINVAL, "rp_deserialize: not a serialized stream");
+    uint64_t st[16];
+    memcpy(st, p + 16, 128);
+    for (int k = kEngines[hdr[1]].words; k < 16; k++)
+        if (st[k]) return fail_rng(rng, RP_EINVAL, "rp_deserialize: not a serialized stream");
+    if (const char *why = state_defect((int)hdr[1], st, 1))
+        return fail_rng(rng, RP_EINVAL, "rp_deserialize: %s is not a state of '%s'", why, kEngines[hdr[1]].id);
     rng->engine = (int)hdr[1];
     rng->phase = hdr[2];
     memcpy(rng->st, p + 16, 128);
@@ -1022,8 +1129,10 @@ extern "C" int rp_streams_create(const rp_rng *base, int kind, uint64_t n, int j
     case RP_SUB_SPAWN:
         break;
     case RP_SUB_JUMP:
-        if (e == RP_SFC64) return fail(RP_EUNSUPPORTED, "sfc64 has no jump");
-        if (jump_log2 < 0 || jump_log2 > 192) return fail(RP_EINVAL, "jump_log2 out of range");
+        if (jump_limit(e) == 0) return fail(RP_EUNSUPPORTED, "'%s' has no jump", kEngines[e].id);
+        if (jump_log2 < 0 || jump_log2 >= jump_limit(e))
+            return fail(RP_EINVAL, "rp_streams_create: jump_log2 %d: 2^k steps must be below the period of '%s' "
+                                   "(k < %d)", jump_log2, kEngines[e].id, jump_limit(e));
         break;
     default:
         return fail(RP_EINVAL, "rp_streams_create: unknown kind %d", kind);
@@ -1032,8 +1141,8 @@ extern "C" int rp_streams_create(const rp_rng *base, int kind, uint64_t n, int j
     std::vector<uint32_t> phase(n, 0);
     rp_rng cur = *base;
     rp_rng jumped = *base;  // JUMP: running state advanced by 2^jump_log2 per substream
-    uint64_t jl = jump_log2 < 64 ? (1ull << jump_log2) : 0;
-    uint64_t jh = (jump_log2 >= 64 && jump_log2 < 128) ? (1ull << (jump_log2 - 64)) : 0;
+    const uint64_t jl = (jump_log2 >= 0 && jump_log2 < 64) ? (1ull << jump_log2) : 0;
+    const uint64_t jh = (jump_log2 >= 64 && jump_log2 < 128) ? (1ull << (jump_log2 - 64)) : 0;
     // precomputed per-step transforms for JUMP
     Poly jpoly;
     uint64_t jmul[9];
@@ -1046,7 +1155,6 @@ extern "C" int rp_streams_create(const rp_rng *base, int kind, uint64_t n, int j
             for (int i = 0; i < jump_log2; i++) base_x = poly_mulmod(base_x, base_x, P);
             jpoly = base_x;
         } else if (e == RP_XORO128 || e == RP_XS128) {
-            if (jump_log2 >= 128) return fail(RP_EINVAL, "%s jump_log2 must be < 128", kEngines[e].id);
             Poly base_x;
             base_x.flip(1);
             const Poly &P = x128_charpoly(e);
@@ -1057,7 +1165,6 @@ extern "C" int rp_streams_create(const rp_rng *base, int kind, uint64_t n, int j
             ex[jump_log2 / 64] = 1ull << (jump_log2 % 64);
             ranlux_pow(ranlux_A(), ex, 4, jmul);
         } else if (e == RP_PCG64) {
-            if (jump_log2 >= 128) return fail(RP_EINVAL, "pcg64 jump_log2 must be < 128");
             jpcg = pcg_power(jl, jh);
         }
     }
@@ -1095,8 +1202,8 @@ extern "C" int rp_streams_create(const rp_rng *base, int kind, uint64_t n, int j
                     s = add128(mul128(jpcg.mult, s), mul128(jpcg.plus, inc));
                     jumped.st[0] = s.lo;
                     jumped.st[1] = s.hi;
-                } else {
-                    int rc = advance_impl(&jumped, jl, jh);
+                } else {  // counters: philox (any k below 256), philox4x32, squares64, chacha20
+                    int rc = jump_pow2(&jumped, jump_log2);
                     if (rc) return rc;
                 }
             }
@@ -1112,6 +1219,7 @@ extern "C" int rp_streams_create(const rp_rng *base, int kind, uint64_t n, int j
     s->n = n;
     s->nwords = nw;
     s->full_mantissa = base->full_mantissa;
+    s->squeeze = base->squeeze;
     hipError_t err = hipGetDevice(&s->device);
     if (err != hipSuccess) {
         delete s;
@@ -1159,12 +1267,35 @@ extern "C" int rp_streams_get(const rp_streams *s, uint64_t *words, uint32_t *ph
 extern "C" int rp_streams_set(rp_streams *s, const uint64_t *words, const uint32_t *phase)
 {
     if (!s || !words || !phase) return fail(RP_ENULL, "rp_streams_set: NULL argument");
-    for (uint64_t i = 0; i < s->n; i++)
+    for (uint64_t i = 0; i < s->n; i++) {
         if (phase[i] >= (uint32_t)kEngines[s->engine].block) return fail(RP_EINVAL, "rp_streams_set: bad phase");
+        if (const char *why = state_defect(s->engine, words + i, s->n))
+            return fail(RP_EINVAL, "rp_streams_set: substream %llu: %s is not a state of '%s'", (unsigned long long)i,
+                        why, kEngines[s->engine].id);
+    }
     hipError_t e = hipDeviceSynchronize();
     if (e == hipSuccess) e = hipMemcpy(s->d_words, words, (size_t)s->nwords * s->n * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(s->d_phase, phase, s->n * 4, hipMemcpyHostToDevice);
     return e == hipSuccess ? RP_OK : hip_fail(e, "rp_streams_set");
+}
+
+extern "C" int rp_streams_set_flag(rp_streams *s, int flag, int value)
+{
+    if (!s) return fail(RP_ENULL, "rp_streams_set_flag: NULL streams");
+    bool *slot = setting_slot(&s->full_mantissa, &s->squeeze, flag);
+    if (!slot) return fail(RP_EINVAL, "rp_streams_set_flag: unknown setting %d", flag);
+    if (value != 0 && value != 1) return fail(RP_EINVAL, "rp_streams_set_flag: value must be 0 or 1, not %d", value);
+    *slot = value == 1;
+    return RP_OK;
+}
+
+extern "C" int rp_streams_get_flag(const rp_streams *s, int flag)
+{
+    if (!s) return fail(RP_ENULL, "rp_streams_get_flag: NULL streams");
+    rp_streams *m = const_cast<rp_streams *>(s);
+    bool *slot = setting_slot(&m->full_mantissa, &m->squeeze, flag);
+    if (!slot) return fail(RP_EINVAL, "rp_streams_get_flag: unknown setting %d", flag);
+    return *slot ? 1 : 0;
 }
 
 extern "C" int rp_streams_duplicate(const rp_streams *s, rp_streams **out)
@@ -1189,8 +1320,9 @@ extern "C" int rp_streams_duplicate(const rp_streams *s, rp_streams **out)
 }
 
 // serialized image of a substream set: magic, engine, state words per
-// substream, full-mantissa setting (4 x u32), n (u64), then the state words
-// (SoA, word k of substream i at k n + i) and the n phases
+// substream, settings (4 x u32; bit 0 the full-mantissa setting, bit 1 the
+// squeeze switched off), n (u64), then the state words (SoA, word k of
+// substream i at k n + i) and the n phases
 static constexpr uint32_t kStreamsMagic = 0x31535052u;  // "RPS1"
 
 extern "C" int rp_streams_serialize(const rp_streams *s, void *buf, size_t len, size_t *needed)
@@ -1206,7 +1338,8 @@ extern "C" int rp_streams_serialize(const rp_streams *s, void *buf, size_t len, 
     const int rc = rp_streams_get(s, words.data(), phase.data());
     if (rc) return rc;
     uint8_t *p = (uint8_t *)buf;
-    const uint32_t hdr[4] = {kStreamsMagic, (uint32_t)s->engine, (uint32_t)s->nwords, s->full_mantissa ? 1u : 0u};
+    const uint32_t hdr[4] = {kStreamsMagic, (uint32_t)s->engine, (uint32_t)s->nwords,
+                             (s->full_mantissa ? 1u : 0u) | (s->squeeze ? 0u : 2u)};
     memcpy(p, hdr, 16);
     memcpy(p + 16, &s->n, 8);
     memcpy(p + 24, words.data(), nw * 8);
@@ -1225,7 +1358,7 @@ extern "C" int rp_streams_deserialize(const void *buf, size_t len, rp_streams **
     memcpy(hdr, p, 16);
     memcpy(&n, p + 16, 8);
     if (hdr[0] != kStreamsMagic || hdr[1] >= RP_NENGINES || hdr[2] != (uint32_t)kEngines[hdr[1]].words ||
-        hdr[3] > 1 || n == 0 || n > (1ull << 32))
+        hdr[3] > 3 || n == 0 || n > (1ull << 32))
         return fail(RP_EINVAL, "rp_streams_deserialize: not a serialized substream set");
     const size_t nw = (size_t)hdr[2] * n;
     if (len < 24 + nw * 8 + n * 4) return fail(RP_EINVAL, "rp_streams_deserialize: image truncated");
@@ -1233,15 +1366,20 @@ extern "C" int rp_streams_deserialize(const void *buf, size_t len, rp_streams **
     std::vector<uint32_t> phase(n);
     memcpy(words.data(), p + 24, nw * 8);
     memcpy(phase.data(), p + 24 + nw * 8, n * 4);
-    for (uint64_t i = 0; i < n; i++)
+    for (uint64_t i = 0; i < n; i++) {
         if (phase[i] >= (uint32_t)kEngines[hdr[1]].block)
             return fail(RP_EINVAL, "rp_streams_deserialize: bad phase of substream %llu", (unsigned long long)i);
+        if (const char *why = state_defect((int)hdr[1], words.data() + i, n))
+            return fail(RP_EINVAL, "rp_streams_deserialize: substream %llu: %s is not a state of '%s'",
+                        (unsigned long long)i, why, kEngines[hdr[1]].id);
+    }
     rp_streams *s = new (std::nothrow) rp_streams;
     if (!s) return fail(RP_ENOMEM, "rp_streams_deserialize: out of memory");
     s->engine = (int)hdr[1];
     s->n = n;
     s->nwords = (int)hdr[2];
-    s->full_mantissa = hdr[3] == 1;
+    s->full_mantissa = (hdr[3] & 1) != 0;
+    s->squeeze = (hdr[3] & 2) == 0;
     hipError_t e = hipGetDevice(&s->device);
     if (e == hipSuccess) e = hipMalloc(&s->d_words, nw * 8);
     if (e == hipSuccess) e = hipMalloc(&s->d_phase, n * 4);
@@ -1294,7 +1432,7 @@ extern "C" int rp_fill(rp_streams *s, int dist, int dtype, uint64_t bound, int f
         if (dtype == RP_U64) a.thresh = (0 - bound) % bound;
         else a.thresh = (uint32_t)(0u - (uint32_t)bound) % (uint32_t)bound;
     }
-    a.flags = flags;
+    a.flags = flags | settings_flags(s);
     return launch_fill(s->engine, dist, dtype, a, (hipStream_t)hip_stream);
 }
 
@@ -1444,6 +1582,7 @@ static int fill_law_impl(rp_streams *s, int law, const double *p, int np, void *
     a.n = s->n;
     a.per_stream = per_stream;
     a.out = d_out;
+    a.flags = settings_flags(s);
     if (law >= RP_LAW_GAMMA) return launch_fill_mix(s->engine, law, f32, a, (hipStream_t)hip_stream);
     return launch_fill_law(s->engine, law, f32, a, (hipStream_t)hip_stream);
 }
@@ -1469,6 +1608,7 @@ static FillArgs state_args(rp_streams *s, uint64_t per_stream)
     a.phase = s->d_phase;
     a.n = s->n;
     a.per_stream = per_stream;
+    a.flags = settings_flags(s);
     return a;
 }
 
@@ -1686,7 +1826,7 @@ extern "C" int rp_fill_serial(rp_rng *rng, int dist, int dtype, uint64_t bound, 
     a.phase = rng->phase;
     a.fa.out = d_out;
     a.fa.bound = bound;
-    a.fa.flags = flags;
+    a.fa.flags = flags | (rng->squeeze ? 0 : kFlagNoSqueeze);
     if (dist == RP_BOUNDED && bound) {
         if (dtype == RP_U64) a.fa.thresh = (0 - bound) % bound;
         else a.fa.thresh = (uint32_t)(0u - (uint32_t)bound) % (uint32_t)bound;

@@ -159,7 +159,7 @@ __global__ __launch_bounds__(256) void k_batched(BatchArgs a)
 {
     __shared__ ZigLds zt;
     __shared__ LogLds lt;
-    load_zig<RP_NORM>(&zt);
+    load_zig<RP_NORM>(&zt, a.f.flags);
     load_logt(&lt);
     __syncthreads();
     const int lane = threadIdx.x & 63;

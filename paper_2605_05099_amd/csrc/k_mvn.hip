@@ -315,6 +315,7 @@ int gen_rows(rp_streams *s, float *z, int d, uint64_t n, bool advance, hipStream
     a.f.words = s->d_words;
     a.f.phase = s->d_phase;
     a.f.n = s->n;
+    a.f.flags = settings_flags(s);
     a.f.per_stream = (uint64_t)d;
     a.count = n;
     a.z = z;

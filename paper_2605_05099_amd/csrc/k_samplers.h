@@ -427,7 +427,7 @@ template <class E>
 __global__ __launch_bounds__(256) void k_norm_moments(SampArgs s)
 {
     __shared__ ZigLds zt;
-    load_zig<RP_NORM>(&zt);
+    load_zig<RP_NORM>(&zt, s.f.flags);
     __syncthreads();
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= s.count) return;
@@ -457,7 +457,7 @@ __global__ __launch_bounds__(256) void k_gamma_elem(SampArgs s)
 {
     __shared__ ZigLds zt;
     __shared__ LogLds lt;
-    load_zig<RP_NORM>(&zt);
+    load_zig<RP_NORM>(&zt, s.f.flags);
     load_logt(&lt);
     __syncthreads();
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -496,7 +496,7 @@ template <class E>
 __global__ __launch_bounds__(256) void k_norm_rows(SampArgs s)
 {
     __shared__ ZigLds zt;
-    load_zig<RP_NORM>(&zt);
+    load_zig<RP_NORM>(&zt, s.f.flags);
     __syncthreads();
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= s.count) return;
@@ -542,7 +542,7 @@ __global__ __launch_bounds__(256) void k_fill_mix(FillArgs f)
 {
     __shared__ ZigLds zt;
     __shared__ LogLds lt;
-    load_zig<RP_NORM>(&zt);
+    load_zig<RP_NORM>(&zt, f.flags);
     load_logt(&lt);
     __syncthreads();
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -615,7 +615,7 @@ __global__ __launch_bounds__(256) void k_fill_gammaf(FillArgs f)
 {
     __shared__ ZigLds zt;
     __shared__ LogLds lt;
-    load_zig<RP_NORM>(&zt);
+    load_zig<RP_NORM>(&zt, f.flags);
     load_logt(&lt);
     __syncthreads();
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;

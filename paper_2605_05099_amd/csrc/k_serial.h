@@ -393,7 +393,7 @@ __global__ __launch_bounds__(ser::kBlk) void k_ser_map(SerialArgs a)
     __shared__ ZigLds zt;
     __shared__ uint16_t lens[ser::kBlk][ser::kS];
     __shared__ SerMap buf[ser::kBlk];
-    if constexpr (ZIG) load_zig<DIST>(&zt);
+    if constexpr (ZIG) load_zig<DIST>(&zt, a.fa.flags);
     __syncthreads();
     const int t = threadIdx.x;
     const uint64_t c = (uint64_t)blockIdx.x * ser::kBlk + t;
@@ -495,7 +495,7 @@ __global__ __launch_bounds__(ser::kBlk) void k_ser_emit(SerialArgs a)
     constexpr bool ZIG = DIST == RP_NORM || DIST == RP_EXP;
     using T = typename OutType<DIST, OT>::T;
     __shared__ ZigLds zt;
-    if constexpr (ZIG) load_zig<DIST>(&zt);
+    if constexpr (ZIG) load_zig<DIST>(&zt, a.fa.flags);
     __syncthreads();
     const uint64_t c = (uint64_t)blockIdx.x * ser::kBlk + threadIdx.x;
     if (c >= a.nchunks) return;

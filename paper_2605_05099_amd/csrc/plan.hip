@@ -29,15 +29,19 @@ struct rp_plan {
     // recorded graph and the arguments it was recorded with
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // every pointer the recorded kernels read or write is part of the key, so
+    // a new set whose state arrays reuse an old address is never served by a
+    // graph that holds the old set's other array
     struct Key {
-        int beta, engine, block, blocks_per_cu, spl;
-        const void *words, *pa, *pb, *count, *out;
+        int beta, engine, device, block, blocks_per_cu, spl;
+        const void *words, *phase, *pa, *pb, *count, *out;
         uint64_t n_sets, n_streams;
         bool operator==(const Key &o) const
         {
-            return beta == o.beta && engine == o.engine && block == o.block && blocks_per_cu == o.blocks_per_cu &&
-                   spl == o.spl && words == o.words && pa == o.pa && pb == o.pb && count == o.count && out == o.out &&
-                   n_sets == o.n_sets && n_streams == o.n_streams;
+            return beta == o.beta && engine == o.engine && device == o.device && block == o.block &&
+                   blocks_per_cu == o.blocks_per_cu && spl == o.spl && words == o.words && phase == o.phase &&
+                   pa == o.pa && pb == o.pb && count == o.count && out == o.out && n_sets == o.n_sets &&
+                   n_streams == o.n_streams;
         }
     } key{};
     bool have_key = false;
@@ -99,6 +103,7 @@ BatchArgs make_args(rp_plan *p, rp_streams *s, const double *pa, const double *p
     a.f.words = s->d_words;
     a.f.phase = s->d_phase;
     a.f.n = s->n;
+    a.f.flags = settings_flags(s);
     a.pa = pa;
     a.pb = pb;
     a.count = count;
@@ -160,8 +165,8 @@ int run_batched(const char *who, rp_streams *s, const double *pa, const double *
     if (rc) return rc;
     rc = ensure_scratch(p, n_sets);
     if (rc) return rc;
-    rp_plan::Key k{beta ? 1 : 0, s->engine, p->block, p->blocks_per_cu, p->spl,
-                   s->d_words, pa, pb, count, out, n_sets, s->n};
+    rp_plan::Key k{beta ? 1 : 0, s->engine, s->device, p->block, p->blocks_per_cu, p->spl,
+                   s->d_words, s->d_phase, pa, pb, count, out, n_sets, s->n};
     if (!p->have_key || !(k == p->key)) {
         rc = record(p, s, make_args(p, s, pa, pb, count, n_sets, out, p->spl), beta);
         if (rc) return rc;

@@ -17,6 +17,7 @@ struct rp_rng {
     std::vector<uint32_t> key;
     std::string err;
     bool full_mantissa = true;  // U(0,1) by method 1 (53/24 bits); false: method 2 (52/23)
+    bool squeeze = true;        // ziggurat wedge tests decided by the squeeze where it can
 };
 
 struct rp_streams {
@@ -27,6 +28,7 @@ struct rp_streams {
     uint32_t *d_phase = nullptr;  // n entries
     int device = 0;
     bool full_mantissa = true;    // taken from the base stream at creation
+    bool squeeze = true;          // taken from the base stream at creation
 };
 
 namespace rp {
@@ -49,6 +51,12 @@ struct PcgAffine {
 
 // device-side constant tables (uploaded once per device)
 int ensure_device_tables();
+
+// internal bits of FillArgs::flags (above the public per-call flags)
+constexpr int kFlagNoSqueeze = 1 << 16;  // wedge tests evaluate f(x) every time
+
+// the FillArgs flag bits a substream set's settings imply
+inline int settings_flags(const rp_streams *s) { return s->squeeze ? 0 : kFlagNoSqueeze; }
 
 // ---- kernel launchers (fill.hip) -------------------------------------------
 struct FillArgs {

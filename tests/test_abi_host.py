@@ -81,7 +81,7 @@ def test_full_mantissa_setting():
 
 def test_streams_deserialize_rejects_bad_images():
     """Images that are not a serialized substream set fail before any device
-    work: wrong magic, engine, word count, setting, n, phase or length."""
+    work: wrong magic, engine, word count, settings, n, phase or length."""
     import struct
     out = ctypes.c_void_p()
 
@@ -91,7 +91,7 @@ def test_streams_deserialize_rejects_bad_images():
                 + struct.pack(f"<{len(phase)}I", *phase))
 
     L = rp.lib()
-    for bad in (image(magic=0), image(engine=len(rp.ENGINES)), image(nw=3), image(fm=2),
+    for bad in (image(magic=0), image(engine=len(rp.ENGINES)), image(nw=3), image(fm=4),
                 image(n=0, words=[], phase=()), image(phase=(0, 1)), image()[:-1], image()[:23]):
         assert L.rp_streams_deserialize(bad, len(bad), ctypes.byref(out)) == rp.RP_EINVAL
         assert not out.value
@@ -243,3 +243,105 @@ def test_ranlux_long_host_draw_matches_oracle():
     r = rp.rp_create("ranlux++").seed(2024)
     o = oracle.Stream.seeded("ranlux++", 2024)
     assert (r.raw_host(9 * 3000 + 5) == o.raw(9 * 3000 + 5)).all()
+
+
+ALL_ENGINES = list(rp.ENGINES)
+# exclusive bound on k for jumps by 2^k steps (the period of one stream)
+JUMP_LIMIT = {"x256++": 256, "x256**": 256, "philox": 256, "ranlux++": 256, "pcg64": 128, "philox4x32": 128,
+              "xoro++": 128, "x128+": 128, "squares": 64, "chacha20": 32, "sfc64": 0}
+
+
+@pytest.mark.parametrize("engine", ALL_ENGINES)
+def test_jump_bounds_follow_the_period(engine):
+    """rp_jump accepts 2^k only below the period of one stream, and
+    rp_streams_create's JUMP family the same k (checked before any device
+    work), so that no accepted jump can make substreams coincide."""
+    lim = JUMP_LIMIT[engine]
+    for k in (32, 64, 96, 128, 192):
+        r = rp.rp_create(engine).seed(5)
+        if lim == 0:
+            assert rp.lib().rp_jump(r.h, k) == rp.RP_EUNSUPPORTED
+        elif k >= lim:
+            assert rp.lib().rp_jump(r.h, k) == rp.RP_EINVAL
+            assert r.get_state()[0] == rp.rp_create(engine).seed(5).get_state()[0]
+        else:
+            r.jump(k)
+            o = oracle.Stream.seeded(engine, 5).advance(2**k)
+            assert r.get_state()[0] == o.state[:rp.STATE_WORDS[rp.ENGINES[engine]]], k
+            assert r.get_state()[0] != rp.rp_create(engine).seed(5).get_state()[0]
+    base = rp.rp_create(engine).seed(5)
+    out = ctypes.c_void_p()
+    bad = [-1, max(lim, 1), 256, 1000]
+    for k in bad:
+        rc = rp.lib().rp_streams_create(base.h, rp.RP_SUB_JUMP, 4, k, ctypes.byref(out))
+        assert rc == (rp.RP_EUNSUPPORTED if lim == 0 else rp.RP_EINVAL), (engine, k, rc)
+        assert not out.value
+
+
+def test_set_state_rejects_states_seeding_never_makes():
+    cases = [("x256++", [0, 0, 0, 0]), ("x256**", [0, 0, 0, 0]), ("xoro++", [0, 0]), ("x128+", [0, 0]),
+             ("pcg64", [1, 2, 4, 0]), ("squares", [7, 10]), ("ranlux++", _rl_words(0)),
+             ("ranlux++", _rl_words(RL_M)), ("ranlux++", _rl_words(2**576 - 1))]
+    for engine, words in cases:
+        r = rp.rp_create(engine).seed(1)
+        before = r.get_state()
+        w = np.asarray(words, dtype=np.uint64)
+        assert rp.lib().rp_set_state(r.h, w.ctypes.data_as(ctypes.c_void_p), len(w), 0) == rp.RP_EINVAL, engine
+        assert "not a state" in r.last_error()
+        assert r.get_state() == before
+        # the same words in a stream image are refused as well
+        img = bytearray(rp.rp_create(engine).seed(1).serialize())
+        img[16:16 + 8 * len(words)] = w.tobytes()
+        assert rp.lib().rp_deserialize(r.h, bytes(img), len(img)) == rp.RP_EINVAL
+    # the nearest valid states are accepted
+    rp.rp_create("x256++").set_state([0, 0, 0, 1])
+    rp.rp_create("pcg64").set_state([1, 2, 3, 0])
+    rp.rp_create("squares").set_state([7, 11])
+    rp.rp_create("ranlux++").set_state(_rl_words(RL_M - 1))
+
+
+def test_deserialize_rejects_long_keys_and_stray_words():
+    import struct
+    r = rp.rp_create("pcg64").seed(3, (1, 2))
+    img = bytearray(r.serialize())
+    ok = rp.rp_create("pcg64").deserialize(bytes(img))
+    assert ok.get_state() == r.get_state()
+    long_key = bytearray(img)
+    long_key[12:16] = struct.pack("<I", 1025)
+    long_key += b"\0" * (1025 * 4)
+    assert rp.lib().rp_deserialize(ok.h, bytes(long_key), len(long_key)) == rp.RP_EINVAL
+    stray = bytearray(img)
+    stray[16 + 8 * 5: 16 + 8 * 6] = struct.pack("<Q", 9)  # word 5 of a 4-word engine
+    assert rp.lib().rp_deserialize(ok.h, bytes(stray), len(stray)) == rp.RP_EINVAL
+
+
+def test_streams_deserialize_rejects_invalid_states():
+    import struct
+    out = ctypes.c_void_p()
+    for engine, words in (("x256++", [0, 1, 0, 2, 0, 3, 0, 4]), ("pcg64", [1, 1, 2, 2, 3, 2, 0, 0])):
+        img = (struct.pack("<4IQ", 0x31535052, rp.ENGINES[engine], 4, 1, 2) + struct.pack("<8Q", *words)
+               + struct.pack("<2I", 0, 0))
+        # x256++: substream 0 is all zero (words 0, 2, 4, 6 of the SoA image);
+        # pcg64: substream 1 has the even increment 2
+        assert rp.lib().rp_streams_deserialize(img, len(img), ctypes.byref(out)) == rp.RP_EINVAL, engine
+        assert not out.value
+        assert "not a state" in rp.rp_errmsg()
+
+
+def test_settings_flags():
+    """rp_set_flag / rp_get_flag: the full-mantissa setting and the squeeze,
+    both on by default, 0 or 1 only, copied by duplicate, kept by seeding."""
+    r = rp.rp_create("philox4x32")
+    assert r.get_flag(rp.RP_FULL_MANTISSA) and r.get_flag(rp.RP_SQUEEZE)
+    r.set_flag(rp.RP_SQUEEZE, 0).seed(4)
+    assert not r.get_flag(rp.RP_SQUEEZE) and r.get_flag(rp.RP_FULL_MANTISSA)
+    assert not r.duplicate().get_flag(rp.RP_SQUEEZE)
+    r.set_flag(rp.RP_FULL_MANTISSA, 0)
+    assert r.full_mantissa is False
+    L = rp.lib()
+    assert L.rp_set_flag(r.h, 3, 1) == rp.RP_EINVAL
+    assert L.rp_set_flag(r.h, rp.RP_SQUEEZE, 2) == rp.RP_EINVAL
+    assert L.rp_get_flag(r.h, 0) == rp.RP_EINVAL
+    assert L.rp_set_flag(None, rp.RP_SQUEEZE, 1) == rp.RP_ENULL
+    assert L.rp_streams_set_flag(None, rp.RP_SQUEEZE, 1) == rp.RP_ENULL
+    assert L.rp_streams_get_flag(None, rp.RP_SQUEEZE) == rp.RP_ENULL

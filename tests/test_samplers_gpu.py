@@ -1,9 +1,10 @@
 """GPU parity of the lane-per-substream samplers against the oracle (MI355X).
 
-rp_norm_moments: the per-substream sums must equal the oracle's in-order
-binary64 sums of the same normals (only tail values may differ, by an ulp of
-log1p, so the sums agree to a few ulps of the partial sums), and the states
-left behind must equal the oracle's.
+rp_norm_moments: the per-substream sums must equal, bit for bit, the
+in-order binary64 sums of the normals rp_fill returns for the same
+substreams, and the oracle's sums bit for bit on every substream whose
+normals hold no tail value (only tail values may differ, by an ulp of
+log1p); the states left behind must equal the oracle's.
 
 rp_gamma_elem / rp_beta_elem: the Marsaglia-Tsang accept/reject decisions
 must all agree (shown by equal states afterwards).  For shape >= 1 the value
@@ -41,18 +42,59 @@ def _moments(S, per):
     return s.cpu().numpy(), q.cpu().numpy()
 
 
+def _fill_normals(S, per):
+    n = len(S)
+    t = torch.empty(n * per, dtype=torch.float64, device="cuda")
+    rp.rp_fill(S, rp.RP_NORM, rp.RP_F64, 0, 0, t, per)
+    torch.cuda.synchronize()
+    return t.cpu().numpy().reshape(n, per)
+
+
+def _in_order(x):
+    """s = x_0 + x_1 + ... and q = RN(x_0 x_0) + RN(x_1 x_1) + ..., each added
+    in index order in binary64 (cumulative sums run strictly left to right)."""
+    if x.shape[-1] == 0:
+        return 0.0, 0.0
+    return np.cumsum(x)[-1], np.cumsum(x * x)[-1]
+
+
+def _check_moments(engine, S, per, ostreams):
+    """The moments equal, bit for bit, the in-order binary64 sums of the very
+    normals rp_fill returns for the same substreams; those normals equal the
+    oracle's except in the tail (|x| > r, where log1p may differ by an ulp),
+    so the moments of every substream without a tail value equal the
+    oracle's bit for bit.  Tail substreams: the oracle's sums within a few
+    ulps of the partial sums."""
+    D = S.duplicate()
+    s, q = _moments(S, per)
+    x = _fill_normals(D, per)
+    r = 3.6541528853610088
+    exact = 0
+    for i, o in ostreams.items():
+        gs, gq = _in_order(x[i])
+        assert s[i] == gs and q[i] == gq, (engine, per, i, s[i] - gs, q[i] - gq)
+        ox = o.copy().norm(per)
+        rs, rq = o.norm_moments(per)
+        if per and np.abs(ox).max() >= r:
+            assert abs(s[i] - rs) <= 1e-13 * max(1.0, rq), (engine, per, i, s[i], rs)
+            assert abs(q[i] - rq) <= 1e-13 * max(1.0, rq), (engine, per, i, q[i], rq)
+        else:
+            assert s[i] == rs and q[i] == rq, (engine, per, i, s[i] - rs, q[i] - rq)
+            exact += 1
+    return exact
+
+
 @pytest.mark.parametrize("engine", ENGINES)
 def test_norm_moments_matches_oracle(engine):
     n = 67 if engine != "ranlux++" else 37
     S = make_streams(engine, n)
     ostreams = {i: oracle_stream(engine, i) for i in range(n)}
+    exact = 0
     for per in (3000, 1, 0, 257):
-        s, q = _moments(S, per)
-        for i in range(n):
-            rs, rq = ostreams[i].norm_moments(per)
-            assert abs(s[i] - rs) <= 1e-13 * max(1.0, rq), (engine, per, i, s[i], rs)
-            assert abs(q[i] - rq) <= 1e-13 * max(1.0, rq), (engine, per, i, q[i], rq)
+        exact += _check_moments(engine, S, per, ostreams)
         _states_equal(S, engine, ostreams)
+    # most substreams of 1, 257 and 3000 normals have no tail value
+    assert exact >= 2 * n, exact
 
 
 def test_norm_moments_continues_a_fill():
@@ -60,31 +102,45 @@ def test_norm_moments_continues_a_fill():
     S = make_streams("philox4x32", 64)
     t = torch.empty(64 * 5, dtype=torch.float64, device="cuda")
     rp.rp_fill(S, rp.RP_NORM, rp.RP_F64, 0, 0, t, 5)
-    s, q = _moments(S, 100)
+    ostreams = {}
     for i in (0, 17, 63):
         o = oracle_stream("philox4x32", i)
         o.norm(5)
-        rs, rq = o.norm_moments(100)
-        assert abs(s[i] - rs) <= 1e-13 * max(1.0, rq)
-        assert abs(q[i] - rq) <= 1e-13 * max(1.0, rq)
+        ostreams[i] = o
+    _check_moments("philox4x32", S, 100, ostreams)
 
 
 @pytest.mark.parametrize("engine,jump_log2", [("ranlux++", 64), ("sfc64", 0)])
 def test_norm_moments_full_size_sampled(engine, jump_log2):
     """2^18 substreams x 2^16 normals (ranlux++ substreams 2^64 steps apart,
-    sfc64 substreams from spawn keys); sampled substreams checked."""
+    sfc64 substreams from spawn keys); sampled substreams checked against the
+    in-order sums of the same normals and against the oracle."""
     n, per = 2**18, 2**16
     S = make_streams(engine, n, jump_log2=jump_log2)
+    D = S.duplicate()
     s, q = _moments(S, per)
     assert np.isfinite(s).all() and np.isfinite(q).all()
     # sum of squares of 2^16 normals: mean 2^16, sd sqrt(2 * 2^16)
     assert abs(q.mean() / per - 1.0) < 1e-3
     assert abs(s.mean()) < 0.05 * np.sqrt(per)
     idx = workloads.sampled_substreams(n, k=24)
-    for i in idx:
+    # the normals of the sampled substreams, from a copy of their states
+    words, phase = D.get()
+    nw = rp.STATE_WORDS[rp.ENGINES[engine]]
+    sub = rp.rp_streams_create(rp.rp_create(engine).seed(1), make_kind(engine), len(idx), jump_log2)
+    sub.set(words[:, idx].reshape(nw, len(idx)), phase[idx])
+    x = _fill_normals(sub, per)
+    for k, i in enumerate(idx):
+        gs, gq = _in_order(x[k])
+        assert s[i] == gs and q[i] == gq, (engine, i, s[i] - gs, q[i] - gq)
         rs, rq = oracle_stream(engine, i, jump_log2=jump_log2).norm_moments(per)
         assert abs(s[i] - rs) <= 1e-12 * rq, (engine, i)
         assert abs(q[i] - rq) <= 1e-12 * rq, (engine, i)
+
+
+def make_kind(engine):
+    from tests.gpu_common import FAMILY
+    return FAMILY[engine][0]
 
 
 # ---------------------------------------------------------------------------

@@ -1,0 +1,152 @@
+"""GPU checks of the stream settings and substream families (MI355X).
+
+Squeeze (Section 3.1, the ziggurat's secant/tangent squeeze): its bands
+carry margins far above the rounding of the secant and of exp, so every
+sampler built on the ziggurat must return the same bits and leave the same
+states with the squeeze on and off.
+
+Jump families: for every engine with a jump and every accepted jump_log2,
+substream i of rp_streams_create(RP_SUB_JUMP) is the base advanced by
+i 2^jump_log2 steps (the oracle's advance), and no two substreams coincide.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2605_05099_amd as rp
+from tests.gpu_common import FAMILY, make_streams
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+WAVE = ["philox4x32", "pcg64", "philox", "squares", "chacha20"]
+LANE = ["x256++", "sfc64", "ranlux++", "xoro++"]
+
+
+def _pair(engine, n):
+    on = make_streams(engine, n)
+    off = on.duplicate().set_flag(rp.RP_SQUEEZE, 0)
+    assert on.get_flag(rp.RP_SQUEEZE) and not off.get_flag(rp.RP_SQUEEZE)
+    return on, off
+
+
+def _same(a, b, what):
+    assert a.dtype == b.dtype
+    assert np.array_equal(np.asarray(a).view(np.uint8), np.asarray(b).view(np.uint8)), what
+
+
+def _states(S):
+    w, ph = S.get()
+    return w.copy(), ph.copy()
+
+
+@pytest.mark.parametrize("engine", WAVE + LANE)
+def test_squeeze_off_gives_identical_fills(engine):
+    n = 64 if engine != "ranlux++" else 32
+    on, off = _pair(engine, n)
+    for dist, dtype, tdt, per in ((rp.RP_NORM, rp.RP_F64, torch.float64, 3001),
+                                  (rp.RP_EXP, rp.RP_F64, torch.float64, 1500),
+                                  (rp.RP_NORM, rp.RP_F32, torch.float32, 2049),
+                                  (rp.RP_EXP, rp.RP_F32, torch.float32, 777)):
+        a = torch.empty(n * per, dtype=tdt, device="cuda")
+        b = torch.empty(n * per, dtype=tdt, device="cuda")
+        rp.rp_fill(on, dist, dtype, 0, 0, a, per)
+        rp.rp_fill(off, dist, dtype, 0, 0, b, per)
+        torch.cuda.synchronize()
+        _same(a.cpu().numpy(), b.cpu().numpy(), (engine, dist, dtype))
+        wa, pa = _states(on)
+        wb, pb = _states(off)
+        assert np.array_equal(wa, wb) and np.array_equal(pa, pb), (engine, dist, dtype)
+
+
+@pytest.mark.parametrize("engine", ["philox4x32", "x256++"])
+def test_squeeze_off_gives_identical_samplers(engine):
+    """Laws, gamma and beta per element, moments, batched gamma, rows of the
+    multivariate normal: all bit-identical with the squeeze off."""
+    n, per = 64, 513
+    on, off = _pair(engine, n)
+
+    def both(fn, shape, dt):
+        a = torch.empty(shape, dtype=dt, device="cuda")
+        b = torch.empty(shape, dtype=dt, device="cuda")
+        fn(on, a)
+        fn(off, b)
+        torch.cuda.synchronize()
+        return a.cpu().numpy(), b.cpu().numpy()
+
+    for law, p in ((rp.RP_LAW_LOGNORMAL, (0.5, 0.75)), (rp.RP_LAW_GAMMA, (2.5, 1.0)),
+                   (rp.RP_LAW_GAMMA, (0.4, 1.0)), (rp.RP_LAW_BETA, (2.0, 5.0)), (rp.RP_LAW_T, (4.5,)),
+                   (rp.RP_LAW_SKEWNORMAL, (1.0, 2.0, 3.0))):
+        a, b = both(lambda S, t: rp.rp_fill_law(S, law, p, t, per), n * per, torch.float64)
+        _same(a, b, ("law", law, p))
+    a, b = both(lambda S, t: rp.rp_fill_lawf(S, rp.RP_LAW_GAMMA, (1.7, 1.0), t, per), n * per, torch.float32)
+    _same(a, b, "lawf gamma")
+    alpha = torch.tensor(np.geomspace(0.05, 50, n).astype(np.float32), device="cuda")
+    a, b = both(lambda S, t: rp.rp_gamma_elem(S, alpha, t, n), n, torch.float32)
+    _same(a, b, "gamma_elem")
+    a, b = both(lambda S, t: rp.rp_beta_elem(S, alpha, alpha.flip(0).contiguous(), t, n), n, torch.float32)
+    _same(a, b, "beta_elem")
+    s1 = torch.empty(n, dtype=torch.float64, device="cuda")
+    s2 = torch.empty(n, dtype=torch.float64, device="cuda")
+    a, b = both(lambda S, t: (rp.rp_norm_moments(S, per, t, s2)), n, torch.float64)
+    _same(a, b, "moments")
+    if engine == "philox4x32":
+        count = torch.tensor((np.arange(n) * 7) % 50, dtype=torch.int64, device="cuda")
+        al = torch.tensor(np.geomspace(0.01, 100, n), device="cuda")
+        total = int(count.sum())
+        plans = [rp.rp_plan_create(), rp.rp_plan_create()]
+        it = iter(plans)
+        a, b = both(lambda S, t: rp.rp_gamma_batched(S, al, count, n, t, next(it)), total, torch.float64)
+        _same(a, b, "batched gamma")
+    d = 24
+    L = torch.eye(d, dtype=torch.float32, device="cuda")
+    mu = torch.zeros(d, dtype=torch.float32, device="cuda")
+    a, b = both(lambda S, t: rp.rp_mvn(S, mu, L, d, n, t), (n, d), torch.float32)
+    _same(a, b, "mvn rows")
+    wa, pa = _states(on)
+    wb, pb = _states(off)
+    assert np.array_equal(wa, wb) and np.array_equal(pa, pb)
+
+
+@pytest.mark.parametrize("engine", ["x256++", "philox4x32", "pcg64"])
+@pytest.mark.parametrize("dist,dtype", [(rp.RP_NORM, rp.RP_F64), (rp.RP_EXP, rp.RP_F32)])
+def test_squeeze_off_one_stream_split(engine, dist, dtype):
+    n = 200_003
+    tdt = torch.float64 if dtype == rp.RP_F64 else torch.float32
+    r_on = rp.rp_create(engine).seed(12345)
+    r_off = rp.rp_create(engine).seed(12345).set_flag(rp.RP_SQUEEZE, 0)
+    a = torch.empty(n, dtype=tdt, device="cuda")
+    b = torch.empty(n, dtype=tdt, device="cuda")
+    rp.rp_fill_serial(r_on, dist, dtype, 0, 0, a, n)
+    rp.rp_fill_serial(r_off, dist, dtype, 0, 0, b, n)
+    torch.cuda.synchronize()
+    _same(a.cpu().numpy(), b.cpu().numpy(), (engine, dist))
+    assert r_on.get_state() == r_off.get_state()
+
+
+def test_streams_settings_roundtrip_through_images():
+    S = make_streams("pcg64", 8).set_flag(rp.RP_SQUEEZE, 0).set_flag(rp.RP_FULL_MANTISSA, 0)
+    T = rp.rp_streams_deserialize(S.serialize())
+    assert not T.get_flag(rp.RP_SQUEEZE) and not T.get_flag(rp.RP_FULL_MANTISSA)
+    base = rp.rp_create("pcg64").seed(3).set_flag(rp.RP_SQUEEZE, 0)
+    U = rp.rp_streams_create(base, rp.RP_SUB_INC, 4)
+    assert not U.get_flag(rp.RP_SQUEEZE) and U.get_flag(rp.RP_FULL_MANTISSA)
+
+
+JUMP_LIMIT = {"x256++": 256, "x256**": 256, "philox": 256, "ranlux++": 256, "pcg64": 128, "philox4x32": 128,
+              "xoro++": 128, "x128+": 128, "squares": 64, "chacha20": 32}
+
+
+@pytest.mark.parametrize("engine", list(JUMP_LIMIT))
+def test_jump_families_on_every_engine(engine):
+    lim = JUMP_LIMIT[engine]
+    for k in sorted({0, 1, 31, lim - 1} | {j for j in (32, 63, 64, 96, 127, 128, 192, 200) if j < lim}):
+        base = rp.rp_create(engine).seed(77)
+        S = rp.rp_streams_create(base, rp.RP_SUB_JUMP, 3, k)
+        words, phase = S.get()
+        nw = rp.STATE_WORDS[rp.ENGINES[engine]]
+        got = [tuple(int(words[w, i]) for w in range(nw)) + (int(phase[i]),) for i in range(3)]
+        assert len(set(got)) == 3, (engine, k)
+        for i in range(3):
+            o = oracle.Stream.seeded(engine, 77).advance(i << k)
+            assert list(got[i][:nw]) == o.state[:nw] and got[i][nw] == o.phase, (engine, k, i)
