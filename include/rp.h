@@ -150,7 +150,9 @@ enum {
  * from 0 up to (not including) the bound rp_jump applies: 256 for x256++,
  * x256**, philox and ranlux++, 128 for pcg64, philox4x32, xoro++ and x128+,
  * 64 for squares and 32 for chacha20 (RP_EINVAL otherwise; RP_EUNSUPPORTED
- * for sfc64), so distinct substreams always start at distinct states. */
+ * for sfc64); the family must also fit in one period, n * 2^jump_log2 <=
+ * the period (2^bound steps, blocks for the block engines, or 2^bound - 1
+ * for the xor engines; RP_EINVAL otherwise), so the substreams never overlap. */
 int rp_streams_create(const rp_rng *base, int kind, uint64_t n, int jump_log2, rp_streams **out);
 void rp_streams_free(rp_streams *s);
 uint64_t rp_streams_count(const rp_streams *s);

@@ -7,7 +7,9 @@ C ABI of include/rp.h.  Flags:
                       as written (the serial definition is bit-reproducible)
   -Xclang -target-feature -Xclang -packed-fp32-ops
                       keep the compiler from emitting packed-FP32 instructions
-Run: python -m paper_2605_05099_amd.build   (or python paper_2605_05099_amd/build.py)
+Run: python -m paper_2605_05099_amd.build [--incremental]
+(--incremental recompiles only objects older than their source or any csrc/
+header).
 """
 import concurrent.futures as cf
 import glob
@@ -34,8 +36,19 @@ def hipcc():
     raise RuntimeError("hipcc not found: the HIP library cannot be built")
 
 
-def _compile(src):
+def _stale(src, obj):
+    """An object is stale when it is missing or older than its source or any
+    header or table in csrc/ (every .hip may include them)."""
+    if not os.path.exists(obj):
+        return True
+    deps = [src] + glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(CSRC, "*.inc"))
+    return max(os.path.getmtime(d) for d in deps) > os.path.getmtime(obj)
+
+
+def _compile(src, incremental=False):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if incremental and not _stale(src, obj):
+        return obj, ""
     cmd = [hipcc(), *COMMON, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
@@ -44,11 +57,12 @@ def _compile(src):
     return obj, err
 
 
-def build(verbose=True):
+def build(verbose=True, incremental=False):
+    """Compiles every source (incremental=True: only stale objects) and links."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        results = list(ex.map(_compile, srcs))
+        results = list(ex.map(lambda s: _compile(s, incremental), srcs))
     for _, err in results:
         if err.strip() and verbose:
             print(err, file=sys.stderr)
@@ -62,4 +76,4 @@ def build(verbose=True):
 
 
 if __name__ == "__main__":
-    print(build())
+    print(build(incremental="--incremental" in sys.argv))

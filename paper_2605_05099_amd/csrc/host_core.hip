@@ -866,6 +866,20 @@ static int jump_limit(int e)
     }
 }
 
+// Whether n substreams of 2^k engine steps each fit in one period without
+// overlap: n * 2^k <= period.  The counter engines and pcg64 have periods of
+// exactly 2^jump_limit steps (blocks for the block engines), the xor engines
+// 2^jump_limit - 1; ranlux++'s period (about 2^570) holds every family.
+static bool jump_family_fits(int e, int k, uint64_t n)
+{
+    if (e == RP_RANLUX) return true;
+    const int room = jump_limit(e) - k;  // >= 1
+    if (room >= 64) return true;         // n <= 2^32 already
+    uint64_t cap = 1ull << room;
+    if (e == RP_X256PP || e == RP_X256SS || e == RP_XORO128 || e == RP_XS128) cap -= 1;
+    return n <= cap;
+}
+
 extern "C" int rp_get_state(const rp_rng *rng, uint64_t *words, size_t n, uint32_t *phase)
 {
     if (!rng || !words) return fail(RP_ENULL, "rp_get_state: NULL argument");
@@ -1133,6 +1147,9 @@ extern "C" int rp_streams_create(const rp_rng *base, int kind, uint64_t n, int j
         if (jump_log2 < 0 || jump_log2 >= jump_limit(e))
             return fail(RP_EINVAL, "rp_streams_create: jump_log2 %d: 2^k steps must be below the period of '%s' "
                                    "(k < %d)", jump_log2, kEngines[e].id, jump_limit(e));
+        if (!jump_family_fits(e, jump_log2, n))
+            return fail(RP_EINVAL, "rp_streams_create: %llu substreams of 2^%d steps overlap within the period of '%s'",
+                        (unsigned long long)n, jump_log2, kEngines[e].id);
         break;
     default:
         return fail(RP_EINVAL, "rp_streams_create: unknown kind %d", kind);

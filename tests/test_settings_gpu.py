@@ -137,16 +137,38 @@ JUMP_LIMIT = {"x256++": 256, "x256**": 256, "philox": 256, "ranlux++": 256, "pcg
               "xoro++": 128, "x128+": 128, "squares": 64, "chacha20": 32}
 
 
+# engines whose period is 2^bound - 1 rather than 2^bound (steps or blocks)
+XOR_PERIOD = {"x256++", "x256**", "xoro++", "x128+"}
+
+
+def _family_cap(engine, k):
+    """Most substreams of 2^k steps that fit in one period (Section 2.3,
+    jumps: substreams by repeated jumps must not overlap)."""
+    if engine == "ranlux++":
+        return None
+    room = JUMP_LIMIT[engine] - k
+    if room >= 64:
+        return None
+    return (1 << room) - (1 if engine in XOR_PERIOD else 0)
+
+
 @pytest.mark.parametrize("engine", list(JUMP_LIMIT))
 def test_jump_families_on_every_engine(engine):
     lim = JUMP_LIMIT[engine]
-    for k in sorted({0, 1, 31, lim - 1} | {j for j in (32, 63, 64, 96, 127, 128, 192, 200) if j < lim}):
+    for k in sorted({0, 1, 31, lim - 2, lim - 1} | {j for j in (32, 63, 64, 96, 127, 128, 192, 200) if j < lim}):
         base = rp.rp_create(engine).seed(77)
-        S = rp.rp_streams_create(base, rp.RP_SUB_JUMP, 3, k)
+        cap = _family_cap(engine, k)
+        n = 3 if cap is None else min(3, cap)
+        while (n - 1) << k >= 2**256:   # the oracle advances by fewer than 2^256 steps
+            n -= 1
+        if cap is not None and cap < 2**32:
+            with pytest.raises(rp.RpError):
+                rp.rp_streams_create(base, rp.RP_SUB_JUMP, cap + 1, k)
+        S = rp.rp_streams_create(base, rp.RP_SUB_JUMP, n, k)
         words, phase = S.get()
         nw = rp.STATE_WORDS[rp.ENGINES[engine]]
-        got = [tuple(int(words[w, i]) for w in range(nw)) + (int(phase[i]),) for i in range(3)]
-        assert len(set(got)) == 3, (engine, k)
-        for i in range(3):
+        got = [tuple(int(words[w, i]) for w in range(nw)) + (int(phase[i]),) for i in range(n)]
+        assert len(set(got)) == n, (engine, k)
+        for i in range(n):
             o = oracle.Stream.seeded(engine, 77).advance(i << k)
             assert list(got[i][:nw]) == o.state[:nw] and got[i][nw] == o.phase, (engine, k, i)
