@@ -421,6 +421,17 @@ int rp_beta_grad(const float *d_z, const float *d_a, const float *d_b, const flo
  * k = 0 does nothing; k > n gives RP_EINVAL.  Asynchronous on hip_stream. */
 int rp_permutations(rp_streams *s, uint32_t n, uint32_t *d_out, void *hip_stream);
 int rp_sample(rp_streams *s, uint32_t n, uint32_t k, uint32_t *d_out, void *hip_stream);
+/* rp_sample for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * identical results and stream advance, but Floyd's membership tables
+ * (k <= n/2) live in a fixed 64 MiB device array inside the library (one per
+ * GPU, held until the process ends) instead of the stream-ordered pool; the
+ * call performs no allocation of any kind.  RP_EINVAL when the tables,
+ * n_substreams x 2^ceil(log2(2k)) x 4 bytes, exceed 64 MiB.  The kernel
+ * clears the tables it uses before reading them.  Every call on one GPU
+ * shares that array: calls that may overlap on one GPU (different HIP
+ * streams, host threads) race and must be serialized by the caller. */
+int rp_sample_noalloc(rp_streams *s, uint32_t n, uint32_t k, uint32_t *d_out, void *hip_stream);
 
 /* ---- multivariate normal (Section 3.1, "Multivariate normal distribution") */
 /* Cholesky factor of a covariance matrix, on the host in binary64: reads the

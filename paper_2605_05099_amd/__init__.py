@@ -91,6 +91,7 @@ _SIGS = {
     "rp_mvn_factor": ([_vp, _int, _vp, _vp], _int),
     "rp_permutations": ([_vp, _u32, _vp, _vp], _int),
     "rp_sample": ([_vp, _u32, _u32, _vp, _vp], _int),
+    "rp_sample_noalloc": ([_vp, _u32, _u32, _vp, _vp], _int),
     "rp_mvn": ([_vp, _vp, _vp, _int, _u64, _vp, _vp], _int),
     "rp_mvn_backward": ([_vp, _vp, _int, _u64, _vp, _vp, _vp], _int),
     "rp_gamma_grad": ([_vp, _vp, _vp, _vp, _u64, _vp], _int),
@@ -199,6 +200,10 @@ def rp_permutations(streams, n, out, stream=None):
 
 def rp_sample(streams, n, k, out, stream=None):
     _check(lib().rp_sample(streams.h, n, k, _dev_ptr(out), _stream_ptr(stream)))
+
+
+def rp_sample_noalloc(streams, n, k, out, stream=None):
+    _check(lib().rp_sample_noalloc(streams.h, n, k, _dev_ptr(out), _stream_ptr(stream)))
 
 
 def rp_fill_law(streams, law, params, out, per_stream, stream=None):

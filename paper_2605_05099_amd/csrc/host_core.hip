@@ -1470,14 +1470,44 @@ extern "C" int rp_permutations(rp_streams *s, uint32_t n, uint32_t *d_out, void 
     return launch_discrete(s->engine, true, a, nullptr, 0, (hipStream_t)hip_stream);
 }
 
-extern "C" int rp_sample(rp_streams *s, uint32_t n, uint32_t k, uint32_t *d_out, void *hip_stream)
+// Samples without allocation: Floyd's membership tables live in a file-scope
+// device array of kSampleScratchBytes, one copy per GPU held until the
+// process ends.  Its host-side name is not a device address: the address
+// comes from hipGetSymbolAddress, taken once per device with that device
+// current, and only that address is handed to kernels.
+static constexpr uint64_t kSampleScratchBytes = 64ull << 20;
+static __device__ __align__(256) uint32_t scratch[kSampleScratchBytes / 4];
+
+static int sample_scratch(uint32_t **out)
 {
-    if (!s) return fail(RP_ENULL, "rp_sample: NULL streams");
-    if (k > n) return fail(RP_EINVAL, "rp_sample: k = %u exceeds n = %u", k, n);
-    if (k >= (1u << 30)) return fail(RP_EINVAL, "rp_sample: k = %u too large", k);
+    static std::mutex mu;
+    static uint32_t *ptr[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(RP_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= 64) return fail(RP_EDEVICE, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(RP_EDEVICE, "rp_sample_noalloc: scratch address on device %d: %s", dev,
+                        hipGetErrorString(e));
+        ptr[dev] = (uint32_t *)p;
+    }
+    *out = ptr[dev];
+    return RP_OK;
+}
+
+static int sample_impl(const char *who, rp_streams *s, uint32_t n, uint32_t k, uint32_t *d_out, void *hip_stream,
+                       bool noalloc)
+{
+    if (!s) return fail(RP_ENULL, "%s: NULL streams", who);
+    if (k > n) return fail(RP_EINVAL, "%s: k = %u exceeds n = %u", who, k, n);
+    if (k >= (1u << 30)) return fail(RP_EINVAL, "%s: k = %u too large", who, k);
     if (k == 0) return RP_OK;
-    if (!d_out) return fail(RP_ENULL, "rp_sample: NULL output");
-    if ((uintptr_t)d_out % 4) return fail(RP_EINVAL, "rp_sample: output not aligned to 4 bytes");
+    if (!d_out) return fail(RP_ENULL, "%s: NULL output", who);
+    if ((uintptr_t)d_out % 4) return fail(RP_EINVAL, "%s: output not aligned to 4 bytes", who);
     int rc = ensure_device_tables();
     if (rc) return rc;
     FillArgs a{};
@@ -1492,13 +1522,36 @@ extern "C" int rp_sample(rp_streams *s, uint32_t n, uint32_t k, uint32_t *d_out,
     int tbits = 1;
     while ((1ull << tbits) < 2 * (uint64_t)k) tbits++;
     const uint64_t cap = 1ull << tbits;
-    if (s->n > UINT64_MAX / (cap * 4)) return fail(RP_EINVAL, "rp_sample: workspace size overflow");
+    if (s->n > UINT64_MAX / (cap * 4)) return fail(RP_EINVAL, "%s: workspace size overflow", who);
+    const uint64_t bytes = s->n * cap * 4;
+    if (noalloc) {
+        if (bytes > kSampleScratchBytes)
+            return fail(RP_EINVAL,
+                        "%s: Floyd tables of %llu substreams x %llu entries need %llu bytes, above the fixed "
+                        "scratch of %llu bytes (use rp_sample)",
+                        who, (unsigned long long)s->n, (unsigned long long)cap, (unsigned long long)bytes,
+                        (unsigned long long)kSampleScratchBytes);
+        uint32_t *tab = nullptr;
+        rc = sample_scratch(&tab);
+        if (rc) return rc;
+        return launch_discrete(s->engine, false, a, tab, tbits, st);
+    }
     uint32_t *tab = nullptr;
-    hipError_t e = hipMallocAsync((void **)&tab, s->n * cap * 4, st);
-    if (e != hipSuccess) return fail(RP_ENOMEM, "rp_sample: workspace: %s", hipGetErrorString(e));
+    hipError_t e = hipMallocAsync((void **)&tab, bytes, st);
+    if (e != hipSuccess) return fail(RP_ENOMEM, "%s: workspace: %s", who, hipGetErrorString(e));
     rc = launch_discrete(s->engine, false, a, tab, tbits, st);
     (void)hipFreeAsync(tab, st);
     return rc;
+}
+
+extern "C" int rp_sample(rp_streams *s, uint32_t n, uint32_t k, uint32_t *d_out, void *hip_stream)
+{
+    return sample_impl("rp_sample", s, n, k, d_out, hip_stream, false);
+}
+
+extern "C" int rp_sample_noalloc(rp_streams *s, uint32_t n, uint32_t k, uint32_t *d_out, void *hip_stream)
+{
+    return sample_impl("rp_sample_noalloc", s, n, k, d_out, hip_stream, true);
 }
 
 // rp_fill_law (binary64 output) and rp_fill_lawf (binary32: the float base
