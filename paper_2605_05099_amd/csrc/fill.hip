@@ -697,10 +697,13 @@ struct ZigG {
     static __device__ __forceinline__ double DM(int j) { return opaque(DIST == RP_NORM ? RP_ZN_DM : RP_ZE_DM)[j]; }
 };
 
-template <int DIST, bool HALF, class Word>
+// INL: exp and log1p inline (no calls, so no registers saved around them)
+template <int DIST, bool HALF, bool INL = false, class Word>
 __device__ __forceinline__ int zig_resolve(const WKe *t, uint64_t w0, Word word, int avail, bool squeeze,
                                            bool &accepted, double &val, bool &has_u1, uint64_t &u1)
 {
+    auto EXP = [](double x) { return INL ? exp(x) : exp_ool(x); };
+    auto LOG1P = [](double x) { return INL ? log1p(x) : log1p_ool(x); };
     const int j = (int)(w0 & 0xff);
     accepted = false;
     has_u1 = false;
@@ -720,9 +723,9 @@ __device__ __forceinline__ int zig_resolve(const WKe *t, uint64_t w0, Word word,
             const double l = fj1 + G::S(j) * (ax - G::X(j - 1));
             if (squeeze && y < l - G::DM(j)) accepted = true;
             else if (squeeze && y > l + G::DP(j)) accepted = false;
-            else accepted = y < exp_ool(DIST == RP_NORM ? -0.5 * ax * ax : -ax);
+            else accepted = y < EXP(DIST == RP_NORM ? -0.5 * ax * ax : -ax);
         } else {
-            val = RP_ZE_R - log1p_ool(-zig_u<HALF>(u));
+            val = RP_ZE_R - LOG1P(-zig_u<HALF>(u));
             accepted = true;
         }
         return 2;
@@ -737,7 +740,16 @@ __device__ __forceinline__ int zig_resolve(const WKe *t, uint64_t w0, Word word,
             return 0;
         }
         double tt;
-        if (normal_tail_pair<HALF>(word(1 + 2 * it), word(2 + 2 * it), tt)) {
+        bool ok;
+        if constexpr (INL) {
+            const double e1 = -log1p(-zig_u<HALF>(word(1 + 2 * it))) / RP_ZN_R;
+            const double e2 = -log1p(-zig_u<HALF>(word(2 + 2 * it)));
+            tt = RP_ZN_R + e1;
+            ok = e2 + e2 > e1 * e1;
+        } else {
+            ok = normal_tail_pair<HALF>(word(1 + 2 * it), word(2 + 2 * it), tt);
+        }
+        if (ok) {
             val = ((w0 >> 8) & 1) ? -tt : tt;
             accepted = true;
             return 3 + 2 * it;
@@ -1681,6 +1693,19 @@ __global__ __launch_bounds__(256) void k_fill_lane(FillArgs a)
     }
 }
 
+#include "k_zig.h"
+
+// wavefront engines that generate in store order take k_zig for binary64
+// ziggurat draws
+template <bool WAVE, class E>
+struct StoreOrder {
+    static constexpr bool value = false;
+};
+template <class E>
+struct StoreOrder<true, E> {
+    static constexpr bool value = E::kDirect;
+};
+
 // ---------------------------------------------------------------------------
 template <bool WAVE, class E, int DIST, int OT, int XF = 0>
 static int launch_one(const FillArgs &a, hipStream_t st)
@@ -1688,7 +1713,9 @@ static int launch_one(const FillArgs &a, hipStream_t st)
     const unsigned threads = 256;
     const unsigned per_block = WAVE ? threads / 64 : threads;
     const uint64_t blocks = (a.n + per_block - 1) / per_block;
-    if constexpr (WAVE)
+    if constexpr (StoreOrder<WAVE, E>::value && (DIST == RP_NORM || DIST == RP_EXP) && OT == RP_F64)
+        hipLaunchKernelGGL((k_zig<E, DIST, XF>), dim3((unsigned)blocks), dim3(threads), 0, st, a);
+    else if constexpr (WAVE)
         hipLaunchKernelGGL((k_fill_wave<E, DIST, OT, XF>), dim3((unsigned)blocks), dim3(threads), 0, st, a);
     else
         hipLaunchKernelGGL((k_fill_lane<E, DIST, OT, XF>), dim3((unsigned)blocks), dim3(threads), 0, st, a);
