@@ -62,7 +62,9 @@ enum {
                        /*              2^k only for k < 128 (both engines)  */
     RP_CHACHA20 = 10,  /* "chacha20"   ChaCha20, key 4 + nonce 1.5 + block  */
                        /*              counter 0.5 (high half of word 5)    */
-    RP_NENGINES = 11
+    RP_CWG128 = 11,    /* "cwg128"     Collatz-Weyl, x 2 + a 2 + Weyl 2 +   */
+                       /*              odd Weyl increment 2 (128-bit words) */
+    RP_NENGINES = 12
 };
 
 typedef struct rp_rng rp_rng;         /* one serial stream, host resident  */
@@ -107,7 +109,8 @@ int rp_state_words(const rp_rng *rng);
  * RP_EINVAL the states that seeding never produces because they are not
  * proper states of the engine: the all-zero state of xoshiro256,
  * xoroshiro128++ and xorshift128+ (a fixed point), an even PCG64 increment,
- * an even squares64 key, and a ranlux++ value outside [1, m). */
+ * an even squares64 key, an even cwg128 Weyl increment, and a ranlux++
+ * value outside [1, m). */
 int rp_get_state(const rp_rng *rng, uint64_t *words, size_t n, uint32_t *phase);
 int rp_set_state(rp_rng *rng, const uint64_t *words, size_t n, uint32_t phase);
 /* Jump by 2^k engine steps, k in {32, 64, 96, 128, 192} (Section 2.3).
@@ -128,6 +131,14 @@ int rp_philox_set_key(rp_rng *rng, uint64_t k0, uint64_t k1);      /* 4x32: key 
 int rp_sfc64_set_abc(rp_rng *rng, uint64_t a, uint64_t b, uint64_t c); /* +18 steps */
 int rp_squares_set_key(rp_rng *rng, uint64_t key);                  /* key |= 1 */
 int rp_chacha20_set_nonce(rp_rng *rng, uint64_t lo, uint64_t hi);   /* 96-bit nonce */
+/* cwg128 (Table 3): the Weyl increment s = lo + hi 2^64 made odd; x, a and
+ * the Weyl sequence are kept; then 96 warm-up steps (the setter's mixing
+ * warm-up, Table 3 caption).  The engine itself (Table 2, Dziala's
+ * Collatz-Weyl generator on 128-bit words) is, per step,
+ *   a += x;  weyl += s;  x = (x >> 1) * (a | 1) ^ weyl;
+ * and the 64-bit word is the low half of (a >> 96) ^ x.  The paper does not
+ * spell the step out; this reading is marked unpinned in the oracle. */
+int rp_cwg128_set_weyl(rp_rng *rng, uint64_t lo, uint64_t hi);      /* inc |= 1, +96 steps */
 /* Checkpointing (Section 4.4): opaque byte image of the stream.  With
  * buf == NULL only *needed is set. */
 int rp_serialize(const rp_rng *rng, void *buf, size_t len, size_t *needed);
@@ -138,7 +149,8 @@ int rp_raw_host(rp_rng *rng, uint64_t *out, size_t n);
 /* ---- device substreams (Section 2.3: duplicate, then set stream or jump) - */
 enum {
     RP_SUB_KEY = 0,   /* philox*: substream i has key i (k1 = 0)             */
-    RP_SUB_INC = 1,   /* pcg64: substream i has increment 2 i + 1            */
+    RP_SUB_INC = 1,   /* pcg64: substream i has increment 2 i + 1; cwg128:   */
+                      /*   Weyl increment 2 i + 1 through its setter        */
     RP_SUB_SPAWN = 2, /* any engine: seeded with (seed, spawn key [i])       */
     RP_SUB_JUMP = 3   /* every engine but sfc64: base advanced by           */
                       /*   i * 2^jump_log2 engine steps                      */

@@ -17,9 +17,9 @@ import numpy as np
 from . import build as _build
 from . import jumppoly
 
-X256PP, PCG64, PHILOX4X32, PHILOX4X64, SFC64, RANLUX, X256SS, SQUARES, XORO128PP, XS128P, CHACHA20 = range(11)
+X256PP, PCG64, PHILOX4X32, PHILOX4X64, SFC64, RANLUX, X256SS, SQUARES, XORO128PP, XS128P, CHACHA20, CWG128 = range(12)
 ENGINE_IDS = {"x256++": X256PP, "x256**": X256SS, "squares": SQUARES, "xoro++": XORO128PP, "x128+": XS128P,
-              "chacha20": CHACHA20,
+              "chacha20": CHACHA20, "cwg128": CWG128,
               "pcg64": PCG64, "philox4x32": PHILOX4X32,
               "philox": PHILOX4X64, "sfc64": SFC64, "ranlux++": RANLUX}
 
@@ -41,6 +41,7 @@ def lib():
             "or_sfc64_set_abc": ([vp, u64, u64, u64], None),
             "or_squares_set_key": ([vp, u64], ctypes.c_int),
             "or_chacha20_set_nonce": ([vp, u64, u64], ctypes.c_int),
+            "or_cwg128_set_weyl": ([vp, u64, u64], ctypes.c_int),
             "or_chacha_qr": ([vp], None),
             "or_x256_apply_poly": ([vp, vp], ctypes.c_int),
             "or_x256_linear_steps": ([vp, vp, sz], None),
@@ -158,6 +159,13 @@ class Stream:
         nonce = int(nonce)
         assert lib().or_chacha20_set_nonce(_p(self.buf), ctypes.c_uint64(nonce & (2**64 - 1)),
                                            ctypes.c_uint64(nonce >> 64)) == 0
+        return self
+
+    def cwg128_set_weyl(self, inc):
+        """The Weyl increment (made odd), then 96 warm-up steps."""
+        inc = int(inc)
+        assert lib().or_cwg128_set_weyl(_p(self.buf), ctypes.c_uint64(inc & (2**64 - 1)),
+                                        ctypes.c_uint64((inc >> 64) & (2**64 - 1))) == 0
         return self
 
     def squares_set_key(self, key):
@@ -377,6 +385,8 @@ def substream(engine, seed, kind, i, jump_log2=64):
     if kind == "nonce":
         return s.chacha20_set_nonce(i)
     if kind == "inc":
+        if engine == "cwg128":
+            return s.cwg128_set_weyl(2 * i + 1)
         return s.pcg64_set_inc(2 * i + 1)
     if kind == "jump":
         return s.advance(i << jump_log2)

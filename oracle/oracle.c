@@ -27,6 +27,8 @@
  *   xoroshiro128++, xorshift128+ cores     pinned: primitive characteristic polynomials (period 2^128-1)
  *   their output scramblers                parity unpinned (no external implementation here)
  *   chacha20 block function                pinned: RFC 8439 quarter-round and block examples
+ *   cwg128 step and output                 parity unpinned (the paper names the engine but does
+ *                                          not define it; reading below; Weyl-part invariants only)
  *   ranlux++                               pinned: modulus/multiplier/period, big-integer arithmetic
  *   seeding mixer (seed_seq_fe128)         pinned: NumPy SeedSequence
  *   u01 / u01f / bounded ints              pinned: NumPy Generator
@@ -64,7 +66,8 @@ enum {
     OR_XORO128PP = 8,
     OR_XS128P = 9,
     OR_CHACHA20 = 10,
-    OR_NENGINE = 11
+    OR_CWG128 = 11,
+    OR_NENGINE = 12
 };
 
 /*
@@ -80,6 +83,8 @@ enum {
  *   philox4x64  st[0..3] = 256-bit counter, st[4..5] = key
  *   sfc64       st[0..3] = a, b, c, counter
  *   ranlux++    st[0..8] = x (576 bits, little-endian limbs), 0 < x < m
+ *   cwg128      st[0..1] = x, st[2..3] = a, st[4..5] = Weyl sequence,
+ *               st[6..7] = Weyl increment (odd); 128-bit words, low first
  * For block engines the current block is the one computed from st; after its
  * last word is consumed st advances (counter + 1, or x <- A x mod m).
  */
@@ -371,6 +376,33 @@ static uint64_t sfc64_word(uint64_t st[4])
 }
 
 /* ------------------------------------------------------------------------ */
+/* cwg128 (Dziala's Collatz-Weyl generator; Table 2 "cwg128", Table 3: state */
+/* of six words plus a two-word Weyl increment).  The paper names the engine */
+/* but does not give its step; the reading here is the generator's published */
+/* 128-bit form: the Weyl sequence grows by the odd increment s each step,   */
+/* a accumulates x, and x becomes (x >> 1) (a | 1) xor weyl, all modulo      */
+/* 2^128; the 128-bit output is (a >> 96) xor x, of which the 64-bit word is */
+/* the low half (the half that every term of the output reaches).            */
+/* ------------------------------------------------------------------------ */
+static uint64_t cwg128_word(uint64_t st[8])
+{
+    u128 x = ((u128)st[1] << 64) | st[0];
+    u128 a = ((u128)st[3] << 64) | st[2];
+    u128 weyl = ((u128)st[5] << 64) | st[4];
+    const u128 inc = ((u128)st[7] << 64) | st[6];
+    a += x;
+    weyl += inc;
+    x = ((x >> 1) * (a | 1)) ^ weyl;
+    st[0] = (uint64_t)x;
+    st[1] = (uint64_t)(x >> 64);
+    st[2] = (uint64_t)a;
+    st[3] = (uint64_t)(a >> 64);
+    st[4] = (uint64_t)weyl;
+    st[5] = (uint64_t)(weyl >> 64);
+    return (uint64_t)((a >> 96) ^ x);
+}
+
+/* ------------------------------------------------------------------------ */
 /* ranlux++ (Sibidanov 2017; Table 2 "ranlux++").  The LCG form of the       */
 /* RANLUX subtract-with-borrow generator with base b = 2^24, lags r = 24,    */
 /* s = 10:  m = b^r - b^s + 1 = 2^576 - 2^240 + 1,  a = m - (m - 1)/b.       */
@@ -647,6 +679,7 @@ static uint64_t next_word(or_stream *s)
     case OR_XS128P: return xs128p_word(s->st);
     case OR_PCG64: return pcg64_word(s->st);
     case OR_SFC64: return sfc64_word(s->st);
+    case OR_CWG128: return cwg128_word(s->st);
     default: {
         int nb = block_words(s->engine);
         if (!s->blk_ok) make_block(s);
@@ -738,11 +771,13 @@ static int seeded_words(uint64_t engine)
     case OR_PHILOX4X64: return 6;
     case OR_SFC64: return 3;
     case OR_RANLUX: return 9;
+    case OR_CWG128: return 8;
     default: return 0;
     }
 }
 
 void or_sfc64_set_abc(or_stream *s, uint64_t a, uint64_t b, uint64_t c);
+int or_cwg128_set_weyl(or_stream *s, uint64_t lo, uint64_t hi);
 
 /*
  * Seeding (Section 2.3): the mixer input is the 64-bit seed as two 32-bit
@@ -807,6 +842,13 @@ int or_seed(or_stream *s, uint64_t engine, uint64_t seed, const uint32_t *key, s
         memcpy(s->st, w, 9 * 8);
         rl_seed_fixup(s->st);
         break;
+    case OR_CWG128:
+        /* x, a and the Weyl sequence from the mixer; the increment goes
+         * through the stream setter (made odd, 96 warm-up steps), as sfc64's
+         * (a, b, c) go through its setter */
+        memcpy(s->st, w, 6 * 8);
+        or_cwg128_set_weyl(s, w[6], w[7]);
+        break;
     }
     return 0;
 }
@@ -860,6 +902,19 @@ int or_chacha20_set_nonce(or_stream *s, uint64_t lo, uint64_t hi)
     s->st[4] = lo;
     s->st[5] = (s->st[5] & 0xffffffff00000000ull) | (uint32_t)hi;
     s->blk_ok = 0;
+    return 0;
+}
+
+/* cwg128 stream setter (Table 3): the Weyl increment, made odd (an even one
+ * would not give the full period of the Weyl sequence), then the 96 warm-up
+ * steps of the Table 3 caption; x, a and the Weyl sequence are kept. */
+int or_cwg128_set_weyl(or_stream *s, uint64_t lo, uint64_t hi)
+{
+    if (s->engine != OR_CWG128) return -1;
+    s->st[6] = lo | 1u;
+    s->st[7] = hi;
+    s->phase = 0;
+    for (int i = 0; i < 96; i++) (void)cwg128_word(s->st);
     return 0;
 }
 

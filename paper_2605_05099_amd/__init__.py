@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "librp.so")
 # status codes, engines, distributions, dtypes (include/rp.h)
 RP_OK, RP_EINVAL, RP_ENOMEM, RP_EUNSUPPORTED, RP_EDEVICE, RP_ENOTSPD, RP_ENULL = 0, -1, -2, -3, -4, -5, -6
 (RP_X256PP, RP_PCG64, RP_PHILOX4X32, RP_PHILOX, RP_SFC64, RP_RANLUX, RP_X256SS, RP_SQUARES, RP_XORO128, RP_XS128,
- RP_CHACHA20) = range(11)
+ RP_CHACHA20, RP_CWG128) = range(12)
 RP_SUB_KEY, RP_SUB_INC, RP_SUB_SPAWN, RP_SUB_JUMP = range(4)
 RP_RAW, RP_U01, RP_BOUNDED, RP_NORM, RP_EXP = range(5)
 RP_U64, RP_U32, RP_F64, RP_F32 = range(4)
@@ -31,8 +31,9 @@ RP_FULL_MANTISSA, RP_SQUEEZE = 1, 2  # settings (rp_set_flag)
 
 ENGINES = {"x256++": RP_X256PP, "x256**": RP_X256SS, "pcg64": RP_PCG64, "philox4x32": RP_PHILOX4X32, "philox": RP_PHILOX,
            "sfc64": RP_SFC64, "ranlux++": RP_RANLUX, "squares": RP_SQUARES, "xoro++": RP_XORO128, "x128+": RP_XS128,
-           "chacha20": RP_CHACHA20}
-STATE_WORDS = {RP_X256PP: 4, RP_PCG64: 4, RP_PHILOX4X32: 3, RP_PHILOX: 6, RP_SFC64: 4, RP_RANLUX: 9, RP_X256SS: 4, RP_SQUARES: 2, RP_XORO128: 2, RP_XS128: 2, RP_CHACHA20: 6}
+           "chacha20": RP_CHACHA20, "cwg128": RP_CWG128}
+STATE_WORDS = {RP_X256PP: 4, RP_PCG64: 4, RP_PHILOX4X32: 3, RP_PHILOX: 6, RP_SFC64: 4, RP_RANLUX: 9, RP_X256SS: 4, RP_SQUARES: 2, RP_XORO128: 2, RP_XS128: 2, RP_CHACHA20: 6,
+               RP_CWG128: 8}
 
 _vp, _sz, _u64, _u32, _int = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
 _SIGS = {
@@ -61,6 +62,7 @@ _SIGS = {
     "rp_streams_set_flag": ([_vp, _int, _int], _int),
     "rp_streams_get_flag": ([_vp, _int], _int),
     "rp_chacha20_set_nonce": ([_vp, _u64, _u64], _int),
+    "rp_cwg128_set_weyl": ([_vp, _u64, _u64], _int),
     "rp_serialize": ([_vp, _vp, _sz, _vp], _int),
     "rp_deserialize": ([_vp, _vp, _sz], _int),
     "rp_raw_host": ([_vp, _vp, _sz], _int),
@@ -394,6 +396,10 @@ class Rng:
 
     def chacha20_set_nonce(self, nonce):
         _check(lib().rp_chacha20_set_nonce(self.h, nonce & (2**64 - 1), nonce >> 64), self.h)
+        return self
+
+    def cwg128_set_weyl(self, inc):
+        _check(lib().rp_cwg128_set_weyl(self.h, inc & (2**64 - 1), (inc >> 64) & (2**64 - 1)), self.h)
         return self
 
     def duplicate(self):

@@ -262,6 +262,23 @@ struct Sfc64 {
 };
 
 // ---------------------------------------------------------------------------
+// cwg128 (Dziala's Collatz-Weyl generator, 128-bit words): per step
+// a += x, weyl += s, x = (x >> 1) * (a | 1) ^ weyl; the word is the low half
+// of (a >> 96) ^ x.  s (the Weyl increment, the stream selector) is odd.
+struct Cwg128 {
+    u128 x, a, w, s;
+    RP_HD uint64_t next()
+    {
+        a = add128(a, x);
+        w = add128(w, s);
+        const u128 xh{(x.lo >> 1) | (x.hi << 63), x.hi >> 1};
+        const u128 p = mul128(xh, u128{a.lo | 1u, a.hi});
+        x = u128{p.lo ^ w.lo, p.hi ^ w.hi};
+        return (a.hi >> 32) ^ x.lo;
+    }
+};
+
+// ---------------------------------------------------------------------------
 // ranlux++: x <- A x mod m, m = 2^576 - 2^240 + 1, on nine 64-bit limbs
 // (little-endian).
 //

@@ -1362,6 +1362,31 @@ struct LaneSfc64 {
     }
 };
 
+// cwg128: x, a, Weyl sequence and increment, two words each
+struct LaneCwg128 {
+    Cwg128 g;
+    __device__ void load(const FillArgs &a, uint64_t i)
+    {
+        const uint64_t n = a.n;
+        g = Cwg128{{a.words[i], a.words[n + i]},
+                   {a.words[2 * n + i], a.words[3 * n + i]},
+                   {a.words[4 * n + i], a.words[5 * n + i]},
+                   {a.words[6 * n + i], a.words[7 * n + i]}};
+    }
+    __device__ uint64_t next() { return g.next(); }
+    __device__ void reserve(int) {}
+    __device__ void store(const FillArgs &a, uint64_t i) const
+    {
+        const uint64_t n = a.n;
+        a.words[i] = g.x.lo;
+        a.words[n + i] = g.x.hi;
+        a.words[2 * n + i] = g.a.lo;
+        a.words[3 * n + i] = g.a.hi;
+        a.words[4 * n + i] = g.w.lo;
+        a.words[5 * n + i] = g.w.hi;
+    }
+};
+
 // Lanes of a wavefront that run serial streams drift apart in how many words
 // they have used, so a per-lane "make a block when the current one is used
 // up" branch would run the block computation for the whole wavefront on
@@ -1761,6 +1786,7 @@ int launch_fill(int engine, int dist, int dtype, const FillArgs &a, hipStream_t 
     case RP_XORO128: return dispatch_dist<false, LaneXoro128>(dist, dtype, a, st);
     case RP_XS128: return dispatch_dist<false, LaneXs128>(dist, dtype, a, st);
     case RP_SFC64: return dispatch_dist<false, LaneSfc64>(dist, dtype, a, st);
+    case RP_CWG128: return dispatch_dist<false, LaneCwg128>(dist, dtype, a, st);
     case RP_RANLUX: return dispatch_dist<false, LaneRanlux>(dist, dtype, a, st);
     }
     return fail(RP_EINVAL, "unknown engine");
@@ -1802,6 +1828,7 @@ int launch_fill_law(int engine, int law, bool f32, const FillArgs &a, hipStream_
     case RP_XORO128: return dispatch_law<false, LaneXoro128>(law, f32, a, st);
     case RP_XS128: return dispatch_law<false, LaneXs128>(law, f32, a, st);
     case RP_SFC64: return dispatch_law<false, LaneSfc64>(law, f32, a, st);
+    case RP_CWG128: return dispatch_law<false, LaneCwg128>(law, f32, a, st);
     case RP_RANLUX: return dispatch_law<false, LaneRanlux>(law, f32, a, st);
     }
     return fail(RP_EINVAL, "unknown engine");

@@ -93,6 +93,7 @@ static const EngineInfo kEngines[RP_NENGINES] = {
     {"xoro++", "xoroshiro128++ (Blackman and Vigna, 2019), 2 state words, period 2^128-1", 2, 1},
     {"x128+", "xorshift128+ (Vigna, 2014), 2 state words, period 2^128-1", 2, 1},
     {"chacha20", "ChaCha20 (Bernstein, 2008), 6 state words, period 2^35 per nonce", 6, 8},
+    {"cwg128", "cwg128 (Dziala, 2022), 8 state words, period 2^128 per Weyl increment", 8, 1},
 };
 
 namespace rp {
@@ -562,6 +563,13 @@ static uint64_t host_next(rp_rng *r)
         st[0] = s.a; st[1] = s.b; st[2] = s.c; st[3] = s.ctr;
         return w;
     }
+    case RP_CWG128: {
+        Cwg128 g{{st[0], st[1]}, {st[2], st[3]}, {st[4], st[5]}, {st[6], st[7]}};
+        const uint64_t w = g.next();
+        st[0] = g.x.lo; st[1] = g.x.hi; st[2] = g.a.lo; st[3] = g.a.hi;
+        st[4] = g.w.lo; st[5] = g.w.hi;
+        return w;
+    }
     case RP_PHILOX4X32: {
         uint64_t w0, w1;
         philox4x32(st[0], st[1], st[2], w0, w1);
@@ -623,6 +631,16 @@ static void sfc64_setabc(rp_rng *r, uint64_t a, uint64_t b, uint64_t c)
     for (int i = 0; i < 18; i++) host_next(r);
 }
 
+// cwg128 stream setter: the Weyl increment made odd, then 96 warm-up steps
+// (Table 3 caption); x, a and the Weyl sequence are kept.
+static void cwg128_setweyl(rp_rng *r, uint64_t lo, uint64_t hi)
+{
+    r->st[6] = lo | 1u;
+    r->st[7] = hi;
+    r->phase = 0;
+    for (int i = 0; i < 96; i++) host_next(r);
+}
+
 static void seed_state(rp_rng *r, uint64_t seed, const uint32_t *key, size_t n_key)
 {
     std::vector<uint32_t> in = {(uint32_t)seed, (uint32_t)(seed >> 32)};
@@ -668,6 +686,10 @@ static void seed_state(rp_rng *r, uint64_t seed, const uint32_t *key, size_t n_k
     case RP_RANLUX:
         memcpy(r->st, w, 72);
         ranlux_fixup(r->st);
+        break;
+    case RP_CWG128:  // x, a, Weyl from the mixer, the increment through the setter
+        memcpy(r->st, w, 48);
+        cwg128_setweyl(r, w[6], w[7]);
         break;
     }
 }
@@ -822,6 +844,9 @@ static const char *state_defect(int e, const uint64_t *w, size_t stride)
         break;
     case RP_SQUARES:
         if (!(W(1) & 1)) return "an even squares64 key";
+        break;
+    case RP_CWG128:
+        if (!(W(6) & 1)) return "an even cwg128 Weyl increment";
         break;
     case RP_RANLUX: {
         // m = 2^576 - 2^240 + 1: limbs 4..8 all ones, limb 3 bits 48..63, limb 0 = 1
@@ -1059,6 +1084,14 @@ extern "C" int rp_chacha20_set_nonce(rp_rng *rng, uint64_t lo, uint64_t hi)
     return RP_OK;
 }
 
+extern "C" int rp_cwg128_set_weyl(rp_rng *rng, uint64_t lo, uint64_t hi)
+{
+    if (!rng) return fail(RP_ENULL, "rp_cwg128_set_weyl: NULL rng");
+    if (rng->engine != RP_CWG128) return fail_rng(rng, RP_EUNSUPPORTED, "cwg128_set_weyl: engine is not cwg128");
+    cwg128_setweyl(rng, lo, hi);
+    return RP_OK;
+}
+
 extern "C" int rp_squares_set_key(rp_rng *rng, uint64_t key)
 {
     if (!rng) return fail(RP_ENULL, "rp_squares_set_key: NULL rng");
@@ -1138,7 +1171,7 @@ extern "C" int rp_streams_create(const rp_rng *base, int kind, uint64_t n, int j
             return fail(RP_EUNSUPPORTED, "RP_SUB_KEY needs a philox or chacha20 engine");
         break;
     case RP_SUB_INC:
-        if (e != RP_PCG64) return fail(RP_EUNSUPPORTED, "RP_SUB_INC needs pcg64");
+        if (e != RP_PCG64 && e != RP_CWG128) return fail(RP_EUNSUPPORTED, "RP_SUB_INC needs pcg64 or cwg128");
         break;
     case RP_SUB_SPAWN:
         break;
@@ -1200,8 +1233,12 @@ extern "C" int rp_streams_create(const rp_rng *base, int kind, uint64_t n, int j
             break;
         case RP_SUB_INC:
             cur = *base;
-            cur.st[2] = 2 * i + 1;
-            cur.st[3] = 0;
+            if (e == RP_CWG128) {
+                cwg128_setweyl(&cur, 2 * i + 1, 0);
+            } else {
+                cur.st[2] = 2 * i + 1;
+                cur.st[3] = 0;
+            }
             break;
         case RP_SUB_SPAWN: {
             cur.engine = e;
@@ -1831,7 +1868,8 @@ int serial_family(int engine)
     case RP_PHILOX:
     case RP_CHACHA20: return RP_SUB_KEY;
     case RP_PCG64: return RP_SUB_INC;
-    case RP_SFC64: return RP_SUB_SPAWN;
+    case RP_SFC64:
+    case RP_CWG128: return RP_SUB_SPAWN;
     default: return RP_SUB_JUMP;
     }
 }
@@ -1888,8 +1926,9 @@ extern "C" int rp_fill_serial(rp_rng *rng, int dist, int dtype, uint64_t bound, 
     int rc = ensure_device_tables();
     if (rc) return rc;
     hipStream_t st = (hipStream_t)hip_stream;
-    // sfc64 has no jump; the 128-bit xor engines have no lane jump tables
-    if (rng->engine == RP_SFC64 || rng->engine == RP_XORO128 || rng->engine == RP_XS128)
+    // sfc64 and cwg128 have no jump; the 128-bit xor engines have no lane jump tables
+    if (rng->engine == RP_SFC64 || rng->engine == RP_XORO128 || rng->engine == RP_XS128 ||
+        rng->engine == RP_CWG128)
         return serial_fallback(rng, dist, dtype, bound, flags, d_out, n, st);
     SerialArgs a{};
     memcpy(a.base, rng->st, sizeof a.base);

@@ -240,6 +240,7 @@ int launch_batched_gen(int engine, const BatchArgs &a, bool beta, unsigned grid,
     case RP_PHILOX4X32: launch_batched_e<LanePhilox32>(a, beta, grid, block, st); break;
     case RP_PHILOX: launch_batched_e<LanePhilox64>(a, beta, grid, block, st); break;
     case RP_SFC64: launch_batched_e<LaneSfc64>(a, beta, grid, block, st); break;
+    case RP_CWG128: launch_batched_e<LaneCwg128>(a, beta, grid, block, st); break;
     case RP_RANLUX: launch_batched_e<LaneRanlux>(a, beta, grid, block, st); break;
     default: return fail(RP_EINVAL, "unknown engine");
     }

@@ -17,6 +17,7 @@ FAMILY = {
     "xoro++": (rp.RP_SUB_JUMP, "jump"),
     "x128+": (rp.RP_SUB_JUMP, "jump"),
     "chacha20": (rp.RP_SUB_KEY, "nonce"),
+    "cwg128": (rp.RP_SUB_INC, "inc"),
 }
 ENGINES = list(FAMILY)
 

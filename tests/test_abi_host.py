@@ -12,7 +12,7 @@ import oracle
 import paper_2605_05099_amd as rp
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-ENGINES = ["x256++", "pcg64", "philox4x32", "philox", "sfc64", "ranlux++"]
+ENGINES = ["x256++", "pcg64", "philox4x32", "philox", "sfc64", "ranlux++", "cwg128"]
 
 
 def declared_functions():
@@ -153,6 +153,14 @@ def test_setters_match_oracle():
     r = rp.rp_create("sfc64").sfc64_set_abc(1, 2, 3)
     o = oracle.Stream("sfc64").sfc64_set_abc(1, 2, 3)
     assert r.get_state()[0] == o.state[:4]
+    r = rp.rp_create("cwg128").seed(1).cwg128_set_weyl(2**90 + 6)
+    o = oracle.Stream.seeded("cwg128", 1).cwg128_set_weyl(2**90 + 6)
+    assert r.get_state()[0] == o.state[:8]
+    assert r.get_state()[0][6:] == [7, 2**26]   # made odd
+    assert (r.raw_host(50) == o.raw(50)).all()
+    with pytest.raises(rp.RpError) as ei:
+        rp.rp_create("pcg64").cwg128_set_weyl(3)
+    assert ei.value.code == rp.RP_EUNSUPPORTED
     with pytest.raises(rp.RpError) as ei:
         rp.rp_create("x256++").pcg64_set_inc(3)
     assert ei.value.code == rp.RP_EUNSUPPORTED
@@ -248,7 +256,7 @@ def test_ranlux_long_host_draw_matches_oracle():
 ALL_ENGINES = list(rp.ENGINES)
 # exclusive bound on k for jumps by 2^k steps (the period of one stream)
 JUMP_LIMIT = {"x256++": 256, "x256**": 256, "philox": 256, "ranlux++": 256, "pcg64": 128, "philox4x32": 128,
-              "xoro++": 128, "x128+": 128, "squares": 64, "chacha20": 32, "sfc64": 0}
+              "xoro++": 128, "x128+": 128, "squares": 64, "chacha20": 32, "sfc64": 0, "cwg128": 0}
 
 
 @pytest.mark.parametrize("engine", ALL_ENGINES)
@@ -280,7 +288,8 @@ def test_jump_bounds_follow_the_period(engine):
 
 def test_set_state_rejects_states_seeding_never_makes():
     cases = [("x256++", [0, 0, 0, 0]), ("x256**", [0, 0, 0, 0]), ("xoro++", [0, 0]), ("x128+", [0, 0]),
-             ("pcg64", [1, 2, 4, 0]), ("squares", [7, 10]), ("ranlux++", _rl_words(0)),
+             ("pcg64", [1, 2, 4, 0]), ("squares", [7, 10]), ("cwg128", [1, 2, 3, 4, 5, 6, 8, 0]),
+             ("ranlux++", _rl_words(0)),
              ("ranlux++", _rl_words(RL_M)), ("ranlux++", _rl_words(2**576 - 1))]
     for engine, words in cases:
         r = rp.rp_create(engine).seed(1)
@@ -297,6 +306,7 @@ def test_set_state_rejects_states_seeding_never_makes():
     rp.rp_create("x256++").set_state([0, 0, 0, 1])
     rp.rp_create("pcg64").set_state([1, 2, 3, 0])
     rp.rp_create("squares").set_state([7, 11])
+    rp.rp_create("cwg128").set_state([1, 2, 3, 4, 5, 6, 9, 0])
     rp.rp_create("ranlux++").set_state(_rl_words(RL_M - 1))
 
 

@@ -478,3 +478,63 @@ def test_chacha_counter_nonce_and_advance():
     c.chacha20_set_nonce((3 << 64) | 11)
     assert c.state[:4] == st[:4] and c.state[4] == 11
     assert c.state[5] == (st[5] & ~0xFFFFFFFF) | 3
+
+
+# ---- cwg128 (Table 2 "cwg128"; Table 3: state 6 + Weyl increment 2) ----------
+# The paper names Dziala's Collatz-Weyl generator but does not give its step;
+# the oracle's reading (x, a, Weyl sequence, odd increment; 128-bit words)
+# has no implementation here to compare with, so the output is parity
+# unpinned.  Checked: the Weyl sequence moves by exactly n s in n steps, a
+# accumulates x, the setter's odd increment and 96 warm-up steps, the seeding
+# recipe, and the statistical quality.
+
+def _u128(lo, hi):
+    return int(lo) | (int(hi) << 64)
+
+
+def test_cwg128_weyl_sequence_and_accumulator():
+    s = Stream.seeded("cwg128", 2024)
+    st = s.state[:8]
+    w0, inc = _u128(st[4], st[5]), _u128(st[6], st[7])
+    assert inc % 2 == 1
+    a, xs = _u128(st[2], st[3]), []
+    for n in (1, 2, 37, 1000):
+        t = Stream.from_state("cwg128", st)
+        x_prev = []
+        for _ in range(n):
+            x_prev.append(_u128(t.state[0], t.state[1]))
+            t.raw(1)
+        ts = t.state[:8]
+        assert _u128(ts[4], ts[5]) == (w0 + n * inc) % 2**128, n
+        assert _u128(ts[6], ts[7]) == inc
+        assert _u128(ts[2], ts[3]) == (a + sum(x_prev)) % 2**128, n
+
+
+def test_cwg128_setter_and_seeding_recipe():
+    # setter: increment made odd, x / a / Weyl kept, then 96 ordinary steps
+    s = Stream.seeded("cwg128", 7)
+    st = s.state[:8]
+    s.cwg128_set_weyl(2**100 + 10)
+    t = Stream.from_state("cwg128", st[:6] + [11, 2**36])
+    t.raw(96)
+    assert s.state[:8] == t.state[:8]
+    # seeding: x, a, Weyl from the first six mixer words, the increment from
+    # the next two through the setter
+    out = np.zeros(16, dtype=np.uint32)
+    key = np.array([7, 0], dtype=np.uint32)
+    oracle.lib().or_seed_seq(key.ctypes.data_as(ctypes.c_void_p), 2, out.ctypes.data_as(ctypes.c_void_p), 16)
+    w = [int(out[2 * i]) | (int(out[2 * i + 1]) << 32) for i in range(8)]
+    u = Stream.from_state("cwg128", w[:6] + [w[6] | 1, w[7]])
+    u.raw(96)
+    assert Stream.seeded("cwg128", 7).state[:8] == u.state[:8]
+
+
+def test_cwg128_streams_differ_and_are_uniform():
+    a = Stream.seeded("cwg128", 5).raw(200000)
+    b = Stream.seeded("cwg128", 5).cwg128_set_weyl(3).raw(200000)
+    assert (a != b).mean() > 0.999
+    for x in (a, b):
+        u = (x >> np.uint64(11)).astype(np.float64) * 2.0**-53
+        assert stats.kstest(u, "uniform").pvalue > 1e-4
+        bits = np.unpackbits(x.view(np.uint8)).reshape(-1, 64).mean(axis=0)
+        assert np.abs(bits - 0.5).max() < 5 * 0.5 / np.sqrt(len(x))
