@@ -64,7 +64,18 @@ enum {
                        /*              counter 0.5 (high half of word 5)    */
     RP_CWG128 = 11,    /* "cwg128"     Collatz-Weyl, x 2 + a 2 + Weyl 2 +   */
                        /*              odd Weyl increment 2 (128-bit words) */
-    RP_NENGINES = 12
+    /* SIMD engines (Section 4.1): eight interleaved scalar sub-streams, 32
+     * state words (sub-stream k at words 4k .. 4k+3), blocks of 8 words
+     * (word 8 t + k is sub-stream k's t-th word; phase counts the words of
+     * the current round already used, the sub-streams moving one step when
+     * all eight are used).  xoshiro sub-stream k is the seeded base jumped by
+     * k 2^253 steps; sfc64 sub-stream k has k 2^61 added to the seeded base's
+     * counter.  Jumps and advances move every sub-stream (k < 253). */
+    RP_X256PPS = 12,   /* "x256++simd" the paper's default engine          */
+    RP_X256SSS = 13,   /* "x256**simd"                                     */
+    RP_SFC64S = 14,    /* "sfc64simd"  (no jump; rp_sfc64_set_abc sets the */
+                       /*              base, then the counter offsets)     */
+    RP_NENGINES = 15
 };
 
 typedef struct rp_rng rp_rng;         /* one serial stream, host resident  */

@@ -10,6 +10,7 @@ The C core is ``oracle/oracle.c`` (built into ``liboracle.so`` by
 construction recipes (seeding, stream setters, jumps) used by the workloads.
 """
 import ctypes
+import functools
 import os
 
 import numpy as np
@@ -17,9 +18,11 @@ import numpy as np
 from . import build as _build
 from . import jumppoly
 
-X256PP, PCG64, PHILOX4X32, PHILOX4X64, SFC64, RANLUX, X256SS, SQUARES, XORO128PP, XS128P, CHACHA20, CWG128 = range(12)
+(X256PP, PCG64, PHILOX4X32, PHILOX4X64, SFC64, RANLUX, X256SS, SQUARES, XORO128PP, XS128P, CHACHA20, CWG128,
+ X256PPS, X256SSS, SFC64S) = range(15)
 ENGINE_IDS = {"x256++": X256PP, "x256**": X256SS, "squares": SQUARES, "xoro++": XORO128PP, "x128+": XS128P,
               "chacha20": CHACHA20, "cwg128": CWG128,
+              "x256++simd": X256PPS, "x256**simd": X256SSS, "sfc64simd": SFC64S,
               "pcg64": PCG64, "philox4x32": PHILOX4X32,
               "philox": PHILOX4X64, "sfc64": SFC64, "ranlux++": RANLUX}
 
@@ -106,6 +109,36 @@ class Counts:
         raise AttributeError(k)
 
 
+# SIMD engines (Section 4.1): eight disjoint scalar sub-streams of the named
+# scalar engine, xoshiro256 sub-stream k jumped by k 2^253 steps, sfc64
+# sub-stream k with k 2^61 added to the counter (modulo 2^64).
+SIMD_BASE = {X256PPS: "x256++", X256SSS: "x256**", SFC64S: "sfc64"}
+SIMD_LANES = 8
+
+
+@functools.lru_cache(maxsize=4096)
+def x256_xpow(n):
+    """x^n mod P for the xoshiro256 characteristic polynomial P (cached)."""
+    return jumppoly.xpow_mod(int(n), jumppoly.x256_char_poly(lib()))
+
+
+def simd_lanes_from_base(engine, base_words):
+    """The 32 state words (sub-stream k at words 4k .. 4k+3) of a SIMD engine
+    whose sub-stream 0 has the scalar state base_words."""
+    words = []
+    if engine == SFC64S:
+        a, b, c, ctr = [int(x) for x in base_words[:4]]
+        for k in range(SIMD_LANES):
+            words += [a, b, c, (ctr + k * 2**61) % 2**64]
+        return words
+    jpoly = x256_xpow(2**253)
+    cur = Stream.from_state(SIMD_BASE[engine], list(base_words[:4]))
+    for k in range(SIMD_LANES):
+        words += cur.state[:4]
+        cur.x256_apply_poly(jpoly)
+    return words
+
+
 class Stream:
     """One serial stream of the oracle (a copy of the C struct)."""
 
@@ -118,6 +151,10 @@ class Stream:
     @classmethod
     def seeded(cls, engine, seed, spawn_key=()):
         s = cls(engine)
+        if s.engine in SIMD_BASE:
+            # seeded as the scalar engine, then the eight sub-streams
+            base = Stream.seeded(SIMD_BASE[s.engine], seed, spawn_key)
+            return Stream.from_state(s.engine, simd_lanes_from_base(s.engine, base.state[:4]))
         key = np.array(list(spawn_key), dtype=np.uint32)
         rc = lib().or_seed(_p(s.buf), s.engine, ctypes.c_uint64(seed), _p(key) if len(key) else None,
                            len(key))
@@ -138,7 +175,7 @@ class Stream:
 
     @property
     def state(self):
-        return [int(x) for x in self.buf[2:18]]
+        return [int(x) for x in self.buf[2:34]]
 
     @property
     def phase(self):
@@ -173,6 +210,10 @@ class Stream:
         return self
 
     def sfc64_set_abc(self, a, b, c):
+        if self.engine == SFC64S:
+            base = Stream("sfc64").sfc64_set_abc(a, b, c)
+            self.buf[:] = Stream.from_state(SFC64S, simd_lanes_from_base(SFC64S, base.state[:4])).buf
+            return self
         lib().or_sfc64_set_abc(_p(self.buf), a, b, c)
         return self
 
@@ -184,6 +225,16 @@ class Stream:
     def advance(self, n):
         """Move forward by n engine steps (blocks for block engines)."""
         n = int(n)
+        if self.engine in (X256PPS, X256SSS):
+            # every sub-stream moves n steps; the phase in the block is kept
+            poly = x256_xpow(n)
+            words = self.state[:32]
+            for k in range(SIMD_LANES):
+                lane = Stream.from_state(SIMD_BASE[self.engine], words[4 * k:4 * k + 4]).x256_apply_poly(poly)
+                words[4 * k:4 * k + 4] = lane.state[:4]
+            ph = self.phase
+            self.buf[:] = Stream.from_state(self.engine, words, ph).buf
+            return self
         if self.engine in (X256PP, X256SS):
             p = jumppoly.x256_char_poly(lib())
             return self.x256_apply_poly(jumppoly.xpow_mod(n, p))
@@ -198,7 +249,7 @@ class Stream:
             w5 = int(self.buf[2 + 5])
             c = ((w5 >> 32) + n) % 2**32
             self.buf[2 + 5] = np.uint64((w5 & (2**32 - 1)) | (c << 32))
-            self.buf[2 + 16 + 9] = np.uint64(0)     # blk_ok
+            self.buf[2 + 32 + 9] = np.uint64(0)     # blk_ok
             return self
         if self.engine == SQUARES:
             # counter engine with period 2^64: the counter word moves by n

@@ -29,6 +29,10 @@
  *   chacha20 block function                pinned: RFC 8439 quarter-round and block examples
  *   cwg128 step and output                 parity unpinned (the paper names the engine but does
  *                                          not define it; reading below; Weyl-part invariants only)
+ *   x256++simd, x256**simd, sfc64simd      interleave of eight scalar sub-streams: pinned to the
+ *                                          scalar engines (each sub-stream equals its jumped or
+ *                                          counter-offset scalar stream); the order of the eight
+ *                                          words of a round is a reading (parity unpinned)
  *   ranlux++                               pinned: modulus/multiplier/period, big-integer arithmetic
  *   seeding mixer (seed_seq_fe128)         pinned: NumPy SeedSequence
  *   u01 / u01f / bounded ints              pinned: NumPy Generator
@@ -67,7 +71,10 @@ enum {
     OR_XS128P = 9,
     OR_CHACHA20 = 10,
     OR_CWG128 = 11,
-    OR_NENGINE = 12
+    OR_X256PPS = 12, /* x256++simd: eight interleaved xoshiro256++ sub-streams */
+    OR_X256SSS = 13, /* x256**simd */
+    OR_SFC64S = 14,  /* sfc64simd: eight interleaved sfc64 sub-streams */
+    OR_NENGINE = 15
 };
 
 /*
@@ -85,13 +92,17 @@ enum {
  *   ranlux++    st[0..8] = x (576 bits, little-endian limbs), 0 < x < m
  *   cwg128      st[0..1] = x, st[2..3] = a, st[4..5] = Weyl sequence,
  *               st[6..7] = Weyl increment (odd); 128-bit words, low first
+ *   *simd       st[4k .. 4k+3] = sub-stream k (k < 8) as the scalar engine's
+ *               four words; a block is one word of each sub-stream, in
+ *               sub-stream order (Section 4.1: eight disjoint scalar streams,
+ *               buffers filled in 8-word chunks)
  * For block engines the current block is the one computed from st; after its
  * last word is consumed st advances (counter + 1, or x <- A x mod m).
  */
 typedef struct {
     uint64_t engine;
     uint64_t phase;
-    uint64_t st[16];
+    uint64_t st[32];
     uint64_t blk[9];
     uint64_t blk_ok;
 } or_stream;
@@ -612,13 +623,32 @@ static int block_words(uint64_t engine)
     case OR_PHILOX4X64: return 4;
     case OR_RANLUX: return 9;
     case OR_CHACHA20: return 8;
+    case OR_X256PPS:
+    case OR_X256SSS:
+    case OR_SFC64S: return 8;
     default: return 1;
     }
+}
+
+/* One word of sub-stream k of a SIMD engine, from a copy (the sub-stream
+ * itself moves only when the whole block has been used). */
+static uint64_t simd_peek(const or_stream *s, int k)
+{
+    uint64_t t[4];
+    memcpy(t, &s->st[4 * k], sizeof t);
+    if (s->engine == OR_X256PPS) return x256pp_word(t);
+    if (s->engine == OR_X256SSS) return x256ss_word(t);
+    return sfc64_word(t);
 }
 
 static void make_block(or_stream *s)
 {
     switch (s->engine) {
+    case OR_X256PPS:
+    case OR_X256SSS:
+    case OR_SFC64S:
+        for (int k = 0; k < 8; k++) s->blk[k] = simd_peek(s, k);
+        break;
     case OR_PHILOX4X32: {
         uint32_t ctr[4] = {(uint32_t)s->st[0], (uint32_t)(s->st[0] >> 32),
                            (uint32_t)s->st[1], (uint32_t)(s->st[1] >> 32)};
@@ -664,6 +694,15 @@ static void advance_block_state(or_stream *s)
         break;
     case OR_CHACHA20: /* 32-bit block counter in the high half of st[5] */
         s->st[5] = (s->st[5] & 0xffffffffu) | ((uint64_t)(uint32_t)((s->st[5] >> 32) + 1u) << 32);
+        break;
+    case OR_X256PPS:
+    case OR_X256SSS:
+    case OR_SFC64S: /* every sub-stream moves one step */
+        for (int k = 0; k < 8; k++) {
+            uint64_t *t = &s->st[4 * k];
+            if (s->engine == OR_SFC64S) (void)sfc64_word(t);
+            else x256_linear(t);
+        }
         break;
     }
     s->blk_ok = 0;
@@ -792,7 +831,9 @@ int or_cwg128_set_weyl(or_stream *s, uint64_t lo, uint64_t hi);
  */
 int or_seed(or_stream *s, uint64_t engine, uint64_t seed, const uint32_t *key, size_t n_key)
 {
-    if (engine >= OR_NENGINE) return -1;
+    /* the SIMD engines are assembled from their seeded scalar engine by the
+     * Python layer (their sub-streams need jump polynomials) */
+    if (engine >= OR_NENGINE || engine >= OR_X256PPS) return -1;
     uint32_t in[64 + 4];
     if (n_key > 64) return -1;
     size_t n_in = 0;
@@ -856,7 +897,7 @@ int or_seed(or_stream *s, uint64_t engine, uint64_t seed, const uint32_t *key, s
 /* Exact state assignment (Section 2.3, set_state). */
 int or_set_state(or_stream *s, uint64_t engine, const uint64_t *st, size_t n, uint64_t phase)
 {
-    if (engine >= OR_NENGINE || n > 16) return -1;
+    if (engine >= OR_NENGINE || n > 32) return -1;
     memset(s, 0, sizeof *s);
     s->engine = engine;
     memcpy(s->st, st, n * 8);

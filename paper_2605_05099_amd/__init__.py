@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "librp.so")
 # status codes, engines, distributions, dtypes (include/rp.h)
 RP_OK, RP_EINVAL, RP_ENOMEM, RP_EUNSUPPORTED, RP_EDEVICE, RP_ENOTSPD, RP_ENULL = 0, -1, -2, -3, -4, -5, -6
 (RP_X256PP, RP_PCG64, RP_PHILOX4X32, RP_PHILOX, RP_SFC64, RP_RANLUX, RP_X256SS, RP_SQUARES, RP_XORO128, RP_XS128,
- RP_CHACHA20, RP_CWG128) = range(12)
+ RP_CHACHA20, RP_CWG128, RP_X256PPS, RP_X256SSS, RP_SFC64S) = range(15)
 RP_SUB_KEY, RP_SUB_INC, RP_SUB_SPAWN, RP_SUB_JUMP = range(4)
 RP_RAW, RP_U01, RP_BOUNDED, RP_NORM, RP_EXP = range(5)
 RP_U64, RP_U32, RP_F64, RP_F32 = range(4)
@@ -31,9 +31,10 @@ RP_FULL_MANTISSA, RP_SQUEEZE = 1, 2  # settings (rp_set_flag)
 
 ENGINES = {"x256++": RP_X256PP, "x256**": RP_X256SS, "pcg64": RP_PCG64, "philox4x32": RP_PHILOX4X32, "philox": RP_PHILOX,
            "sfc64": RP_SFC64, "ranlux++": RP_RANLUX, "squares": RP_SQUARES, "xoro++": RP_XORO128, "x128+": RP_XS128,
-           "chacha20": RP_CHACHA20, "cwg128": RP_CWG128}
+           "chacha20": RP_CHACHA20, "cwg128": RP_CWG128, "x256++simd": RP_X256PPS, "x256**simd": RP_X256SSS,
+           "sfc64simd": RP_SFC64S}
 STATE_WORDS = {RP_X256PP: 4, RP_PCG64: 4, RP_PHILOX4X32: 3, RP_PHILOX: 6, RP_SFC64: 4, RP_RANLUX: 9, RP_X256SS: 4, RP_SQUARES: 2, RP_XORO128: 2, RP_XS128: 2, RP_CHACHA20: 6,
-               RP_CWG128: 8}
+               RP_CWG128: 8, RP_X256PPS: 32, RP_X256SSS: 32, RP_SFC64S: 32}
 
 _vp, _sz, _u64, _u32, _int = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
 _SIGS = {

@@ -1387,6 +1387,85 @@ struct LaneCwg128 {
     }
 };
 
+// SIMD engines (Section 4.1): eight sub-streams per substream.  A round is one
+// word of each sub-stream, in sub-stream order, formed together; the
+// sub-streams move one step when the round is used.  `used` is the phase
+// (words of the round already returned); the round's words are picked with a
+// select chain.
+template <int KIND>  // RP_X256PPS, RP_X256SSS or RP_SFC64S
+struct LaneSimd {
+    uint64_t s[32];   // sub-stream k at s[4 k .. 4 k + 3]
+    uint64_t cur[8];  // the round formed from s
+    int used;
+    __device__ void round()
+    {
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            if constexpr (KIND == RP_SFC64S) {
+                cur[k] = s[4 * k] + s[4 * k + 1] + s[4 * k + 3];
+            } else {
+                X256 c{s[4 * k], s[4 * k + 1], s[4 * k + 2], s[4 * k + 3]};
+                cur[k] = KIND == RP_X256SSS ? c.next_ss() : c.next();
+            }
+        }
+    }
+    __device__ void step()
+    {
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            if constexpr (KIND == RP_SFC64S) {
+                Sfc64 c{s[4 * k], s[4 * k + 1], s[4 * k + 2], s[4 * k + 3]};
+                (void)c.next();
+                s[4 * k] = c.a;
+                s[4 * k + 1] = c.b;
+                s[4 * k + 2] = c.c;
+                s[4 * k + 3] = c.ctr;
+            } else {
+                X256 c{s[4 * k], s[4 * k + 1], s[4 * k + 2], s[4 * k + 3]};
+                c.linear();
+                s[4 * k] = c.s0;
+                s[4 * k + 1] = c.s1;
+                s[4 * k + 2] = c.s2;
+                s[4 * k + 3] = c.s3;
+            }
+        }
+    }
+    __device__ void load(const FillArgs &a, uint64_t i)
+    {
+#pragma unroll
+        for (int w = 0; w < 32; w++) s[w] = a.words[(uint64_t)w * a.n + i];
+        used = (int)a.phase[i];
+        round();
+    }
+    __device__ uint64_t next()
+    {
+        if (used == 8) {
+            step();
+            round();
+            used = 0;
+        }
+        uint64_t w = cur[0];
+#pragma unroll
+        for (int k = 1; k < 8; k++) w = (used == k) ? cur[k] : w;
+        used++;
+        return w;
+    }
+    __device__ void reserve(int) {}
+    __device__ void store(const FillArgs &a, uint64_t i)
+    {
+        if (used == 8) {
+            step();
+            used = 0;
+        }
+#pragma unroll
+        for (int w = 0; w < 32; w++) a.words[(uint64_t)w * a.n + i] = s[w];
+        a.phase[i] = (uint32_t)used;
+    }
+};
+using LaneX256Simd = LaneSimd<RP_X256PPS>;
+using LaneX256SSSimd = LaneSimd<RP_X256SSS>;
+using LaneSfc64Simd = LaneSimd<RP_SFC64S>;
+
 // Lanes of a wavefront that run serial streams drift apart in how many words
 // they have used, so a per-lane "make a block when the current one is used
 // up" branch would run the block computation for the whole wavefront on
@@ -1787,6 +1866,9 @@ int launch_fill(int engine, int dist, int dtype, const FillArgs &a, hipStream_t 
     case RP_XS128: return dispatch_dist<false, LaneXs128>(dist, dtype, a, st);
     case RP_SFC64: return dispatch_dist<false, LaneSfc64>(dist, dtype, a, st);
     case RP_CWG128: return dispatch_dist<false, LaneCwg128>(dist, dtype, a, st);
+    case RP_X256PPS: return dispatch_dist<false, LaneX256Simd>(dist, dtype, a, st);
+    case RP_X256SSS: return dispatch_dist<false, LaneX256SSSimd>(dist, dtype, a, st);
+    case RP_SFC64S: return dispatch_dist<false, LaneSfc64Simd>(dist, dtype, a, st);
     case RP_RANLUX: return dispatch_dist<false, LaneRanlux>(dist, dtype, a, st);
     }
     return fail(RP_EINVAL, "unknown engine");
@@ -1829,6 +1911,9 @@ int launch_fill_law(int engine, int law, bool f32, const FillArgs &a, hipStream_
     case RP_XS128: return dispatch_law<false, LaneXs128>(law, f32, a, st);
     case RP_SFC64: return dispatch_law<false, LaneSfc64>(law, f32, a, st);
     case RP_CWG128: return dispatch_law<false, LaneCwg128>(law, f32, a, st);
+    case RP_X256PPS: return dispatch_law<false, LaneX256Simd>(law, f32, a, st);
+    case RP_X256SSS: return dispatch_law<false, LaneX256SSSimd>(law, f32, a, st);
+    case RP_SFC64S: return dispatch_law<false, LaneSfc64Simd>(law, f32, a, st);
     case RP_RANLUX: return dispatch_law<false, LaneRanlux>(law, f32, a, st);
     }
     return fail(RP_EINVAL, "unknown engine");

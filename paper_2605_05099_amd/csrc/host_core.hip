@@ -94,7 +94,15 @@ static const EngineInfo kEngines[RP_NENGINES] = {
     {"x128+", "xorshift128+ (Vigna, 2014), 2 state words, period 2^128-1", 2, 1},
     {"chacha20", "ChaCha20 (Bernstein, 2008), 6 state words, period 2^35 per nonce", 6, 8},
     {"cwg128", "cwg128 (Dziala, 2022), 8 state words, period 2^128 per Weyl increment", 8, 1},
+    {"x256++simd", "xoshiro256++ x 8 interleaved (Vigna and Blackman, 2019), 32 state words", 32, 8},
+    {"x256**simd", "xoshiro256** x 8 interleaved (Blackman and Vigna, 2018), 32 state words", 32, 8},
+    {"sfc64simd", "sfc64 x 8 interleaved (Chris Doty-Humphrey, 2010), 32 state words", 32, 8},
 };
+
+namespace {
+bool is_simd(int e) { return e == RP_X256PPS || e == RP_X256SSS || e == RP_SFC64S; }
+bool is_x256(int e) { return e == RP_X256PP || e == RP_X256SS || e == RP_X256PPS || e == RP_X256SSS; }
+}  // namespace
 
 namespace rp {
 int state_words(int e) { return kEngines[e].words; }
@@ -563,6 +571,37 @@ static uint64_t host_next(rp_rng *r)
         st[0] = s.a; st[1] = s.b; st[2] = s.c; st[3] = s.ctr;
         return w;
     }
+    case RP_X256PPS:
+    case RP_X256SSS:
+    case RP_SFC64S: {
+        // word `phase` of the round: sub-stream `phase`'s next word, taken
+        // from a copy; all eight sub-streams move once the round is used
+        uint64_t *l = st + 4 * r->phase;
+        uint64_t w;
+        if (r->engine == RP_SFC64S) {
+            Sfc64 c{l[0], l[1], l[2], l[3]};
+            w = c.next();
+        } else {
+            X256 c{l[0], l[1], l[2], l[3]};
+            w = r->engine == RP_X256SSS ? c.next_ss() : c.next();
+        }
+        if (++r->phase == 8) {
+            r->phase = 0;
+            for (int k = 0; k < 8; k++) {
+                uint64_t *m = st + 4 * k;
+                if (r->engine == RP_SFC64S) {
+                    Sfc64 c{m[0], m[1], m[2], m[3]};
+                    (void)c.next();
+                    m[0] = c.a; m[1] = c.b; m[2] = c.c; m[3] = c.ctr;
+                } else {
+                    X256 c{m[0], m[1], m[2], m[3]};
+                    c.linear();
+                    m[0] = c.s0; m[1] = c.s1; m[2] = c.s2; m[3] = c.s3;
+                }
+            }
+        }
+        return w;
+    }
     case RP_CWG128: {
         Cwg128 g{{st[0], st[1]}, {st[2], st[3]}, {st[4], st[5]}, {st[6], st[7]}};
         const uint64_t w = g.next();
@@ -631,6 +670,43 @@ static void sfc64_setabc(rp_rng *r, uint64_t a, uint64_t b, uint64_t c)
     for (int i = 0; i < 18; i++) host_next(r);
 }
 
+// SIMD engines (Section 4.1): the eight sub-streams from the scalar base
+// state: xoshiro sub-stream k is the base jumped by k 2^253 steps (x^(2^253)
+// mod P applied k times), sfc64 sub-stream k has k 2^61 added to the counter.
+static const Poly &x256_lane_jump()
+{
+    static const Poly J = [] {
+        Poly x;
+        x.flip(1);
+        const Poly &P = x256_charpoly();
+        for (int i = 0; i < 253; i++) x = poly_mulmod(x, x, P);
+        return x;
+    }();
+    return J;
+}
+
+static void simd_from_base(rp_rng *r, const uint64_t base[4])
+{
+    uint64_t cur[4];
+    memcpy(cur, base, sizeof cur);
+    for (int k = 0; k < 8; k++) {
+        if (r->engine == RP_SFC64S) {
+            memcpy(r->st + 4 * k, base, 24);
+            r->st[4 * k + 3] = base[3] + ((uint64_t)k << 61);
+        } else {
+            memcpy(r->st + 4 * k, cur, sizeof cur);
+            x256_apply(cur, x256_lane_jump());
+        }
+    }
+    r->phase = 0;
+}
+
+// the scalar engine a SIMD engine interleaves
+static int simd_base_engine(int e)
+{
+    return e == RP_X256PPS ? RP_X256PP : e == RP_X256SSS ? RP_X256SS : RP_SFC64;
+}
+
 // cwg128 stream setter: the Weyl increment made odd, then 96 warm-up steps
 // (Table 3 caption); x, a and the Weyl sequence are kept.
 static void cwg128_setweyl(rp_rng *r, uint64_t lo, uint64_t hi)
@@ -643,6 +719,14 @@ static void cwg128_setweyl(rp_rng *r, uint64_t lo, uint64_t hi)
 
 static void seed_state(rp_rng *r, uint64_t seed, const uint32_t *key, size_t n_key)
 {
+    if (is_simd(r->engine)) {  // seeded as the scalar engine, then the sub-streams
+        rp_rng b;
+        b.engine = simd_base_engine(r->engine);
+        seed_state(&b, seed, key, n_key);
+        memset(r->st, 0, sizeof r->st);
+        simd_from_base(r, b.st);
+        return;
+    }
     std::vector<uint32_t> in = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     if (n_key) {
         in.resize(4, 0u);  // keep "no key" and "key [0]" distinct
@@ -848,6 +932,12 @@ static const char *state_defect(int e, const uint64_t *w, size_t stride)
     case RP_CWG128:
         if (!(W(6) & 1)) return "an even cwg128 Weyl increment";
         break;
+    case RP_X256PPS:
+    case RP_X256SSS:
+        for (int k = 0; k < 8; k++)
+            if (!(W(4 * k) | W(4 * k + 1) | W(4 * k + 2) | W(4 * k + 3)))
+                return "an all-zero xoshiro256 sub-stream (a fixed point)";
+        break;
     case RP_RANLUX: {
         // m = 2^576 - 2^240 + 1: limbs 4..8 all ones, limb 3 bits 48..63, limb 0 = 1
         static const uint64_t m[9] = {1, 0, 0, 0xFFFF000000000000ull, ~0ull, ~0ull, ~0ull, ~0ull, ~0ull};
@@ -886,6 +976,9 @@ static int jump_limit(int e)
         return 64;
     case RP_CHACHA20:  // 32-bit block counter per nonce
         return 32;
+    case RP_X256PPS:  // every sub-stream moves; they are 2^253 steps apart
+    case RP_X256SSS:
+        return 253;
     default:
         return 0;
     }
@@ -894,7 +987,9 @@ static int jump_limit(int e)
 // Whether n substreams of 2^k engine steps each fit in one period without
 // overlap: n * 2^k <= period.  The counter engines and pcg64 have periods of
 // exactly 2^jump_limit steps (blocks for the block engines), the xor engines
-// 2^jump_limit - 1; ranlux++'s period (about 2^570) holds every family.
+// 2^jump_limit - 1; ranlux++'s period (about 2^570) holds every family; the
+// sub-streams of the SIMD engines are 2^253 steps apart, each substream
+// taking 2^k steps of every sub-stream.
 static bool jump_family_fits(int e, int k, uint64_t n)
 {
     if (e == RP_RANLUX) return true;
@@ -938,6 +1033,12 @@ static int advance_impl(rp_rng *rng, uint64_t lo, uint64_t hi)
     case RP_X256SS:
         x256_apply(st, poly_xpow(lo, hi, x256_charpoly()));
         return RP_OK;
+    case RP_X256PPS:  // every sub-stream moves n steps; the phase is kept
+    case RP_X256SSS: {
+        const Poly p = poly_xpow(lo, hi, x256_charpoly());
+        for (int k = 0; k < 8; k++) x256_apply(st + 4 * k, p);
+        return RP_OK;
+    }
     case RP_SQUARES:  // period 2^64: hi 2^64 steps are a full period
         st[0] += lo;
         return RP_OK;
@@ -998,12 +1099,15 @@ static int jump_pow2(rp_rng *rng, int k)
     if (k < 128) return advance_impl(rng, k < 64 ? (1ull << k) : 0, k >= 64 ? (1ull << (k - 64)) : 0);
     switch (rng->engine) {
     case RP_X256PP:
-    case RP_X256SS: {
+    case RP_X256SS:
+    case RP_X256PPS:
+    case RP_X256SSS: {
         Poly x;
         x.flip(1);
         const Poly &P = x256_charpoly();
         for (int i = 0; i < k; i++) x = poly_mulmod(x, x, P);  // x^(2^k)
-        x256_apply(rng->st, x);
+        const int lanes = is_simd(rng->engine) ? 8 : 1;
+        for (int l = 0; l < lanes; l++) x256_apply(rng->st + 4 * l, x);
         return RP_OK;
     }
     case RP_PHILOX: {  // add 2^k to the 256-bit block counter
@@ -1068,6 +1172,14 @@ extern "C" int rp_philox_set_key(rp_rng *rng, uint64_t k0, uint64_t k1)
 extern "C" int rp_sfc64_set_abc(rp_rng *rng, uint64_t a, uint64_t b, uint64_t c)
 {
     if (!rng) return fail(RP_ENULL, "rp_sfc64_set_abc: NULL rng");
+    if (rng->engine == RP_SFC64S) {  // the base as the scalar setter makes it, then the counters
+        rp_rng t;
+        t.engine = RP_SFC64;
+        sfc64_setabc(&t, a, b, c);
+        memset(rng->st, 0, sizeof rng->st);
+        simd_from_base(rng, t.st);
+        return RP_OK;
+    }
     if (rng->engine != RP_SFC64) return fail_rng(rng, RP_EUNSUPPORTED, "sfc64_set_abc: engine is not sfc64");
     sfc64_setabc(rng, a, b, c);
     return RP_OK;
@@ -1100,46 +1212,50 @@ extern "C" int rp_squares_set_key(rp_rng *rng, uint64_t key)
     return RP_OK;
 }
 
-// serialized image: magic, engine, phase, 16 state words, seed, key length, key
-static constexpr uint32_t kMagic = 0x52503031u;  // "RP01"
+// serialized image: magic, engine, phase, key length, 32 state words, seed,
+// key (version 2: 32 state words, for the SIMD engines)
+static constexpr uint32_t kMagic = 0x52503032u;  // "RP02"
+static constexpr size_t kImgWords = 32;
+static constexpr size_t kImgSeed = 16 + 8 * kImgWords;  // offset of the seed
+static constexpr size_t kImgKey = kImgSeed + 8;         // offset of the key
 
 extern "C" int rp_serialize(const rp_rng *rng, void *buf, size_t len, size_t *needed)
 {
     if (!rng) return fail(RP_ENULL, "rp_serialize: NULL rng");
-    size_t need = 4 * 4 + 16 * 8 + 8 + rng->key.size() * 4;
+    size_t need = kImgKey + rng->key.size() * 4;
     if (needed) *needed = need;
     if (!buf) return RP_OK;
     if (len < need) return fail_rng(rng, RP_EINVAL, "rp_serialize: buffer too small (%zu < %zu)", len, need);
     uint8_t *p = (uint8_t *)buf;
     uint32_t hdr[4] = {kMagic, (uint32_t)rng->engine, rng->phase, (uint32_t)rng->key.size()};
     memcpy(p, hdr, 16);
-    memcpy(p + 16, rng->st, 128);
-    memcpy(p + 144, &rng->seed, 8);
-    if (!rng->key.empty()) memcpy(p + 152, rng->key.data(), rng->key.size() * 4);
+    memcpy(p + 16, rng->st, 8 * kImgWords);
+    memcpy(p + kImgSeed, &rng->seed, 8);
+    if (!rng->key.empty()) memcpy(p + kImgKey, rng->key.data(), rng->key.size() * 4);
     return RP_OK;
 }
 
 extern "C" int rp_deserialize(rp_rng *rng, const void *buf, size_t len)
 {
     if (!rng || !buf) return fail(RP_ENULL, "rp_deserialize: NULL argument");
-    if (len < 152) return fail_rng(rng, RP_EINVAL, "rp_deserialize: buffer too small");
+    if (len < kImgKey) return fail_rng(rng, RP_EINVAL, "rp_deserialize: buffer too small");
     const uint8_t *p = (const uint8_t *)buf;
     uint32_t hdr[4];
     memcpy(hdr, p, 16);
     if (hdr[0] != kMagic || hdr[1] >= RP_NENGINES || hdr[2] >= (uint32_t)kEngines[hdr[1]].block || hdr[3] > 1024 ||
-        len < 152 + (size_t)hdr[3] * 4)
+        len < kImgKey + (size_t)hdr[3] * 4)
         return fail_rng(rng, RP_EINVAL, "rp_deserialize: not a serialized stream");
-    uint64_t st[16];
-    memcpy(st, p + 16, 128);
-    for (int k = kEngines[hdr[1]].words; k < 16; k++)
+    uint64_t st[kImgWords];
+    memcpy(st, p + 16, sizeof st);
+    for (int k = kEngines[hdr[1]].words; k < (int)kImgWords; k++)
         if (st[k]) return fail_rng(rng, RP_EINVAL, "rp_deserialize: not a serialized stream");
     if (const char *why = state_defect((int)hdr[1], st, 1))
         return fail_rng(rng, RP_EINVAL, "rp_deserialize: %s is not a state of '%s'", why, kEngines[hdr[1]].id);
     rng->engine = (int)hdr[1];
     rng->phase = hdr[2];
-    memcpy(rng->st, p + 16, 128);
-    memcpy(&rng->seed, p + 144, 8);
-    rng->key.assign((const uint32_t *)(p + 152), (const uint32_t *)(p + 152) + hdr[3]);
+    memcpy(rng->st, st, sizeof st);
+    memcpy(&rng->seed, p + kImgSeed, 8);
+    rng->key.assign((const uint32_t *)(p + kImgKey), (const uint32_t *)(p + kImgKey) + hdr[3]);
     return RP_OK;
 }
 
@@ -1198,7 +1314,7 @@ extern "C" int rp_streams_create(const rp_rng *base, int kind, uint64_t n, int j
     uint64_t jmul[9];
     PcgAffine jpcg{};
     if (kind == RP_SUB_JUMP && n > 1) {
-        if (e == RP_X256PP || e == RP_X256SS) {
+        if (is_x256(e)) {
             Poly base_x;
             base_x.flip(1);
             const Poly &P = x256_charpoly();
@@ -1248,7 +1364,10 @@ extern "C" int rp_streams_create(const rp_rng *base, int kind, uint64_t n, int j
         }
         case RP_SUB_JUMP:
             if (i > 0) {
-                if (e == RP_X256PP || e == RP_X256SS) x256_apply(jumped.st, jpoly);
+                if (is_x256(e)) {
+                    const int lanes = is_simd(e) ? 8 : 1;  // SIMD engines: every sub-stream
+                    for (int l = 0; l < lanes; l++) x256_apply(jumped.st + 4 * l, jpoly);
+                }
                 else if (e == RP_XORO128 || e == RP_XS128) x128_apply(e, jumped.st, jpoly);
                 else if (e == RP_RANLUX) rl_mulmod(jumped.st, jmul, jumped.st);
                 else if (e == RP_PCG64) {
@@ -1869,7 +1988,10 @@ int serial_family(int engine)
     case RP_CHACHA20: return RP_SUB_KEY;
     case RP_PCG64: return RP_SUB_INC;
     case RP_SFC64:
-    case RP_CWG128: return RP_SUB_SPAWN;
+    case RP_CWG128:
+    case RP_X256PPS:
+    case RP_X256SSS:
+    case RP_SFC64S: return RP_SUB_SPAWN;
     default: return RP_SUB_JUMP;
     }
 }
@@ -1882,7 +2004,7 @@ int serial_fallback(rp_rng *rng, int dist, int dtype, uint64_t bound, int flags,
     rp_streams *s = nullptr;
     int rc = rp_streams_create(rng, serial_family(rng->engine), 1, 64, &s);
     if (rc) return rc;
-    uint64_t words[16];
+    uint64_t words[32];
     uint32_t ph = rng->phase;
     memcpy(words, rng->st, sizeof words);
     rc = rp_streams_set(s, words, &ph);
@@ -1926,9 +2048,9 @@ extern "C" int rp_fill_serial(rp_rng *rng, int dist, int dtype, uint64_t bound, 
     int rc = ensure_device_tables();
     if (rc) return rc;
     hipStream_t st = (hipStream_t)hip_stream;
-    // sfc64 and cwg128 have no jump; the 128-bit xor engines have no lane jump tables
+    // sfc64 and cwg128 have no jump; the 128-bit xor and SIMD engines have no lane jump tables
     if (rng->engine == RP_SFC64 || rng->engine == RP_XORO128 || rng->engine == RP_XS128 ||
-        rng->engine == RP_CWG128)
+        rng->engine == RP_CWG128 || is_simd(rng->engine))
         return serial_fallback(rng, dist, dtype, bound, flags, d_out, n, st);
     SerialArgs a{};
     memcpy(a.base, rng->st, sizeof a.base);

@@ -241,6 +241,9 @@ int launch_batched_gen(int engine, const BatchArgs &a, bool beta, unsigned grid,
     case RP_PHILOX: launch_batched_e<LanePhilox64>(a, beta, grid, block, st); break;
     case RP_SFC64: launch_batched_e<LaneSfc64>(a, beta, grid, block, st); break;
     case RP_CWG128: launch_batched_e<LaneCwg128>(a, beta, grid, block, st); break;
+    case RP_X256PPS: launch_batched_e<LaneX256Simd>(a, beta, grid, block, st); break;
+    case RP_X256SSS: launch_batched_e<LaneX256SSSimd>(a, beta, grid, block, st); break;
+    case RP_SFC64S: launch_batched_e<LaneSfc64Simd>(a, beta, grid, block, st); break;
     case RP_RANLUX: launch_batched_e<LaneRanlux>(a, beta, grid, block, st); break;
     default: return fail(RP_EINVAL, "unknown engine");
     }

@@ -177,6 +177,9 @@ int launch_discrete(int engine, bool perm, const FillArgs &f, uint32_t *tab, int
     case RP_PHILOX: launch_discrete_e<LanePhilox64>(perm, f, tab, tbits, st); break;
     case RP_SFC64: launch_discrete_e<LaneSfc64>(perm, f, tab, tbits, st); break;
     case RP_CWG128: launch_discrete_e<LaneCwg128>(perm, f, tab, tbits, st); break;
+    case RP_X256PPS: launch_discrete_e<LaneX256Simd>(perm, f, tab, tbits, st); break;
+    case RP_X256SSS: launch_discrete_e<LaneX256SSSimd>(perm, f, tab, tbits, st); break;
+    case RP_SFC64S: launch_discrete_e<LaneSfc64Simd>(perm, f, tab, tbits, st); break;
     case RP_RANLUX: launch_discrete_e<LaneRanlux>(perm, f, tab, tbits, st); break;
     case RP_SQUARES: launch_discrete_e<LaneSquares>(perm, f, tab, tbits, st); break;
     case RP_XORO128: launch_discrete_e<LaneXoro128>(perm, f, tab, tbits, st); break;

@@ -658,6 +658,9 @@ int launch_fill_mix(int engine, int law, bool f32, const FillArgs &f, hipStream_
     case RP_PHILOX: rc = launch_mix_any<LanePhilox64>(law, f32, f, st); break;
     case RP_SFC64: rc = launch_mix_any<LaneSfc64>(law, f32, f, st); break;
     case RP_CWG128: rc = launch_mix_any<LaneCwg128>(law, f32, f, st); break;
+    case RP_X256PPS: rc = launch_mix_any<LaneX256Simd>(law, f32, f, st); break;
+    case RP_X256SSS: rc = launch_mix_any<LaneX256SSSimd>(law, f32, f, st); break;
+    case RP_SFC64S: rc = launch_mix_any<LaneSfc64Simd>(law, f32, f, st); break;
     case RP_RANLUX: rc = launch_mix_any<LaneRanlux>(law, f32, f, st); break;
     default: return fail(RP_EINVAL, "unknown engine");
     }
@@ -700,6 +703,9 @@ int launch_moments(int engine, const SampArgs &s, hipStream_t st)
     case RP_PHILOX: launch_moments_e<LanePhilox64>(s, st); break;
     case RP_SFC64: launch_moments_e<LaneSfc64>(s, st); break;
     case RP_CWG128: launch_moments_e<LaneCwg128>(s, st); break;
+    case RP_X256PPS: launch_moments_e<LaneX256Simd>(s, st); break;
+    case RP_X256SSS: launch_moments_e<LaneX256SSSimd>(s, st); break;
+    case RP_SFC64S: launch_moments_e<LaneSfc64Simd>(s, st); break;
     case RP_RANLUX: launch_moments_e<LaneRanlux>(s, st); break;
     default: return fail(RP_EINVAL, "unknown engine");
     }
@@ -722,6 +728,9 @@ int launch_norm_rows(int engine, const SampArgs &s, hipStream_t st)
     case RP_PHILOX: hipLaunchKernelGGL(k_norm_rows<LanePhilox64>, grid, block, 0, st, s); break;
     case RP_SFC64: hipLaunchKernelGGL(k_norm_rows<LaneSfc64>, grid, block, 0, st, s); break;
     case RP_CWG128: hipLaunchKernelGGL(k_norm_rows<LaneCwg128>, grid, block, 0, st, s); break;
+    case RP_X256PPS: hipLaunchKernelGGL(k_norm_rows<LaneX256Simd>, grid, block, 0, st, s); break;
+    case RP_X256SSS: hipLaunchKernelGGL(k_norm_rows<LaneX256SSSimd>, grid, block, 0, st, s); break;
+    case RP_SFC64S: hipLaunchKernelGGL(k_norm_rows<LaneSfc64Simd>, grid, block, 0, st, s); break;
     case RP_RANLUX: hipLaunchKernelGGL(k_norm_rows<LaneRanlux>, grid, block, 0, st, s); break;
     default: return fail(RP_EINVAL, "unknown engine");
     }
@@ -743,6 +752,9 @@ int launch_gamma_elem(int engine, const SampArgs &s, bool beta, hipStream_t st)
     case RP_PHILOX: launch_elem_e<LanePhilox64>(s, beta, st); break;
     case RP_SFC64: launch_elem_e<LaneSfc64>(s, beta, st); break;
     case RP_CWG128: launch_elem_e<LaneCwg128>(s, beta, st); break;
+    case RP_X256PPS: launch_elem_e<LaneX256Simd>(s, beta, st); break;
+    case RP_X256SSS: launch_elem_e<LaneX256SSSimd>(s, beta, st); break;
+    case RP_SFC64S: launch_elem_e<LaneSfc64Simd>(s, beta, st); break;
     case RP_RANLUX: launch_elem_e<LaneRanlux>(s, beta, st); break;
     default: return fail(RP_EINVAL, "unknown engine");
     }

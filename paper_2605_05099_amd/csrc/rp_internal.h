@@ -11,7 +11,7 @@
 
 struct rp_rng {
     int engine = RP_X256PP;
-    uint64_t st[16] = {0};  // state words, Table 3 order
+    uint64_t st[32] = {0};  // state words, Table 3 order (32 for the SIMD engines)
     uint32_t phase = 0;     // words used from the current block (block engines)
     uint64_t seed = 0;      // last seed given to rp_seed (base for substreams)
     std::vector<uint32_t> key;

@@ -18,6 +18,9 @@ FAMILY = {
     "x128+": (rp.RP_SUB_JUMP, "jump"),
     "chacha20": (rp.RP_SUB_KEY, "nonce"),
     "cwg128": (rp.RP_SUB_INC, "inc"),
+    "x256++simd": (rp.RP_SUB_JUMP, "jump"),
+    "x256**simd": (rp.RP_SUB_JUMP, "jump"),
+    "sfc64simd": (rp.RP_SUB_SPAWN, "spawn"),
 }
 ENGINES = list(FAMILY)
 

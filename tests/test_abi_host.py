@@ -12,7 +12,8 @@ import oracle
 import paper_2605_05099_amd as rp
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-ENGINES = ["x256++", "pcg64", "philox4x32", "philox", "sfc64", "ranlux++", "cwg128"]
+ENGINES = ["x256++", "pcg64", "philox4x32", "philox", "sfc64", "ranlux++", "cwg128", "x256++simd", "x256**simd",
+           "sfc64simd"]
 
 
 def declared_functions():
@@ -256,7 +257,8 @@ def test_ranlux_long_host_draw_matches_oracle():
 ALL_ENGINES = list(rp.ENGINES)
 # exclusive bound on k for jumps by 2^k steps (the period of one stream)
 JUMP_LIMIT = {"x256++": 256, "x256**": 256, "philox": 256, "ranlux++": 256, "pcg64": 128, "philox4x32": 128,
-              "xoro++": 128, "x128+": 128, "squares": 64, "chacha20": 32, "sfc64": 0, "cwg128": 0}
+              "xoro++": 128, "x128+": 128, "squares": 64, "chacha20": 32, "sfc64": 0, "cwg128": 0,
+              "x256++simd": 253, "x256**simd": 253, "sfc64simd": 0}
 
 
 @pytest.mark.parametrize("engine", ALL_ENGINES)
@@ -289,6 +291,7 @@ def test_jump_bounds_follow_the_period(engine):
 def test_set_state_rejects_states_seeding_never_makes():
     cases = [("x256++", [0, 0, 0, 0]), ("x256**", [0, 0, 0, 0]), ("xoro++", [0, 0]), ("x128+", [0, 0]),
              ("pcg64", [1, 2, 4, 0]), ("squares", [7, 10]), ("cwg128", [1, 2, 3, 4, 5, 6, 8, 0]),
+             ("x256++simd", [k + 1 for k in range(12)] + [0, 0, 0, 0] + [5] * 16),
              ("ranlux++", _rl_words(0)),
              ("ranlux++", _rl_words(RL_M)), ("ranlux++", _rl_words(2**576 - 1))]
     for engine, words in cases:

@@ -538,3 +538,47 @@ def test_cwg128_streams_differ_and_are_uniform():
         assert stats.kstest(u, "uniform").pvalue > 1e-4
         bits = np.unpackbits(x.view(np.uint8)).reshape(-1, 64).mean(axis=0)
         assert np.abs(bits - 0.5).max() < 5 * 0.5 / np.sqrt(len(x))
+
+
+# ---- SIMD engines (Section 4.1: x256++simd, x256**simd, sfc64simd) ------------
+# Eight disjoint scalar sub-streams: xoshiro sub-stream k is the seeded base
+# jumped by k 2^253 steps, sfc64 sub-stream k has k 2^61 added to the
+# counter.  The paper fixes the sub-streams and that buffers fill in 8-word
+# chunks; the order within a chunk (sub-stream order) is the reading taken.
+# Each sub-stream is checked against the scalar engine built independently
+# (jumps pinned above as equal to stepping).
+
+@pytest.mark.parametrize("engine,scalar", [("x256++simd", "x256++"), ("x256**simd", "x256**")])
+def test_x256_simd_interleaves_jumped_scalar_streams(engine, scalar):
+    t = 300
+    words = Stream.seeded(engine, 31).raw(8 * t).reshape(t, 8)
+    for k in range(8):
+        ref = Stream.seeded(scalar, 31).advance(k * 2**253).raw(t)
+        assert np.array_equal(words[:, k], ref), k
+
+
+def test_sfc64_simd_interleaves_counter_offset_streams():
+    t = 300
+    s = Stream.seeded("sfc64simd", 8)
+    base = Stream.seeded("sfc64", 8).state[:4]
+    words = s.raw(8 * t).reshape(t, 8)
+    for k in range(8):
+        ref = Stream.from_state("sfc64", base[:3] + [(base[3] + k * 2**61) % 2**64]).raw(t)
+        assert np.array_equal(words[:, k], ref), k
+    # the stream setter: the scalar setter's state, then the counter offsets
+    a = Stream("sfc64simd").sfc64_set_abc(1, 2, 3).raw(16).reshape(2, 8)
+    b = Stream("sfc64").sfc64_set_abc(1, 2, 3).state[:4]
+    for k in (0, 5):
+        ref = Stream.from_state("sfc64", b[:3] + [b[3] + k * 2**61]).raw(2)
+        assert np.array_equal(a[:, k], ref)
+
+
+def test_x256_simd_advance_moves_every_substream_and_keeps_the_phase():
+    s = Stream.seeded("x256++simd", 4)
+    s.raw(3)                        # three words of the first round used
+    a = s.copy().advance(1000)      # 1000 rounds of every sub-stream
+    b = s.copy()
+    b.raw(5 + 8 * 999)              # the rest of this round and 999 more...
+    b.raw(3)                        # ...and the same three words of the next
+    assert a.phase == b.phase == 3
+    assert a.raw(40).tolist() == b.raw(40).tolist()

@@ -17,7 +17,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 ENGINES = ["x256++", "pcg64", "philox4x32", "philox", "ranlux++", "sfc64", "x256**", "squares", "chacha20",
-           "xoro++", "x128+", "cwg128"]
+           "xoro++", "x128+", "cwg128", "x256++simd", "x256**simd", "sfc64simd"]
 CASES = [
     (rp.RP_RAW, rp.RP_U64, 0, 0),
     (rp.RP_RAW, rp.RP_U32, 0, 0),
@@ -63,13 +63,13 @@ def test_serial_matches_oracle(engine, case):
     dist, dtype, bound, flags = case
     rng = rp.rp_create(engine).seed(7)
     o = oracle.Stream.seeded(engine, 7)
-    if engine in ("sfc64", "cwg128"):   # no jump: move on by drawing
+    if engine in ("sfc64", "cwg128", "sfc64simd"):   # no jump: move on by drawing
         rng.raw_host(3)
         o.raw(3)
     else:
         rng.advance(3)
         o.advance(3)
-    if engine in ("philox4x32", "philox", "ranlux++", "chacha20"):
+    if engine in ("philox4x32", "philox", "ranlux++", "chacha20", "x256++simd", "x256**simd", "sfc64simd"):
         rng.raw_host(1)                 # and with a partly used block
         o.raw(1)
     for n in (1, 777, 40001):           # successive calls continue the stream

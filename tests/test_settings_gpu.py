@@ -134,7 +134,7 @@ def test_streams_settings_roundtrip_through_images():
 
 
 JUMP_LIMIT = {"x256++": 256, "x256**": 256, "philox": 256, "ranlux++": 256, "pcg64": 128, "philox4x32": 128,
-              "xoro++": 128, "x128+": 128, "squares": 64, "chacha20": 32}
+              "xoro++": 128, "x128+": 128, "squares": 64, "chacha20": 32, "x256++simd": 253, "x256**simd": 253}
 
 
 # engines whose period is 2^bound - 1 rather than 2^bound (steps or blocks)
