@@ -304,10 +304,13 @@ def part_mvn(torch, rp, workloads, tm, sp, np):
         gm = torch.empty(d, dtype=torch.float32, device="cuda")
         gL = torch.empty((d, d), dtype=torch.float32, device="cuda")
         ms_b = tm(lambda: rp.rp_mvn_backward(S, G, d, nr, gm, gL, sp))
-        fl = 2.0 * nr * d * d
+        # the method's own flops: row i needs sum_c (c + 1) multiply-adds with
+        # a lower-triangular L, i.e. d (d + 1) flops (2 d^2 for a full matrix)
+        fl = 1.0 * nr * d * (d + 1)
         mv[f"d{d}"] = {"fwd_ms": round(ms_f, 4), "fwd_tflops": round(fl / ms_f / 1e9, 2),
                        "fwd_mfma_frac": round(fl / ms_f / 1e9 / FP32_MFMA_PEAK_TFLOPS, 4),
-                       "bwd_ms": round(ms_b, 4), "bwd_tflops": round(fl / 2 / ms_b / 1e9, 2),
+                       "flops_per_row": d * (d + 1),
+                       "bwd_ms": round(ms_b, 4), "bwd_tflops": round(fl / ms_b / 1e9, 2),
                        "rows_per_s_g": round(nr / ms_f / 1e6, 3)}
         del S, X, G
     out["mvn_2p20_rows"] = mv

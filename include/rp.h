@@ -305,8 +305,10 @@ int rp_fill(rp_streams *s, int dist, int dtype, uint64_t bound, int flags, void 
  * binary32; d_out holds n * per_stream floats (4-byte aligned).  Law 9 is
  * the float gamma: Marsaglia-Tsang on 32-bit items (the float ziggurat's
  * binary32 normal, 24-bit uniforms for the test and the shape < 1 boost),
- * binary64 arithmetic, theta G rounded once.  Laws 10-14 give
- * RP_EUNSUPPORTED. */
+ * binary64 arithmetic, theta G rounded once.  Laws 10-14 combine, on one
+ * item stream per call, float gammas (the law 9 draw in binary64, before any
+ * rounding) and binary32 normals of the float ziggurat as their binary64
+ * forms above do, in binary64, rounded once to binary32. */
 enum {
     RP_LAW_UNIF = 1,
     RP_LAW_NORMAL = 2,
@@ -476,11 +478,14 @@ int rp_mvn_factor(const double *Sigma, int d, double *A, int *rank);
 /* Row i < n of X (n x d, row-major, binary32) is mu + L z_i, where z_i is the
  * next d standard normals of substream i (ziggurat in binary64, rounded to
  * binary32); that is X = mu + Z L^T.  The contraction runs on the matrix
- * cores in binary32 with binary32 accumulation.  L is the d x d lower
- * factor (row-major binary32; the entries above the diagonal are read, so
- * they must be zero), mu has d entries.  Substreams i < n are advanced by
+ * cores in binary32 with binary32 accumulation.  L is the d x d factor
+ * (row-major binary32), the Cholesky factor or any A from rp_mvn_factor:
+ * the whole matrix is read, and when every entry above the diagonal is +0
+ * the contraction skips the products with them (exact zeros; the check runs
+ * on the device).  mu has d entries.  Substreams i < n are advanced by
  * their d normals.  Device pointers owned by the caller; a workspace of
- * n x d floats is taken from the device's stream-ordered pool. */
+ * n x d floats (plus 256 bytes) is taken from the device's stream-ordered
+ * pool. */
 int rp_mvn(rp_streams *s, const float *d_mu, const float *d_L, int d, uint64_t n, float *d_X, void *hip_stream);
 /* Backward of rp_mvn for upstream gradient G (n x d): gmu = sum of the rows
  * of G, gL = tril(G^T Z) (d x d row-major, zeros above the diagonal).  Z is

@@ -62,6 +62,7 @@ def lib():
             "or_normf": ([vp, vp, sz], None), "or_expf": ([vp, vp, sz], None),
             "or_permutation": ([vp, ctypes.c_uint32, vp], None),
             "or_gammaf": ([vp, ctypes.c_double, ctypes.c_double, vp, sz], None),
+            "or_mixf": ([vp, ctypes.c_int, vp, vp, sz], None),
             "or_sample": ([vp, ctypes.c_uint32, ctypes.c_uint32, vp], None),
             "or_norm_moments": ([vp, sz, vp, vp], None),
             "or_gamma": ([vp, ctypes.c_double, vp, sz, vp], None),
@@ -323,6 +324,15 @@ class Stream:
         """n binary32 Gamma(alpha, theta) draws (float gamma)."""
         out = np.empty(n, dtype=np.float32)
         lib().or_gammaf(_p(self.buf), float(alpha), float(theta), _p(out), n)
+        return out
+
+    def mixf(self, law, params, n):
+        """n binary32 draws of a law of several draws (10 beta, 11 chi2, 12 t,
+        13 F, 14 skew-normal): float base draws, binary64 combination, one
+        rounding."""
+        out = np.empty(n, dtype=np.float32)
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float64))
+        lib().or_mixf(_p(self.buf), int(law), _p(p), _p(out), n)
         return out
 
     def permutation(self, n):

@@ -122,11 +122,16 @@ BASE_F32 = {"u01": "u01f", "norm": "normf", "exp": "expf"}
 
 
 def draw_f32(stream, law, p, n):
-    """n binary32 draws of a transform law (the paper's float versions): the
-    binary32 base draw, the transform in binary64 on that value, one
-    rounding to binary32; Gamma(alpha, theta) is the float gamma."""
+    """n binary32 draws of a law (the paper's float versions): the binary32
+    base draw, the transform in binary64 on that value, one rounding to
+    binary32; Gamma(alpha, theta) is the float gamma; the laws of several
+    draws combine float gammas (binary64, unrounded) and binary32 normals of
+    one item stream in binary64, as their binary64 forms do, with one
+    rounding (oracle.c, or_mixf)."""
     if law == GAMMA:
         return stream.gammaf(p[0], n, p[1])
+    if law in (BETA, CHI2, T, F, SKEWNORMAL):
+        return stream.mixf(law, p, n)
     if law not in BASE:
         raise ValueError(f"law {law} has no binary32 form")
     base = getattr(stream, BASE_F32[BASE[law]])(n).astype(np.float64)

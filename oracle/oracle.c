@@ -1476,18 +1476,68 @@ static double mt_gammaf(half_reader *h, double a)
     }
 }
 
+/* The float gamma draw in binary64 (shape < 1: Gamma(a + 1), then the
+ * U^(1/a) boost on the next item's 24-bit uniform). */
+static double gammaf_draw(half_reader *h, double a)
+{
+    if (a < 1.0) {
+        double g = mt_gammaf(h, a + 1.0);
+        return g * or_boost_pow(u01_24(next32(h)), a);
+    }
+    return mt_gammaf(h, a);
+}
+
 void or_gammaf(or_stream *s, double a, double theta, float *out, size_t n)
 {
     half_reader h = {s, 0, 0};
+    for (size_t i = 0; i < n; i++) out[i] = (float)(theta * gammaf_draw(&h, a));
+}
+
+/* Float versions (Section 4.4) of the laws of several draws (Table 4), law
+ * numbers as rp_fill_lawf's: 10 beta(a, b), 11 chi2(nu), 12 t(nu),
+ * 13 F(nu1, nu2), 14 skew-normal(mu, sigma, alpha).  The base draws are the
+ * float gamma (binary64, unrounded) and the binary32 normal of the float
+ * ziggurat, all on the 32-bit items of one call (a half left over at the end
+ * is dropped); the combination is as for the binary64 laws, in binary64,
+ * rounded once to binary32. */
+void or_mixf(or_stream *s, int law, const double *p, float *out, size_t n)
+{
+    half_reader h = {s, 0, 0};
     for (size_t i = 0; i < n; i++) {
-        double g;
-        if (a < 1.0) {
-            g = mt_gammaf(&h, a + 1.0);
-            g = g * or_boost_pow(u01_24(next32(&h)), a);
-        } else {
-            g = mt_gammaf(&h, a);
+        double v = 0.0;
+        switch (law) {
+        case 10: {
+            double x = gammaf_draw(&h, p[0]);
+            double y = gammaf_draw(&h, p[1]);
+            double t = x + y;
+            v = (t == 0.0) ? p[0] / (p[0] + p[1]) : x / t;
+            break;
         }
-        out[i] = (float)(theta * g);
+        case 11:
+            v = 2.0 * gammaf_draw(&h, p[0] / 2.0);
+            break;
+        case 12: {
+            double z = (double)normf_one(&h);
+            double w = 2.0 * gammaf_draw(&h, p[0] / 2.0);
+            v = z / sqrt(w / p[0]);
+            break;
+        }
+        case 13: {
+            double x = gammaf_draw(&h, p[0] / 2.0);
+            double y = gammaf_draw(&h, p[1] / 2.0);
+            v = (x / p[0]) / (y / p[1]);
+            break;
+        }
+        case 14: {
+            double d = p[2] / sqrt(1.0 + p[2] * p[2]);
+            double c = sqrt(1.0 - d * d);
+            double z0 = (double)normf_one(&h);
+            double z1 = (double)normf_one(&h);
+            v = p[0] + p[1] * (d * fabs(z0) + c * z1);
+            break;
+        }
+        }
+        out[i] = (float)v;
     }
 }
 

@@ -1795,8 +1795,6 @@ static int fill_law_impl(rp_streams *s, int law, const double *p, int np, void *
     }
     }
     if (!ok) return fail(RP_EINVAL, "rp_fill_law: parameters outside the law's domain");
-    if (f32 && law > RP_LAW_GAMMA)
-        return fail(RP_EUNSUPPORTED, "rp_fill_lawf: law %d has no binary32 form (laws 1-9 only)", law);
     if (per_stream == 0) return RP_OK;
     if (!d_out) return fail(RP_ENULL, "rp_fill_law: NULL output");
     if ((uintptr_t)d_out % (f32 ? 4 : 8)) return fail(RP_EINVAL, "rp_fill_law: output not aligned to its element size");

@@ -57,12 +57,32 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb)
 __device__ __forceinline__ int acc_row(int v, int h) { return 8 * (v >> 2) + 4 * h + (v & 3); }
 
 // ---------------------------------------------------------------------------
+// Whether the factor has an entry above the diagonal that is not +0 (*flag
+// = 1; NaN and -0 count) or is lower triangular (0).  For a lower factor
+// column c of X needs only k <= c, so each column tile of the forward stops
+// its k loop after its own last column (half the products at large d); the
+// skipped products are exact zeros.
+__global__ void k_upper_clear(int *flag) { *flag = 0; }
+
+__global__ __launch_bounds__(256) void k_upper_scan(const float *L, int d, int *flag)
+{
+    const uint64_t dd = (uint64_t)d, total = dd * dd;
+    bool nz = false;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t r = e / dd, c = e - r * dd;
+        if (c > r && __float_as_uint(L[e]) != 0u) nz = true;
+    }
+    if (__syncthreads_or(nz) && threadIdx.x == 0) atomicOr(flag, 1);
+}
+
 // forward: block tile 128 rows x BN columns, 4 waves as 2 x 2, wave tile
 // 64 x BN/2 (2 x BN/64 MFMA tiles).  Each lane half takes four consecutive k
 // of an eight-k step, so operand fragments are single 16-byte LDS reads.
+// upper: the flag of k_upper_scan.
 template <int BN>
 __global__ __launch_bounds__(256) void k_mvn_fwd(const float *Z, const float *L, const float *mu, float *X,
-                                                 uint64_t n, int d, unsigned ncol_tiles, int vec)
+                                                 uint64_t n, int d, unsigned ncol_tiles, int vec, const int *upper)
 {
     constexpr int TN = BN / 64;
     __shared__ __align__(16) float As[kTile * kLdK];
@@ -81,7 +101,11 @@ __global__ __launch_bounds__(256) void k_mvn_fwd(const float *Z, const float *L,
 #pragma unroll
             for (int v = 0; v < 16; v++) acc[a][b][v] = 0.f;
     float4 ra[4], rb[BN / 32];
-    const int nk = (d + kKT - 1) / kKT;
+    int nk = (d + kKT - 1) / kKT;
+    if (__builtin_amdgcn_readfirstlane(*upper) == 0) {
+        const int last = (col0 + BN + kKT - 1) / kKT;  // k tiles holding columns < col0 + BN
+        nk = nk < last ? nk : last;
+    }
     const uint64_t dd = (uint64_t)d;
 #pragma unroll
     for (int r = 0; r < 4; r++) {
@@ -351,9 +375,17 @@ extern "C" int rp_mvn(rp_streams *s, const float *d_mu, const float *d_L, int d,
     hipStream_t st = (hipStream_t)hip_stream;
     keep_pool(st);
     float *z = nullptr;
-    hipError_t e = hipMallocAsync((void **)&z, n * (uint64_t)d * sizeof(float), st);
+    const uint64_t zbytes = (n * (uint64_t)d * sizeof(float) + 255) & ~(uint64_t)255;
+    hipError_t e = hipMallocAsync((void **)&z, zbytes + 256, st);
     if (e != hipSuccess) return fail(RP_ENOMEM, "rp_mvn: workspace of %llu floats: %s",
                                      (unsigned long long)(n * (uint64_t)d), hipGetErrorString(e));
+    int *upper = (int *)((char *)z + zbytes);
+    hipLaunchKernelGGL(k_upper_clear, dim3(1), dim3(1), 0, st, upper);
+    {
+        const uint64_t total = (uint64_t)d * (uint64_t)d;
+        const uint64_t blocks = std::min<uint64_t>((total + 255) / 256, 1024);
+        hipLaunchKernelGGL(k_upper_scan, dim3((unsigned)blocks), dim3(256), 0, st, d_L, d, upper);
+    }
     rc = gen_rows(s, z, d, n, true, st);
     if (rc == RP_OK) {
         const int vec = (d % 4 == 0) && al16(d_L) && al16(z) ? 1 : 0;
@@ -361,11 +393,11 @@ extern "C" int rp_mvn(rp_streams *s, const float *d_mu, const float *d_L, int d,
         if (d <= 64) {
             const unsigned nct = 1;
             hipLaunchKernelGGL(k_mvn_fwd<64>, dim3((unsigned)(nrt * nct)), dim3(256), 0, st, z, d_L, d_mu, d_X, n, d,
-                               nct, vec);
+                               nct, vec, (const int *)upper);
         } else {
             const unsigned nct = (unsigned)((d + 127) / 128);
             hipLaunchKernelGGL(k_mvn_fwd<128>, dim3((unsigned)(nrt * nct)), dim3(256), 0, st, z, d_L, d_mu, d_X, n,
-                               d, nct, vec);
+                               d, nct, vec, (const int *)upper);
         }
         e = hipGetLastError();
         if (e != hipSuccess) rc = hip_fail(e, "rp_mvn launch");

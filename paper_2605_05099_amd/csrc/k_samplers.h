@@ -634,12 +634,69 @@ __global__ __launch_bounds__(256) void k_fill_gammaf(FillArgs f)
     eng.store(f, i);
 }
 
+// Float versions of the laws of several draws (rp_fill_lawf): the float
+// gamma (GamMachine on 32-bit items, binary64, unrounded) and the binary32
+// normal of the float ziggurat, combined as in k_fill_mix, in binary64, and
+// rounded once to binary32.  xp as for k_fill_mix.
+template <class E, int LAW>
+__global__ __launch_bounds__(256) void k_fill_mixf(FillArgs f)
+{
+    __shared__ ZigLds zt;
+    __shared__ LogLds lt;
+    load_zig<RP_NORM>(&zt, f.flags);
+    load_logt(&lt);
+    __syncthreads();
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= f.n) return;
+    E eng;
+    eng.load(f, i);
+    ItemEng<E> it(eng);
+    const uint64_t P = f.per_stream;
+    float *out = (float *)f.out + i * P;
+    constexpr int GM = LAW == RP_LAW_BETA ? 1 : (LAW == RP_LAW_F ? 2 : 0);
+    GamMachine<GM, true> gm;
+    if constexpr (LAW == RP_LAW_BETA || LAW == RP_LAW_F) gm.set(f.xp[0], f.xp[1]);
+    else gm.set(f.xp[0], 1.0);
+    for (uint64_t t = 0; t < P;) {
+        double v;
+        if constexpr (LAW == RP_LAW_BETA || LAW == RP_LAW_F || LAW == RP_LAW_CHI2) {
+            if (gm.step(it, &zt, &lt, v)) {
+                if constexpr (LAW == RP_LAW_CHI2) v = 2.0 * v;
+                out[t++] = (float)v;
+            }
+        } else if constexpr (LAW == RP_LAW_T) {
+            double z;
+            while (!zig_candidate<ItemEng<E>, true>(it, &zt, z)) {
+            }
+            while (!gm.step(it, &zt, &lt, v)) {
+            }
+            out[t++] = (float)(z / sqrt((2.0 * v) / f.xp[1]));
+        } else {  // skew-normal
+            double z0, z1;
+            while (!zig_candidate<ItemEng<E>, true>(it, &zt, z0)) {
+            }
+            while (!zig_candidate<ItemEng<E>, true>(it, &zt, z1)) {
+            }
+            out[t++] = (float)(f.xp[0] + f.xp[1] * (f.xp[2] * fabs(z0) + f.xp[3] * z1));
+        }
+    }
+    eng.store(f, i);
+}
+
 template <class E>
 static int launch_mix_any(int law, bool f32, const FillArgs &f, hipStream_t st)
 {
     if (!f32) return launch_mix_e<E>(law, f, st);
-    if (law != RP_LAW_GAMMA) return fail(RP_EUNSUPPORTED, "law %d has no binary32 form", law);
-    hipLaunchKernelGGL(k_fill_gammaf<E>, dim3((unsigned)((f.n + 255) / 256)), dim3(256), 0, st, f);
+    const dim3 grid((unsigned)((f.n + 255) / 256)), block(256);
+    switch (law) {
+    case RP_LAW_GAMMA: hipLaunchKernelGGL(k_fill_gammaf<E>, grid, block, 0, st, f); break;
+    case RP_LAW_BETA: hipLaunchKernelGGL((k_fill_mixf<E, RP_LAW_BETA>), grid, block, 0, st, f); break;
+    case RP_LAW_CHI2: hipLaunchKernelGGL((k_fill_mixf<E, RP_LAW_CHI2>), grid, block, 0, st, f); break;
+    case RP_LAW_T: hipLaunchKernelGGL((k_fill_mixf<E, RP_LAW_T>), grid, block, 0, st, f); break;
+    case RP_LAW_F: hipLaunchKernelGGL((k_fill_mixf<E, RP_LAW_F>), grid, block, 0, st, f); break;
+    case RP_LAW_SKEWNORMAL: hipLaunchKernelGGL((k_fill_mixf<E, RP_LAW_SKEWNORMAL>), grid, block, 0, st, f); break;
+    default: return fail(RP_EINVAL, "unknown law");
+    }
     return RP_OK;
 }
 

@@ -87,3 +87,27 @@ def test_float_gamma_ks_and_mean(alpha):
     x = oracle.Stream.seeded("x256++", 43).gammaf(alpha, 200000, 1.5).astype(np.float64)
     assert stats.kstest(x, stats.gamma(alpha, scale=1.5).cdf).pvalue > 1e-4
     assert abs(x.mean() - 1.5 * alpha) < 6 * 1.5 * np.sqrt(alpha / len(x))
+
+
+@pytest.mark.parametrize("law,p,dist", [c for c in CASES if c[0] in (laws.BETA, laws.CHI2, laws.T, laws.F,
+                                                                      laws.SKEWNORMAL)],
+                         ids=lambda c: str(c) if not hasattr(c, "cdf") else "")
+def test_float_mix_laws_ks(law, p, dist):
+    """The binary32 laws of several draws (float gammas and binary32
+    normals, binary64 combination, one rounding) follow the named law (a
+    swapped parameter or a wrong combination fails the KS test)."""
+    x = laws.draw_f32(oracle.Stream.seeded("x256++", 2000 + law), law, p, N if law not in (laws.T, laws.F) else N // 2)
+    assert x.dtype == np.float32
+    assert np.isfinite(x).all()
+    assert stats.kstest(x.astype(np.float64), dist.cdf).pvalue > 1e-3
+
+
+def test_float_mix_laws_reduce_to_the_float_gamma():
+    """chi2(nu) in binary32 is 2 G(nu / 2) of the float gamma on the same
+    items, and t and F advance the stream as their draws say."""
+    a = oracle.Stream.seeded("pcg64", 77)
+    b = a.copy()
+    x = laws.draw_f32(a, laws.CHI2, (3.0,), 500)
+    y = b.gammaf(1.5, 500, 2.0)
+    assert np.array_equal(x, y)
+    assert a.state == b.state
