@@ -24,8 +24,7 @@ namespace {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int kKT = 32;         // k per LDS stage
-constexpr int kLdK = kKT + 4;   // forward LDS row stride (floats), rows indexed by m / n
+constexpr int kKT = 32;         // backward k (rows of G and Z) per LDS stage
 constexpr int kTile = 128;      // rows of a block tile
 constexpr int kLdT = kTile + 4; // backward LDS row stride (floats), rows indexed by k
 
@@ -79,101 +78,135 @@ __global__ __launch_bounds__(256) void k_upper_scan(const float *L, int d, int *
 // forward: block tile 128 rows x BN columns, 4 waves as 2 x 2, wave tile
 // 64 x BN/2 (2 x BN/64 MFMA tiles).  Each lane half takes four consecutive k
 // of an eight-k step, so operand fragments are single 16-byte LDS reads.
+// The k loop runs in stages of kFK with two LDS buffers (one barrier a
+// stage): the global loads of stage t + 2 are in flight while stage t + 1 is
+// written and stage t is contracted.
+//
+// With a lower factor, column tile c of X needs the k tiles up to its own
+// last column, so its cost grows with c.  Block (row tile r, pair p) does
+// column tiles p and nct - 1 - p of row tile r one after the other, so every
+// block carries about the same number of k stages (blocks of unequal length
+// leave the compute units that drew the long ones working alone at the end).
 // upper: the flag of k_upper_scan.
+constexpr int kFK = 16;          // forward k per LDS stage
+constexpr int kFLd = kFK + 4;    // forward LDS row stride (floats), rows indexed by m / n
+constexpr int kFCpr = kFK / 4;   // threads per operand row of a stage (16 bytes each)
+constexpr int kFRpp = 256 / kFCpr;  // operand rows per pass of the block
+
 template <int BN>
 __global__ __launch_bounds__(256) void k_mvn_fwd(const float *Z, const float *L, const float *mu, float *X,
                                                  uint64_t n, int d, unsigned ncol_tiles, int vec, const int *upper)
 {
     constexpr int TN = BN / 64;
-    __shared__ __align__(16) float As[kTile * kLdK];
-    __shared__ __align__(16) float Bs[BN * kLdK];
-    const unsigned w = xcd_tile(blockIdx.x, gridDim.x);
-    const uint64_t row0 = (uint64_t)(w / ncol_tiles) * kTile;
-    const int col0 = (int)(w % ncol_tiles) * BN;
+    constexpr int NA = kTile / kFRpp, NB = BN / kFRpp;
+    __shared__ __align__(16) float As[2][kTile * kFLd];
+    __shared__ __align__(16) float Bs[2][BN * kFLd];
+    const unsigned npair = (ncol_tiles + 1) / 2;
+    const unsigned wp = xcd_tile(blockIdx.x, gridDim.x);
+    const unsigned rt = wp / npair, pr = wp % npair;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, l32 = lane & 31;
     const int wr = wave >> 1, wc = wave & 1;
-    f32x16 acc[2][TN];
-#pragma unroll
-    for (int a = 0; a < 2; a++)
-#pragma unroll
-        for (int b = 0; b < TN; b++)
-#pragma unroll
-            for (int v = 0; v < 16; v++) acc[a][b][v] = 0.f;
-    float4 ra[4], rb[BN / 32];
-    int nk = (d + kKT - 1) / kKT;
-    if (__builtin_amdgcn_readfirstlane(*upper) == 0) {
-        const int last = (col0 + BN + kKT - 1) / kKT;  // k tiles holding columns < col0 + BN
-        nk = nk < last ? nk : last;
-    }
+    const int lr = tid / kFCpr, lc = 4 * (tid % kFCpr);
     const uint64_t dd = (uint64_t)d;
-#pragma unroll
-    for (int r = 0; r < 4; r++) {
-        const int u = tid + 256 * r;
-        ra[r] = load4(Z, n, dd, row0 + (u >> 3), 4 * (u & 7), vec);
-    }
-#pragma unroll
-    for (int r = 0; r < BN / 32; r++) {
-        const int u = tid + 256 * r;
-        rb[r] = load4(L, dd, dd, (uint64_t)(col0 + (u >> 3)), 4 * (u & 7), vec);
-    }
-    for (int kt = 0; kt < nk; kt++) {
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < 4; r++) {
-            const int u = tid + 256 * r;
-            *(float4 *)&As[(u >> 3) * kLdK + 4 * (u & 7)] = ra[r];
-        }
-#pragma unroll
-        for (int r = 0; r < BN / 32; r++) {
-            const int u = tid + 256 * r;
-            *(float4 *)&Bs[(u >> 3) * kLdK + 4 * (u & 7)] = rb[r];
-        }
-        __syncthreads();
-        if (kt + 1 < nk) {
-            const uint64_t k0 = (uint64_t)(kt + 1) * kKT;
-#pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const int u = tid + 256 * r;
-                ra[r] = load4(Z, n, dd, row0 + (u >> 3), k0 + 4 * (u & 7), vec);
-            }
-#pragma unroll
-            for (int r = 0; r < BN / 32; r++) {
-                const int u = tid + 256 * r;
-                rb[r] = load4(L, dd, dd, (uint64_t)(col0 + (u >> 3)), k0 + 4 * (u & 7), vec);
-            }
-        }
-#pragma unroll
-        for (int s = 0; s < kKT / 8; s++) {
-            float4 af[2], bf[TN];
-#pragma unroll
-            for (int a = 0; a < 2; a++) af[a] = *(const float4 *)&As[(wr * 64 + a * 32 + l32) * kLdK + 8 * s + 4 * h];
-#pragma unroll
-            for (int b = 0; b < TN; b++)
-                bf[b] = *(const float4 *)&Bs[(wc * (BN / 2) + b * 32 + l32) * kLdK + 8 * s + 4 * h];
-#pragma unroll
-            for (int a = 0; a < 2; a++)
-#pragma unroll
-                for (int b = 0; b < TN; b++) {
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a].x, bf[b].x, acc[a][b], 0, 0, 0);
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a].y, bf[b].y, acc[a][b], 0, 0, 0);
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a].z, bf[b].z, acc[a][b], 0, 0, 0);
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a].w, bf[b].w, acc[a][b], 0, 0, 0);
-                }
-        }
-    }
-#pragma unroll
-    for (int b = 0; b < TN; b++) {
-        const int j = col0 + wc * (BN / 2) + b * 32 + l32;
-        if (j >= d) continue;
-        const float m = mu[j];
+    const uint64_t row0 = (uint64_t)rt * kTile;
+    const bool tri = __builtin_amdgcn_readfirstlane(*upper) == 0;
+#pragma unroll 1
+    for (int q = 0; q < 2; q++) {
+        const unsigned ct = q == 0 ? pr : ncol_tiles - 1 - pr;
+        if (q == 1 && ct == pr) break;
+        const int col0 = (int)ct * BN;
+        f32x16 acc[2][TN];
 #pragma unroll
         for (int a = 0; a < 2; a++)
 #pragma unroll
-            for (int v = 0; v < 16; v++) {
-                const uint64_t i = row0 + (uint64_t)(wr * 64 + a * 32 + acc_row(v, h));
-                if (i < n) X[i * dd + j] = acc[a][b][v] + m;
+            for (int b = 0; b < TN; b++)
+#pragma unroll
+                for (int v = 0; v < 16; v++) acc[a][b][v] = 0.f;
+        int nk = (d + kFK - 1) / kFK;
+        if (tri) {
+            const int last = (col0 + BN + kFK - 1) / kFK;  // k tiles holding columns < col0 + BN
+            nk = nk < last ? nk : last;
+        }
+        // unconditional 16-byte loads when the whole tile is inside Z and L
+        const bool full = vec && row0 + kTile <= n && d % kFK == 0 && col0 + BN <= d;
+        const float *pa = Z + (row0 + lr) * dd + lc;
+        const float *pb = L + (uint64_t)(col0 + lr) * dd + lc;
+        float4 ra[NA], rb[NB];
+        auto gload = [&](int kt) {
+            const uint64_t k0 = (uint64_t)kt * kFK;
+            if (full) {
+#pragma unroll
+                for (int r = 0; r < NA; r++) ra[r] = *(const float4 *)(pa + (uint64_t)(r * kFRpp) * dd + k0);
+#pragma unroll
+                for (int r = 0; r < NB; r++) rb[r] = *(const float4 *)(pb + (uint64_t)(r * kFRpp) * dd + k0);
+            } else {
+#pragma unroll
+                for (int r = 0; r < NA; r++) ra[r] = load4(Z, n, dd, row0 + lr + r * kFRpp, k0 + lc, vec);
+#pragma unroll
+                for (int r = 0; r < NB; r++)
+                    rb[r] = load4(L, dd, dd, (uint64_t)(col0 + lr + r * kFRpp), k0 + lc, vec);
             }
+        };
+        auto swrite = [&](int buf) {
+#pragma unroll
+            for (int r = 0; r < NA; r++) *(float4 *)&As[buf][(lr + r * kFRpp) * kFLd + lc] = ra[r];
+#pragma unroll
+            for (int r = 0; r < NB; r++) *(float4 *)&Bs[buf][(lr + r * kFRpp) * kFLd + lc] = rb[r];
+        };
+        auto compute = [&](int buf) {
+#pragma unroll
+            for (int s = 0; s < kFK / 8; s++) {
+                float4 af[2], bf[TN];
+#pragma unroll
+                for (int a = 0; a < 2; a++)
+                    af[a] = *(const float4 *)&As[buf][(wr * 64 + a * 32 + l32) * kFLd + 8 * s + 4 * h];
+#pragma unroll
+                for (int b = 0; b < TN; b++)
+                    bf[b] = *(const float4 *)&Bs[buf][(wc * (BN / 2) + b * 32 + l32) * kFLd + 8 * s + 4 * h];
+#pragma unroll
+                for (int a = 0; a < 2; a++)
+#pragma unroll
+                    for (int b = 0; b < TN; b++) {
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a].x, bf[b].x, acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a].y, bf[b].y, acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a].z, bf[b].z, acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a].w, bf[b].w, acc[a][b], 0, 0, 0);
+                    }
+            }
+        };
+        gload(0);
+        swrite(0);
+        __syncthreads();
+        if (nk > 1) gload(1);
+        for (int kt = 0; kt < nk; kt++) {
+            compute(kt & 1);
+            if (kt + 1 < nk) {
+                swrite((kt + 1) & 1);
+                __syncthreads();
+                if (kt + 2 < nk) gload(kt + 2);
+            }
+        }
+        // element v of a lane's MFMA tile is row 8 (v / 4) + 4 h + v % 4: the
+        // store pointer steps by one row, and by five after every fourth
+        const bool rows_full = row0 + kTile <= n;
+#pragma unroll
+        for (int b = 0; b < TN; b++) {
+            const int j = col0 + wc * (BN / 2) + b * 32 + l32;
+            if (j >= d) continue;
+            const float m = mu[j];
+            const uint64_t i0 = row0 + (uint64_t)(wr * 64 + 4 * h);
+            float *p = X + i0 * dd + j;
+#pragma unroll
+            for (int a = 0; a < 2; a++)
+#pragma unroll
+                for (int v = 0; v < 16; v++) {
+                    const int r = a * 32 + acc_row(v, 0);
+                    if (rows_full || i0 + r < n) *p = acc[a][b][v] + m;
+                    p += ((v & 3) == 3) ? 5 * dd : dd;
+                }
+        }
+        __syncthreads();  // the next tile of the pair rewrites both LDS buffers
     }
 }
 
@@ -392,12 +425,12 @@ extern "C" int rp_mvn(rp_streams *s, const float *d_mu, const float *d_L, int d,
         const uint64_t nrt = (n + kTile - 1) / kTile;
         if (d <= 64) {
             const unsigned nct = 1;
-            hipLaunchKernelGGL(k_mvn_fwd<64>, dim3((unsigned)(nrt * nct)), dim3(256), 0, st, z, d_L, d_mu, d_X, n, d,
-                               nct, vec, (const int *)upper);
+            hipLaunchKernelGGL(k_mvn_fwd<64>, dim3((unsigned)nrt), dim3(256), 0, st, z, d_L, d_mu, d_X, n, d, nct,
+                               vec, (const int *)upper);
         } else {
-            const unsigned nct = (unsigned)((d + 127) / 128);
-            hipLaunchKernelGGL(k_mvn_fwd<128>, dim3((unsigned)(nrt * nct)), dim3(256), 0, st, z, d_L, d_mu, d_X, n,
-                               d, nct, vec, (const int *)upper);
+            const unsigned nct = (unsigned)((d + 127) / 128), npair = (nct + 1) / 2;
+            hipLaunchKernelGGL(k_mvn_fwd<128>, dim3((unsigned)(nrt * npair)), dim3(256), 0, st, z, d_L, d_mu, d_X,
+                               n, d, nct, vec, (const int *)upper);
         }
         e = hipGetLastError();
         if (e != hipSuccess) rc = hip_fail(e, "rp_mvn launch");

@@ -51,7 +51,7 @@ def _z_oracle(rows, d):
     return oracle.StreamArray([oracle_stream("philox4x32", int(i)) for i in rows]).mvn_z(d)
 
 
-@pytest.mark.parametrize("d", [1, 3, 64, 100, 256])
+@pytest.mark.parametrize("d", [1, 3, 64, 100, 256, 300, 520])
 def test_mvn_forward_backward_small(d):
     n = 1000
     mu, L = _factor(d)
