@@ -65,7 +65,7 @@ def parse():
     p.add_argument("--no-parts", action="store_true", help="time only the ten-fill step")
     p.add_argument("--parts", default=None,
                    help="comma-separated parts to time after the step: serial, batched, elem, mvn, "
-                        "moments, laws, float, engines, discrete, setup (default all; none with --only)")
+                        "moments, laws, float, bitexact, engines, discrete, setup (default all; none with --only)")
     p.add_argument("--only", default="", help="comma-separated fill names to run (profiling)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="run only plain fill/copy kernels of known size (counter calibration)")
@@ -200,6 +200,8 @@ def parts(torch, rp, workloads, stream, only):
         out.update(part_laws(torch, rp, workloads, tm, sp))
     if "float" in only:
         out.update(part_float(torch, rp, workloads, tm, sp))
+    if "bitexact" in only:
+        out.update(part_bitexact(torch, rp, workloads, tm, sp))
     if "engines" in only:
         out.update(part_engines(torch, rp, workloads, tm, sp))
     if "discrete" in only:
@@ -354,6 +356,34 @@ def part_laws(torch, rp, workloads, tm, sp):
                      "hbm_frac": round(8.0 * n * per / ms / 1e6 / HBM_PEAK_GBS, 4)}
     del buf, S
     return {"laws_philox4x32_2p16x2p14": res}
+
+
+def part_bitexact(torch, rp, workloads, tm, sp):
+    """The bitexact setting (correctly rounded exp / log / log1p / pow) on
+    the substream workload, Philox4x32-10: time with the setting on, and the
+    ratio to the same call with it off."""
+    n, per = workloads.SUB_N, workloads.SUB_PER
+    buf = torch.empty(n * per, dtype=torch.float64, device="cuda")
+    res = {}
+    cases = (("normal", None, rp.RP_NORM, ()), ("exp", None, rp.RP_EXP, ()),
+             ("lognormal", rp.RP_LAW_LOGNORMAL, None, (0.5, 0.75)), ("gumbel", rp.RP_LAW_GUMBEL, None, (1.0, 2.0)),
+             ("pareto", rp.RP_LAW_PARETO, None, (1.5, 3.0)), ("weibull", rp.RP_LAW_WEIBULL, None, (1.7, 4.0)),
+             ("gamma", rp.RP_LAW_GAMMA, None, (2.5, 1.5)), ("gamma_0.4", rp.RP_LAW_GAMMA, None, (0.4, 1.0)),
+             ("beta", rp.RP_LAW_BETA, None, (2.0, 5.0)))
+    for name, law, dist, p in cases:
+        ms = {}
+        for on in (0, 1):
+            S = rp.rp_streams_create(rp.rp_create("philox4x32").seed(workloads.BASE_SEED), rp.RP_SUB_KEY, n)
+            S.set_flag(rp.RP_BITEXACT, on)
+            if law is None:
+                ms[on] = tm(lambda: rp.rp_fill(S, dist, rp.RP_F64, 0, 0, buf, per, sp), reps=3)
+            else:
+                ms[on] = tm(lambda: rp.rp_fill_law(S, law, p, buf, per, sp), reps=3)
+            del S
+        res[name] = {"ms": round(ms[1], 4), "gsamples_s": round(n * per / ms[1] / 1e6, 2),
+                     "slowdown": round(ms[1] / ms[0], 3)}
+    del buf
+    return {"bitexact_philox4x32_2p16x2p14": res}
 
 
 def part_float(torch, rp, workloads, tm, sp):
@@ -558,7 +588,7 @@ def main():
                      "algorithmic_bytes_per_launch": total * dom[4], "avg_launch_ms": round(dom_ms, 4)},
         "rows": rows,
     }
-    want = args.parts if args.parts is not None else ("" if args.only else "serial,batched,elem,mvn,moments,laws,float,engines,discrete,setup")
+    want = args.parts if args.parts is not None else ("" if args.only else "serial,batched,elem,mvn,moments,laws,float,bitexact,engines,discrete,setup")
     if not args.no_parts and want:
         result["parts"] = parts(torch, rp, workloads, stream, set(want.split(",")))
     if not args.no_cpu_baseline:

@@ -240,9 +240,26 @@ int rp_get_full_mantissa(const rp_rng *rng);
  *                     every sampler built on the ziggurat (normal,
  *                     exponential, the laws, gamma, beta, moments, rows of
  *                     the multivariate normal, the one-stream split).
+ *   RP_BITEXACT       (Section 4.2, exact reproducibility across platforms)
+ *                     every exp, log, log1p and pow a sampler evaluates is
+ *                     the correctly rounded one (rp_crmath below): the
+ *                     ziggurat's wedge tests and tails, the gamma's log test
+ *                     and its U^(1/a) boost (taken as the correctly rounded
+ *                     u^(1/a), 1/a unrounded), and the transforms of
+ *                     lognormal, Gumbel, Pareto, generalized Pareto and
+ *                     Weibull.  A correctly rounded function has one
+ *                     admissible result, so every value and every state is
+ *                     then the same on any platform that evaluates the same
+ *                     formulas; the affine parts are plain binary64
+ *                     operations in the documented order here in every
+ *                     mode.  Default 0 (the platform's exp / log, faithful
+ *                     to an ulp; values can then differ in the last bit
+ *                     where a result lands next to a rounding boundary).
+ *                     Read by every sampler that calls those functions
+ *                     (not by rp_mvn's matrix product, nor by the gradients).
  * rp_get_flag / rp_streams_get_flag return 1 or 0.  Errors: RP_ENULL;
  * RP_EINVAL for an unknown setting or a value other than 0 and 1. */
-enum { RP_FULL_MANTISSA = 1, RP_SQUEEZE = 2 };
+enum { RP_FULL_MANTISSA = 1, RP_SQUEEZE = 2, RP_BITEXACT = 3 };
 int rp_set_flag(rp_rng *rng, int flag, int value);
 int rp_get_flag(const rp_rng *rng, int flag);
 int rp_streams_set_flag(rp_streams *s, int flag, int value);
@@ -496,6 +513,28 @@ int rp_mvn(rp_streams *s, const float *d_mu, const float *d_L, int d, uint64_t n
  * partials from the stream-ordered pool. */
 int rp_mvn_backward(rp_streams *s, const float *d_G, int d, uint64_t n, float *d_gmu, float *d_gL,
                     void *hip_stream);
+
+/* ---- correctly rounded elementary functions (Section 4.2) ---------------- */
+/* The functions the samplers call under the RP_BITEXACT setting, correctly
+ * rounded to binary64 (round to nearest, ties to even) for every argument:
+ *   RP_CR_EXP     exp(x)
+ *   RP_CR_LOG     log(x)
+ *   RP_CR_LOG1P   log(1 + x)
+ *   RP_CR_POW     x^y, with the special values of C99 Annex F (F.9.4.4)
+ *   RP_CR_POWINV  x^(1/y) for x >= 0, y > 0, the exponent 1/y exact (not
+ *                 rounded), as exp(log(x)/y); NaN outside that domain.
+ * Evaluation is in triple-double arithmetic (relative error below about
+ * 2^-135) with one final correctly rounded three-term sum; for pow and
+ * powinv a result that is itself exactly a binary64 midpoint is rounded
+ * from that evaluation.  rp_crmath_host evaluates out[i] = f(x[i], y[i]) for
+ * i < n on the host (host memory); rp_crmath does the same on the device
+ * (device memory, queued on hip_stream, no allocation).  y is read only for
+ * RP_CR_POW and RP_CR_POWINV (else it may be NULL).  The two give identical
+ * bits.  Errors: RP_EINVAL for an unknown fn, RP_ENULL for a NULL x, out or
+ * (when read) y, RP_EDEVICE for a failed launch. */
+enum { RP_CR_EXP = 0, RP_CR_LOG = 1, RP_CR_LOG1P = 2, RP_CR_POW = 3, RP_CR_POWINV = 4 };
+int rp_crmath_host(int fn, const double *x, const double *y, double *out, uint64_t n);
+int rp_crmath(int fn, const double *d_x, const double *d_y, double *d_out, uint64_t n, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -73,6 +73,9 @@ def lib():
             "or_beta_elem": ([vp, vp, vp, vp, sz], None),
             "or_mvn_z": ([vp, ctypes.c_int, sz, vp], None),
             "or_boost_pow": ([ctypes.c_double, ctypes.c_double], ctypes.c_double),
+            "or_set_bitexact": ([ctypes.c_int], None),
+            "or_get_bitexact": ([], ctypes.c_int),
+            "or_crmath": ([ctypes.c_int, vp, vp, vp, sz], None),
             "or_seed_seq": ([vp, sz, vp, sz], None),
             "or_philox4x32_block": ([vp, vp, vp], None),
             "or_philox4x64_block": ([vp, vp, vp], None),
@@ -456,6 +459,40 @@ def substream(engine, seed, kind, i, jump_log2=64):
 
 def boost_pow(u, a):
     return lib().or_boost_pow(float(u), float(a))
+
+
+CR_EXP, CR_LOG, CR_LOG1P, CR_POW, CR_POWINV = range(5)
+
+
+def crmath(fn, x, y=None):
+    """Correctly rounded f(x, y) elementwise (binary128 rounded once to
+    binary64): 0 exp, 1 log, 2 log1p, 3 pow, 4 x^(1/y)."""
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1))
+    yy = np.ascontiguousarray(np.broadcast_to(np.asarray(0.0 if y is None else y, dtype=np.float64), x.shape))
+    out = np.empty_like(x)
+    lib().or_crmath(fn, _p(x), _p(yy), _p(out), len(x))
+    return out
+
+
+class bitexact:
+    """Context manager: the oracle's samplers use correctly rounded exp, log
+    and log1p (the bitexact setting) inside the block."""
+
+    def __init__(self, on=True):
+        self.on = bool(on)
+
+    def __enter__(self):
+        self.prev = lib().or_get_bitexact()
+        lib().or_set_bitexact(1 if self.on else 0)
+        return self
+
+    def __exit__(self, *exc):
+        lib().or_set_bitexact(self.prev)
+        return False
+
+
+def bitexact_on():
+    return lib().or_get_bitexact() != 0
 
 
 def time_fills(streams, what, per, threads):

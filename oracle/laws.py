@@ -43,10 +43,20 @@ BASE = {UNIF: "u01", NORMAL: "norm", LOGNORMAL: "norm", EXP: "exp", GUMBEL: "u01
         GPARETO: "exp", WEIBULL: "exp"}
 
 
-def transform(law, base, p):
-    """The law's value for each base draw (a float64 array)."""
+def transform(law, base, p, bitexact=None):
+    """The law's value for each base draw (a float64 array).  bitexact (default:
+    the oracle's current setting) takes exp, log and pow correctly rounded."""
+    from oracle import bitexact_on, crmath, CR_EXP, CR_LOG, CR_POW
     x = np.asarray(base, dtype=np.float64)
     p = [float(v) for v in p]
+    if bitexact is None:
+        bitexact = bitexact_on()
+    if bitexact:
+        exp = lambda t: crmath(CR_EXP, t).reshape(np.shape(t))
+        log = lambda t: crmath(CR_LOG, t).reshape(np.shape(t))
+        power = lambda t, e: crmath(CR_POW, t, e).reshape(np.shape(t))
+    else:
+        exp, log, power = np.exp, np.log, np.power
     with np.errstate(divide="ignore", over="ignore", invalid="ignore"):
         if law == UNIF:
             a, b = p
@@ -56,27 +66,27 @@ def transform(law, base, p):
             return mu + sigma * x
         if law == LOGNORMAL:
             mu, sigma = p
-            return np.exp(mu + sigma * x)
+            return exp(mu + sigma * x)
         if law == EXP:
             (beta,) = p
             return beta * x
         if law == GUMBEL:
             mu, beta = p
-            return mu - beta * np.log(-np.log(x))
+            return mu - beta * log(-log(x))
         if law == PARETO:
             xm, alpha = p
-            return xm * np.exp(x / alpha)
+            return xm * exp(x / alpha)
         if law == GPARETO:
             mu, s, xi = p
             if xi == 0.0:
                 return mu + s * x
-            P = np.exp(x / (1.0 / abs(xi)))
+            P = exp(x / (1.0 / abs(xi)))
             if xi > 0.0:
                 return mu + (s * (P - 1.0)) / xi
             return mu - (s * (1.0 - 1.0 / P)) / xi
         if law == WEIBULL:
             k, lam = p
-            return lam * np.power(x, 1.0 / k)
+            return lam * power(x, 1.0 / k)
     raise ValueError(f"unknown law {law}")
 
 

@@ -1253,6 +1253,53 @@ void or_sample(or_stream *s, uint32_t n, uint32_t k, uint32_t *out)
 }
 
 /* ------------------------------------------------------------------------ */
+/* The bitexact setting (Section 4.2: library function calls made the same  */
+/* on every platform).  Reading taken here: with the setting on, every exp, */
+/* log and log1p of a sampler is the correctly rounded binary64 value,      */
+/* taken as the binary128 value of libquadmath (about 2^-112 relative)      */
+/* rounded once to binary64; pow and the gamma boost the same way.  Off,    */
+/* they are the C library's.  The setting is global to the oracle (test     */
+/* infrastructure, one caller at a time): or_set_bitexact.                  */
+/* ------------------------------------------------------------------------ */
+static int or_bx = 0;
+
+void or_set_bitexact(int on) { or_bx = on != 0; }
+int or_get_bitexact(void) { return or_bx; }
+
+static double q_exp(double x) { return (double)expq((__float128)x); }
+static double q_log(double x) { return (double)logq((__float128)x); }
+static double q_log1p(double x) { return (double)log1pq((__float128)x); }
+static double q_pow(double x, double y) { return (double)powq((__float128)x, (__float128)y); }
+/* u^(1/a) with the quotient log(u)/a in binary128 (1/a not rounded) */
+static double q_powinv(double u, double a)
+{
+    if (u != u || a != a) return u + a;
+    if (u < 0.0 || a <= 0.0) return NAN;
+    if (u == 0.0 || u == 1.0 || a == 1.0 || isinf(u)) return u;
+    if (isinf(a)) return 1.0;
+    return (double)expq(logq((__float128)u) / (__float128)a);
+}
+
+static double OR_EXP(double x) { return or_bx ? q_exp(x) : exp(x); }
+static double OR_LOG(double x) { return or_bx ? q_log(x) : log(x); }
+static double OR_LOG1P(double x) { return or_bx ? q_log1p(x) : log1p(x); }
+
+/* out[i] = f(x[i], y[i]) for f = 0 exp, 1 log, 2 log1p, 3 pow, 4 u^(1/a), */
+/* each the binary128 value rounded once to binary64 (y read for 3 and 4)   */
+void or_crmath(int fn, const double *x, const double *y, double *out, size_t n)
+{
+    for (size_t i = 0; i < n; i++) {
+        switch (fn) {
+        case 0: out[i] = q_exp(x[i]); break;
+        case 1: out[i] = q_log(x[i]); break;
+        case 2: out[i] = q_log1p(x[i]); break;
+        case 3: out[i] = q_pow(x[i], y[i]); break;
+        default: out[i] = q_powinv(x[i], y[i]); break;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Ziggurat normal and exponential (Section 3.1 and the ziggurat figure).   */
 /* Strip j = low byte of a 64-bit word.  Normal: bit 8 = sign, bits 9..60 =  */
 /* 52-bit magnitude m.  Exponential: bits 8..60 = 53-bit magnitude m.  The   */
@@ -1280,8 +1327,8 @@ static double norm_one(or_stream *s, or_counts *c)
         if (j == 0) {
             if (c) c->tail_entries++;
             for (;;) {
-                double e1 = -log1p(-u01_53(nx(s, c))) / OR_NORM_R;
-                double e2 = -log1p(-u01_53(nx(s, c)));
+                double e1 = -OR_LOG1P(-u01_53(nx(s, c))) / OR_NORM_R;
+                double e2 = -OR_LOG1P(-u01_53(nx(s, c)));
                 if (c) c->tail_logs += 2;
                 if (e2 + e2 > e1 * e1) {
                     double t = OR_NORM_R + e1;
@@ -1291,7 +1338,7 @@ static double norm_one(or_stream *s, or_counts *c)
         }
         double y = OR_NORM_F[j] + u01_53(nx(s, c)) * (OR_NORM_F[j - 1] - OR_NORM_F[j]);
         if (c) c->pdf_evals++;
-        if (y < exp(-0.5 * x * x)) return neg ? -x : x;
+        if (y < OR_EXP(-0.5 * x * x)) return neg ? -x : x;
         if (c) c->rejections++;
     }
 }
@@ -1310,11 +1357,11 @@ static double exp_one(or_stream *s, or_counts *c)
                 c->tail_entries++;
                 c->tail_logs++;
             }
-            return OR_EXP_R - log1p(-u01_53(nx(s, c)));
+            return OR_EXP_R - OR_LOG1P(-u01_53(nx(s, c)));
         }
         double y = OR_EXP_F[j] + u01_53(nx(s, c)) * (OR_EXP_F[j - 1] - OR_EXP_F[j]);
         if (c) c->pdf_evals++;
-        if (y < exp(-x)) return x;
+        if (y < OR_EXP(-x)) return x;
         if (c) c->rejections++;
     }
 }
@@ -1344,8 +1391,8 @@ static float normf_one(half_reader *h)
         if (m < OR_NORM_K[j]) return (float)(neg ? -x : x);
         if (j == 0) {
             for (;;) {
-                double e1 = -log1p(-u01_24(next32(h))) / OR_NORM_R;
-                double e2 = -log1p(-u01_24(next32(h)));
+                double e1 = -OR_LOG1P(-u01_24(next32(h))) / OR_NORM_R;
+                double e2 = -OR_LOG1P(-u01_24(next32(h)));
                 if (e2 + e2 > e1 * e1) {
                     double t = OR_NORM_R + e1;
                     return (float)(neg ? -t : t);
@@ -1353,7 +1400,7 @@ static float normf_one(half_reader *h)
             }
         }
         double y = OR_NORM_F[j] + u01_24(next32(h)) * (OR_NORM_F[j - 1] - OR_NORM_F[j]);
-        if (y < exp(-0.5 * x * x)) return (float)(neg ? -x : x);
+        if (y < OR_EXP(-0.5 * x * x)) return (float)(neg ? -x : x);
     }
 }
 
@@ -1365,9 +1412,9 @@ static float expf_one(half_reader *h)
         uint64_t m = (uint64_t)(u >> 8) << 29;
         double x = (double)m * OR_EXP_W[j];
         if (m < OR_EXP_K[j]) return (float)x;
-        if (j == 0) return (float)(OR_EXP_R - log1p(-u01_24(next32(h))));
+        if (j == 0) return (float)(OR_EXP_R - OR_LOG1P(-u01_24(next32(h))));
         double y = OR_EXP_F[j] + u01_24(next32(h)) * (OR_EXP_F[j - 1] - OR_EXP_F[j]);
-        if (y < exp(-x)) return (float)x;
+        if (y < OR_EXP(-x)) return (float)x;
     }
 }
 
@@ -1434,7 +1481,7 @@ static double mt_gamma(or_stream *s, double a, or_counts *cn)
         if (cn) cn->mt_attempts++;
         if (u < 1.0 - 0.0331 * (x2 * x2)) return d * v;
         if (cn) cn->mt_logtests++;
-        if (log(u) < 0.5 * x2 + d * ((1.0 - v) + log(v))) return d * v;
+        if (OR_LOG(u) < 0.5 * x2 + d * ((1.0 - v) + OR_LOG(v))) return d * v;
     }
 }
 
@@ -1472,7 +1519,7 @@ static double mt_gammaf(half_reader *h, double a)
         double u = u01_24(next32(h));
         double x2 = x * x;
         if (u < 1.0 - 0.0331 * (x2 * x2)) return d * v;
-        if (log(u) < 0.5 * x2 + d * ((1.0 - v) + log(v))) return d * v;
+        if (OR_LOG(u) < 0.5 * x2 + d * ((1.0 - v) + OR_LOG(v))) return d * v;
     }
 }
 

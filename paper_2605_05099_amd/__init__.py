@@ -25,7 +25,8 @@ RP_SUB_KEY, RP_SUB_INC, RP_SUB_SPAWN, RP_SUB_JUMP = range(4)
 RP_RAW, RP_U01, RP_BOUNDED, RP_NORM, RP_EXP = range(5)
 RP_U64, RP_U32, RP_F64, RP_F32 = range(4)
 RP_FLAG_52BIT = 1
-RP_FULL_MANTISSA, RP_SQUEEZE = 1, 2  # settings (rp_set_flag)
+RP_FULL_MANTISSA, RP_SQUEEZE, RP_BITEXACT = 1, 2, 3  # settings (rp_set_flag)
+RP_CR_EXP, RP_CR_LOG, RP_CR_LOG1P, RP_CR_POW, RP_CR_POWINV = range(5)
 (RP_LAW_UNIF, RP_LAW_NORMAL, RP_LAW_LOGNORMAL, RP_LAW_EXP, RP_LAW_GUMBEL, RP_LAW_PARETO, RP_LAW_GPARETO,
  RP_LAW_WEIBULL, RP_LAW_GAMMA, RP_LAW_BETA, RP_LAW_CHI2, RP_LAW_T, RP_LAW_F, RP_LAW_SKEWNORMAL) = range(1, 15)
 
@@ -95,6 +96,8 @@ _SIGS = {
     "rp_permutations": ([_vp, _u32, _vp, _vp], _int),
     "rp_sample": ([_vp, _u32, _u32, _vp, _vp], _int),
     "rp_sample_noalloc": ([_vp, _u32, _u32, _vp, _vp], _int),
+    "rp_crmath_host": ([_int, _vp, _vp, _vp, _u64], _int),
+    "rp_crmath": ([_int, _vp, _vp, _vp, _u64, _vp], _int),
     "rp_mvn": ([_vp, _vp, _vp, _int, _u64, _vp, _vp], _int),
     "rp_mvn_backward": ([_vp, _vp, _int, _u64, _vp, _vp, _vp], _int),
     "rp_gamma_grad": ([_vp, _vp, _vp, _vp, _u64, _vp], _int),
@@ -207,6 +210,21 @@ def rp_sample(streams, n, k, out, stream=None):
 
 def rp_sample_noalloc(streams, n, k, out, stream=None):
     _check(lib().rp_sample_noalloc(streams.h, n, k, _dev_ptr(out), _stream_ptr(stream)))
+
+
+def rp_crmath_host(fn, x, y=None):
+    """Correctly rounded f(x[i], y[i]) on the host (numpy arrays)."""
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1))
+    yy = None if y is None else np.ascontiguousarray(np.broadcast_to(np.asarray(y, dtype=np.float64), x.shape))
+    out = np.empty_like(x)
+    _check(lib().rp_crmath_host(fn, _ptr(x), _ptr(yy) if yy is not None else None, _ptr(out), len(x)))
+    return out
+
+
+def rp_crmath(fn, x, y, out, stream=None):
+    """Correctly rounded f(x[i], y[i]) on the device (float64 tensors; y may be None)."""
+    _check(lib().rp_crmath(fn, _dev_ptr(x), _dev_ptr(y) if y is not None else None, _dev_ptr(out), out.numel(),
+                           _stream_ptr(stream)))
 
 
 def rp_fill_law(streams, law, params, out, per_stream, stream=None):

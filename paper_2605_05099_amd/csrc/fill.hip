@@ -30,6 +30,7 @@
 
 #define RP_TBL __device__ const
 #include "zig_tables.inc"
+#include "crmath.h"
 
 namespace rp {
 
@@ -158,6 +159,46 @@ struct ZigLds {
     double DM[256];
 };
 
+// The elementary functions of the bitexact setting (correctly rounded, the
+// same on every platform), out of line.  Kernels take the setting as a
+// template parameter (BX): the ordinary instantiations call none of these,
+// so their registers and occupancy are those of the platform functions.
+__device__ __noinline__ double bx_exp(double x) { return crm::cr_exp(x); }
+__device__ __noinline__ double bx_log(double x) { return crm::cr_log(x); }
+__device__ __noinline__ double bx_log1p(double x) { return crm::cr_log1p(x); }
+__device__ __noinline__ double bx_pow(double x, double y) { return crm::cr_pow(x, y); }
+__device__ __noinline__ double bx_powinv(double u, double a) { return crm::cr_powinv(u, a); }
+template <bool BX>
+__device__ __forceinline__ double f_exp(double x)
+{
+    if constexpr (BX) return bx_exp(x);
+    else return exp(x);
+}
+template <bool BX>
+__device__ __forceinline__ double f_log(double x)
+{
+    if constexpr (BX) return bx_log(x);
+    else return log(x);
+}
+template <bool BX>
+__device__ __forceinline__ double f_log1p(double x)
+{
+    if constexpr (BX) return bx_log1p(x);
+    else return log1p(x);
+}
+template <bool BX>
+__device__ __forceinline__ double f_pow(double x, double y)
+{
+    if constexpr (BX) return bx_pow(x, y);
+    else return pow(x, y);
+}
+
+// The transform code XF of the fill kernels: the law (bits 0..5) and the
+// bitexact setting (kXfBx).
+constexpr int kXfBx = 64;
+constexpr int xf_law(int xf) { return xf & (kXfBx - 1); }
+constexpr bool xf_bx(int xf) { return (xf & kXfBx) != 0; }
+
 // flags: the FillArgs flags of the call.  With the squeeze switched off the
 // bands are infinite, so neither squeeze test decides and every wedge test
 // evaluates f(x) (the decisions, and so the values, are the same).
@@ -182,7 +223,7 @@ __device__ __forceinline__ void load_zig(ZigLds *t, int flags)
 // decides most cases without exp(); its bounds carry a margin far above the
 // rounding of the secant and of exp, so a squeeze decision always equals the
 // plain test evaluated in binary64.
-template <int DIST, bool HALF = false>
+template <int DIST, bool HALF = false, bool BX = false>
 __device__ __forceinline__ bool wedge_accept(const ZigLds *t, int j, double x, uint64_t uword)
 {
     double U = zig_u<HALF>(uword);
@@ -191,8 +232,8 @@ __device__ __forceinline__ bool wedge_accept(const ZigLds *t, int j, double x, u
     double l = fj1 + t->S[j] * (x - t->X[j - 1]);
     if (y < l - t->DM[j]) return true;
     if (y > l + t->DP[j]) return false;
-    if (DIST == RP_NORM) return y < exp(-0.5 * x * x);
-    return y < exp(-x);
+    if (DIST == RP_NORM) return y < f_exp<BX>(-0.5 * x * x);
+    return y < f_exp<BX>(-x);
 }
 
 // ---------------------------------------------------------------------------
@@ -670,11 +711,11 @@ __device__ __forceinline__ void wave_sync()
 __device__ __noinline__ double exp_ool(double x) { return exp(x); }
 __device__ __noinline__ double log1p_ool(double x) { return log1p(x); }
 // one pair of the normal tail test: accepted iff e2 + e2 > e1 e1; t = r + e1
-template <bool HALF>
+template <bool HALF, bool BX>
 __device__ __noinline__ bool normal_tail_pair(uint64_t a, uint64_t b, double &t)
 {
-    const double e1 = -log1p(-zig_u<HALF>(a)) / RP_ZN_R;
-    const double e2 = -log1p(-zig_u<HALF>(b));
+    const double e1 = -f_log1p<BX>(-zig_u<HALF>(a)) / RP_ZN_R;
+    const double e2 = -f_log1p<BX>(-zig_u<HALF>(b));
     t = RP_ZN_R + e1;
     return e2 + e2 > e1 * e1;
 }
@@ -697,13 +738,15 @@ struct ZigG {
     static __device__ __forceinline__ double DM(int j) { return opaque(DIST == RP_NORM ? RP_ZN_DM : RP_ZE_DM)[j]; }
 };
 
-// INL: exp and log1p inline (no calls, so no registers saved around them)
-template <int DIST, bool HALF, bool INL = false, class Word>
-__device__ __forceinline__ int zig_resolve(const WKe *t, uint64_t w0, Word word, int avail, bool squeeze,
+// INL: exp and log1p inline (no calls, so no registers saved around them).
+// BX: the bitexact setting.  zflags: the FillArgs flags (the squeeze switch).
+template <int DIST, bool HALF, bool INL = false, bool BX = false, class Word>
+__device__ __forceinline__ int zig_resolve(const WKe *t, uint64_t w0, Word word, int avail, int zflags,
                                            bool &accepted, double &val, bool &has_u1, uint64_t &u1)
 {
-    auto EXP = [](double x) { return INL ? exp(x) : exp_ool(x); };
-    auto LOG1P = [](double x) { return INL ? log1p(x) : log1p_ool(x); };
+    const bool squeeze = !(zflags & kFlagNoSqueeze);
+    auto EXP = [](double x) { return BX ? bx_exp(x) : (INL ? exp(x) : exp_ool(x)); };
+    auto LOG1P = [](double x) { return BX ? bx_log1p(x) : (INL ? log1p(x) : log1p_ool(x)); };
     const int j = (int)(w0 & 0xff);
     accepted = false;
     has_u1 = false;
@@ -742,12 +785,12 @@ __device__ __forceinline__ int zig_resolve(const WKe *t, uint64_t w0, Word word,
         double tt;
         bool ok;
         if constexpr (INL) {
-            const double e1 = -log1p(-zig_u<HALF>(word(1 + 2 * it))) / RP_ZN_R;
-            const double e2 = -log1p(-zig_u<HALF>(word(2 + 2 * it)));
+            const double e1 = -f_log1p<BX>(-zig_u<HALF>(word(1 + 2 * it))) / RP_ZN_R;
+            const double e2 = -f_log1p<BX>(-zig_u<HALF>(word(2 + 2 * it)));
             tt = RP_ZN_R + e1;
             ok = e2 + e2 > e1 * e1;
         } else {
-            ok = normal_tail_pair<HALF>(word(1 + 2 * it), word(2 + 2 * it), tt);
+            ok = normal_tail_pair<HALF, BX>(word(1 + 2 * it), word(2 + 2 * it), tt);
         }
         if (ok) {
             val = ((w0 >> 8) & 1) ? -tt : tt;
@@ -786,30 +829,33 @@ __device__ __forceinline__ double zbase(double v)
 
 // The derived laws of rp_fill_law: one transform of one base draw (U, Z or
 // E), in binary64, in the order the boundary documents, fused into the store
-// of the base fill.  XF = 0 is the base value itself.
-template <int XF>
+// of the base fill.  Law 0 is the base value itself.  Under the bitexact
+// setting (xf_bx) the exp, log and pow are the correctly rounded ones.
+template <int XFC>
 __device__ __forceinline__ double xform(double v, const FillArgs &a)
 {
+    constexpr int XF = xf_law(XFC);
+    constexpr bool BX = xf_bx(XFC);
     if constexpr (XF == RP_LAW_UNIF) {
         return a.xp[0] + a.xp[1] * v;  // a + (b - a) U, b - a formed on the host
     } else if constexpr (XF == RP_LAW_NORMAL) {
         return a.xp[0] + a.xp[1] * v;
     } else if constexpr (XF == RP_LAW_LOGNORMAL) {
-        return exp(a.xp[0] + a.xp[1] * v);
+        return f_exp<BX>(a.xp[0] + a.xp[1] * v);
     } else if constexpr (XF == RP_LAW_EXP) {
         return a.xp[0] * v;
     } else if constexpr (XF == RP_LAW_GUMBEL) {
-        return a.xp[0] - a.xp[1] * log(-log(v));
+        return a.xp[0] - a.xp[1] * f_log<BX>(-f_log<BX>(v));
     } else if constexpr (XF == RP_LAW_PARETO) {
-        return a.xp[0] * exp(v / a.xp[1]);
+        return a.xp[0] * f_exp<BX>(v / a.xp[1]);
     } else if constexpr (XF == RP_LAW_GPARETO) {
         const double mu = a.xp[0], sg = a.xp[1], xi = a.xp[2];
         if (xi == 0.0) return mu + sg * v;
-        const double P = exp(v / a.xp[3]);
+        const double P = f_exp<BX>(v / a.xp[3]);
         if (xi > 0.0) return mu + (sg * (P - 1.0)) / xi;
         return mu - (sg * (1.0 - 1.0 / P)) / xi;
     } else if constexpr (XF == RP_LAW_WEIBULL) {
-        return a.xp[1] * pow(v, a.xp[2]);
+        return a.xp[1] * f_pow<BX>(v, a.xp[2]);
     } else {
         return v;
     }
@@ -1077,9 +1123,9 @@ __global__ __launch_bounds__(256, (DIST == RP_NORM || (DIST == RP_EXP && OT == R
                         q = cp ? -1 : (int)sp;
                         const int off = cp ? -1 - hu : q;
                         w0 = cp ? pend_w : wbuf[wpos(q)];
-                        L = zig_resolve<DIST, ZH>(
+                        L = zig_resolve<DIST, ZH, false, xf_bx(XF)>(
                             zt, w0, [&](int kk) { return (hu && kk == 1) ? pend_u1 : wbuf[wpos(off + kk)]; },
-                            cp ? CHW + hu : CHW - 1 - q, !(a.flags & kFlagNoSqueeze), acc, v, hu_out, u1o);
+                            cp ? CHW + hu : CHW - 1 - q, a.flags, acc, v, hu_out, u1o);
                     }
                     int i0 = 0;
                     if (npre && base == 0) {
@@ -1571,7 +1617,7 @@ struct LaneRanlux {
 // serial ziggurat (identical decisions to the wavefront classifier)
 // One serial ziggurat draw.  next() yields the next 64-bit word (binary64
 // draws) or 32-bit item (float draws, HALF).
-template <int DIST, bool HALF, class Next>
+template <int DIST, bool HALF, bool BX = false, class Next>
 __device__ __forceinline__ double zig_serial_g(const ZigLds *t, Next next)
 {
     for (;;) {
@@ -1586,8 +1632,8 @@ __device__ __forceinline__ double zig_serial_g(const ZigLds *t, Next next)
             if (m < e.k) return neg ? -x : x;
             if (j == 0) {
                 for (int k = 0; k < kMaxTailIters; k++) {
-                    const double e1 = -log1p(-zig_u<HALF>(next())) / RP_ZN_R;
-                    const double e2 = -log1p(-zig_u<HALF>(next()));
+                    const double e1 = -f_log1p<BX>(-zig_u<HALF>(next())) / RP_ZN_R;
+                    const double e2 = -f_log1p<BX>(-zig_u<HALF>(next()));
                     if (e2 + e2 > e1 * e1) {
                         const double tt = RP_ZN_R + e1;
                         return neg ? -tt : tt;
@@ -1595,21 +1641,21 @@ __device__ __forceinline__ double zig_serial_g(const ZigLds *t, Next next)
                 }
                 continue;  // unreachable in practice (see kMaxTailIters)
             }
-            if (wedge_accept<DIST, HALF>(t, j, x, next())) return neg ? -x : x;
+            if (wedge_accept<DIST, HALF, BX>(t, j, x, next())) return neg ? -x : x;
         } else {
             const uint64_t m = (w >> 8) & ((1ull << 53) - 1);
             const WKe e = t->WK[j];
             const double x = (double)m * e.w;
             if (m < e.k) return x;
-            if (j == 0) return RP_ZE_R - log1p(-zig_u<HALF>(next()));
-            if (wedge_accept<DIST, HALF>(t, j, x, next())) return x;
+            if (j == 0) return RP_ZE_R - f_log1p<BX>(-zig_u<HALF>(next()));
+            if (wedge_accept<DIST, HALF, BX>(t, j, x, next())) return x;
         }
     }
 }
 
 // the binary64 draw, written out with the engine's next() (no callable
 // wrapper, so an engine's out-of-line step sees only its own live values)
-template <int DIST, class E>
+template <int DIST, bool BX = false, class E>
 __device__ double zig_serial(const ZigLds *t, E &eng)
 {
     for (;;) {
@@ -1623,8 +1669,8 @@ __device__ double zig_serial(const ZigLds *t, E &eng)
             if (m < e.k) return neg ? -x : x;
             if (j == 0) {
                 for (int k = 0; k < kMaxTailIters; k++) {
-                    const double e1 = -log1p(-u01_53(eng.next())) / RP_ZN_R;
-                    const double e2 = -log1p(-u01_53(eng.next()));
+                    const double e1 = -f_log1p<BX>(-u01_53(eng.next())) / RP_ZN_R;
+                    const double e2 = -f_log1p<BX>(-u01_53(eng.next()));
                     if (e2 + e2 > e1 * e1) {
                         const double tt = RP_ZN_R + e1;
                         return neg ? -tt : tt;
@@ -1632,14 +1678,14 @@ __device__ double zig_serial(const ZigLds *t, E &eng)
                 }
                 continue;  // unreachable in practice (see kMaxTailIters)
             }
-            if (wedge_accept<DIST>(t, j, x, eng.next())) return neg ? -x : x;
+            if (wedge_accept<DIST, false, BX>(t, j, x, eng.next())) return neg ? -x : x;
         } else {
             const uint64_t m = (w >> 8) & ((1ull << 53) - 1);
             const WKe e = t->WK[j];
             const double x = (double)m * e.w;
             if (m < e.k) return x;
-            if (j == 0) return RP_ZE_R - log1p(-u01_53(eng.next()));
-            if (wedge_accept<DIST>(t, j, x, eng.next())) return x;
+            if (j == 0) return RP_ZE_R - f_log1p<BX>(-u01_53(eng.next()));
+            if (wedge_accept<DIST, false, BX>(t, j, x, eng.next())) return x;
         }
     }
 }
@@ -1695,7 +1741,7 @@ __global__ __launch_bounds__(256) void k_fill_lane(FillArgs a)
         for (uint64_t t = 0; t < P;) {
             if constexpr (ZIG && HALF) {
                 eng.reserve(2);
-                out[t++] = (T)xform<XF>(zbase<true>(zig_serial_g<DIST, true>(zt,
+                out[t++] = (T)xform<XF>(zbase<true>(zig_serial_g<DIST, true, xf_bx(XF)>(zt,
                                                                [&]() -> uint64_t {
                                                                    if (have) {
                                                                        have = false;
@@ -1709,7 +1755,7 @@ __global__ __launch_bounds__(256) void k_fill_lane(FillArgs a)
                                         a);
             } else if constexpr (ZIG) {
                 eng.reserve(3);
-                out[t++] = (T)xform<XF>(zig_serial<DIST>(zt, eng), a);
+                out[t++] = (T)xform<XF>(zig_serial<DIST, xf_bx(XF)>(zt, eng), a);
             } else {
                 eng.reserve(1);
                 uint64_t it;
@@ -1754,10 +1800,10 @@ __global__ __launch_bounds__(256) void k_fill_lane(FillArgs a)
         auto produce = [&]() __attribute__((always_inline)) -> T {
             if constexpr (ZIG && HALF) {
                 eng.reserve(2);
-                return (T)xform<XF>(zbase<true>(zig_serial_g<DIST, true>(zt, next32)), a);
+                return (T)xform<XF>(zbase<true>(zig_serial_g<DIST, true, xf_bx(XF)>(zt, next32)), a);
             } else if constexpr (ZIG) {
                 eng.reserve(3);
-                return (T)xform<XF>(zig_serial<DIST>(zt, eng), a);
+                return (T)xform<XF>(zig_serial<DIST, xf_bx(XF)>(zt, eng), a);
             } else {
                 T v;
                 for (;;) {
@@ -1811,8 +1857,17 @@ struct StoreOrder<true, E> {
 };
 
 // ---------------------------------------------------------------------------
-template <bool WAVE, class E, int DIST, int OT, int XF = 0>
-static int launch_one(const FillArgs &a, hipStream_t st)
+// whether a fill kernel evaluates exp, log, log1p or pow (the ziggurat's
+// rare paths, or the law's transform): those have a bitexact instantiation
+template <int DIST, int XF>
+constexpr bool uses_elementary()
+{
+    return DIST == RP_NORM || DIST == RP_EXP || XF == RP_LAW_LOGNORMAL || XF == RP_LAW_GUMBEL ||
+           XF == RP_LAW_PARETO || XF == RP_LAW_GPARETO || XF == RP_LAW_WEIBULL;
+}
+
+template <bool WAVE, class E, int DIST, int OT, int XF>
+static int launch_kernel(const FillArgs &a, hipStream_t st)
 {
     const unsigned threads = 256;
     const unsigned per_block = WAVE ? threads / 64 : threads;
@@ -1826,6 +1881,14 @@ static int launch_one(const FillArgs &a, hipStream_t st)
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(RP_EDEVICE, "fill kernel launch: %s", hipGetErrorString(e));
     return RP_OK;
+}
+
+template <bool WAVE, class E, int DIST, int OT, int XF = 0>
+static int launch_one(const FillArgs &a, hipStream_t st)
+{
+    if constexpr (uses_elementary<DIST, XF>())
+        if (a.flags & kFlagBitexact) return launch_kernel<WAVE, E, DIST, OT, XF | kXfBx>(a, st);
+    return launch_kernel<WAVE, E, DIST, OT, XF>(a, st);
 }
 
 template <bool WAVE, class E>

@@ -857,14 +857,17 @@ extern "C" int rp_get_full_mantissa(const rp_rng *rng)
     return rng->full_mantissa ? 1 : 0;
 }
 
-// Settings of a stream or substream set (RP_FULL_MANTISSA, RP_SQUEEZE).
-static bool *setting_slot(bool *full_mantissa, bool *squeeze, int flag)
+// Settings of a stream or substream set (RP_FULL_MANTISSA, RP_SQUEEZE,
+// RP_BITEXACT).
+static bool *setting_slot(bool *full_mantissa, bool *squeeze, bool *bitexact, int flag)
 {
     switch (flag) {
     case RP_FULL_MANTISSA:
         return full_mantissa;
     case RP_SQUEEZE:
         return squeeze;
+    case RP_BITEXACT:
+        return bitexact;
     default:
         return nullptr;
     }
@@ -873,7 +876,7 @@ static bool *setting_slot(bool *full_mantissa, bool *squeeze, int flag)
 extern "C" int rp_set_flag(rp_rng *rng, int flag, int value)
 {
     if (!rng) return fail(RP_ENULL, "rp_set_flag: NULL rng");
-    bool *slot = setting_slot(&rng->full_mantissa, &rng->squeeze, flag);
+    bool *slot = setting_slot(&rng->full_mantissa, &rng->squeeze, &rng->bitexact, flag);
     if (!slot) return fail_rng(rng, RP_EINVAL, "rp_set_flag: unknown setting %d", flag);
     if (value != 0 && value != 1) return fail_rng(rng, RP_EINVAL, "rp_set_flag: value must be 0 or 1, not %d", value);
     *slot = value == 1;
@@ -884,7 +887,7 @@ extern "C" int rp_get_flag(const rp_rng *rng, int flag)
 {
     if (!rng) return fail(RP_ENULL, "rp_get_flag: NULL rng");
     rp_rng *r = const_cast<rp_rng *>(rng);
-    bool *slot = setting_slot(&r->full_mantissa, &r->squeeze, flag);
+    bool *slot = setting_slot(&r->full_mantissa, &r->squeeze, &r->bitexact, flag);
     if (!slot) return fail_rng(rng, RP_EINVAL, "rp_get_flag: unknown setting %d", flag);
     return *slot ? 1 : 0;
 }
@@ -1393,6 +1396,7 @@ extern "C" int rp_streams_create(const rp_rng *base, int kind, uint64_t n, int j
     s->nwords = nw;
     s->full_mantissa = base->full_mantissa;
     s->squeeze = base->squeeze;
+    s->bitexact = base->bitexact;
     hipError_t err = hipGetDevice(&s->device);
     if (err != hipSuccess) {
         delete s;
@@ -1455,7 +1459,7 @@ extern "C" int rp_streams_set(rp_streams *s, const uint64_t *words, const uint32
 extern "C" int rp_streams_set_flag(rp_streams *s, int flag, int value)
 {
     if (!s) return fail(RP_ENULL, "rp_streams_set_flag: NULL streams");
-    bool *slot = setting_slot(&s->full_mantissa, &s->squeeze, flag);
+    bool *slot = setting_slot(&s->full_mantissa, &s->squeeze, &s->bitexact, flag);
     if (!slot) return fail(RP_EINVAL, "rp_streams_set_flag: unknown setting %d", flag);
     if (value != 0 && value != 1) return fail(RP_EINVAL, "rp_streams_set_flag: value must be 0 or 1, not %d", value);
     *slot = value == 1;
@@ -1466,7 +1470,7 @@ extern "C" int rp_streams_get_flag(const rp_streams *s, int flag)
 {
     if (!s) return fail(RP_ENULL, "rp_streams_get_flag: NULL streams");
     rp_streams *m = const_cast<rp_streams *>(s);
-    bool *slot = setting_slot(&m->full_mantissa, &m->squeeze, flag);
+    bool *slot = setting_slot(&m->full_mantissa, &m->squeeze, &m->bitexact, flag);
     if (!slot) return fail(RP_EINVAL, "rp_streams_get_flag: unknown setting %d", flag);
     return *slot ? 1 : 0;
 }
@@ -1494,7 +1498,7 @@ extern "C" int rp_streams_duplicate(const rp_streams *s, rp_streams **out)
 
 // serialized image of a substream set: magic, engine, state words per
 // substream, settings (4 x u32; bit 0 the full-mantissa setting, bit 1 the
-// squeeze switched off), n (u64), then the state words (SoA, word k of
+// squeeze switched off, bit 2 bitexact), n (u64), then the state words (SoA, word k of
 // substream i at k n + i) and the n phases
 static constexpr uint32_t kStreamsMagic = 0x31535052u;  // "RPS1"
 
@@ -1512,7 +1516,7 @@ extern "C" int rp_streams_serialize(const rp_streams *s, void *buf, size_t len, 
     if (rc) return rc;
     uint8_t *p = (uint8_t *)buf;
     const uint32_t hdr[4] = {kStreamsMagic, (uint32_t)s->engine, (uint32_t)s->nwords,
-                             (s->full_mantissa ? 1u : 0u) | (s->squeeze ? 0u : 2u)};
+                             (s->full_mantissa ? 1u : 0u) | (s->squeeze ? 0u : 2u) | (s->bitexact ? 4u : 0u)};
     memcpy(p, hdr, 16);
     memcpy(p + 16, &s->n, 8);
     memcpy(p + 24, words.data(), nw * 8);
@@ -1531,7 +1535,7 @@ extern "C" int rp_streams_deserialize(const void *buf, size_t len, rp_streams **
     memcpy(hdr, p, 16);
     memcpy(&n, p + 16, 8);
     if (hdr[0] != kStreamsMagic || hdr[1] >= RP_NENGINES || hdr[2] != (uint32_t)kEngines[hdr[1]].words ||
-        hdr[3] > 3 || n == 0 || n > (1ull << 32))
+        hdr[3] > 7 || n == 0 || n > (1ull << 32))
         return fail(RP_EINVAL, "rp_streams_deserialize: not a serialized substream set");
     const size_t nw = (size_t)hdr[2] * n;
     if (len < 24 + nw * 8 + n * 4) return fail(RP_EINVAL, "rp_streams_deserialize: image truncated");
@@ -1553,6 +1557,7 @@ extern "C" int rp_streams_deserialize(const void *buf, size_t len, rp_streams **
     s->nwords = (int)hdr[2];
     s->full_mantissa = (hdr[3] & 1) != 0;
     s->squeeze = (hdr[3] & 2) == 0;
+    s->bitexact = (hdr[3] & 4) != 0;
     hipError_t e = hipGetDevice(&s->device);
     if (e == hipSuccess) e = hipMalloc(&s->d_words, nw * 8);
     if (e == hipSuccess) e = hipMalloc(&s->d_phase, n * 4);
@@ -2055,7 +2060,7 @@ extern "C" int rp_fill_serial(rp_rng *rng, int dist, int dtype, uint64_t bound, 
     a.phase = rng->phase;
     a.fa.out = d_out;
     a.fa.bound = bound;
-    a.fa.flags = flags | (rng->squeeze ? 0 : kFlagNoSqueeze);
+    a.fa.flags = flags | (rng->squeeze ? 0 : kFlagNoSqueeze) | (rng->bitexact ? kFlagBitexact : 0);
     if (dist == RP_BOUNDED && bound) {
         if (dtype == RP_U64) a.fa.thresh = (0 - bound) % bound;
         else a.fa.thresh = (uint32_t)(0u - (uint32_t)bound) % (uint32_t)bound;

@@ -154,7 +154,7 @@ __global__ __launch_bounds__(bat::kScanBlock) void k_bat_apply(BatchArgs a)
 // Persistent generator.  Lane l of a wave that popped group g works through
 // the sorted positions g*64*spl + s*64 + l, s = 0 .. spl-1, moving to its next
 // set as soon as the current one is done.
-template <class E, bool BETA>
+template <class E, bool BETA, bool BX = false>
 __global__ __launch_bounds__(256) void k_batched(BatchArgs a)
 {
     __shared__ ZigLds zt;
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(256) void k_batched(BatchArgs a)
         int64_t cnt = 0, t = 0;
         double *out = nullptr;
         E eng;
-        GamMachine<BETA> gm;
+        GamMachine<BETA, false, BX> gm;
         for (;;) {
             if (s < a.spl && !valid) {
                 // open the next set of this lane (or skip past the end)
@@ -220,10 +220,15 @@ __global__ __launch_bounds__(256) void k_batched(BatchArgs a)
 template <class E>
 static int launch_batched_e(const BatchArgs &a, bool beta, unsigned grid, unsigned block, hipStream_t st)
 {
-    if (beta)
-        hipLaunchKernelGGL((k_batched<E, true>), dim3(grid), dim3(block), 0, st, a);
+    const bool bx = (a.f.flags & kFlagBitexact) != 0;
+    if (beta && bx)
+        hipLaunchKernelGGL((k_batched<E, true, true>), dim3(grid), dim3(block), 0, st, a);
+    else if (beta)
+        hipLaunchKernelGGL((k_batched<E, true, false>), dim3(grid), dim3(block), 0, st, a);
+    else if (bx)
+        hipLaunchKernelGGL((k_batched<E, false, true>), dim3(grid), dim3(block), 0, st, a);
     else
-        hipLaunchKernelGGL((k_batched<E, false>), dim3(grid), dim3(block), 0, st, a);
+        hipLaunchKernelGGL((k_batched<E, false, false>), dim3(grid), dim3(block), 0, st, a);
     return RP_OK;
 }
 

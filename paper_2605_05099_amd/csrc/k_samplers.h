@@ -201,8 +201,10 @@ __device__ __forceinline__ void log_dd(double u, double &lh, double &ll, const L
     ll = sl - (lh - sh);
 }
 
+template <bool BX>
 __device__ double boost_pow(double u, double a, double ia, const LogLds *lt)
 {
+    if constexpr (BX) return bx_powinv(u, a);  // correctly rounded u^(1/a)
     if (u == 0.0) return 0.0;
     double lh, ll;
     log_dd(u, lh, ll, lt);
@@ -218,7 +220,7 @@ __device__ double boost_pow(double u, double a, double ia, const LogLds *lt)
 // the value when it is accepted, false when rejected (the caller starts a
 // new candidate, exactly where the serial sampler would).
 // HALF: the float ziggurat on 32-bit items (the binary32 value it returns).
-template <class E, bool HALF = false>
+template <class E, bool HALF = false, bool BX = false>
 __device__ __forceinline__ bool zig_candidate(E &eng, const ZigLds *zt, double &x)
 {
     const uint64_t w = HALF ? item_word<RP_NORM>(eng.next()) : eng.next();
@@ -233,8 +235,8 @@ __device__ __forceinline__ bool zig_candidate(E &eng, const ZigLds *zt, double &
     }
     if (j == 0) {
         for (int it = 0; it < kMaxTailIters; it++) {
-            const double e1 = -log1p(-zig_u<HALF>(eng.next())) / RP_ZN_R;
-            const double e2 = -log1p(-zig_u<HALF>(eng.next()));
+            const double e1 = -f_log1p<BX>(-zig_u<HALF>(eng.next())) / RP_ZN_R;
+            const double e2 = -f_log1p<BX>(-zig_u<HALF>(eng.next()));
             if (e2 + e2 > e1 * e1) {
                 const double t = RP_ZN_R + e1;
                 x = zbase<HALF>(neg ? -t : t);
@@ -243,7 +245,7 @@ __device__ __forceinline__ bool zig_candidate(E &eng, const ZigLds *zt, double &
         }
         return false;
     }
-    if (wedge_accept<RP_NORM, HALF>(zt, j, xx, eng.next())) {
+    if (wedge_accept<RP_NORM, HALF, BX>(zt, j, xx, eng.next())) {
         x = zbase<HALF>(neg ? -xx : xx);
         return true;
     }
@@ -280,12 +282,12 @@ struct NormMachine {
     int tail;  // tail pairs taken for the current candidate, -1 outside the tail
     bool neg;
     __device__ void reset() { tail = -1; }
-    template <class E>
+    template <bool BX = false, class E>
     __device__ __forceinline__ bool step(E &eng, const ZigLds *zt, double &x)
     {
         if (tail >= 0) {
-            const double e1 = -log1p(-u01_53(eng.next())) / RP_ZN_R;
-            const double e2 = -log1p(-u01_53(eng.next()));
+            const double e1 = -f_log1p<BX>(-u01_53(eng.next())) / RP_ZN_R;
+            const double e2 = -f_log1p<BX>(-u01_53(eng.next()));
             if (e2 + e2 > e1 * e1) {
                 tail = -1;
                 const double t = RP_ZN_R + e1;
@@ -309,7 +311,7 @@ struct NormMachine {
             tail = 0;
             return false;
         }
-        if (wedge_accept<RP_NORM>(zt, j, xx, eng.next())) {
+        if (wedge_accept<RP_NORM, false, BX>(zt, j, xx, eng.next())) {
             x = neg ? -xx : xx;
             return true;
         }
@@ -327,6 +329,7 @@ struct NormMachine {
 // exactly as written.  About one attempt in twelve reaches this test, so a
 // wavefront meets it at almost every step: the bound saves the two binary64
 // logarithms there.
+template <bool BX>
 __device__ __forceinline__ bool mt_log_test(double u, double x2, double v, double d)
 {
     constexpr double kLn2 = 0x1.62e42fefa39efp-1;
@@ -336,7 +339,7 @@ __device__ __forceinline__ bool mt_log_test(double u, double x2, double v, doubl
     const double e = 0x1p-16 * (1.0 + fabs(lu) + d * (1.0 + fabs(lv))) + 1e-13 * (x2 + d * (1.0 + v));
     if (lu < r - e) return true;
     if (lu > r + e) return false;
-    return log(u) < 0.5 * x2 + d * ((1.0 - v) + log(v));
+    return f_log<BX>(u) < 0.5 * x2 + d * ((1.0 - v) + f_log<BX>(v));
 }
 
 // Marsaglia-Tsang constants of one shape: d = s - 1/3, c = 1/sqrt(9 d) for
@@ -370,7 +373,7 @@ __device__ __forceinline__ GamParam gam_param(double a)
 // doublings exact).  X is drawn before Y.
 // HALF: the float gamma (32-bit items: the float ziggurat's binary32 normal,
 // 24-bit uniforms for the test and the boost; binary64 arithmetic)
-template <int MODE, bool HALF = false>
+template <int MODE, bool HALF = false, bool BX = false>
 struct GamMachine {
     static constexpr bool BETA = MODE != 0;
     GamParam pa, pb;
@@ -389,19 +392,19 @@ struct GamMachine {
         const bool sb = BETA && second;
         const double d = sb ? pb.d : pa.d, c = sb ? pb.c : pa.c;
         double x;
-        if (!zig_candidate<E, HALF>(eng, zt, x)) return false;
+        if (!zig_candidate<E, HALF, BX>(eng, zt, x)) return false;
         double v = 1.0 + c * x;
         if (v <= 0.0) return false;
         v = v * v * v;
         const double u = zig_u<HALF>(eng.next());
         const double x2 = x * x;
         bool acc = u < 1.0 - 0.0331 * (x2 * x2);
-        if (!acc) acc = mt_log_test(u, x2, v, d);
+        if (!acc) acc = mt_log_test<BX>(u, x2, v, d);
         if (!acc) return false;
         double g = d * v;
         if (sb ? pb.boost : pa.boost) {
             const double a = sb ? pb.a : pa.a, ia = sb ? pb.ia : pa.ia;
-            g = g * boost_pow(zig_u<HALF>(eng.next()), a, ia, lt);
+            g = g * boost_pow<BX>(zig_u<HALF>(eng.next()), a, ia, lt);
         }
         if (!BETA) {
             val = g;
@@ -423,7 +426,7 @@ struct GamMachine {
     }
 };
 
-template <class E>
+template <class E, bool BX = false>
 __global__ __launch_bounds__(256) void k_norm_moments(SampArgs s)
 {
     __shared__ ZigLds zt;
@@ -439,7 +442,7 @@ __global__ __launch_bounds__(256) void k_norm_moments(SampArgs s)
     for (uint64_t t = 0; t < s.f.per_stream;) {
         eng.reserve(2);
         double x;
-        if (nm.step(eng, &zt, x)) {
+        if (nm.template step<BX>(eng, &zt, x)) {
             a = a + x;
             q = q + x * x;
             t++;
@@ -452,7 +455,7 @@ __global__ __launch_bounds__(256) void k_norm_moments(SampArgs s)
 
 // Element e draws from substream e.  Lanes take elements e, e + stride, ...
 // and move to their next element as soon as the current one is accepted.
-template <class E, bool BETA>
+template <class E, bool BETA, bool BX = false>
 __global__ __launch_bounds__(256) void k_gamma_elem(SampArgs s)
 {
     __shared__ ZigLds zt;
@@ -463,7 +466,7 @@ __global__ __launch_bounds__(256) void k_gamma_elem(SampArgs s)
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     E eng;
-    GamMachine<BETA> gm;
+    GamMachine<BETA, false, BX> gm;
     bool open = false;
     for (;;) {
         if (!open) {
@@ -492,7 +495,7 @@ __global__ __launch_bounds__(256) void k_gamma_elem(SampArgs s)
 // Row i of z (count rows of per_stream = d values) holds the next d normals
 // of substream i rounded to binary32.  With d a multiple of 4 each lane
 // writes its row as 16-byte pieces.
-template <class E>
+template <class E, bool BX = false>
 __global__ __launch_bounds__(256) void k_norm_rows(SampArgs s)
 {
     __shared__ ZigLds zt;
@@ -508,16 +511,16 @@ __global__ __launch_bounds__(256) void k_norm_rows(SampArgs s)
         for (uint64_t t = 0; t < d; t += 4) {
             float4 v;
             eng.reserve(9);  // four normals rarely take more than nine words
-            v.x = (float)zig_serial<RP_NORM>(&zt, eng);
-            v.y = (float)zig_serial<RP_NORM>(&zt, eng);
-            v.z = (float)zig_serial<RP_NORM>(&zt, eng);
-            v.w = (float)zig_serial<RP_NORM>(&zt, eng);
+            v.x = (float)zig_serial<RP_NORM, BX>(&zt, eng);
+            v.y = (float)zig_serial<RP_NORM, BX>(&zt, eng);
+            v.z = (float)zig_serial<RP_NORM, BX>(&zt, eng);
+            v.w = (float)zig_serial<RP_NORM, BX>(&zt, eng);
             *(float4 *)(row + t) = v;
         }
     } else {
         for (uint64_t t = 0; t < d; t++) {
             eng.reserve(3);
-            row[t] = (float)zig_serial<RP_NORM>(&zt, eng);
+            row[t] = (float)zig_serial<RP_NORM, BX>(&zt, eng);
         }
     }
     if (s.advance) eng.store(s.f, i);
@@ -537,9 +540,12 @@ __global__ __launch_bounds__(256) void k_norm_rows(SampArgs s)
 //   SKEW    mu + sigma (delta |U0| + c U1), U0 then U1 normal,
 //           delta = alpha / sqrt(1 + alpha^2), c = sqrt(1 - delta^2)
 //                                                   xp = {mu, sigma, delta, c}
-template <class E, int LAW>
+// LAWC: the law, with kXfBx for the bitexact setting
+template <class E, int LAWC>
 __global__ __launch_bounds__(256) void k_fill_mix(FillArgs f)
 {
+    constexpr int LAW = xf_law(LAWC);
+    constexpr bool BX = xf_bx(LAWC);
     __shared__ ZigLds zt;
     __shared__ LogLds lt;
     load_zig<RP_NORM>(&zt, f.flags);
@@ -552,7 +558,7 @@ __global__ __launch_bounds__(256) void k_fill_mix(FillArgs f)
     const uint64_t P = f.per_stream;
     double *out = (double *)f.out + i * P;
     constexpr int GM = LAW == RP_LAW_BETA ? 1 : (LAW == RP_LAW_F ? 2 : 0);
-    GamMachine<GM> gm;
+    GamMachine<GM, false, BX> gm;
     NormMachine nm;
     nm.reset();
     if constexpr (LAW == RP_LAW_GAMMA) gm.set(f.xp[0], 1.0);
@@ -572,13 +578,13 @@ __global__ __launch_bounds__(256) void k_fill_mix(FillArgs f)
             }
         } else if constexpr (LAW == RP_LAW_T) {
             if (phase == 0) {
-                if (nm.step(eng, &zt, z0)) phase = 1;
+                if (nm.template step<BX>(eng, &zt, z0)) phase = 1;
             } else if (gm.step(eng, &zt, &lt, v)) {
                 out[t++] = z0 / sqrt((2.0 * v) / f.xp[1]);
                 phase = 0;
             }
         } else {  // skew-normal
-            if (nm.step(eng, &zt, v)) {
+            if (nm.template step<BX>(eng, &zt, v)) {
                 if (phase == 0) {
                     z0 = v;
                     phase = 1;
@@ -592,17 +598,18 @@ __global__ __launch_bounds__(256) void k_fill_mix(FillArgs f)
     eng.store(f, i);
 }
 
-template <class E>
+template <class E, bool BX>
 static int launch_mix_e(int law, const FillArgs &f, hipStream_t st)
 {
     const dim3 grid((unsigned)((f.n + 255) / 256)), block(256);
+    constexpr int B = BX ? kXfBx : 0;
     switch (law) {
-    case RP_LAW_GAMMA: hipLaunchKernelGGL((k_fill_mix<E, RP_LAW_GAMMA>), grid, block, 0, st, f); break;
-    case RP_LAW_BETA: hipLaunchKernelGGL((k_fill_mix<E, RP_LAW_BETA>), grid, block, 0, st, f); break;
-    case RP_LAW_CHI2: hipLaunchKernelGGL((k_fill_mix<E, RP_LAW_CHI2>), grid, block, 0, st, f); break;
-    case RP_LAW_T: hipLaunchKernelGGL((k_fill_mix<E, RP_LAW_T>), grid, block, 0, st, f); break;
-    case RP_LAW_F: hipLaunchKernelGGL((k_fill_mix<E, RP_LAW_F>), grid, block, 0, st, f); break;
-    case RP_LAW_SKEWNORMAL: hipLaunchKernelGGL((k_fill_mix<E, RP_LAW_SKEWNORMAL>), grid, block, 0, st, f); break;
+    case RP_LAW_GAMMA: hipLaunchKernelGGL((k_fill_mix<E, RP_LAW_GAMMA | B>), grid, block, 0, st, f); break;
+    case RP_LAW_BETA: hipLaunchKernelGGL((k_fill_mix<E, RP_LAW_BETA | B>), grid, block, 0, st, f); break;
+    case RP_LAW_CHI2: hipLaunchKernelGGL((k_fill_mix<E, RP_LAW_CHI2 | B>), grid, block, 0, st, f); break;
+    case RP_LAW_T: hipLaunchKernelGGL((k_fill_mix<E, RP_LAW_T | B>), grid, block, 0, st, f); break;
+    case RP_LAW_F: hipLaunchKernelGGL((k_fill_mix<E, RP_LAW_F | B>), grid, block, 0, st, f); break;
+    case RP_LAW_SKEWNORMAL: hipLaunchKernelGGL((k_fill_mix<E, RP_LAW_SKEWNORMAL | B>), grid, block, 0, st, f); break;
     default: return fail(RP_EINVAL, "unknown law");
     }
     return RP_OK;
@@ -610,7 +617,7 @@ static int launch_mix_e(int law, const FillArgs &f, hipStream_t st)
 
 // Float gamma (rp_fill_lawf with RP_LAW_GAMMA): theta G rounded to
 // binary32, G the float Marsaglia-Tsang draw on the substream's items.
-template <class E>
+template <class E, bool BX = false>
 __global__ __launch_bounds__(256) void k_fill_gammaf(FillArgs f)
 {
     __shared__ ZigLds zt;
@@ -625,7 +632,7 @@ __global__ __launch_bounds__(256) void k_fill_gammaf(FillArgs f)
     ItemEng<E> it(eng);
     const uint64_t P = f.per_stream;
     float *out = (float *)f.out + i * P;
-    GamMachine<0, true> gm;
+    GamMachine<0, true, BX> gm;
     gm.set(f.xp[0], 1.0);
     for (uint64_t t = 0; t < P;) {
         double v;
@@ -638,9 +645,11 @@ __global__ __launch_bounds__(256) void k_fill_gammaf(FillArgs f)
 // gamma (GamMachine on 32-bit items, binary64, unrounded) and the binary32
 // normal of the float ziggurat, combined as in k_fill_mix, in binary64, and
 // rounded once to binary32.  xp as for k_fill_mix.
-template <class E, int LAW>
+template <class E, int LAWC>
 __global__ __launch_bounds__(256) void k_fill_mixf(FillArgs f)
 {
+    constexpr int LAW = xf_law(LAWC);
+    constexpr bool BX = xf_bx(LAWC);
     __shared__ ZigLds zt;
     __shared__ LogLds lt;
     load_zig<RP_NORM>(&zt, f.flags);
@@ -654,7 +663,7 @@ __global__ __launch_bounds__(256) void k_fill_mixf(FillArgs f)
     const uint64_t P = f.per_stream;
     float *out = (float *)f.out + i * P;
     constexpr int GM = LAW == RP_LAW_BETA ? 1 : (LAW == RP_LAW_F ? 2 : 0);
-    GamMachine<GM, true> gm;
+    GamMachine<GM, true, BX> gm;
     if constexpr (LAW == RP_LAW_BETA || LAW == RP_LAW_F) gm.set(f.xp[0], f.xp[1]);
     else gm.set(f.xp[0], 1.0);
     for (uint64_t t = 0; t < P;) {
@@ -666,16 +675,16 @@ __global__ __launch_bounds__(256) void k_fill_mixf(FillArgs f)
             }
         } else if constexpr (LAW == RP_LAW_T) {
             double z;
-            while (!zig_candidate<ItemEng<E>, true>(it, &zt, z)) {
+            while (!zig_candidate<ItemEng<E>, true, BX>(it, &zt, z)) {
             }
             while (!gm.step(it, &zt, &lt, v)) {
             }
             out[t++] = (float)(z / sqrt((2.0 * v) / f.xp[1]));
         } else {  // skew-normal
             double z0, z1;
-            while (!zig_candidate<ItemEng<E>, true>(it, &zt, z0)) {
+            while (!zig_candidate<ItemEng<E>, true, BX>(it, &zt, z0)) {
             }
-            while (!zig_candidate<ItemEng<E>, true>(it, &zt, z1)) {
+            while (!zig_candidate<ItemEng<E>, true, BX>(it, &zt, z1)) {
             }
             out[t++] = (float)(f.xp[0] + f.xp[1] * (f.xp[2] * fabs(z0) + f.xp[3] * z1));
         }
@@ -683,21 +692,28 @@ __global__ __launch_bounds__(256) void k_fill_mixf(FillArgs f)
     eng.store(f, i);
 }
 
-template <class E>
-static int launch_mix_any(int law, bool f32, const FillArgs &f, hipStream_t st)
+template <class E, bool BX>
+static int launch_mix_bx(int law, bool f32, const FillArgs &f, hipStream_t st)
 {
-    if (!f32) return launch_mix_e<E>(law, f, st);
+    if (!f32) return launch_mix_e<E, BX>(law, f, st);
     const dim3 grid((unsigned)((f.n + 255) / 256)), block(256);
+    constexpr int B = BX ? kXfBx : 0;
     switch (law) {
-    case RP_LAW_GAMMA: hipLaunchKernelGGL(k_fill_gammaf<E>, grid, block, 0, st, f); break;
-    case RP_LAW_BETA: hipLaunchKernelGGL((k_fill_mixf<E, RP_LAW_BETA>), grid, block, 0, st, f); break;
-    case RP_LAW_CHI2: hipLaunchKernelGGL((k_fill_mixf<E, RP_LAW_CHI2>), grid, block, 0, st, f); break;
-    case RP_LAW_T: hipLaunchKernelGGL((k_fill_mixf<E, RP_LAW_T>), grid, block, 0, st, f); break;
-    case RP_LAW_F: hipLaunchKernelGGL((k_fill_mixf<E, RP_LAW_F>), grid, block, 0, st, f); break;
-    case RP_LAW_SKEWNORMAL: hipLaunchKernelGGL((k_fill_mixf<E, RP_LAW_SKEWNORMAL>), grid, block, 0, st, f); break;
+    case RP_LAW_GAMMA: hipLaunchKernelGGL((k_fill_gammaf<E, BX>), grid, block, 0, st, f); break;
+    case RP_LAW_BETA: hipLaunchKernelGGL((k_fill_mixf<E, RP_LAW_BETA | B>), grid, block, 0, st, f); break;
+    case RP_LAW_CHI2: hipLaunchKernelGGL((k_fill_mixf<E, RP_LAW_CHI2 | B>), grid, block, 0, st, f); break;
+    case RP_LAW_T: hipLaunchKernelGGL((k_fill_mixf<E, RP_LAW_T | B>), grid, block, 0, st, f); break;
+    case RP_LAW_F: hipLaunchKernelGGL((k_fill_mixf<E, RP_LAW_F | B>), grid, block, 0, st, f); break;
+    case RP_LAW_SKEWNORMAL: hipLaunchKernelGGL((k_fill_mixf<E, RP_LAW_SKEWNORMAL | B>), grid, block, 0, st, f); break;
     default: return fail(RP_EINVAL, "unknown law");
     }
     return RP_OK;
+}
+
+template <class E>
+static int launch_mix_any(int law, bool f32, const FillArgs &f, hipStream_t st)
+{
+    return (f.flags & kFlagBitexact) ? launch_mix_bx<E, true>(law, f32, f, st) : launch_mix_bx<E, false>(law, f32, f, st);
 }
 
 int launch_fill_mix(int engine, int law, bool f32, const FillArgs &f, hipStream_t st)
@@ -730,7 +746,10 @@ template <class E>
 static int launch_moments_e(const SampArgs &s, hipStream_t st)
 {
     const uint64_t blocks = (s.count + 255) / 256;
-    hipLaunchKernelGGL((k_norm_moments<E>), dim3((unsigned)blocks), dim3(256), 0, st, s);
+    if (s.f.flags & kFlagBitexact)
+        hipLaunchKernelGGL((k_norm_moments<E, true>), dim3((unsigned)blocks), dim3(256), 0, st, s);
+    else
+        hipLaunchKernelGGL((k_norm_moments<E, false>), dim3((unsigned)blocks), dim3(256), 0, st, s);
     return RP_OK;
 }
 
@@ -739,10 +758,15 @@ static int launch_elem_e(const SampArgs &s, bool beta, hipStream_t st)
 {
     uint64_t blocks = (s.count + 255) / 256;
     if (blocks > 4096) blocks = 4096;  // lanes then take several elements each
-    if (beta)
-        hipLaunchKernelGGL((k_gamma_elem<E, true>), dim3((unsigned)blocks), dim3(256), 0, st, s);
+    const bool bx = (s.f.flags & kFlagBitexact) != 0;
+    if (beta && bx)
+        hipLaunchKernelGGL((k_gamma_elem<E, true, true>), dim3((unsigned)blocks), dim3(256), 0, st, s);
+    else if (beta)
+        hipLaunchKernelGGL((k_gamma_elem<E, true, false>), dim3((unsigned)blocks), dim3(256), 0, st, s);
+    else if (bx)
+        hipLaunchKernelGGL((k_gamma_elem<E, false, true>), dim3((unsigned)blocks), dim3(256), 0, st, s);
     else
-        hipLaunchKernelGGL((k_gamma_elem<E, false>), dim3((unsigned)blocks), dim3(256), 0, st, s);
+        hipLaunchKernelGGL((k_gamma_elem<E, false, false>), dim3((unsigned)blocks), dim3(256), 0, st, s);
     return RP_OK;
 }
 
@@ -770,25 +794,32 @@ int launch_moments(int engine, const SampArgs &s, hipStream_t st)
     return e == hipSuccess ? RP_OK : fail(RP_EDEVICE, "moments launch: %s", hipGetErrorString(e));
 }
 
+template <class E>
+static void launch_rows_e(const SampArgs &s, dim3 grid, dim3 block, hipStream_t st)
+{
+    if (s.f.flags & kFlagBitexact) hipLaunchKernelGGL((k_norm_rows<E, true>), grid, block, 0, st, s);
+    else hipLaunchKernelGGL((k_norm_rows<E, false>), grid, block, 0, st, s);
+}
+
 int launch_norm_rows(int engine, const SampArgs &s, hipStream_t st)
 {
     const dim3 grid((unsigned)((s.count + 255) / 256)), block(256);
     switch (engine) {
-    case RP_X256PP: hipLaunchKernelGGL(k_norm_rows<LaneX256>, grid, block, 0, st, s); break;
-    case RP_X256SS: hipLaunchKernelGGL(k_norm_rows<LaneX256SS>, grid, block, 0, st, s); break;
-    case RP_SQUARES: hipLaunchKernelGGL(k_norm_rows<LaneSquares>, grid, block, 0, st, s); break;
-    case RP_XORO128: hipLaunchKernelGGL(k_norm_rows<LaneXoro128>, grid, block, 0, st, s); break;
-    case RP_XS128: hipLaunchKernelGGL(k_norm_rows<LaneXs128>, grid, block, 0, st, s); break;
-    case RP_CHACHA20: hipLaunchKernelGGL(k_norm_rows<LaneChacha>, grid, block, 0, st, s); break;
-    case RP_PCG64: hipLaunchKernelGGL(k_norm_rows<LanePcg>, grid, block, 0, st, s); break;
-    case RP_PHILOX4X32: hipLaunchKernelGGL(k_norm_rows<LanePhilox32>, grid, block, 0, st, s); break;
-    case RP_PHILOX: hipLaunchKernelGGL(k_norm_rows<LanePhilox64>, grid, block, 0, st, s); break;
-    case RP_SFC64: hipLaunchKernelGGL(k_norm_rows<LaneSfc64>, grid, block, 0, st, s); break;
-    case RP_CWG128: hipLaunchKernelGGL(k_norm_rows<LaneCwg128>, grid, block, 0, st, s); break;
-    case RP_X256PPS: hipLaunchKernelGGL(k_norm_rows<LaneX256Simd>, grid, block, 0, st, s); break;
-    case RP_X256SSS: hipLaunchKernelGGL(k_norm_rows<LaneX256SSSimd>, grid, block, 0, st, s); break;
-    case RP_SFC64S: hipLaunchKernelGGL(k_norm_rows<LaneSfc64Simd>, grid, block, 0, st, s); break;
-    case RP_RANLUX: hipLaunchKernelGGL(k_norm_rows<LaneRanlux>, grid, block, 0, st, s); break;
+    case RP_X256PP: launch_rows_e<LaneX256>(s, grid, block, st); break;
+    case RP_X256SS: launch_rows_e<LaneX256SS>(s, grid, block, st); break;
+    case RP_SQUARES: launch_rows_e<LaneSquares>(s, grid, block, st); break;
+    case RP_XORO128: launch_rows_e<LaneXoro128>(s, grid, block, st); break;
+    case RP_XS128: launch_rows_e<LaneXs128>(s, grid, block, st); break;
+    case RP_CHACHA20: launch_rows_e<LaneChacha>(s, grid, block, st); break;
+    case RP_PCG64: launch_rows_e<LanePcg>(s, grid, block, st); break;
+    case RP_PHILOX4X32: launch_rows_e<LanePhilox32>(s, grid, block, st); break;
+    case RP_PHILOX: launch_rows_e<LanePhilox64>(s, grid, block, st); break;
+    case RP_SFC64: launch_rows_e<LaneSfc64>(s, grid, block, st); break;
+    case RP_CWG128: launch_rows_e<LaneCwg128>(s, grid, block, st); break;
+    case RP_X256PPS: launch_rows_e<LaneX256Simd>(s, grid, block, st); break;
+    case RP_X256SSS: launch_rows_e<LaneX256SSSimd>(s, grid, block, st); break;
+    case RP_SFC64S: launch_rows_e<LaneSfc64Simd>(s, grid, block, st); break;
+    case RP_RANLUX: launch_rows_e<LaneRanlux>(s, grid, block, st); break;
     default: return fail(RP_EINVAL, "unknown engine");
     }
     hipError_t e = hipGetLastError();

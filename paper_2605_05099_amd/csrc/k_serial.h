@@ -274,7 +274,7 @@ __global__ __launch_bounds__(256) void k_ser_gen(SerialArgs a)
 // sample, and the sample.  The decisions are those of the serial ziggurat
 // (zig_serial; the float ziggurat on 32-bit items for binary32 output) and
 // of Lemire's method.
-template <int DIST, int OT>
+template <int DIST, int OT, bool BX = false>
 __device__ __forceinline__ uint32_t ser_attempt(const SerialArgs &a, const ZigLds *zt, uint64_t P, bool &acc,
                                                 typename OutType<DIST, OT>::T &val)
 {
@@ -303,8 +303,8 @@ __device__ __forceinline__ uint32_t ser_attempt(const SerialArgs &a, const ZigLd
             }
             if (j == 0) {
                 for (int it = 0; it < kMaxTailIters; it++) {
-                    const double e1 = -log1p(-zig_u<HALF>(unit(P + 1 + 2 * it))) / RP_ZN_R;
-                    const double e2 = -log1p(-zig_u<HALF>(unit(P + 2 + 2 * it)));
+                    const double e1 = -f_log1p<BX>(-zig_u<HALF>(unit(P + 1 + 2 * it))) / RP_ZN_R;
+                    const double e2 = -f_log1p<BX>(-zig_u<HALF>(unit(P + 2 + 2 * it)));
                     if (e2 + e2 > e1 * e1) {
                         const double t = RP_ZN_R + e1;
                         acc = true;
@@ -315,7 +315,7 @@ __device__ __forceinline__ uint32_t ser_attempt(const SerialArgs &a, const ZigLd
                 acc = false;
                 return 1 + 2 * kMaxTailIters;
             }
-            acc = wedge_accept<DIST, HALF>(zt, j, x, unit(P + 1));
+            acc = wedge_accept<DIST, HALF, BX>(zt, j, x, unit(P + 1));
             val = (typename OutType<DIST, OT>::T)(neg ? -x : x);
             return 2;
         } else {
@@ -329,10 +329,10 @@ __device__ __forceinline__ uint32_t ser_attempt(const SerialArgs &a, const ZigLd
             }
             if (j == 0) {
                 acc = true;
-                val = (typename OutType<DIST, OT>::T)(RP_ZE_R - log1p(-zig_u<HALF>(unit(P + 1))));
+                val = (typename OutType<DIST, OT>::T)(RP_ZE_R - f_log1p<BX>(-zig_u<HALF>(unit(P + 1))));
                 return 2;
             }
-            acc = wedge_accept<DIST, HALF>(zt, j, x, unit(P + 1));
+            acc = wedge_accept<DIST, HALF, BX>(zt, j, x, unit(P + 1));
             val = (typename OutType<DIST, OT>::T)x;
             return 2;
         }
@@ -386,7 +386,7 @@ __device__ __forceinline__ void ser_block_scan(SerMap *buf, SerMap &cur)
     cur = buf[t];
 }
 
-template <int DIST, int OT>
+template <int DIST, int OT, bool BX = false>
 __global__ __launch_bounds__(ser::kBlk) void k_ser_map(SerialArgs a)
 {
     constexpr bool ZIG = DIST == RP_NORM || DIST == RP_EXP;
@@ -405,7 +405,7 @@ __global__ __launch_bounds__(ser::kBlk) void k_ser_map(SerialArgs a)
         for (int p = 0; p < seff; p++) {
             bool acc;
             typename OutType<DIST, OT>::T v;
-            const uint32_t len = ser_attempt<DIST, OT>(a, &zt, c0 + p, acc, v);
+            const uint32_t len = ser_attempt<DIST, OT, BX>(a, &zt, c0 + p, acc, v);
             lens[t][p] = (uint16_t)(len | (acc ? 0x8000u : 0u));
         }
 #pragma unroll
@@ -489,7 +489,7 @@ __global__ __launch_bounds__(1024) void k_ser_blocks(SerialArgs a)
     }
 }
 
-template <int DIST, int OT>
+template <int DIST, int OT, bool BX = false>
 __global__ __launch_bounds__(ser::kBlk) void k_ser_emit(SerialArgs a)
 {
     constexpr bool ZIG = DIST == RP_NORM || DIST == RP_EXP;
@@ -519,7 +519,7 @@ __global__ __launch_bounds__(ser::kBlk) void k_ser_emit(SerialArgs a)
         bool acc;
         T v;
         const uint64_t P = c0 + pos;
-        const uint32_t len = ser_attempt<DIST, OT>(a, &zt, P, acc, v);
+        const uint32_t len = ser_attempt<DIST, OT, BX>(a, &zt, P, acc, v);
         if (acc) {
             out[base] = v;
             if (base == a.n - 1) a.result[0] = P + len;
@@ -571,13 +571,22 @@ int launch_serial_fixed(int engine, int dist, int dtype, const SerialArgs &a, hi
     return e == hipSuccess ? RP_OK : fail(RP_EDEVICE, "serial fill launch: %s", hipGetErrorString(e));
 }
 
+template <int DIST, int OT, bool BX = false>
+static void ser_stitch_bx(const SerialArgs &a, hipStream_t st)
+{
+    const dim3 grid((unsigned)a.nblocks);
+    hipLaunchKernelGGL((k_ser_map<DIST, OT, BX>), grid, dim3(ser::kBlk), 0, st, a);
+    hipLaunchKernelGGL(k_ser_blocks, dim3(1), dim3(1024), 0, st, a);
+    hipLaunchKernelGGL((k_ser_emit<DIST, OT, BX>), grid, dim3(ser::kBlk), 0, st, a);
+}
+
+// the ziggurat's rare paths take exp / log1p: a bitexact instantiation
 template <int DIST, int OT>
 static void ser_stitch_kernels(const SerialArgs &a, hipStream_t st)
 {
-    const dim3 grid((unsigned)a.nblocks);
-    hipLaunchKernelGGL((k_ser_map<DIST, OT>), grid, dim3(ser::kBlk), 0, st, a);
-    hipLaunchKernelGGL(k_ser_blocks, dim3(1), dim3(1024), 0, st, a);
-    hipLaunchKernelGGL((k_ser_emit<DIST, OT>), grid, dim3(ser::kBlk), 0, st, a);
+    if constexpr (DIST == RP_NORM || DIST == RP_EXP)
+        if (a.fa.flags & kFlagBitexact) return ser_stitch_bx<DIST, OT, true>(a, st);
+    ser_stitch_bx<DIST, OT, false>(a, st);
 }
 
 int launch_serial_stitch(int engine, int dist, int dtype, const SerialArgs &a, hipStream_t st)

@@ -40,8 +40,9 @@ struct ZigConsecutive<WavePcg> {
 // blocks per compute unit) measured fastest: 3.2 ms for 2^30 Philox4x32-10
 // normals against 3.6 ms at four and 4.3 ms at eight (spills).  Transforms
 // with exp, log or pow in the store need more registers and take four.
-template <int XF>
+template <int XFC>
 struct ZigWaves {
+    static constexpr int XF = xf_law(XFC);
     static constexpr int value = (XF == 0 || XF == RP_LAW_NORMAL || XF == RP_LAW_EXP) ? 6 : 4;
 };
 
@@ -72,7 +73,7 @@ __global__ __launch_bounds__(256, ZigWaves<XF>::value) void k_zig(FillArgs a)
     uint64_t *const wb = wb_all[wib];
     uint16_t *const rinf = rinf_all[wib];
     double *const out = (double *)a.out + sub * P;
-    const bool squeeze = !(a.flags & kFlagNoSqueeze);
+    const int zflags = a.flags;  // squeeze switch and bitexact setting
 
     // Engines whose consecutive words are cheaper than the store-order ones
     // (PCG64: ordinary steps instead of stride-127 jumps) generate R
@@ -163,8 +164,8 @@ __global__ __launch_bounds__(256, ZigWaves<XF>::value) void k_zig(FillArgs a)
             bool acc = false, hu_o = false;
             double cv = 0.0;
             uint64_t u1o = 0;
-            int L = zig_resolve<DIST, false>(
-                zt, c_w0, [&](int k) { return (hu && k == 1) ? c_u1 : wb[k - 1 - hu]; }, CHW + hu, squeeze, acc, cv,
+            int L = zig_resolve<DIST, false, false, xf_bx(XF)>(
+                zt, c_w0, [&](int k) { return (hu && k == 1) ? c_u1 : wb[k - 1 - hu]; }, CHW + hu, zflags, acc, cv,
                 hu_o, u1o);
             L = __builtin_amdgcn_readfirstlane(L);
             if (L == 0) {  // it uses the whole chunk
@@ -201,8 +202,8 @@ __global__ __launch_bounds__(256, ZigWaves<XF>::value) void k_zig(FillArgs a)
                 bool acc, hu_o;
                 double val;
                 uint64_t u1o;
-                const int L = zig_resolve<DIST, false>(
-                    zt, w0, [&](int k) { return wb[p + k]; }, CHW - 1 - p, squeeze, acc, val, hu_o, u1o);
+                const int L = zig_resolve<DIST, false, false, xf_bx(XF)>(
+                    zt, w0, [&](int k) { return wb[p + k]; }, CHW - 1 - p, zflags, acc, val, hu_o, u1o);
                 rinf[p] = (uint16_t)(L | (acc ? 0x8000 : 0));
                 accb |= (acc ? 1u : 0u) << i;
                 if ((w0 & 0xff) == 0) {
@@ -386,8 +387,8 @@ __global__ __launch_bounds__(256, ZigWaves<XF>::value) void k_zig(FillArgs a)
                         if ((w0 & 0xff) == 0) {
                             bool acc, hu_o;
                             uint64_t u1o;
-                            (void)zig_resolve<DIST, false>(
-                                zt, w0, [&](int k) { return wb[p + k]; }, CHW - 1 - p, squeeze, acc, x, hu_o, u1o);
+                            (void)zig_resolve<DIST, false, false, xf_bx(XF)>(
+                                zt, w0, [&](int k) { return wb[p + k]; }, CHW - 1 - p, zflags, acc, x, hu_o, u1o);
                         }
                     }
                     dst[idx] = xform<XF>(x, a);
@@ -410,8 +411,8 @@ __global__ __launch_bounds__(256, ZigWaves<XF>::value) void k_zig(FillArgs a)
                 double cv;
                 uint64_t u1o = 0;
                 const int p = pend_q;
-                (void)zig_resolve<DIST, false>(
-                    zt, c_w0, [&](int k) { return wb[p + k]; }, CHW - 1 - p, squeeze, acc, cv, hu_o, u1o);
+                (void)zig_resolve<DIST, false, false, xf_bx(XF)>(
+                    zt, c_w0, [&](int k) { return wb[p + k]; }, CHW - 1 - p, zflags, acc, cv, hu_o, u1o);
                 c_hu = __builtin_amdgcn_readfirstlane(hu_o ? 1 : 0) != 0;
                 c_u1 = uni64(u1o);
             }

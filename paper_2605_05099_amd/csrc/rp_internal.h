@@ -18,6 +18,7 @@ struct rp_rng {
     std::string err;
     bool full_mantissa = true;  // U(0,1) by method 1 (53/24 bits); false: method 2 (52/23)
     bool squeeze = true;        // ziggurat wedge tests decided by the squeeze where it can
+    bool bitexact = false;      // every exp / log / log1p / pow of a sampler correctly rounded
 };
 
 struct rp_streams {
@@ -29,6 +30,7 @@ struct rp_streams {
     int device = 0;
     bool full_mantissa = true;    // taken from the base stream at creation
     bool squeeze = true;          // taken from the base stream at creation
+    bool bitexact = false;        // taken from the base stream at creation
 };
 
 namespace rp {
@@ -54,9 +56,13 @@ int ensure_device_tables();
 
 // internal bits of FillArgs::flags (above the public per-call flags)
 constexpr int kFlagNoSqueeze = 1 << 16;  // wedge tests evaluate f(x) every time
+constexpr int kFlagBitexact = 1 << 17;   // correctly rounded elementary functions
 
 // the FillArgs flag bits a substream set's settings imply
-inline int settings_flags(const rp_streams *s) { return s->squeeze ? 0 : kFlagNoSqueeze; }
+inline int settings_flags(const rp_streams *s)
+{
+    return (s->squeeze ? 0 : kFlagNoSqueeze) | (s->bitexact ? kFlagBitexact : 0);
+}
 
 // ---- kernel launchers (fill.hip) -------------------------------------------
 struct FillArgs {

@@ -92,7 +92,7 @@ def test_streams_deserialize_rejects_bad_images():
                 + struct.pack(f"<{len(phase)}I", *phase))
 
     L = rp.lib()
-    for bad in (image(magic=0), image(engine=len(rp.ENGINES)), image(nw=3), image(fm=4),
+    for bad in (image(magic=0), image(engine=len(rp.ENGINES)), image(nw=3), image(fm=8),
                 image(n=0, words=[], phase=()), image(phase=(0, 1)), image()[:-1], image()[:23]):
         assert L.rp_streams_deserialize(bad, len(bad), ctypes.byref(out)) == rp.RP_EINVAL
         assert not out.value
@@ -343,16 +343,22 @@ def test_streams_deserialize_rejects_invalid_states():
 
 def test_settings_flags():
     """rp_set_flag / rp_get_flag: the full-mantissa setting and the squeeze,
-    both on by default, 0 or 1 only, copied by duplicate, kept by seeding."""
+    both on by default, and bitexact, off by default; 0 or 1 only, copied by
+    duplicate, kept by seeding."""
     r = rp.rp_create("philox4x32")
     assert r.get_flag(rp.RP_FULL_MANTISSA) and r.get_flag(rp.RP_SQUEEZE)
+    assert r.get_flag(rp.RP_BITEXACT) == 0
+    r.set_flag(rp.RP_BITEXACT, 1).seed(5)
+    assert r.get_flag(rp.RP_BITEXACT) == 1 and r.duplicate().get_flag(rp.RP_BITEXACT) == 1
+    r.set_flag(rp.RP_BITEXACT, 0)
     r.set_flag(rp.RP_SQUEEZE, 0).seed(4)
     assert not r.get_flag(rp.RP_SQUEEZE) and r.get_flag(rp.RP_FULL_MANTISSA)
     assert not r.duplicate().get_flag(rp.RP_SQUEEZE)
     r.set_flag(rp.RP_FULL_MANTISSA, 0)
     assert r.full_mantissa is False
     L = rp.lib()
-    assert L.rp_set_flag(r.h, 3, 1) == rp.RP_EINVAL
+    assert L.rp_set_flag(r.h, 4, 1) == rp.RP_EINVAL
+    assert L.rp_set_flag(r.h, rp.RP_BITEXACT, 2) == rp.RP_EINVAL
     assert L.rp_set_flag(r.h, rp.RP_SQUEEZE, 2) == rp.RP_EINVAL
     assert L.rp_get_flag(r.h, 0) == rp.RP_EINVAL
     assert L.rp_set_flag(None, rp.RP_SQUEEZE, 1) == rp.RP_ENULL
