@@ -97,6 +97,8 @@ _SIGS = {
     "rp_sample": ([_vp, _u32, _u32, _vp, _vp], _int),
     "rp_sample_noalloc": ([_vp, _u32, _u32, _vp, _vp], _int),
     "rp_crmath_host": ([_int, _vp, _vp, _vp, _u64], _int),
+    "rp_gamma_grad_host": ([_vp, _vp, _vp, _vp, _u64], _int),
+    "rp_beta_grad_host": ([_vp, _vp, _vp, _vp, _vp, _vp, _u64], _int),
     "rp_crmath": ([_int, _vp, _vp, _vp, _u64, _vp], _int),
     "rp_mvn": ([_vp, _vp, _vp, _int, _u64, _vp, _vp], _int),
     "rp_mvn_backward": ([_vp, _vp, _int, _u64, _vp, _vp, _vp], _int),
@@ -219,6 +221,22 @@ def rp_crmath_host(fn, x, y=None):
     out = np.empty_like(x)
     _check(lib().rp_crmath_host(fn, _ptr(x), _ptr(yy) if yy is not None else None, _ptr(out), len(x)))
     return out
+
+
+def rp_gamma_grad_host(z, alpha, gz):
+    """Binary64 gradient evaluation on the host (numpy float32 arrays)."""
+    z, alpha, gz = (np.ascontiguousarray(np.asarray(v, dtype=np.float32).reshape(-1)) for v in (z, alpha, gz))
+    out = np.empty_like(z)
+    _check(lib().rp_gamma_grad_host(_ptr(z), _ptr(alpha), _ptr(gz), _ptr(out), len(z)))
+    return out
+
+
+def rp_beta_grad_host(z, a, b, gz):
+    """Binary64 gradient evaluation on the host (numpy float32 arrays)."""
+    z, a, b, gz = (np.ascontiguousarray(np.asarray(v, dtype=np.float32).reshape(-1)) for v in (z, a, b, gz))
+    ga, gb = np.empty_like(z), np.empty_like(z)
+    _check(lib().rp_beta_grad_host(_ptr(z), _ptr(a), _ptr(b), _ptr(gz), _ptr(ga), _ptr(gb), len(z)))
+    return ga, gb
 
 
 def rp_crmath(fn, x, y, out, stream=None):

@@ -29,6 +29,13 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", f"--offload-arch={A
           "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unknown-pragmas"]
 
 
+# per-source flags: the gradient kernels flush binary32 subnormals (their
+# binary32 series run an order of magnitude slower on subnormal terms;
+# binary64 keeps gradual underflow, and elements whose binary32 evaluation
+# could meet a subnormal are evaluated in binary64)
+EXTRA = {"k_grad.hip": ["-fgpu-flush-denormals-to-zero"]}
+
+
 def hipcc():
     for c in (shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
         if c and os.path.exists(c):
@@ -49,7 +56,7 @@ def _compile(src, incremental=False):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     if incremental and not _stale(src, obj):
         return obj, ""
-    cmd = [hipcc(), *COMMON, "-c", src, "-o", obj]
+    cmd = [hipcc(), *COMMON, *EXTRA.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:
