@@ -113,6 +113,34 @@ def test_batched_matches_oracle_with_replays(kind):
         assert [int(words[k, i]) for k in range(3)] == oracle_stream(engine, i).state[:3]
 
 
+@pytest.mark.parametrize("kind", ["gamma", "beta"])
+@pytest.mark.parametrize("engine", ["philox4x32", "philox"])
+def test_batched_long_sets(engine, kind):
+    """Sets of a few thousand values among short ones (the longest sets sort
+    first and run longest): values, decisions and final states must be the
+    oracle's, on both sides of the shape-1 boundary; two calls in a row
+    (graph replay) continue every substream."""
+    n = 160
+    g = np.random.default_rng(9)
+    alpha = np.exp(g.uniform(np.log(0.05), np.log(30.0), n))
+    alpha[:4] = [0.3, 0.999, 1.0, 7.5]
+    bpar = np.exp(g.uniform(np.log(0.1), np.log(10.0), n))
+    count = g.integers(0, 60, n).astype(np.int64)
+    count[::16] = g.integers(1025, 3000, len(count[::16]))  # ten long sets
+    count[1] = 1025
+    count[2] = 1024
+    params = (alpha,) if kind == "gamma" else (np.clip(alpha, 0.1, 10.0), bpar)
+    total = int(count.sum())
+    S = make_streams(engine, n)
+    ostreams = [oracle_stream(engine, i) for i in range(n)]
+    plan = rp.rp_plan_create()
+    for rep in range(2):
+        got = _run(kind, S, params, count, plan, total)
+        ref, ostreams = _oracle(kind, ostreams, params, count)
+        _compare(got, ref, _exact_mask(kind, params, count), _tol(kind))
+        _states_equal(S, engine, ostreams)
+
+
 @pytest.mark.parametrize("engine", ENGINES)
 def test_batched_all_engines(engine):
     n = 300 if engine != "ranlux++" else 120
