@@ -53,7 +53,7 @@ def alu_ops_per_value(fill):
 METRIC = "Gsamples/s per engine x distribution, % HBM-write roofline; gamma grad/s"
 # counter summaries: profiles/pmc_fill_<engine>_<output>.md
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_fill_{}.md")
-KERNEL_SOURCES = ["fill.hip", "engines.h", "rp_internal.h", "zig_tables.inc"]
+KERNEL_SOURCES = ["fill.hip", "engines.h", "rp_internal.h", "zig_tables.inc", "k_zig.h", "crmath.h", "crmath_tables.inc"]
 
 
 def parse():
