@@ -725,17 +725,21 @@ template <int DIST>
 struct ZigG {
     // Each table address passes through an opaque copy where it is used: the
     // wedge test is a rare path, and five table addresses hoisted out of the
-    // chunk loop would hold ten scalar registers for the whole kernel.
-    static __device__ __forceinline__ const double *opaque(const double *p)
+    // chunk loop would hold ten scalar registers for the whole kernel.  The
+    // copy is an integer, turned back into a global pointer, so that the
+    // loads stay global loads, issued together.
+    using GP = const __attribute__((address_space(1))) double *;
+    static __device__ __forceinline__ double ld(const double *p, int j)
     {
-        asm volatile("" : "+s"(p));
-        return p;
+        uint64_t a = (uint64_t)p;
+        asm volatile("" : "+s"(a));
+        return ((GP)a)[j];
     }
-    static __device__ __forceinline__ double F(int j) { return opaque(DIST == RP_NORM ? RP_ZN_F : RP_ZE_F)[j]; }
-    static __device__ __forceinline__ double X(int j) { return opaque(DIST == RP_NORM ? RP_ZN_X : RP_ZE_X)[j]; }
-    static __device__ __forceinline__ double S(int j) { return opaque(DIST == RP_NORM ? RP_ZN_S : RP_ZE_S)[j]; }
-    static __device__ __forceinline__ double DP(int j) { return opaque(DIST == RP_NORM ? RP_ZN_DP : RP_ZE_DP)[j]; }
-    static __device__ __forceinline__ double DM(int j) { return opaque(DIST == RP_NORM ? RP_ZN_DM : RP_ZE_DM)[j]; }
+    static __device__ __forceinline__ double F(int j) { return ld(DIST == RP_NORM ? RP_ZN_F : RP_ZE_F, j); }
+    static __device__ __forceinline__ double X(int j) { return ld(DIST == RP_NORM ? RP_ZN_X : RP_ZE_X, j); }
+    static __device__ __forceinline__ double S(int j) { return ld(DIST == RP_NORM ? RP_ZN_S : RP_ZE_S, j); }
+    static __device__ __forceinline__ double DP(int j) { return ld(DIST == RP_NORM ? RP_ZN_DP : RP_ZE_DP, j); }
+    static __device__ __forceinline__ double DM(int j) { return ld(DIST == RP_NORM ? RP_ZN_DM : RP_ZE_DM, j); }
 };
 
 // INL: exp and log1p inline (no calls, so no registers saved around them).
@@ -761,11 +765,13 @@ __device__ __forceinline__ int zig_resolve(const WKe *t, uint64_t w0, Word word,
             const double ax = DIST == RP_NORM ? fabs(x) : x;
             const double U = zig_u<HALF>(u);
             using G = ZigG<DIST>;
-            const double fj = G::F(j), fj1 = G::F(j - 1);
+            // every table value loaded up front: one memory round trip
+            const double fj = G::F(j), fj1 = G::F(j - 1), sj = G::S(j), xj1 = G::X(j - 1);
+            const double dm = G::DM(j), dp = G::DP(j);
             const double y = fj + U * (fj1 - fj);
-            const double l = fj1 + G::S(j) * (ax - G::X(j - 1));
-            if (squeeze && y < l - G::DM(j)) accepted = true;
-            else if (squeeze && y > l + G::DP(j)) accepted = false;
+            const double l = fj1 + sj * (ax - xj1);
+            if (squeeze && y < l - dm) accepted = true;
+            else if (squeeze && y > l + dp) accepted = false;
             else accepted = y < EXP(DIST == RP_NORM ? -0.5 * ax * ax : -ax);
         } else {
             val = RP_ZE_R - LOG1P(-zig_u<HALF>(u));

@@ -18,10 +18,13 @@
 //     sample and a few mask operations give the group's values; otherwise a
 //     scalar walk over the long items in stream order decides which start
 //     samples (one inside an earlier long sample does not) and which fast
-//     words they cover.  The group's values are then formed again from the
-//     words in LDS (a wedge accept has the fast candidate's value, a tail is
-//     resolved once more) and stored at their ranks in stream order
-//     (ballot + mbcnt), which keeps no per-word value live across the chunk.
+//     words they cover.  Only a group where a normal tail starts takes the
+//     walk on its account.  The values are stored at their ranks in stream
+//     order (ballot + mbcnt); a wedge accept has the fast candidate's value.
+//     A tail that yields is resolved once more from the words in LDS: the
+//     exponential one where it is stored, the normal one (its own loop of
+//     pairs) after the walk, written by the same lane over the candidate
+//     stored at its rank.
 //
 // A sample that needs words past the chunk is carried into the next chunk
 // (its first word, and for the normal tail an unused first word of a
@@ -61,6 +64,11 @@ __global__ __launch_bounds__(256, ZigWaves<XF>::value) void k_zig(FillArgs a)
     __shared__ __align__(16) WKe zt[256];
     __shared__ __align__(16) uint64_t wb_all[4][CHW];
     __shared__ uint16_t rinf_all[4][CHW];  // long item at a position: words used | 0x8000 if it yields
+    // normal tails with a value: each walked group's final masks and first
+    // rank, for the fix-up after the walk
+    constexpr bool TFIX = DIST == RP_NORM;
+    __shared__ uint64_t fy_all[4][TFIX ? R : 1];
+    __shared__ uint32_t fnv_all[4][TFIX ? NG : 1];
     for (int k = threadIdx.x; k < 256; k += blockDim.x) {
         zt[k].w = DIST == RP_NORM ? RP_ZN_W[k] : RP_ZE_W[k];
         zt[k].k = DIST == RP_NORM ? RP_ZN_K[k] : RP_ZE_K[k];
@@ -191,6 +199,7 @@ __global__ __launch_bounds__(256, ZigWaves<XF>::value) void k_zig(FillArgs a)
         }
         uint32_t rem = lb & live;
         uint32_t accb = 0;       // bit i: long item i yields a value if it starts a sample
+        uint32_t tlb = 0;        // bit i: long item i starts a normal tail
         bool tails = false;      // a normal tail (words used vary) among the long items
         bool tail_vals = false;  // a tail (strip 0) that yields a value
         while (__ballot(rem != 0)) {
@@ -209,6 +218,7 @@ __global__ __launch_bounds__(256, ZigWaves<XF>::value) void k_zig(FillArgs a)
                 if ((w0 & 0xff) == 0) {
                     tails = tails || DIST == RP_NORM;
                     tail_vals = tail_vals || acc;
+                    if (DIST == RP_NORM) tlb |= 1u << i;
                 }
             }
         }
@@ -226,6 +236,7 @@ __global__ __launch_bounds__(256, ZigWaves<XF>::value) void k_zig(FillArgs a)
         double *const dst = out + produced;
         uint32_t nv = 0;                     // values of this chunk so far
         bool done = false;
+        int walked = 0;                      // groups walked (tail fix-up)
         if (have_first) {
             if (lane == 0) dst[0] = xform<XF>(first_v, a);
             nv = 1;
@@ -262,7 +273,16 @@ __global__ __launch_bounds__(256, ZigWaves<XF>::value) void k_zig(FillArgs a)
 #pragma unroll
             for (int j = 0; j < G; j++) chain |= Cn[j] & Lm[j];
             const bool last_long = g == NG - 1 && (Lm[G - 1] >> 63) != 0;
-            if (!any_tail && !chain && !last_long) {
+            // only a group where a normal tail starts needs the walk for its
+            // sake (a tail before it is seen through cover_end)
+            bool gtail = false;
+            if (any_tail) {
+                uint64_t tm = 0;
+#pragma unroll
+                for (int j = 0; j < G; j++) tm |= __ballot((tlb >> (G * g + j)) & 1);
+                gtail = tm != 0;
+            }
+            if (!gtail && !chain && !last_long) {
                 // common case: every long item starts a two-word sample and
                 // covers only the word after it
 #pragma unroll
@@ -370,6 +390,14 @@ __global__ __launch_bounds__(256, ZigWaves<XF>::value) void k_zig(FillArgs a)
                 cnt = (uint32_t)(need - nv);
                 done = true;
             }
+            if (TFIX && any_tail_val) {
+                if (lane == 0) {
+#pragma unroll
+                    for (int j = 0; j < G; j++) fy_all[wib][G * g + j] = Y[j];
+                    fnv_all[wib][g] = nv;
+                }
+                walked = g + 1;
+            }
             // values at their ranks in stream order
             uint32_t idx = nv;
 #pragma unroll
@@ -379,7 +407,7 @@ __global__ __launch_bounds__(256, ZigWaves<XF>::value) void k_zig(FillArgs a)
                 const bool mine = (Y[j] >> lane) & 1;
                 if (mine) {
                     double x = v[G * g + j];
-                    if (any_tail_val && ((Lm[j] >> lane) & 1)) {
+                    if (!TFIX && any_tail_val && ((Lm[j] >> lane) & 1)) {
                         // a tail (strip 0) that starts a sample: its value
                         // from the tail draw, resolved again
                         const int p = g0 + G * lane + j;
@@ -396,6 +424,36 @@ __global__ __launch_bounds__(256, ZigWaves<XF>::value) void k_zig(FillArgs a)
                 idx += mine ? 1u : 0u;
             }
             nv += cnt;
+        }
+        if (TFIX && any_tail_val) {
+            // A normal tail that starts a sample was stored above with its
+            // fast candidate; the same lane stores its value over it, resolved
+            // again from the words in LDS.  Kept out of the unrolled walk:
+            // inline there, the rare resolution costs the common path.
+            wave_sync();
+#pragma unroll 1
+            for (int g = 0; g < walked; g++) {
+                uint64_t Yg[G];
+#pragma unroll
+                for (int j = 0; j < G; j++) Yg[j] = uni64(fy_all[wib][G * g + j]);
+                uint32_t idx = (uint32_t)__builtin_amdgcn_readfirstlane((int)fnv_all[wib][g]);
+#pragma unroll
+                for (int j = 0; j < G; j++) idx += mbcnt64(Yg[j]);
+#pragma unroll
+                for (int j = 0; j < G; j++) {
+                    const bool mine = (Yg[j] >> lane) & 1;
+                    if (mine && ((tlb >> (G * g + j)) & 1)) {
+                        const int p = GW * g + G * lane + j;
+                        bool acc, hu_o;
+                        uint64_t u1o;
+                        double x;
+                        (void)zig_resolve<DIST, false, false, xf_bx(XF)>(
+                            zt, wb[p], [&](int k) { return wb[p + k]; }, CHW - 1 - p, zflags, acc, x, hu_o, u1o);
+                        dst[idx] = xform<XF>(x, a);
+                    }
+                    idx += mine ? 1u : 0u;
+                }
+            }
         }
         produced += nv;
         if (done) break;
