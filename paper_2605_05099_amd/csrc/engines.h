@@ -23,6 +23,23 @@ RP_HD uint64_t mulhi64(uint64_t a, uint64_t b)
 #endif
 }
 
+// a ^ b ^ c: on the device one three-input bitwise instruction of gfx950
+// (truth table 0x96), where the compiler would otherwise issue two xors
+RP_HD uint32_t xor3_32(uint32_t a, uint32_t b, uint32_t c)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+#else
+    return a ^ b ^ c;
+#endif
+}
+
+RP_HD uint64_t xor3_64(uint64_t a, uint64_t b, uint64_t c)
+{
+    return (uint64_t)xor3_32((uint32_t)a, (uint32_t)b, (uint32_t)c) |
+           ((uint64_t)xor3_32((uint32_t)(a >> 32), (uint32_t)(b >> 32), (uint32_t)(c >> 32)) << 32);
+}
+
 // ---------------------------------------------------------------------------
 // 128-bit unsigned arithmetic (PCG64 state, Philox4x32 counter).
 struct u128 {
@@ -214,8 +231,8 @@ RP_HD void philox4x32(uint64_t c_lo, uint64_t c_hi, uint64_t key, uint64_t &w0, 
     for (int r = 0; r < 10; r++) {
         uint64_t p0 = (uint64_t)kPh32M0 * x0;
         uint64_t p1 = (uint64_t)kPh32M1 * x2;
-        uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
-        uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        uint32_t y0 = xor3_32((uint32_t)(p1 >> 32), x1, k0);
+        uint32_t y2 = xor3_32((uint32_t)(p0 >> 32), x3, k1);
         x1 = (uint32_t)p1;
         x3 = (uint32_t)p0;
         x0 = y0;
@@ -234,8 +251,8 @@ RP_HD void philox4x64(const uint64_t c[4], uint64_t k0, uint64_t k1, uint64_t ou
     for (int r = 0; r < 10; r++) {
         uint64_t h0 = mulhi64(kPh64M0, x0), l0 = kPh64M0 * x0;
         uint64_t h1 = mulhi64(kPh64M1, x2), l1 = kPh64M1 * x2;
-        uint64_t y0 = h1 ^ x1 ^ k0;
-        uint64_t y2 = h0 ^ x3 ^ k1;
+        uint64_t y0 = xor3_64(h1, x1, k0);
+        uint64_t y2 = xor3_64(h0, x3, k1);
         x1 = l1;
         x3 = l0;
         x0 = y0;
