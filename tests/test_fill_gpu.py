@@ -99,6 +99,29 @@ def test_ziggurat_long_run_with_tails(engine, dtype):
     assert tails > 30
 
 
+@pytest.mark.parametrize("dist", [rp.RP_NORM, rp.RP_EXP])
+@pytest.mark.parametrize("engine", ["philox4x32", "pcg64", "philox", "squares"])
+def test_ziggurat_tails_across_ragged_calls(engine, dist):
+    """The store-order ziggurat over successive calls of ragged lengths (a
+    call ending inside a group of 128 positions, samples carried across
+    chunks and calls) with a few hundred tail draws among them: a tail's
+    value written after the walk, the walk taken only by groups where a
+    normal tail starts.  Values, decisions and states equal the oracle's."""
+    n = 400
+    S = make_streams(engine, n)
+    ost = {i: oracle_stream(engine, i) for i in range(n)}
+    r = 3.6541528853610088 if dist == rp.RP_NORM else 7.69711747013105
+    tails = 0
+    for per in (1, 2, 7, 64, 130, 511, 512, 513, 1000):
+        got = _gpu_fill(S, dist, rp.RP_F64, per, 0, 0)
+        for i in range(n):
+            ref = oracle_fill(ost[i], dist, rp.RP_F64, per)
+            _compare(got[i], ref, dist)
+            tails += int((np.abs(ref) > r).sum())
+        _states_equal(S, engine, ost)
+    assert tails > 100
+
+
 @pytest.mark.parametrize("engine", ["philox4x32", "pcg64", "philox", "x256++", "sfc64"])
 def test_float_exponential_long_run_with_tails(engine):
     """Float exponentials over many chunks; the tail (P = 4.5e-4) included."""
