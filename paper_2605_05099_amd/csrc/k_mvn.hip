@@ -94,7 +94,7 @@ constexpr int kFCpr = kFK / 4;   // threads per operand row of a stage (16 bytes
 constexpr int kFRpp = 256 / kFCpr;  // operand rows per pass of the block
 
 template <int BN>
-__global__ __launch_bounds__(256) void k_mvn_fwd(const float *Z, const float *L, const float *mu, float *X,
+__global__ __launch_bounds__(256, 3) void k_mvn_fwd(const float *Z, const float *L, const float *mu, float *X,
                                                  uint64_t n, int d, unsigned ncol_tiles, int vec, const int *upper)
 {
     constexpr int TN = BN / 64;
@@ -154,9 +154,15 @@ __global__ __launch_bounds__(256) void k_mvn_fwd(const float *Z, const float *L,
 #pragma unroll
             for (int r = 0; r < NB; r++) *(float4 *)&Bs[buf][(lr + r * kFRpp) * kFLd + lc] = rb[r];
         };
-        auto compute = [&](int buf) {
+        // with a triangular factor, the k steps past a 32-column sub-tile's
+        // last column multiply zeros: the sub-tile skips them
+        int jlast[TN];
+#pragma unroll
+        for (int b = 0; b < TN; b++) jlast[b] = tri ? col0 + wc * (BN / 2) + b * 32 + 31 : d;
+        auto compute = [&](int buf, int kt) {
 #pragma unroll
             for (int s = 0; s < kFK / 8; s++) {
+                const int k8 = kt * kFK + 8 * s;  // first k of this step
                 float4 af[2], bf[TN];
 #pragma unroll
                 for (int a = 0; a < 2; a++)
@@ -168,6 +174,7 @@ __global__ __launch_bounds__(256) void k_mvn_fwd(const float *Z, const float *L,
                 for (int a = 0; a < 2; a++)
 #pragma unroll
                     for (int b = 0; b < TN; b++) {
+                        if (k8 > jlast[b]) continue;  // wave-uniform
                         acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a].x, bf[b].x, acc[a][b], 0, 0, 0);
                         acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a].y, bf[b].y, acc[a][b], 0, 0, 0);
                         acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a].z, bf[b].z, acc[a][b], 0, 0, 0);
@@ -180,7 +187,7 @@ __global__ __launch_bounds__(256) void k_mvn_fwd(const float *Z, const float *L,
         __syncthreads();
         if (nk > 1) gload(1);
         for (int kt = 0; kt < nk; kt++) {
-            compute(kt & 1);
+            compute(kt & 1, kt);
             if (kt + 1 < nk) {
                 swrite((kt + 1) & 1);
                 __syncthreads();
